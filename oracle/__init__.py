@@ -1,0 +1,8 @@
+"""FP64 CPU oracle for GlassNet (test infrastructure only).
+
+Only tests, the smoke check and the benchmark's CPU-baseline leg import this
+package.  It shares no code with the HIP library and never imports it.
+"""
+from .glassnet_oracle import (alpha_blend, all_slot_orders, forward,  # noqa: F401
+                              forward_bruteforce, grad, l1_loss, n_params, pack,
+                              relu_signature, unpack)

@@ -1,0 +1,357 @@
+"""FP64 CPU oracle for GlassNet's per-pixel evaluation.  TEST INFRASTRUCTURE ONLY.
+
+Only the test-suite, the smoke check and the benchmark's CPU-baseline leg may
+import this module.  The HIP library never calls it and shares no code with it.
+
+What is computed (Zhang & Simo-Serra, "Neural Scene Baking for Permutation
+Invariant Transparency Rendering with Real-time Global Illumination"):
+
+  Sec. 3.4  F, the scene encoder, maps the opaque G-buffer plus the variable
+            scene parameters to the scene representation sigma.
+  Sec. 3.3, Eq. (5)
+            tau = g(h(b_1, sigma), ..., h(b_t, sigma)) with g = addition: one
+            network h shared by every transparency buffer b_i, followed by a
+            symmetric pool, hence permutation invariant.
+  Sec. 3.4  B blends sigma and tau into the neural buffer phi; R maps phi and
+            the direct light L_d to the output radiance.
+  Sec. 3.5  Training uses an L1 term (the SSIM term is not part of this oracle).
+
+Readings where the paper leaves details open (each listed in the design notes):
+  * every network is a per-pixel 3-layer MLP (Linear-ReLU-Linear-ReLU-Linear),
+    hidden and latent width W, R has 3 linear outputs;
+  * h takes the concatenation [b_i ; sigma] (slot channels first);
+  * slot i participates iff alpha_i > 0 (hard mask, no gradient through it);
+  * pool "sum" is Eq. (5) literally; pool "mean" divides by max(#active, 1);
+    no active slot gives tau = 0;
+  * B takes [sigma ; tau]; R takes [phi ; L_d] with L_d = G-buffer planes 11..13;
+  * L1 loss = mean |y - t| over every output element, with subgradient 0 at
+    y == t and ReLU'(0) = 0.
+
+Everything is evaluated in float64 from the float32 inputs, literally in the
+order above: no hoisting of sigma out of h, no fusion.  `forward_bruteforce`
+is a scalar Python-loop twin used to pin `forward` on tiny inputs.
+"""
+from __future__ import annotations
+
+import itertools
+
+import numpy as np
+
+NG, NL, NS, NOUT = 14, 12, 16, 3
+NETS = ("F", "T", "B", "R")
+
+
+def _shapes(W):
+    fan_in = {"F": (NG + NS, W, W), "T": (NL + W, W, W), "B": (2 * W, W, W),
+              "R": (W + 3, W, W)}
+    fan_out = {"F": (W, W, W), "T": (W, W, W), "B": (W, W, W), "R": (W, W, NOUT)}
+    return fan_in, fan_out
+
+
+def n_params(W: int) -> int:
+    fi, fo = _shapes(W)
+    return sum(fo[n][j] * fi[n][j] + fo[n][j] for n in NETS for j in range(3))
+
+
+def unpack(w, W: int):
+    """Flat float vector -> {net: [(A1, c1), (A2, c2), (A3, c3)]} in float64.
+
+    Order: nets F, T, B, R; layers 1..3; matrix row-major [out][in], then bias.
+    """
+    w = np.asarray(w, dtype=np.float64).ravel()
+    if w.size != n_params(W):
+        raise ValueError(f"expected {n_params(W)} weights for W={W}, got {w.size}")
+    fi, fo = _shapes(W)
+    out, off = {}, 0
+    for net in NETS:
+        layers = []
+        for j in range(3):
+            o, i = fo[net][j], fi[net][j]
+            A = w[off:off + o * i].reshape(o, i)
+            off += o * i
+            c = w[off:off + o]
+            off += o
+            layers.append((A, c))
+        out[net] = layers
+    return out
+
+
+def pack(params) -> np.ndarray:
+    """Inverse of `unpack` (used to build gradients in the same layout)."""
+    parts = []
+    for net in NETS:
+        for A, c in params[net]:
+            parts.append(np.asarray(A, dtype=np.float64).ravel())
+            parts.append(np.asarray(c, dtype=np.float64).ravel())
+    return np.concatenate(parts)
+
+
+def _relu(x):
+    return np.maximum(x, 0.0)
+
+
+def _mlp(layers, x):
+    """x: [in, P] -> [out, P]; ReLU after layers 1 and 2, none after layer 3."""
+    (A1, c1), (A2, c2), (A3, c3) = layers
+    a = _relu(A1 @ x + c1[:, None])
+    a = _relu(A2 @ a + c2[:, None])
+    return A3 @ a + c3[:, None]
+
+
+def _pixels(gbuf, layers, scene):
+    """Flatten frames to pixel columns.  Returns G [14,P], L [k,12,P], S [16,P]."""
+    g = np.asarray(gbuf, dtype=np.float64)
+    L = np.asarray(layers, dtype=np.float64)
+    s = np.asarray(scene, dtype=np.float64)
+    n, _, h, w = g.shape
+    k = L.shape[1]
+    G = np.moveaxis(g, 1, 0).reshape(NG, n * h * w)
+    Lp = np.moveaxis(L, (1, 2), (0, 1)).reshape(k, NL, n * h * w)
+    S = np.repeat(s.T, h * w, axis=1)  # [16, P]
+    return G, Lp, S, (n, h, w)
+
+
+def _forward_cols(P, G, L, S, W, pool, keep=False):
+    """Column-wise forward over pixels.  P = unpacked params."""
+    x = np.concatenate([G, S], axis=0)                     # [30, P]
+    sigma = _mlp(P["F"], x)                                 # [W, P]
+    k = L.shape[0]
+    Ssum = np.zeros_like(sigma)
+    cnt = np.zeros(sigma.shape[1])
+    for i in range(k):
+        b = L[i]                                            # [12, P]
+        h = _mlp(P["T"], np.concatenate([b, sigma], axis=0))  # Eq. (5): h(b_i, sigma)
+        m = (b[9] > 0.0).astype(np.float64)                 # alpha > 0
+        Ssum += m[None, :] * h
+        cnt += m
+    if pool == "sum":
+        tau = Ssum
+    elif pool == "mean":
+        tau = Ssum / np.maximum(cnt, 1.0)[None, :]
+    else:
+        raise ValueError(pool)
+    phi = _mlp(P["B"], np.concatenate([sigma, tau], axis=0))
+    y = _mlp(P["R"], np.concatenate([phi, G[11:14]], axis=0))
+    if keep:
+        return y, dict(sigma=sigma, tau=tau, phi=phi, count=cnt, S=Ssum)
+    return y
+
+
+def forward(w, W, gbuf, layers, scene, pool="mean", chunk=16384, return_latents=False):
+    """Vectorised FP64 forward.  Returns y [n][3][h][w] (float64).
+
+    With return_latents=True also returns dict of sigma, tau, phi [n][W][h][w]
+    and the active count [n][h][w].
+    """
+    P = unpack(w, W)
+    G, L, S, (n, h, wd) = _pixels(gbuf, layers, scene)
+    npx = G.shape[1]
+    y = np.empty((NOUT, npx))
+    lat = {key: np.empty((W, npx)) for key in ("sigma", "tau", "phi", "S")}
+    lat["count"] = np.empty(npx)
+    for a in range(0, npx, chunk):
+        b = min(npx, a + chunk)
+        if return_latents:
+            yy, d = _forward_cols(P, G[:, a:b], L[:, :, a:b], S[:, a:b], W, pool, keep=True)
+            for key in lat:
+                lat[key][..., a:b] = d[key]
+        else:
+            yy = _forward_cols(P, G[:, a:b], L[:, :, a:b], S[:, a:b], W, pool)
+        y[:, a:b] = yy
+
+    def img(v):
+        return np.moveaxis(v.reshape(v.shape[0], n, h, wd), 0, 1)
+
+    out = img(y)
+    if return_latents:
+        lat_img = {key: img(v) for key, v in lat.items() if key != "count"}
+        lat_img["count"] = lat["count"].reshape(n, h, wd)
+        return out, lat_img
+    return out
+
+
+def forward_bruteforce(w, W, gbuf, layers, scene, pool="mean"):
+    """Scalar Python loops over pixels, slots and neurons (tiny inputs only)."""
+    P = unpack(w, W)
+
+    def dense(layer, v, act):
+        A, c = layer
+        res = []
+        for r in range(A.shape[0]):
+            acc = float(c[r])
+            for q in range(A.shape[1]):
+                acc += float(A[r, q]) * v[q]
+            res.append(max(acc, 0.0) if act else acc)
+        return res
+
+    def net(name, v):
+        v = dense(P[name][0], v, True)
+        v = dense(P[name][1], v, True)
+        return dense(P[name][2], v, False)
+
+    g = np.asarray(gbuf, dtype=np.float64)
+    L = np.asarray(layers, dtype=np.float64)
+    s = np.asarray(scene, dtype=np.float64)
+    n, _, h, wd = g.shape
+    k = L.shape[1]
+    y = np.zeros((n, NOUT, h, wd))
+    for f in range(n):
+        for r in range(h):
+            for c in range(wd):
+                gp = [float(g[f, ch, r, c]) for ch in range(NG)]
+                sigma = net("F", gp + [float(v) for v in s[f]])
+                tau = [0.0] * W
+                active = 0
+                for i in range(k):
+                    b = [float(L[f, i, ch, r, c]) for ch in range(NL)]
+                    if b[9] > 0.0:
+                        hi = net("T", b + sigma)
+                        tau = [t + v for t, v in zip(tau, hi)]
+                        active += 1
+                if pool == "mean" and active > 0:
+                    tau = [t / active for t in tau]
+                phi = net("B", sigma + tau)
+                out = net("R", phi + gp[11:14])
+                for ch in range(NOUT):
+                    y[f, ch, r, c] = out[ch]
+    return y
+
+
+def l1_loss(y, target):
+    """Sec. 3.5 L1 term: mean absolute error over every element, and dL/dy."""
+    y = np.asarray(y, dtype=np.float64)
+    t = np.asarray(target, dtype=np.float64)
+    d = y - t
+    return float(np.abs(d).mean()), np.sign(d) / d.size
+
+
+def _mlp_fwd_keep(layers, x):
+    (A1, c1), (A2, c2), (A3, c3) = layers
+    z1 = A1 @ x + c1[:, None]
+    a1 = _relu(z1)
+    z2 = A2 @ a1 + c2[:, None]
+    a2 = _relu(z2)
+    return A3 @ a2 + c3[:, None], (x, z1, a1, z2, a2)
+
+
+def _mlp_bwd(layers, cache, dout, grads):
+    """Backprop through one MLP.  Accumulates into grads [(dA, dc)]*3, returns dx."""
+    (A1, _), (A2, _), (A3, _) = layers
+    x, z1, a1, z2, a2 = cache
+    grads[2][0] += dout @ a2.T
+    grads[2][1] += dout.sum(axis=1)
+    d = (A3.T @ dout) * (z2 > 0.0)
+    grads[1][0] += d @ a1.T
+    grads[1][1] += d.sum(axis=1)
+    d = (A2.T @ d) * (z1 > 0.0)
+    grads[0][0] += d @ x.T
+    grads[0][1] += d.sum(axis=1)
+    return A1.T @ d
+
+
+def grad(w, W, gbuf, layers, scene, target, pool="mean", chunk=16384):
+    """L1 loss and its gradient w.r.t. the flat weight vector (FP64 backprop).
+
+    The transparency mask alpha > 0 is a hard selection (no gradient flows
+    through it); gradients flow into sigma through every active slot's h.
+    """
+    P = unpack(w, W)
+    G, L, S, (n, h, wd) = _pixels(gbuf, layers, scene)
+    t = np.asarray(target, dtype=np.float64)
+    T = np.moveaxis(t, 1, 0).reshape(NOUT, -1)
+    npx = G.shape[1]
+    total = NOUT * npx
+    grads = {net: [[np.zeros_like(A), np.zeros_like(c)] for A, c in P[net]] for net in NETS}
+    loss = 0.0
+    for a0 in range(0, npx, chunk):
+        b0 = min(npx, a0 + chunk)
+        Gc, Lc, Sc = G[:, a0:b0], L[:, :, a0:b0], S[:, a0:b0]
+        x = np.concatenate([Gc, Sc], axis=0)
+        sigma, cF = _mlp_fwd_keep(P["F"], x)
+        k = Lc.shape[0]
+        Ssum = np.zeros_like(sigma)
+        cnt = np.zeros(sigma.shape[1])
+        cT, ms = [], []
+        for i in range(k):
+            hi, ci = _mlp_fwd_keep(P["T"], np.concatenate([Lc[i], sigma], axis=0))
+            m = (Lc[i][9] > 0.0).astype(np.float64)
+            Ssum += m[None, :] * hi
+            cnt += m
+            cT.append(ci)
+            ms.append(m)
+        if pool == "sum":
+            tau, scale = Ssum, np.ones_like(cnt)
+        else:
+            scale = 1.0 / np.maximum(cnt, 1.0)
+            tau = Ssum * scale[None, :]
+        phi, cB = _mlp_fwd_keep(P["B"], np.concatenate([sigma, tau], axis=0))
+        y, cR = _mlp_fwd_keep(P["R"], np.concatenate([phi, Gc[11:14]], axis=0))
+        diff = y - T[:, a0:b0]
+        loss += np.abs(diff).sum()
+        dy = np.sign(diff) / total
+        dR_in = _mlp_bwd(P["R"], cR, dy, grads["R"])
+        dphi = dR_in[:W]
+        dB_in = _mlp_bwd(P["B"], cB, dphi, grads["B"])
+        dsigma = dB_in[:W].copy()
+        dS = dB_in[W:] * scale[None, :]
+        for i in range(k):
+            dh = dS * ms[i][None, :]
+            dv = _mlp_bwd(P["T"], cT[i], dh, grads["T"])
+            dsigma += dv[NL:]
+        _mlp_bwd(P["F"], cF, dsigma, grads["F"])
+    flat = pack({net: [(gA, gc) for gA, gc in grads[net]] for net in NETS})
+    return loss / total, flat
+
+
+def relu_signature(w, W, gbuf, layers, scene, target, pool="mean"):
+    """Every branch decision of the loss (ReLU signs, slot masks, L1 signs).
+
+    Two parameter vectors with equal signatures lie on the same smooth piece
+    of the loss, where central finite differences are valid.
+    """
+    P = unpack(w, W)
+    G, L, S, _ = _pixels(gbuf, layers, scene)
+    T = np.moveaxis(np.asarray(target, dtype=np.float64), 1, 0).reshape(NOUT, -1)
+    sig = []
+
+    def run(name, x):
+        out, (_, z1, _, z2, _) = _mlp_fwd_keep(P[name], x)
+        sig.append(z1 > 0.0)
+        sig.append(z2 > 0.0)
+        return out
+
+    x = np.concatenate([G, S], axis=0)
+    sigma = run("F", x)
+    Ssum = np.zeros_like(sigma)
+    cnt = np.zeros(sigma.shape[1])
+    for i in range(L.shape[0]):
+        hi = run("T", np.concatenate([L[i], sigma], axis=0))
+        m = (L[i][9] > 0.0).astype(np.float64)
+        Ssum += m * hi
+        cnt += m
+    tau = Ssum if pool == "sum" else Ssum / np.maximum(cnt, 1.0)
+    phi = run("B", np.concatenate([sigma, tau], axis=0))
+    y = run("R", np.concatenate([phi, G[11:14]], axis=0))
+    sig.append(y > T)
+    return np.concatenate([s.ravel() for s in sig])
+
+
+def alpha_blend(colors, alphas):
+    """Order-dependent alpha compositing of Eqs. (3)-(4), front-to-back.
+
+    colors [t][...], alphas [t][...]; slot 0 is the front-most surface and
+    z_i is the transmittance of the surfaces in front of slot i.
+    """
+    colors = np.asarray(colors, dtype=np.float64)
+    alphas = np.asarray(alphas, dtype=np.float64)
+    out = np.zeros(colors.shape[1:])
+    trans = np.ones(alphas.shape[1:])
+    for i in range(colors.shape[0]):
+        out = out + alphas[i] * colors[i] * trans
+        trans = trans * (1.0 - alphas[i])
+    return out
+
+
+def all_slot_orders(k):
+    """Every permutation of k slots (small k only)."""
+    return list(itertools.permutations(range(k)))

@@ -1,0 +1,184 @@
+/*
+ * glassnet.h -- C ABI of the GlassNet per-pixel evaluator for MI355X (gfx950).
+ *
+ * The method (Zhang & Simo-Serra, "Neural Scene Baking for Permutation
+ * Invariant Transparency Rendering with Real-time Global Illumination"):
+ *   Sec. 3.2   a separated opaque G-buffer plus one transparency buffer per
+ *              transparent object, w x h x c*(t+1) planes in total;
+ *   Sec. 3.3   Eq. (5): tau = sum_i h(b_i, sigma), one network h shared by all
+ *              transparency buffers followed by a symmetric pool;
+ *   Sec. 3.4   scene encoder F -> sigma, blend network B([sigma; tau]) -> phi,
+ *              rendering network R([phi; L_d]) -> output radiance;
+ *   Sec. 3.5   end-to-end training with an L1 term.
+ * Every network is a per-pixel 3-layer MLP (Linear-ReLU-Linear-ReLU-Linear) of
+ * hidden width W; a transparency slot takes part iff its alpha > 0.
+ *
+ * Conventions shared by every call
+ *   - Plain C types only.  Pointers documented "device" are HIP device
+ *     allocations owned by the caller; "host" pointers are ordinary memory.
+ *   - Every call returns a gn_status; nothing throws across the ABI.  On
+ *     failure glassnet_last_error() gives a message for the calling thread.
+ *   - Compute calls are asynchronous and stream-ordered on the hip_stream the
+ *     caller passes (a hipStream_t; NULL = the null stream).  Device buffers
+ *     must stay valid until that stream work has completed.
+ *   - A handle's forward/backward/l1/set_weights calls are used by one host
+ *     thread at a time; serve_submit/serve_poll may be called concurrently.
+ *   - An asynchronous device fault observed by the library poisons the handle:
+ *     every later call returns GN_E_DEVICE.
+ */
+#ifndef GLASSNET_H
+#define GLASSNET_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Planes per pixel (fp32).  G-buffer: position(3), unit normal(3), albedo(3),
+ * roughness, metallic, direct light L_d(3) -- L_d are planes 11..13.
+ * Transparency layer: position(3), unit normal(3), tint(3), alpha (plane 9),
+ * IOR, depth.  Scene vector: 16 variable scene parameters per frame. */
+#define GN_NUM_G 14
+#define GN_NUM_L 12
+#define GN_NUM_S 16
+#define GN_NUM_OUT 3
+#define GN_ALPHA_PLANE 9
+#define GN_MAX_K 64
+
+typedef int32_t gn_status;
+#define GN_OK 0
+#define GN_E_INVAL (-1)        /* bad argument: shape, pointer, alignment, size */
+#define GN_E_NOMEM (-2)        /* device or host allocation failed */
+#define GN_E_DEVICE (-3)       /* HIP runtime or kernel error; handle poisoned */
+#define GN_E_UNSUPPORTED (-4)  /* valid request this build does not implement */
+#define GN_E_AGAIN (-5)        /* serving: result not ready yet */
+#define GN_E_BUSY (-6)         /* serving: pending queue full */
+
+/* Arithmetic of the forward pass.
+ *   GN_FP32    fp32 weights and activations on the vector ALUs.
+ *   GN_BF16    bf16 weights/activations on MFMA, fp32 accumulation, fp32 pool.
+ *   GN_FP8_T   the per-slot hidden layer of h in FP8-E4M3 (per-output-channel
+ *              fp32 weight scales, static activation scale), the rest as GN_BF16.
+ * Backward and loss always accumulate in fp32. */
+typedef int32_t gn_precision;
+#define GN_FP32 0
+#define GN_BF16 1
+#define GN_FP8_T 2
+
+/* The symmetric function g of Eq. (5).
+ *   GN_POOL_SUM   tau = sum over active slots of h(b_i, sigma)   (Eq. (5))
+ *   GN_POOL_MEAN  tau = that sum / max(#active, 1); no active slot gives 0. */
+typedef int32_t gn_pool;
+#define GN_POOL_MEAN 0
+#define GN_POOL_SUM 1
+
+typedef struct gn_config {
+  int32_t width;              /* W: 64 or 128 */
+  int32_t k_max;              /* largest slot count a call may pass, 0..GN_MAX_K */
+  gn_pool pool;
+  gn_precision precision;
+  uint64_t hbm_budget_bytes;  /* serving admission budget; 0 = 64 GiB */
+  int32_t device;             /* HIP device ordinal */
+  int32_t max_pending;        /* serving: pending-queue bound; 0 = 65536 */
+} gn_config;
+
+typedef struct gn_handle gn_handle;
+
+/* A batch of n frames of h x w pixels with k transparency slots each.  All
+ * three arrays are device memory, fp32, C-contiguous, 4-byte aligned:
+ *   gbuf   [n][GN_NUM_G][h][w]
+ *   layers [n][k][GN_NUM_L][h][w]   (may be NULL when k == 0)
+ *   scene  [n][GN_NUM_S]                                                  */
+typedef struct gn_frame {
+  int32_t n, h, w, k;
+  const float *gbuf;
+  const float *layers;
+  const float *scene;
+} gn_frame;
+
+/* Serving timestamps, seconds on the host's steady clock. */
+typedef struct gn_timing {
+  double t_submit, t_admit, t_start, t_done;
+} gn_timing;
+
+/* Number of fp32 parameters for width W: 11 W^2 + 59 W + 3.
+ * Flat layout: nets F, T, B, R; layers 1, 2, 3; per layer the matrix row-major
+ * [out][in] then the bias.  Input order: F [G-buffer 0..13; scene 0..15],
+ * T [slot planes 0..11; sigma], B [sigma; tau], R [phi; L_d].  Returns 0 for
+ * an unsupported width. */
+size_t glassnet_num_params(int32_t width);
+
+/* Create a handle on cfg->device and upload host_weights (host, n floats,
+ * n == glassnet_num_params(width)).  The library owns the fp32 master copy,
+ * its bf16/fp8 packed forms and every workspace.  *out is set on GN_OK. */
+gn_status glassnet_create(const gn_config *cfg, const float *host_weights, size_t n,
+                          gn_handle **out);
+
+/* Drain outstanding serving work, free every library allocation.  NULL is a no-op. */
+gn_status glassnet_destroy(gn_handle *h);
+
+/* Copy the fp32 master weights to host memory (n floats).  Synchronous. */
+gn_status glassnet_get_weights(gn_handle *h, float *host_weights, size_t n);
+
+/* Replace the master weights from DEVICE memory (n floats) and re-derive the
+ * packed forms, stream-ordered on hip_stream (used by training loops). */
+gn_status glassnet_set_weights(gn_handle *h, const float *dev_weights, size_t n,
+                               void *hip_stream);
+
+/* GN_FP8_T: static activation scale of the FP8 layer's input (the per-slot
+ * hidden activation of h).  scales[0] > 0 maps the activation range onto
+ * E4M3; n must be 1.  The default is derived at create time. */
+gn_status glassnet_set_act_scales(gn_handle *h, const float *scales, size_t n);
+
+/* Forward (Sec. 3.3-3.4): out [n][GN_NUM_OUT][h][w] fp32 device.
+ * Requires 0 <= k <= k_max and n, h, w >= 1.  Out must not alias inputs. */
+gn_status glassnet_forward(gn_handle *h, const gn_frame *frame, float *out, void *hip_stream);
+
+/* Backward of the forward above with respect to the weights (Sec. 3.5), fp32.
+ * grad_out is dL/d(out), device, shaped like out.  grad_w (device, n_params
+ * floats) is overwritten with dL/dw in the flat layout.  Per-slot activations
+ * of h are recomputed, never stored for all k.  The transparency mask is a
+ * hard selection: no gradient flows through alpha's threshold. */
+gn_status glassnet_backward(gn_handle *h, const gn_frame *frame, const float *grad_out,
+                            float *grad_w, void *hip_stream);
+
+/* L1 term of Sec. 3.5 over count elements: *loss = mean |out - target| and
+ * grad_out = sign(out - target) / count (0 where equal).  All device.
+ * grad_out may be NULL. */
+gn_status glassnet_l1_loss(gn_handle *h, const float *out, const float *target,
+                           uint64_t count, float *loss, float *grad_out, void *hip_stream);
+
+/* Device bytes the handle holds for forward work: weights, packed forms and
+ * workspaces.  Independent of the slot count k (the pool is a running sum). */
+gn_status glassnet_workspace_bytes(gn_handle *h, uint64_t *bytes);
+
+/* Serving (continuous batching).  serve_submit enqueues a frame batch whose
+ * device buffers the library may read until serve_poll reports done; out is
+ * written then.  Frames are admitted while the bytes of admitted-but-unfinished
+ * frames (inputs + output) fit hbm_budget_bytes; tiles of admitted frames of
+ * any size and k share kernel launches.  Returns GN_E_INVAL for a frame larger
+ * than the whole budget, GN_E_BUSY when the pending queue is full.  Never
+ * blocks on the GPU. */
+gn_status serve_submit(gn_handle *h, const gn_frame *frame, float *out, uint64_t *ticket);
+
+/* *done = 1 once the ticket's output is complete (timing filled, may be NULL),
+ * 0 otherwise.  A ticket whose work failed returns GN_E_DEVICE; an unknown
+ * ticket GN_E_INVAL.  A completed ticket may be polled again until the next
+ * serve_forget or destroy. */
+gn_status serve_poll(gn_handle *h, uint64_t ticket, int32_t *done, gn_timing *timing);
+
+/* Block until every submitted frame is done (or failed). */
+gn_status serve_drain(gn_handle *h);
+
+/* Drop the bookkeeping of a completed ticket. */
+gn_status serve_forget(gn_handle *h, uint64_t ticket);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char *glassnet_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GLASSNET_H */

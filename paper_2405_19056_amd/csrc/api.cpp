@@ -1,0 +1,290 @@
+// The C ABI of libglassnet: argument validation, handle state, launches.
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <mutex>
+#include <string>
+
+#include "gn_api_state.h"
+
+namespace {
+
+thread_local std::string g_err;
+
+gn_status fail(gn_status code, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+// Sets the handle's device for the duration of a call, restores the caller's.
+struct DeviceGuard {
+  int prev = -1;
+  bool ok = false;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    ok = hipSetDevice(dev) == hipSuccess;
+  }
+  ~DeviceGuard() {
+    if (prev >= 0) (void)hipSetDevice(prev);
+  }
+};
+
+bool aligned4(const void *p) { return ((uintptr_t)p & 3u) == 0; }
+
+bool overlaps(const void *a, size_t an, const void *b, size_t bn) {
+  if (!a || !b || !an || !bn) return false;
+  const char *x = (const char *)a, *y = (const char *)b;
+  return x < y + bn && y < x + an;
+}
+
+}  // namespace
+
+gn_status gn_set_error(gn_status code, const char *msg) { return fail(code, "%s", msg); }
+
+gn_status gn_check_device(gn_handle *h, hipError_t e, const char *what) {
+  if (e == hipSuccess) return GN_OK;
+  h->poisoned = true;
+  return fail(GN_E_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+gn_status gn_validate_frame(gn_handle *h, const gn_frame *f, const float *out) {
+  if (!f) return fail(GN_E_INVAL, "frame is NULL");
+  if (f->n < 1 || f->h < 1 || f->w < 1)
+    return fail(GN_E_INVAL, "frame shape n=%d h=%d w=%d must be >= 1", f->n, f->h, f->w);
+  if (f->k < 0 || f->k > h->cfg.k_max)
+    return fail(GN_E_INVAL, "k=%d outside [0, k_max=%d]", f->k, h->cfg.k_max);
+  const int64_t hw = (int64_t)f->h * f->w;
+  if (hw * gn::kNG > INT32_MAX || (int64_t)f->n * hw > INT32_MAX ||
+      hw * (int64_t)std::max(f->k, 1) * gn::kNL > ((int64_t)1 << 40))
+    return fail(GN_E_INVAL, "frame too large (%d x %d x %d)", f->n, f->h, f->w);
+  if (!f->gbuf || !f->scene) return fail(GN_E_INVAL, "gbuf and scene must be non-NULL");
+  if (f->k > 0 && !f->layers) return fail(GN_E_INVAL, "layers is NULL with k=%d", f->k);
+  if (!aligned4(f->gbuf) || !aligned4(f->scene) || !aligned4(f->layers) || !aligned4(out))
+    return fail(GN_E_INVAL, "device pointers must be 4-byte aligned");
+  if (out) {
+    const size_t ob = sizeof(float) * (size_t)f->n * gn::kNOUT * hw;
+    if (overlaps(out, ob, f->gbuf, sizeof(float) * (size_t)f->n * gn::kNG * hw) ||
+        overlaps(out, ob, f->layers, sizeof(float) * (size_t)f->n * f->k * gn::kNL * hw) ||
+        overlaps(out, ob, f->scene, sizeof(float) * (size_t)f->n * gn::kNS))
+      return fail(GN_E_INVAL, "out aliases an input buffer");
+  }
+  return GN_OK;
+}
+
+static gn_status precheck(gn_handle *h) {
+  if (!h) return fail(GN_E_INVAL, "handle is NULL");
+  if (h->poisoned) return fail(GN_E_DEVICE, "handle poisoned by an earlier device error");
+  // surface asynchronous faults from earlier work on this device
+  hipError_t e = hipPeekAtLastError();
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return gn_check_device(h, e, "earlier asynchronous device error");
+  }
+  return GN_OK;
+}
+
+gn_status gn_prepare_weights(gn_handle *h, hipStream_t stream) {
+  hipError_t e = gn::launch_transpose_master(h->W, h->d_master, h->d_master_t, stream);
+  if (e == hipSuccess) e = gn::launch_pack_weights(h->d_master, h->d_packed, h->pl, h->act_scale, stream);
+  return gn_check_device(h, e, "weight packing");
+}
+
+extern "C" {
+
+size_t glassnet_num_params(int32_t width) { return gn::num_params(width); }
+
+const char *glassnet_last_error(void) { return g_err.c_str(); }
+
+gn_status glassnet_create(const gn_config *cfg, const float *host_weights, size_t n,
+                          gn_handle **out) {
+  if (!cfg || !out) return fail(GN_E_INVAL, "cfg and out must be non-NULL");
+  *out = nullptr;
+  if (cfg->width != 64 && cfg->width != 128)
+    return fail(GN_E_UNSUPPORTED, "width %d not supported (64 or 128)", cfg->width);
+  if (cfg->k_max < 0 || cfg->k_max > GN_MAX_K)
+    return fail(GN_E_INVAL, "k_max %d outside [0, %d]", cfg->k_max, GN_MAX_K);
+  if (cfg->pool != GN_POOL_MEAN && cfg->pool != GN_POOL_SUM)
+    return fail(GN_E_INVAL, "unknown pool %d", cfg->pool);
+  if (cfg->precision != GN_FP32 && cfg->precision != GN_BF16 && cfg->precision != GN_FP8_T)
+    return fail(GN_E_INVAL, "unknown precision %d", cfg->precision);
+  if (cfg->precision == GN_FP8_T && cfg->width != 128)
+    return fail(GN_E_UNSUPPORTED, "GN_FP8_T needs width 128");
+  if (!host_weights) return fail(GN_E_INVAL, "host_weights is NULL");
+  const size_t np = gn::num_params(cfg->width);
+  if (n != np) return fail(GN_E_INVAL, "expected %zu weights for width %d, got %zu", np, cfg->width, n);
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1)
+    return fail(GN_E_DEVICE, "no HIP device available");
+  if (cfg->device < 0 || cfg->device >= ndev)
+    return fail(GN_E_INVAL, "device %d outside [0, %d)", cfg->device, ndev);
+  DeviceGuard dg(cfg->device);
+  if (!dg.ok) return fail(GN_E_DEVICE, "hipSetDevice(%d) failed", cfg->device);
+
+  gn_handle *h = new (std::nothrow) gn_handle();
+  if (!h) return fail(GN_E_NOMEM, "host allocation failed");
+  h->cfg = *cfg;
+  if (!h->cfg.hbm_budget_bytes) h->cfg.hbm_budget_bytes = (uint64_t)64 << 30;
+  if (!h->cfg.max_pending) h->cfg.max_pending = 65536;
+  h->W = cfg->width;
+  h->device = cfg->device;
+  h->nparams = np;
+  h->act_scale = 8.0f / 448.0f;
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, cfg->device) != hipSuccess) {
+    delete h;
+    return fail(GN_E_DEVICE, "hipGetDeviceProperties failed");
+  }
+  h->num_cus = prop.multiProcessorCount;
+  gn::make_packed_layout(h->W, &h->pl);
+  h->scratch_threads = gn::fp32_scratch_threads(h->num_cus);
+  h->l1_npart = 4 * h->num_cus;
+
+  const size_t wbytes = sizeof(float) * np;
+  const size_t scratch_bytes = sizeof(float) * 4 * (size_t)h->W * h->scratch_threads;
+  hipError_t e = hipSuccess;
+  if (e == hipSuccess) e = hipMalloc((void **)&h->d_master, wbytes);
+  if (e == hipSuccess) e = hipMalloc((void **)&h->d_master_t, wbytes);
+  if (e == hipSuccess) e = hipMalloc((void **)&h->d_packed, (size_t)h->pl.total_bytes);
+  if (e == hipSuccess && cfg->precision == GN_FP32)
+    e = hipMalloc((void **)&h->d_scratch, scratch_bytes);
+  if (e == hipSuccess) e = hipMalloc((void **)&h->d_l1_partials, sizeof(float) * h->l1_npart);
+  if (e == hipSuccess) e = hipMemcpy(h->d_master, host_weights, wbytes, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemset(h->d_packed, 0, (size_t)h->pl.total_bytes);
+  if (e != hipSuccess) {
+    gn_status st = (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation)
+                       ? fail(GN_E_NOMEM, "device allocation failed: %s", hipGetErrorString(e))
+                       : fail(GN_E_DEVICE, "device setup failed: %s", hipGetErrorString(e));
+    glassnet_destroy(h);
+    return st;
+  }
+  h->bytes_held = 2 * wbytes + (size_t)h->pl.total_bytes + sizeof(float) * h->l1_npart +
+                  (cfg->precision == GN_FP32 ? scratch_bytes : 0);
+  gn_status st = gn_prepare_weights(h, nullptr);
+  if (st == GN_OK) {
+    e = hipDeviceSynchronize();
+    st = gn_check_device(h, e, "weight packing");
+  }
+  if (st != GN_OK) {
+    std::string msg = g_err;
+    glassnet_destroy(h);
+    return fail(st, "%s", msg.c_str());
+  }
+  st = gn_serve_init(h);
+  if (st != GN_OK) {
+    std::string msg = g_err;
+    glassnet_destroy(h);
+    return fail(st, "%s", msg.c_str());
+  }
+  *out = h;
+  return GN_OK;
+}
+
+gn_status glassnet_destroy(gn_handle *h) {
+  if (!h) return GN_OK;
+  DeviceGuard dg(h->device);
+  gn_serve_shutdown(h);
+  gn_bwd_free(h);
+  if (!h->poisoned) (void)hipDeviceSynchronize();
+  (void)hipFree(h->d_master);
+  (void)hipFree(h->d_master_t);
+  (void)hipFree(h->d_packed);
+  (void)hipFree(h->d_scratch);
+  (void)hipFree(h->d_l1_partials);
+  delete h;
+  return GN_OK;
+}
+
+gn_status glassnet_get_weights(gn_handle *h, float *host_weights, size_t n) {
+  gn_status st = precheck(h);
+  if (st != GN_OK) return st;
+  if (!host_weights || n != h->nparams)
+    return fail(GN_E_INVAL, "need a host buffer of %zu floats", h->nparams);
+  DeviceGuard dg(h->device);
+  hipError_t e = hipDeviceSynchronize();
+  if (e == hipSuccess)
+    e = hipMemcpy(host_weights, h->d_master, sizeof(float) * n, hipMemcpyDeviceToHost);
+  return gn_check_device(h, e, "get_weights");
+}
+
+gn_status glassnet_set_weights(gn_handle *h, const float *dev_weights, size_t n,
+                               void *hip_stream) {
+  gn_status st = precheck(h);
+  if (st != GN_OK) return st;
+  if (!dev_weights || n != h->nparams || !aligned4(dev_weights))
+    return fail(GN_E_INVAL, "need %zu aligned device floats", h->nparams);
+  DeviceGuard dg(h->device);
+  hipStream_t s = (hipStream_t)hip_stream;
+  hipError_t e = hipSuccess;
+  if (dev_weights != h->d_master)
+    e = hipMemcpyAsync(h->d_master, dev_weights, sizeof(float) * n, hipMemcpyDeviceToDevice, s);
+  if (e != hipSuccess) return gn_check_device(h, e, "set_weights copy");
+  return gn_prepare_weights(h, s);
+}
+
+gn_status glassnet_set_act_scales(gn_handle *h, const float *scales, size_t n) {
+  gn_status st = precheck(h);
+  if (st != GN_OK) return st;
+  if (!scales || n != 1 || !(scales[0] > 0.0f) || !(scales[0] < 1e30f))
+    return fail(GN_E_INVAL, "need exactly one finite positive activation scale");
+  h->act_scale = scales[0];
+  return GN_OK;
+}
+
+gn_status glassnet_workspace_bytes(gn_handle *h, uint64_t *bytes) {
+  if (!h || !bytes) return fail(GN_E_INVAL, "NULL argument");
+  *bytes = h->bytes_held + gn_bwd_bytes(h);
+  return GN_OK;
+}
+
+gn_status glassnet_forward(gn_handle *h, const gn_frame *frame, float *out, void *hip_stream) {
+  gn_status st = precheck(h);
+  if (st != GN_OK) return st;
+  if (!out) return fail(GN_E_INVAL, "out is NULL");
+  st = gn_validate_frame(h, frame, out);
+  if (st != GN_OK) return st;
+  DeviceGuard dg(h->device);
+  hipStream_t s = (hipStream_t)hip_stream;
+  gn::FwdBatch b;
+  b.gbuf = frame->gbuf;
+  b.layers = frame->layers;
+  b.scene = frame->scene;
+  b.out = out;
+  b.n = frame->n;
+  b.hw = frame->h * frame->w;
+  b.k = frame->k;
+  hipError_t e;
+  if (h->cfg.precision == GN_FP32) {
+    e = gn::launch_fwd_fp32(h->W, h->cfg.pool, h->d_master, h->d_master_t, b, h->d_scratch,
+                            h->scratch_threads, s);
+  } else {
+    const int tpf = (b.hw + gn::kTilePx - 1) / gn::kTilePx;
+    e = gn::launch_fwd_mfma(h->W, h->cfg.precision, h->cfg.pool, h->d_packed, h->pl, &b, nullptr,
+                            nullptr, b.n * tpf, h->act_scale, h->num_cus, s);
+  }
+  return gn_check_device(h, e, "forward launch");
+}
+
+gn_status glassnet_l1_loss(gn_handle *h, const float *out, const float *target, uint64_t count,
+                           float *loss, float *grad_out, void *hip_stream) {
+  gn_status st = precheck(h);
+  if (st != GN_OK) return st;
+  if (!out || !target || !loss) return fail(GN_E_INVAL, "out, target and loss must be non-NULL");
+  if (!aligned4(out) || !aligned4(target) || !aligned4(loss) || !aligned4(grad_out))
+    return fail(GN_E_INVAL, "device pointers must be 4-byte aligned");
+  if (grad_out && (overlaps(grad_out, 4 * count, out, 4 * count) ||
+                   overlaps(grad_out, 4 * count, target, 4 * count)))
+    return fail(GN_E_INVAL, "grad_out aliases out or target");
+  DeviceGuard dg(h->device);
+  hipError_t e = gn::launch_l1(out, target, count, loss, grad_out, h->d_l1_partials, h->l1_npart,
+                               (hipStream_t)hip_stream);
+  return gn_check_device(h, e, "l1 launch");
+}
+
+}  // extern "C"

@@ -1,0 +1,627 @@
+// Fused GlassNet forward on the gfx950 matrix cores (bf16 / fp8 in, fp32 acc).
+//
+// Formulation.  Every layer is Y^T = A X^T with the weights A as the MFMA
+// "A" operand (16 output neurons per M-tile) and 16 pixels per N-tile as the
+// "B" operand.  The fp32 accumulator of v_mfma_f32_16x16x32_bf16 leaves lane
+// l holding 4 consecutive output rows (4*(l>>4) + r) of pixel l & 15; two
+// M-tiles give exactly the 8 values that lane must present as the B operand
+// of the next layer's 32-deep K-step.  The next layer's weights are stored
+// with their input columns permuted the same way, so activations go from one
+// layer to the next by a ReLU and a bf16 convert, without leaving registers.
+//
+// Work split.  A workgroup of 8 waves owns a tile of 256 pixels (32 per wave,
+// two N-tiles).  Weights are staged into LDS chunk by chunk with direct
+// global->LDS loads, double-buffered: while a stage computes, the next
+// stage's chunk streams in.  The weights of the per-slot network h that run
+// inside the slot loop stay resident.  Grid = number of CUs; each workgroup
+// walks tiles with a stride of the grid (tiles may come from a table that
+// mixes frames of different sizes and slot counts).
+//
+// The method (Sec. 3.3-3.4): sigma = F([G; s]); tau = pool_i h(b_i, sigma)
+// over slots with alpha_i > 0 (Eq. (5)); phi = B([sigma; tau]);
+// y = R([phi; L_d]).  Two exact rewrites of h are used: its first layer's
+// sigma part is computed once per pixel (u = W1s sigma + c1), and because its
+// last layer is affine the masked pool moves in front of it:
+// sum_i m_i (A3 a_i + c3) = A3 (sum_i m_i a_i) + (sum_i m_i) c3.  The running
+// sum is fp32 in registers, so memory does not grow with the slot count.
+#include "gn_internal.h"
+
+namespace gn {
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef int i32x8 __attribute__((ext_vector_type(8)));
+
+constexpr int kWaves = 8;
+constexpr int kNT = 2;                 // N-tiles of 16 pixels per wave
+constexpr int kThreads = kWaves * 64;
+static_assert(kWaves * kNT * 16 == kTilePx, "tile = waves x N-tiles x 16 pixels");
+constexpr int kFrag = 1024;            // one bf16 A fragment: 64 lanes x 16 B
+
+struct MfmaArgs {
+  const uint8_t *packed;
+  int64_t stage_off[kNumStages + 1];
+  int64_t res_off, res_bytes, bias_off, t2q_off, t2s_off;
+  FwdBatch b;
+  const FrameDesc *frames;
+  const TileRef *tiles;
+  int ntiles;
+  int tiles_per_frame;
+  int pool;
+  float sa, inv_sa;                    // fp8 activation scale and its inverse
+};
+
+__device__ __forceinline__ uint32_t pk_bf16(float a, float b) {
+  bf16x2 v = {(__bf16)a, (__bf16)b};
+  return __builtin_bit_cast(uint32_t, v);
+}
+
+__device__ __forceinline__ f32x4 mma(u32x4 a, u32x4 b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a),
+                                                 __builtin_bit_cast(bf16x8, b), c, 0, 0, 0);
+}
+
+__device__ __forceinline__ f32x4 relu4(f32x4 v) {
+  return f32x4{fmaxf(v.x, 0.f), fmaxf(v.y, 0.f), fmaxf(v.z, 0.f), fmaxf(v.w, 0.f)};
+}
+
+// bf16 pairs back to fp32 (exact: bf16 is the top half of an fp32).
+__device__ __forceinline__ f32x4 unpk_bf16(uint32_t a, uint32_t b) {
+  return f32x4{__uint_as_float(a << 16), __uint_as_float(a & 0xffff0000u),
+               __uint_as_float(b << 16), __uint_as_float(b & 0xffff0000u)};
+}
+
+// ReLU of two packed bf16: sign-magnitude values order like signed 16-bit
+// integers, so max(x, 0) as int16 zeroes exactly the negative numbers.
+__device__ __forceinline__ uint32_t relu_bf16x2(uint32_t x) {
+  typedef short s16x2 __attribute__((ext_vector_type(2)));
+  s16x2 v = __builtin_bit_cast(s16x2, x);
+  s16x2 z = {0, 0};
+  v = __builtin_elementwise_max(v, z);
+  return __builtin_bit_cast(uint32_t, v);
+}
+
+__device__ __forceinline__ void wait_vm() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
+
+// Copy `bytes` (a multiple of 1 KiB) from global to LDS: each wave moves whole
+// 1 KiB blocks, lane i writing bytes [16 i, 16 i + 16) of its block.
+__device__ __forceinline__ void lds_fill(uint8_t *dst, const uint8_t *src, int64_t bytes,
+                                         int wave, int lane) {
+  for (int64_t off = (int64_t)wave * kFrag; off < bytes; off += kWaves * kFrag) {
+    __builtin_amdgcn_global_load_lds(
+        (const void *)(src + off + lane * 16),
+        (__attribute__((address_space(3))) void *)(dst + off), 16, 0, 0);
+  }
+}
+
+__device__ __forceinline__ u32x4 ld_frag(const uint8_t *chunk, int idx, int lane) {
+  return *(const u32x4 *)(chunk + (size_t)idx * kFrag + lane * 16);
+}
+
+// acc[t][mt] += A(chunk) . in[t]   over the chunk's KS_ K-steps.
+template <int MT_, int KS_>
+__device__ __forceinline__ void mm(f32x4 (&acc)[kNT][MT_], const uint8_t *chunk,
+                                   const u32x4 (&in)[kNT][KS_], int lane) {
+#pragma unroll
+  for (int mt = 0; mt < MT_; ++mt) {
+#pragma unroll
+    for (int ks = 0; ks < KS_; ++ks) {
+      const u32x4 w = ld_frag(chunk, mt * KS_ + ks, lane);
+#pragma unroll
+      for (int t = 0; t < kNT; ++t) acc[t][mt] = mma(w, in[t][ks], acc[t][mt]);
+    }
+  }
+}
+
+template <int MT_>
+__device__ __forceinline__ void bias_init(f32x4 (&acc)[kNT][MT_], const float *bias, int g) {
+#pragma unroll
+  for (int mt = 0; mt < MT_; ++mt) {
+    const f32x4 b = *(const f32x4 *)(bias + 16 * mt + 4 * g);
+#pragma unroll
+    for (int t = 0; t < kNT; ++t) acc[t][mt] = b;
+  }
+}
+
+// Accumulator rows -> next layer's B fragments (M-tiles 2j and 2j+1 make K-step j).
+template <int MT_, bool RELU>
+__device__ __forceinline__ void to_frags(const f32x4 (&acc)[kNT][MT_], u32x4 (&out)[kNT][MT_ / 2]) {
+#pragma unroll
+  for (int t = 0; t < kNT; ++t) {
+#pragma unroll
+    for (int mt = 0; mt < MT_; ++mt) {
+      const f32x4 v = RELU ? relu4(acc[t][mt]) : acc[t][mt];
+      out[t][mt >> 1][2 * (mt & 1)] = pk_bf16(v.x, v.y);
+      out[t][mt >> 1][2 * (mt & 1) + 1] = pk_bf16(v.z, v.w);
+    }
+  }
+}
+
+// One chained layer, an M-tile pair at a time: out[t][p] = pack(act(A in + bias))
+// for M-tiles 2p and 2p+1.  Keeps only 2 x kNT accumulators live.
+// bias_scale[t] multiplies the bias (1 for ordinary layers).
+template <int MT_, int KS_, bool RELU>
+__device__ __forceinline__ void layer(u32x4 (&out)[kNT][MT_ / 2], const uint8_t *chunk,
+                                      const u32x4 (&in)[kNT][KS_], const float *bias, int g,
+                                      int lane) {
+#pragma unroll
+  for (int p = 0; p < MT_ / 2; ++p) {
+    f32x4 acc[kNT][2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const f32x4 b = *(const f32x4 *)(bias + 16 * (2 * p + h) + 4 * g);
+#pragma unroll
+      for (int t = 0; t < kNT; ++t) acc[t][h] = b;
+    }
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+#pragma unroll
+      for (int ks = 0; ks < KS_; ++ks) {
+        const u32x4 w = ld_frag(chunk, (2 * p + h) * KS_ + ks, lane);
+#pragma unroll
+        for (int t = 0; t < kNT; ++t) acc[t][h] = mma(w, in[t][ks], acc[t][h]);
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < kNT; ++t) {
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const f32x4 v = RELU ? relu4(acc[t][h]) : acc[t][h];
+        out[t][p][2 * h] = pk_bf16(v.x, v.y);
+        out[t][p][2 * h + 1] = pk_bf16(v.z, v.w);
+      }
+    }
+  }
+}
+
+template <int W>
+struct Shape {
+  static constexpr int MT = W / 16, KS = W / 32;
+  static constexpr int kBiasBytes = kNumLayers * W * 4;
+};
+
+template <int W, int PREC>
+__global__ __launch_bounds__(kThreads) void fwd_mfma_kernel(MfmaArgs a) {
+  constexpr int MT = Shape<W>::MT, KS = Shape<W>::KS;
+  extern __shared__ __attribute__((aligned(1024))) uint8_t lds[];
+  const int wave = threadIdx.x >> 6;
+
+  // LDS map: [resident | biases | stage buffer 0 | stage buffer 1]
+  const int64_t res_bytes = a.res_bytes;
+  uint8_t *L_res = lds;
+  float *L_bias = (float *)(lds + res_bytes);
+  int64_t stage_max = 0;
+#pragma unroll
+  for (int s = 0; s < kNumStages; ++s)
+    stage_max = max(stage_max, a.stage_off[s + 1] - a.stage_off[s]);
+  uint8_t *L_stage0 = lds + res_bytes + Shape<W>::kBiasBytes;
+  uint8_t *L_stage1 = L_stage0 + stage_max;
+  auto stage_buf = [&](int s) { return (s & 1) ? L_stage1 : L_stage0; };
+  // resident weights of the slot loop and all biases, once per workgroup
+  const int lane0 = threadIdx.x & 63;
+  auto fill_stage0 = [&](int s) {
+    lds_fill(stage_buf(s), a.packed + a.stage_off[s], a.stage_off[s + 1] - a.stage_off[s], wave,
+             lane0);
+  };
+  lds_fill(L_res, a.packed + a.res_off, res_bytes, wave, lane0);
+  lds_fill((uint8_t *)L_bias, a.packed + a.bias_off, Shape<W>::kBiasBytes, wave, lane0);
+  if ((int)blockIdx.x < a.ntiles) fill_stage0(0);
+  wait_vm();
+  __syncthreads();
+
+  const uint8_t *T1A = L_res;
+  const uint8_t *T2 = L_res + MT * kFrag;
+  const float *bF1 = L_bias + L_F1 * W, *bF2 = L_bias + L_F2 * W, *bF3 = L_bias + L_F3 * W;
+  const float *bT1 = L_bias + L_T1 * W, *bT2 = L_bias + L_T2 * W, *bT3 = L_bias + L_T3 * W;
+  const float *bB1 = L_bias + L_B1 * W, *bB2 = L_bias + L_B2 * W, *bB3 = L_bias + L_B3 * W;
+  const float *bR1 = L_bias + L_R1 * W, *bR2 = L_bias + L_R2 * W, *bR3 = L_bias + L_R3 * W;
+  const int64_t f1_bytes = (int64_t)MT * kFrag;          // F1 precedes F2 in stage 0
+  const int64_t r1p_bytes = (int64_t)MT * KS * kFrag;    // R1P precedes R1L in stage 8
+  const int64_t r2_bytes = (int64_t)MT * KS * kFrag;     // R2 precedes R3 in stage 9
+
+  for (int tile = blockIdx.x; tile < a.ntiles; tile += gridDim.x) {
+    const bool has_next = tile + (int)gridDim.x < a.ntiles;
+    // Opaque per-tile copies of the lane id and the packed-weight base keep
+    // the compiler from hoisting every derived address (staging sources of
+    // all stages, channel masks) out of the tile loop and holding them in
+    // registers for its whole length.
+    int lane = threadIdx.x & 63;
+    const uint8_t *packed = a.packed;
+    asm volatile("" : "+v"(lane), "+s"(packed));
+    const int g = lane >> 4, col = lane & 15;
+    auto fill_stage = [&](int s) {
+      lds_fill(stage_buf(s), packed + a.stage_off[s], a.stage_off[s + 1] - a.stage_off[s], wave,
+               lane);
+    };
+    // ---- resolve the tile's frame
+    const float *Gp, *Lp, *Sp;
+    float *Op;
+    int hw, K, q0;
+    if (a.tiles) {
+      const TileRef tr = a.tiles[tile];
+      const FrameDesc fd = a.frames[tr.frame];
+      Gp = fd.g; Lp = fd.L; Sp = fd.s; Op = fd.out; hw = fd.hw; K = fd.k; q0 = tr.q0;
+    } else {
+      const int f = tile / a.tiles_per_frame;
+      hw = a.b.hw;
+      K = a.b.k;
+      q0 = (tile - f * a.tiles_per_frame) * kTilePx;
+      Gp = a.b.gbuf + (size_t)f * kNG * hw;
+      Lp = a.b.layers + (size_t)f * K * kNL * hw;
+      Sp = a.b.scene + (size_t)f * kNS;
+      Op = a.b.out + (size_t)f * kNOUT * hw;
+    }
+    int qc[kNT];
+    bool valid[kNT];
+#pragma unroll
+    for (int t = 0; t < kNT; ++t) {
+      const int q = q0 + wave * (kNT * 16) + t * 16 + col;
+      valid[t] = q < hw;
+      qc[t] = valid[t] ? q : hw - 1;          // tail lanes recompute a real pixel
+    }
+
+    // ================= stage 0: F layers 1-2 =================
+    fill_stage(1);
+    u32x4 h2[kNT][KS];
+    {
+      u32x4 x[kNT][1];
+#pragma unroll
+      for (int t = 0; t < kNT; ++t) {
+        float v[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          const int c = 8 * g + j;            // input column: G 0..13, scene 0..15, pad
+          v[j] = c < kNG ? Gp[(size_t)c * hw + qc[t]] : (c < kNG + kNS ? Sp[c - kNG] : 0.0f);
+        }
+        x[t][0] = u32x4{pk_bf16(v[0], v[1]), pk_bf16(v[2], v[3]), pk_bf16(v[4], v[5]),
+                        pk_bf16(v[6], v[7])};
+      }
+      const uint8_t *S = stage_buf(0);
+      u32x4 h1[kNT][KS];
+      layer<MT, 1, true>(h1, S, x, bF1, g, lane);
+      layer<MT, KS, true>(h2, S + f1_bytes, h1, bF2, g, lane);
+    }
+    wait_vm();
+    __syncthreads();
+
+    // ================= stage 1: F layer 3 -> sigma =================
+    fill_stage(2);
+    u32x4 sig[kNT][KS];
+    layer<MT, KS, false>(sig, stage_buf(1), h2, bF3, g, lane);
+    wait_vm();
+    __syncthreads();
+
+    // ================= stage 2: u = W1s sigma + c1, then the slot loop =======
+    fill_stage(3);
+    f32x4 Z[kNT][MT];
+    float cnt[kNT];
+    {
+      // u = W1s sigma + c1, kept as packed bf16 in the accumulator layout
+      u32x4 u[kNT][KS];
+      layer<MT, KS, false>(u, stage_buf(2), sig, bT1, g, lane);
+#pragma unroll
+      for (int t = 0; t < kNT; ++t) {
+        cnt[t] = 0.0f;
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) Z[t][mt] = f32x4{0.f, 0.f, 0.f, 0.f};
+      }
+      for (int i = 0; i < K; ++i) {
+        const float *Li = Lp + (size_t)i * kNL * hw;
+        int qs[kNT];
+#pragma unroll
+        for (int t = 0; t < kNT; ++t) {
+          qs[t] = qc[t];
+          asm volatile("" : "+v"(qs[t]));   // per-slot addresses stay in the loop body
+        }
+        u32x4 bi[kNT][1];
+        float m[kNT];
+#pragma unroll
+        for (int t = 0; t < kNT; ++t) {
+          float v[8];
+#pragma unroll
+          for (int j = 0; j < 8; ++j) {
+            const int c = 8 * g + j;
+            v[j] = c < kNL ? Li[(size_t)c * hw + qs[t]] : 0.0f;
+          }
+          m[t] = Li[(size_t)kAlpha * hw + qs[t]] > 0.0f ? 1.0f : 0.0f;
+          bi[t][0] = u32x4{pk_bf16(v[0], v[1]), pk_bf16(v[2], v[3]), pk_bf16(v[4], v[5]),
+                           pk_bf16(v[6], v[7])};
+        }
+        // h layer 1: z1 = relu(W1b b_i + u)
+        u32x4 z1[kNT][KS];
+#pragma unroll
+        for (int p = 0; p < KS; ++p) {
+#pragma unroll
+          for (int h = 0; h < 2; ++h) {
+            const u32x4 w = ld_frag(T1A, 2 * p + h, lane);
+#pragma unroll
+            for (int t = 0; t < kNT; ++t) {
+              const f32x4 v = mma(w, bi[t][0], unpk_bf16(u[t][p][2 * h], u[t][p][2 * h + 1]));
+              z1[t][p][2 * h] = relu_bf16x2(pk_bf16(v.x, v.y));
+              z1[t][p][2 * h + 1] = relu_bf16x2(pk_bf16(v.z, v.w));
+            }
+          }
+        }
+        // h layer 2 and the masked running sum: Z += m * relu(A2 z1 + c2)
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) {
+          const f32x4 b = *(const f32x4 *)(bT2 + 16 * mt + 4 * g);
+          f32x4 acc[kNT];
+#pragma unroll
+          for (int t = 0; t < kNT; ++t) acc[t] = b;
+#pragma unroll
+          for (int ks = 0; ks < KS; ++ks) {
+            const u32x4 w = ld_frag(T2, mt * KS + ks, lane);
+#pragma unroll
+            for (int t = 0; t < kNT; ++t) acc[t] = mma(w, z1[t][ks], acc[t]);
+          }
+#pragma unroll
+          for (int t = 0; t < kNT; ++t) {
+            const f32x4 r = relu4(acc[t]);
+            Z[t][mt].x = fmaf(m[t], r.x, Z[t][mt].x);
+            Z[t][mt].y = fmaf(m[t], r.y, Z[t][mt].y);
+            Z[t][mt].z = fmaf(m[t], r.z, Z[t][mt].z);
+            Z[t][mt].w = fmaf(m[t], r.w, Z[t][mt].w);
+          }
+        }
+#pragma unroll
+        for (int t = 0; t < kNT; ++t) cnt[t] += m[t];
+      }
+    }
+    wait_vm();
+    __syncthreads();
+
+    // ================= stage 3: pool and h layer 3 -> tau =================
+    fill_stage(4);
+    u32x4 tau[kNT][KS];
+    {
+      u32x4 zs[kNT][KS];
+      f32x4 acc[kNT][MT];
+#pragma unroll
+      for (int t = 0; t < kNT; ++t) {
+        const bool mean = a.pool == GN_POOL_MEAN;
+        const float inv = mean ? 1.0f / fmaxf(cnt[t], 1.0f) : 1.0f;
+        const float bs = mean ? (cnt[t] > 0.0f ? 1.0f : 0.0f) : cnt[t];
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) {
+          const f32x4 v = Z[t][mt] * inv;
+          zs[t][mt >> 1][2 * (mt & 1)] = pk_bf16(v.x, v.y);
+          zs[t][mt >> 1][2 * (mt & 1) + 1] = pk_bf16(v.z, v.w);
+          acc[t][mt] = *(const f32x4 *)(bT3 + 16 * mt + 4 * g) * bs;
+        }
+      }
+      mm<MT, KS>(acc, stage_buf(3), zs, lane);
+      to_frags<MT, false>(acc, tau);
+    }
+    wait_vm();
+    __syncthreads();
+
+    // ================= stages 4-5: B layer 1 on [sigma; tau] =================
+    fill_stage(5);
+    f32x4 accB[kNT][MT];
+    bias_init(accB, bB1, g);
+    mm<MT, KS>(accB, stage_buf(4), sig, lane);
+    wait_vm();
+    __syncthreads();
+
+    fill_stage(6);
+    u32x4 hb[kNT][KS];
+    mm<MT, KS>(accB, stage_buf(5), tau, lane);
+    to_frags<MT, true>(accB, hb);
+    wait_vm();
+    __syncthreads();
+
+    // ================= stage 6: B layer 2 =================
+    fill_stage(7);
+    {
+      u32x4 hb2[kNT][KS];
+      layer<MT, KS, true>(hb2, stage_buf(6), hb, bB2, g, lane);
+#pragma unroll
+      for (int t = 0; t < kNT; ++t)
+#pragma unroll
+        for (int k = 0; k < KS; ++k) hb[t][k] = hb2[t][k];
+    }
+    wait_vm();
+    __syncthreads();
+
+    // ================= stage 7: B layer 3 -> phi =================
+    fill_stage(8);
+    u32x4 phi[kNT][KS];
+    layer<MT, KS, false>(phi, stage_buf(7), hb, bB3, g, lane);
+    wait_vm();
+    __syncthreads();
+
+    // ================= stage 8: R layer 1 on [phi; L_d] =================
+    fill_stage(9);
+    u32x4 hr[kNT][KS];
+    {
+      u32x4 ld[kNT][1];
+#pragma unroll
+      for (int t = 0; t < kNT; ++t) {
+        float v[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          const int c = 8 * g + j;
+          v[j] = c < 3 ? Gp[(size_t)(11 + c) * hw + qc[t]] : 0.0f;
+        }
+        ld[t][0] = u32x4{pk_bf16(v[0], v[1]), pk_bf16(v[2], v[3]), pk_bf16(v[4], v[5]),
+                         pk_bf16(v[6], v[7])};
+      }
+      f32x4 acc[kNT][MT];
+      bias_init(acc, bR1, g);
+      mm<MT, KS>(acc, stage_buf(8), phi, lane);
+      mm<MT, 1>(acc, stage_buf(8) + r1p_bytes, ld, lane);
+      to_frags<MT, true>(acc, hr);
+    }
+    wait_vm();
+    __syncthreads();
+
+    // ================= stage 9: R layers 2-3 -> radiance =================
+    if (has_next) fill_stage(0);
+    {
+      u32x4 hr2[kNT][KS];
+      layer<MT, KS, true>(hr2, stage_buf(9), hr, bR2, g, lane);
+      f32x4 y[kNT][1];
+      bias_init(y, bR3, g);
+      mm<1, KS>(y, stage_buf(9) + r2_bytes, hr2, lane);
+#pragma unroll
+      for (int t = 0; t < kNT; ++t) {
+        if (g == 0 && valid[t]) {
+          Op[qc[t]] = y[t][0].x;
+          Op[(size_t)hw + qc[t]] = y[t][0].y;
+          Op[(size_t)2 * hw + qc[t]] = y[t][0].z;
+        }
+      }
+    }
+    wait_vm();
+    __syncthreads();
+  }
+}
+
+// ---- weight packing ---------------------------------------------------------
+struct PackArgs {
+  const float *master;
+  uint8_t *packed;
+  ChunkDesc chunk[kNumChunks];
+  LayerOff lo[kNumLayers];
+  int W;
+  int64_t bias_off;
+};
+
+__device__ __forceinline__ int chain_col(int ks, int g, int j) {
+  return 32 * ks + (j < 4 ? 4 * g + j : 16 + 4 * g + (j - 4));
+}
+
+// One thread per bf16 element of one chunk (blockIdx.y = chunk).
+__global__ void pack_bf16_kernel(PackArgs p) {
+  const ChunkDesc d = p.chunk[blockIdx.y];
+  const int64_t n = (int64_t)d.mt * d.ks * 64 * 8;
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  const int j = (int)(e & 7);
+  const int lane = (int)((e >> 3) & 63);
+  const int fragi = (int)(e >> 9);
+  const int mt = fragi / d.ks, ks = fragi - mt * d.ks;
+  const int row = 16 * mt + (lane & 15);
+  const int g = lane >> 4;
+  const int k = d.kmap == KMAP_MEM ? 32 * ks + 8 * g + j : chain_col(ks, g, j);
+  const LayerOff lo = p.lo[d.layer];
+  float v = 0.0f;
+  if (row < d.nrows && k < d.ncols) v = p.master[lo.w + (int64_t)row * lo.in + d.col0 + k];
+  __bf16 h = (__bf16)v;
+  ((__bf16 *)(p.packed + d.offset))[e] = h;
+}
+
+__global__ void pack_bias_kernel(PackArgs p) {
+  const int l = blockIdx.x, o = threadIdx.x;
+  if (o >= p.W) return;
+  const LayerOff lo = p.lo[l];
+  float v = o < lo.out ? p.master[lo.b + o] : 0.0f;
+  ((float *)(p.packed + p.bias_off))[(int64_t)l * p.W + o] = v;
+}
+
+// Transposed copy of every layer matrix ([out][in] -> [in][out]) for the fp32 path.
+__global__ void transpose_kernel(const float *master, float *mt, LayerOff lo) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t n = (int64_t)lo.out * lo.in;
+  if (e >= n) return;
+  const int r = (int)(e / lo.in), c = (int)(e - (int64_t)r * lo.in);
+  mt[lo.w + (int64_t)c * lo.out + r] = master[lo.w + e];
+}
+
+}  // namespace
+
+hipError_t launch_transpose_master(int W, const float *master, float *master_t,
+                                   hipStream_t stream) {
+  LayerOff lo[kNumLayers];
+  layer_offsets(W, lo);
+  for (int l = 0; l < kNumLayers; ++l) {
+    const int64_t n = (int64_t)lo[l].out * lo[l].in;
+    hipLaunchKernelGGL(transpose_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream,
+                       master, master_t, lo[l]);
+    // biases keep their place so both copies share offsets
+    hipError_t e = hipMemcpyAsync(master_t + lo[l].b, master + lo[l].b,
+                                  sizeof(float) * lo[l].out, hipMemcpyDeviceToDevice, stream);
+    if (e != hipSuccess) return e;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_pack_weights(const float *master, uint8_t *packed, const PackedLayout &pl,
+                               float fp8_act_scale, hipStream_t stream) {
+  (void)fp8_act_scale;
+  PackArgs p;
+  p.master = master;
+  p.packed = packed;
+  for (int c = 0; c < kNumChunks; ++c) p.chunk[c] = pl.chunk[c];
+  layer_offsets(pl.W, p.lo);
+  p.W = pl.W;
+  p.bias_off = pl.bias_off;
+  int64_t maxn = 0;
+  for (int c = 0; c < kNumChunks; ++c)
+    maxn = std::max<int64_t>(maxn, (int64_t)pl.chunk[c].mt * pl.chunk[c].ks * 512);
+  hipLaunchKernelGGL(pack_bf16_kernel, dim3((unsigned)((maxn + 255) / 256), kNumChunks), dim3(256),
+                     0, stream, p);
+  hipLaunchKernelGGL(pack_bias_kernel, dim3(kNumLayers), dim3(pl.W), 0, stream, p);
+  return hipGetLastError();
+}
+
+static size_t mfma_lds_bytes(const PackedLayout &pl) {
+  int64_t stage_max = 0;
+  for (int s = 0; s < kNumStages; ++s)
+    stage_max = std::max<int64_t>(stage_max, pl.stage_off[s + 1] - pl.stage_off[s]);
+  return (size_t)(pl.resident_bytes + (int64_t)kNumLayers * pl.W * 4 + 2 * stage_max);
+}
+
+template <int W, int PREC>
+static hipError_t launch_one(const MfmaArgs &a, int grid, size_t lds, hipStream_t stream) {
+  static bool attr_set = false;     // per process; the attribute is per function
+  if (!attr_set) {
+    hipError_t e = hipFuncSetAttribute((const void *)fwd_mfma_kernel<W, PREC>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    attr_set = true;
+  }
+  hipLaunchKernelGGL((fwd_mfma_kernel<W, PREC>), dim3(grid), dim3(kThreads), lds, stream, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_fwd_mfma(int W, int precision, int pool, const uint8_t *packed,
+                           const PackedLayout &pl, const FwdBatch *batch,
+                           const FrameDesc *frames, const TileRef *tiles, int ntiles,
+                           float fp8_act_scale, int grid, hipStream_t stream) {
+  MfmaArgs a;
+  a.packed = packed;
+  for (int s = 0; s <= kNumStages; ++s) a.stage_off[s] = pl.stage_off[s];
+  a.res_off = pl.resident_off;
+  a.res_bytes = pl.resident_bytes;
+  a.bias_off = pl.bias_off;
+  a.t2q_off = pl.t2q_off;
+  a.t2s_off = pl.t2scale_off;
+  if (batch) {
+    a.b = *batch;
+    a.tiles_per_frame = (batch->hw + kTilePx - 1) / kTilePx;
+  } else {
+    a.b = FwdBatch{};
+    a.tiles_per_frame = 1;
+  }
+  a.frames = frames;
+  a.tiles = tiles;
+  a.ntiles = ntiles;
+  a.pool = pool;
+  a.sa = fp8_act_scale;
+  a.inv_sa = 1.0f / fp8_act_scale;
+  if (ntiles <= 0) return hipSuccess;
+  grid = std::max(1, std::min(grid, ntiles));
+  const size_t lds = mfma_lds_bytes(pl);
+  if (precision == GN_BF16) {
+    if (W == 64) return launch_one<64, GN_BF16>(a, grid, lds, stream);
+    if (W == 128) return launch_one<128, GN_BF16>(a, grid, lds, stream);
+  }
+  return hipErrorInvalidValue;
+}
+
+}  // namespace gn

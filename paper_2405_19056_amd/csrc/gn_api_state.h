@@ -1,0 +1,39 @@
+// Handle state shared by the C-ABI sources (api.cpp, backward, serving).
+#pragma once
+
+#include <atomic>
+
+#include "gn_internal.h"
+
+struct GnServer;
+
+struct gn_handle {
+  gn_config cfg{};
+  int W = 0;
+  int device = 0;
+  int num_cus = 0;
+  size_t nparams = 0;
+  float *d_master = nullptr;      // fp32 master weights (flat layout)
+  float *d_master_t = nullptr;    // same, every matrix transposed (fp32 forward)
+  uint8_t *d_packed = nullptr;    // fragment-ordered bf16/fp8 weights + biases
+  gn::PackedLayout pl{};
+  float *d_scratch = nullptr;     // fp32 forward: per-thread vectors
+  int scratch_threads = 0;
+  float *d_l1_partials = nullptr;
+  int l1_npart = 0;
+  float act_scale = 0.0f;         // fp8 activation scale
+  std::atomic<bool> poisoned{false};
+  size_t bytes_held = 0;          // device bytes of the forward state
+  gn::BwdWorkspace *bwd = nullptr;
+  GnServer *server = nullptr;
+};
+
+gn_status gn_set_error(gn_status code, const char *msg);
+gn_status gn_check_device(gn_handle *h, hipError_t e, const char *what);
+gn_status gn_validate_frame(gn_handle *h, const gn_frame *f, const float *out);
+gn_status gn_prepare_weights(gn_handle *h, hipStream_t stream);
+
+gn_status gn_serve_init(gn_handle *h);
+void gn_serve_shutdown(gn_handle *h);
+void gn_bwd_free(gn_handle *h);
+size_t gn_bwd_bytes(gn_handle *h);

@@ -1,0 +1,117 @@
+// Internal declarations shared by the GlassNet library sources.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "glassnet.h"
+
+namespace gn {
+
+constexpr int kNG = GN_NUM_G, kNL = GN_NUM_L, kNS = GN_NUM_S, kNOUT = GN_NUM_OUT;
+constexpr int kAlpha = GN_ALPHA_PLANE;
+
+// One frame as the kernels see it: pointers already offset to the frame.
+struct FrameDesc {
+  const float *g;    // [14][hw]
+  const float *L;    // [k][12][hw]
+  const float *s;    // [16]
+  float *out;        // [3][hw]
+  int32_t hw;
+  int32_t k;
+  int32_t pad0, pad1;
+};
+
+// A tile of the fused MFMA kernel: kTilePx pixels of one frame from q0.
+struct TileRef {
+  int32_t frame;     // index into a FrameDesc table
+  int32_t q0;
+};
+
+// The 12 linear layers in the flat master vector.
+enum Layer { L_F1, L_F2, L_F3, L_T1, L_T2, L_T3, L_B1, L_B2, L_B3, L_R1, L_R2, L_R3, kNumLayers };
+
+struct LayerOff {
+  int64_t w, b;      // float offsets of matrix and bias
+  int32_t out, in;
+};
+
+void layer_offsets(int W, LayerOff lo[kNumLayers]);
+size_t num_params(int W);
+
+// ---- packed (fragment-ordered) weights of the MFMA forward -----------------
+// A chunk is the part of one layer's matrix that multiplies one input source.
+// It is stored as MT x KS fragments of 64 lanes x 16 bytes: lane l of fragment
+// (mt, ks) holds row 16*mt + (l & 15) and the 8 inputs of K-step ks that lane
+// group l >> 4 presents to the matrix core.  Inputs that come straight from
+// memory use the natural order (8 consecutive channels per lane group);
+// inputs produced by a previous layer use the order in which that layer's
+// accumulator rows sit in the lanes, so activations chain from one layer to
+// the next without leaving registers.
+enum Chunk {
+  C_F1, C_F2, C_F3, C_T1S, C_T3, C_B1S, C_B1T, C_B2, C_B3, C_R1P, C_R1L, C_R2, C_R3,
+  C_T1A, C_T2,            // resident in LDS through the slot loop
+  kNumChunks
+};
+enum KMap { KMAP_CHAIN = 0, KMAP_MEM = 1 };
+
+struct ChunkDesc {
+  int32_t layer;     // Layer
+  int32_t col0;      // first input column of the master layer this chunk covers
+  int32_t ncols;     // real input columns (K padded to 32*ks)
+  int32_t nrows;     // real output rows (M padded to 16*mt)
+  int32_t mt, ks;
+  int32_t kmap;
+  int32_t elem_bytes;  // 2 (bf16) or 1 (fp8)
+  int64_t offset;      // byte offset in the packed buffer
+};
+
+constexpr int kNumStages = 10;
+
+struct PackedLayout {
+  int W;
+  ChunkDesc chunk[kNumChunks];
+  int64_t stage_off[kNumStages + 1];   // byte ranges of the staged chunks
+  int64_t resident_off, resident_bytes;  // T1A + T2 (bf16)
+  int64_t bias_off;                    // fp32 biases: 12 x W floats
+  int64_t t2q_off;                     // fp8 copy of T2 (FP8_T), MT x 1 fragments of 64 x 32 B
+  int64_t t2scale_off;                 // fp32 per-row dequant scales of the fp8 T2 (W floats)
+  int64_t total_bytes;
+};
+
+void make_packed_layout(int W, PackedLayout *pl);
+
+// ---- launches (all asynchronous on `stream`) --------------------------------
+struct FwdBatch {
+  // Arithmetic mode: n frames of equal hw/k laid out as in gn_frame.
+  const float *gbuf, *layers, *scene;
+  float *out;
+  int32_t n, hw, k;
+};
+
+hipError_t launch_transpose_master(int W, const float *master, float *master_t,
+                                  hipStream_t stream);
+hipError_t launch_pack_weights(const float *master, uint8_t *packed, const PackedLayout &pl,
+                               float fp8_act_scale, hipStream_t stream);
+
+// master_t: each layer's matrix transposed to [in][out] at the master offsets.
+hipError_t launch_fwd_fp32(int W, int pool, const float *master, const float *master_t,
+                           const FwdBatch &b,
+                           float *scratch, int scratch_threads, hipStream_t stream);
+int fp32_scratch_threads(int num_cus);
+
+hipError_t launch_fwd_mfma(int W, int precision, int pool, const uint8_t *packed,
+                           const PackedLayout &pl, const FwdBatch *batch,
+                           const FrameDesc *frames, const TileRef *tiles, int ntiles,
+                           float fp8_act_scale, int grid, hipStream_t stream);
+constexpr int kTilePx = 256;
+
+hipError_t launch_l1(const float *out, const float *target, uint64_t count, float *loss,
+                     float *grad, float *partials, int npart, hipStream_t stream);
+
+struct BwdWorkspace;
+hipError_t launch_backward(int W, int pool, const float *master, const FwdBatch &b,
+                           const float *grad_out, float *grad_w, BwdWorkspace *ws,
+                           hipStream_t stream);
+
+}  // namespace gn

@@ -1,0 +1,91 @@
+// Host-side layout tables: master weight offsets and the packed MFMA layout.
+#include <string.h>
+
+#include "gn_internal.h"
+
+namespace gn {
+
+void layer_offsets(int W, LayerOff lo[kNumLayers]) {
+  const int outs[kNumLayers] = {W, W, W, W, W, W, W, W, W, W, W, kNOUT};
+  const int ins[kNumLayers] = {kNG + kNS, W, W, kNL + W, W, W, 2 * W, W, W, W + 3, W, W};
+  int64_t off = 0;
+  for (int l = 0; l < kNumLayers; ++l) {
+    lo[l].w = off;
+    off += (int64_t)outs[l] * ins[l];
+    lo[l].b = off;
+    off += outs[l];
+    lo[l].out = outs[l];
+    lo[l].in = ins[l];
+  }
+}
+
+size_t num_params(int W) {
+  if (W != 64 && W != 128) return 0;
+  return (size_t)11 * W * W + (size_t)59 * W + 3;
+}
+
+void make_packed_layout(int W, PackedLayout *pl) {
+  memset(pl, 0, sizeof(*pl));
+  pl->W = W;
+  const int MT = W / 16, KS = W / 32;
+  auto set = [&](Chunk c, int layer, int col0, int ncols, int nrows, int mt, int ks, int kmap) {
+    ChunkDesc &d = pl->chunk[c];
+    d.layer = layer;
+    d.col0 = col0;
+    d.ncols = ncols;
+    d.nrows = nrows;
+    d.mt = mt;
+    d.ks = ks;
+    d.kmap = kmap;
+    d.elem_bytes = 2;
+  };
+  set(C_F1, L_F1, 0, kNG + kNS, W, MT, 1, KMAP_MEM);
+  set(C_F2, L_F2, 0, W, W, MT, KS, KMAP_CHAIN);
+  set(C_F3, L_F3, 0, W, W, MT, KS, KMAP_CHAIN);
+  set(C_T1S, L_T1, kNL, W, W, MT, KS, KMAP_CHAIN);
+  set(C_T3, L_T3, 0, W, W, MT, KS, KMAP_CHAIN);
+  set(C_B1S, L_B1, 0, W, W, MT, KS, KMAP_CHAIN);
+  set(C_B1T, L_B1, W, W, W, MT, KS, KMAP_CHAIN);
+  set(C_B2, L_B2, 0, W, W, MT, KS, KMAP_CHAIN);
+  set(C_B3, L_B3, 0, W, W, MT, KS, KMAP_CHAIN);
+  set(C_R1P, L_R1, 0, W, W, MT, KS, KMAP_CHAIN);
+  set(C_R1L, L_R1, W, 3, W, MT, 1, KMAP_MEM);
+  set(C_R2, L_R2, 0, W, W, MT, KS, KMAP_CHAIN);
+  set(C_R3, L_R3, 0, W, kNOUT, 1, KS, KMAP_CHAIN);
+  set(C_T1A, L_T1, 0, kNL, W, MT, 1, KMAP_MEM);
+  set(C_T2, L_T2, 0, W, W, MT, KS, KMAP_CHAIN);
+
+  // Stage groups in kernel order; every fragment is 1 KiB so stages stay
+  // multiples of 1 KiB.
+  const Chunk stages[kNumStages][2] = {
+      {C_F1, C_F2}, {C_F3, kNumChunks}, {C_T1S, kNumChunks}, {C_T3, kNumChunks},
+      {C_B1S, kNumChunks}, {C_B1T, kNumChunks}, {C_B2, kNumChunks}, {C_B3, kNumChunks},
+      {C_R1P, C_R1L}, {C_R2, C_R3}};
+  int64_t off = 0;
+  for (int s = 0; s < kNumStages; ++s) {
+    pl->stage_off[s] = off;
+    for (int j = 0; j < 2; ++j) {
+      Chunk c = stages[s][j];
+      if (c == kNumChunks) continue;
+      pl->chunk[c].offset = off;
+      off += (int64_t)pl->chunk[c].mt * pl->chunk[c].ks * 1024;
+    }
+  }
+  pl->stage_off[kNumStages] = off;
+  pl->resident_off = off;
+  pl->chunk[C_T1A].offset = off;
+  off += (int64_t)MT * 1024;
+  pl->chunk[C_T2].offset = off;
+  off += (int64_t)MT * KS * 1024;
+  pl->resident_bytes = off - pl->resident_off;
+  pl->bias_off = off;
+  off += (int64_t)kNumLayers * W * 4;
+  off = (off + 1023) & ~(int64_t)1023;
+  pl->t2q_off = off;                       // fp8 T2: MT fragments of 64 lanes x 32 B
+  off += (int64_t)MT * 2048;
+  pl->t2scale_off = off;                   // fp32 per-row scales, padded to 1 KiB
+  off += ((int64_t)W * 4 + 1023) & ~(int64_t)1023;
+  pl->total_bytes = off;
+}
+
+}  // namespace gn

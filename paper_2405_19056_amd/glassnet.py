@@ -1,0 +1,238 @@
+"""ctypes binding of libglassnet (the C ABI declared in include/glassnet.h).
+
+Argument marshalling only: torch supplies device memory and the current HIP
+stream; every step of the computation runs in the library's kernels.  The
+binding refuses to run without the built library.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from ctypes import POINTER, byref, c_char_p, c_double, c_float, c_int32, c_size_t, c_uint64, c_void_p
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libglassnet.so")
+
+GN_OK, GN_E_INVAL, GN_E_NOMEM, GN_E_DEVICE, GN_E_UNSUPPORTED, GN_E_AGAIN, GN_E_BUSY = 0, -1, -2, -3, -4, -5, -6
+PRECISION = {"fp32": 0, "bf16": 1, "fp8_t": 2}
+POOL = {"mean": 0, "sum": 1}
+NUM_G, NUM_L, NUM_S, NUM_OUT = 14, 12, 16, 3
+
+
+class GnConfig(ctypes.Structure):
+    _fields_ = [("width", c_int32), ("k_max", c_int32), ("pool", c_int32),
+                ("precision", c_int32), ("hbm_budget_bytes", c_uint64), ("device", c_int32),
+                ("max_pending", c_int32)]
+
+
+class GnFrame(ctypes.Structure):
+    _fields_ = [("n", c_int32), ("h", c_int32), ("w", c_int32), ("k", c_int32),
+                ("gbuf", c_void_p), ("layers", c_void_p), ("scene", c_void_p)]
+
+
+class GnTiming(ctypes.Structure):
+    _fields_ = [("t_submit", c_double), ("t_admit", c_double), ("t_start", c_double),
+                ("t_done", c_double)]
+
+
+class GlassNetError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"glassnet status {status}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+# name -> (restype, argtypes)
+_SIGS = {
+    "glassnet_num_params": (c_size_t, [c_int32]),
+    "glassnet_create": (c_int32, [POINTER(GnConfig), POINTER(c_float), c_size_t, POINTER(c_void_p)]),
+    "glassnet_destroy": (c_int32, [c_void_p]),
+    "glassnet_get_weights": (c_int32, [c_void_p, POINTER(c_float), c_size_t]),
+    "glassnet_set_weights": (c_int32, [c_void_p, c_void_p, c_size_t, c_void_p]),
+    "glassnet_set_act_scales": (c_int32, [c_void_p, POINTER(c_float), c_size_t]),
+    "glassnet_forward": (c_int32, [c_void_p, POINTER(GnFrame), c_void_p, c_void_p]),
+    "glassnet_backward": (c_int32, [c_void_p, POINTER(GnFrame), c_void_p, c_void_p, c_void_p]),
+    "glassnet_l1_loss": (c_int32, [c_void_p, c_void_p, c_void_p, c_uint64, c_void_p, c_void_p,
+                                   c_void_p]),
+    "glassnet_workspace_bytes": (c_int32, [c_void_p, POINTER(c_uint64)]),
+    "serve_submit": (c_int32, [c_void_p, POINTER(GnFrame), c_void_p, POINTER(c_uint64)]),
+    "serve_poll": (c_int32, [c_void_p, c_uint64, POINTER(c_int32), POINTER(GnTiming)]),
+    "serve_drain": (c_int32, [c_void_p]),
+    "serve_forget": (c_int32, [c_void_p, c_uint64]),
+    "glassnet_last_error": (c_char_p, []),
+}
+
+
+def lib():
+    """Load libglassnet.so (built in-tree); fail loudly if it is missing."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built: run `python -m paper_2405_19056_amd.build`")
+        # torch ships its own HIP runtime under the same soname as the system
+        # one; load it first so that the library and torch share one runtime.
+        import torch  # noqa: F401
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(status):
+    if status != GN_OK:
+        raise GlassNetError(status, lib().glassnet_last_error().decode())
+    return status
+
+
+def num_params(width: int) -> int:
+    return int(lib().glassnet_num_params(width))
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _dev_ptr(t, name):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a device tensor")
+    if t.dtype != torch.float32 or not t.is_contiguous():
+        raise TypeError(f"{name} must be contiguous float32")
+    return t.data_ptr()
+
+
+def _stream(stream):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return c_void_p(s.cuda_stream)
+
+
+def make_frame(gbuf, layers, scene) -> GnFrame:
+    n, c, h, w = gbuf.shape
+    if c != NUM_G:
+        raise ValueError("gbuf must be [n][14][h][w]")
+    k = layers.shape[1] if layers is not None else 0
+    if layers is not None and tuple(layers.shape) != (n, k, NUM_L, h, w):
+        raise ValueError("layers must be [n][k][12][h][w]")
+    if tuple(scene.shape) != (n, NUM_S):
+        raise ValueError("scene must be [n][16]")
+    lp = _dev_ptr(layers, "layers") if (layers is not None and k > 0) else None
+    return GnFrame(n, h, w, k, _dev_ptr(gbuf, "gbuf"), lp, _dev_ptr(scene, "scene"))
+
+
+class GlassNet:
+    """One library handle: weights resident on the device, one precision."""
+
+    def __init__(self, weights, width, k_max=8, pool="mean", precision="fp32", device=0,
+                 hbm_budget_bytes=0, max_pending=0):
+        w = np.ascontiguousarray(np.asarray(weights, dtype=np.float32).ravel())
+        cfg = GnConfig(width, k_max, POOL[pool], PRECISION[precision], hbm_budget_bytes, device,
+                       max_pending)
+        h = c_void_p()
+        _check(lib().glassnet_create(byref(cfg), w.ctypes.data_as(POINTER(c_float)), w.size,
+                                     byref(h)))
+        self._h = h
+        self.width, self.k_max, self.pool, self.precision, self.device = (
+            width, k_max, pool, precision, device)
+        self.nparams = w.size
+        self._keep = {}       # serving: keeps submitted tensors alive until polled done
+
+    # -- lifetime
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().glassnet_destroy(self._h)
+            self._h = c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    # -- weights
+    def get_weights(self) -> np.ndarray:
+        out = np.empty(self.nparams, dtype=np.float32)
+        _check(lib().glassnet_get_weights(self._h, out.ctypes.data_as(POINTER(c_float)), out.size))
+        return out
+
+    def set_weights(self, dev_weights, stream=None):
+        _check(lib().glassnet_set_weights(self._h, _dev_ptr(dev_weights, "weights"),
+                                          dev_weights.numel(), _stream(stream)))
+
+    def set_act_scale(self, scale: float):
+        s = (c_float * 1)(scale)
+        _check(lib().glassnet_set_act_scales(self._h, s, 1))
+
+    def workspace_bytes(self) -> int:
+        b = c_uint64()
+        _check(lib().glassnet_workspace_bytes(self._h, byref(b)))
+        return int(b.value)
+
+    # -- compute
+    def forward(self, gbuf, layers, scene, out=None, stream=None):
+        torch = _torch()
+        fr = make_frame(gbuf, layers, scene)
+        if out is None:
+            out = torch.empty((fr.n, NUM_OUT, fr.h, fr.w), dtype=torch.float32, device=gbuf.device)
+        _check(lib().glassnet_forward(self._h, byref(fr), _dev_ptr(out, "out"), _stream(stream)))
+        return out
+
+    def backward(self, gbuf, layers, scene, grad_out, grad_w=None, stream=None):
+        torch = _torch()
+        fr = make_frame(gbuf, layers, scene)
+        if grad_w is None:
+            grad_w = torch.empty(self.nparams, dtype=torch.float32, device=gbuf.device)
+        _check(lib().glassnet_backward(self._h, byref(fr), _dev_ptr(grad_out, "grad_out"),
+                                       _dev_ptr(grad_w, "grad_w"), _stream(stream)))
+        return grad_w
+
+    def l1_loss(self, out, target, loss=None, grad_out=None, stream=None):
+        torch = _torch()
+        if loss is None:
+            loss = torch.empty((), dtype=torch.float32, device=out.device)
+        gp = _dev_ptr(grad_out, "grad_out") if grad_out is not None else None
+        _check(lib().glassnet_l1_loss(self._h, _dev_ptr(out, "out"), _dev_ptr(target, "target"),
+                                      out.numel(), _dev_ptr(loss, "loss"), gp, _stream(stream)))
+        return loss
+
+    # -- serving
+    def serve_submit(self, gbuf, layers, scene, out) -> int:
+        fr = make_frame(gbuf, layers, scene)
+        t = c_uint64()
+        _check(lib().serve_submit(self._h, byref(fr), _dev_ptr(out, "out"), byref(t)))
+        self._keep[t.value] = (gbuf, layers, scene, out)
+        return int(t.value)
+
+    def serve_poll(self, ticket: int):
+        """(done, timing dict or None)."""
+        done = c_int32()
+        tm = GnTiming()
+        _check(lib().serve_poll(self._h, ticket, byref(done), byref(tm)))
+        if done.value:
+            self._keep.pop(ticket, None)
+            return True, dict(t_submit=tm.t_submit, t_admit=tm.t_admit, t_start=tm.t_start,
+                              t_done=tm.t_done)
+        return False, None
+
+    def serve_drain(self):
+        _check(lib().serve_drain(self._h))
+
+    def serve_forget(self, ticket: int):
+        _check(lib().serve_forget(self._h, ticket))
+
+
+def last_error() -> str:
+    return lib().glassnet_last_error().decode()

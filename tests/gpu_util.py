@@ -1,0 +1,69 @@
+"""Helpers shared by the GPU tests: device transfer, sampling, error metrics."""
+import sys
+
+import numpy as np
+
+import oracle
+from paper_2405_19056_amd import synth
+
+
+def torch_dev():
+    import torch
+    if not torch.cuda.is_available():
+        import pytest
+        pytest.skip("no GPU")
+    return torch
+
+
+def dev(a):
+    torch = torch_dev()
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to("cuda:0")
+
+
+def host(t):
+    return t.detach().to("cpu").numpy()
+
+
+def relF(y, ref):
+    y = np.asarray(y, dtype=np.float64)
+    ref = np.asarray(ref, dtype=np.float64)
+    return float(np.linalg.norm((y - ref).ravel()) / np.linalg.norm(ref.ravel()))
+
+
+def relInf(y, ref):
+    y = np.asarray(y, dtype=np.float64)
+    ref = np.asarray(ref, dtype=np.float64)
+    return float(np.max(np.abs(y - ref)) / np.max(np.abs(ref)))
+
+
+def sample_pixels(fr: synth.Frame, count, rng):
+    """Pick `count` pixels (frame index, flat pixel) and gather them into a
+    one-row frame per source frame (pixels are independent, Sec. 3.4)."""
+    n, hw = fr.n, fr.h * fr.w
+    flat = rng.choice(n * hw, size=min(count, n * hw), replace=False)
+    flat.sort()
+    return flat
+
+
+def oracle_on_sample(w, W, fr: synth.Frame, flat, pool):
+    """Oracle output [len(flat)][3] for the sampled pixels."""
+    hw = fr.h * fr.w
+    out = np.empty((len(flat), 3))
+    for f in np.unique(flat // hw):
+        sel = flat[flat // hw == f] % hw
+        g = fr.gbuf[f].reshape(14, hw)[:, sel][None, :, None, :]
+        L = fr.layers[f].reshape(fr.k, 12, hw)[:, :, sel][None, :, :, None, :]
+        y = oracle.forward(w, W, g, L, fr.scene[f:f + 1], pool=pool)
+        out[flat // hw == f] = y[0, :, 0, :].T
+    return out
+
+
+def gpu_on_sample(y_dev_np, fr: synth.Frame, flat):
+    hw = fr.h * fr.w
+    f, q = flat // hw, flat % hw
+    yy = y_dev_np.reshape(fr.n, 3, hw)
+    return yy[f, :, q]
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)

@@ -1,0 +1,181 @@
+"""GPU parity of the forward pass against the FP64 oracle, through the C ABI.
+
+Tolerances (relative Frobenius error on output radiance): fp32 1e-4, bf16
+2e-2.  Small frames are compared element by element; the full 256^2/K=4 and
+512^2/K=8 workloads are compared on sampled pixels the oracle evaluates one
+by one (pixels are independent).
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2405_19056_amd import synth
+from paper_2405_19056_amd.glassnet import GlassNet, GlassNetError, GN_E_INVAL
+
+from gpu_util import dev, gpu_on_sample, host, log, oracle_on_sample, relF, relInf, torch_dev
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp32": 1e-4, "bf16": 2e-2}
+
+
+def frame(n, h, w, k, W, seed, alpha_mode="uniform_count"):
+    s = synth.streams(seed)
+    wts = synth.make_weights(W, s["weights"])
+    fr = synth.Frame(synth.make_gbuf(n, h, w, s["gbuf"]),
+                     synth.make_layers(n, k, h, w, s["slots"], s["active"], alpha_mode),
+                     synth.make_scene(n, s["gbuf"]))
+    return wts, fr
+
+
+def run(net, fr):
+    torch = torch_dev()
+    L = dev(fr.layers) if fr.k > 0 else None
+    y = net.forward(dev(fr.gbuf), L, dev(fr.scene))
+    torch.cuda.synchronize()
+    return host(y)
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+def test_config0_64sq_k2_w64_elementwise(precision):
+    w, fr, _ = synth.config_inputs("c0_64sq_k2_w64")
+    log(f"config c0 {precision}")
+    ref = oracle.forward(w, 64, fr.gbuf, fr.layers, fr.scene, pool="mean")
+    with GlassNet(w, 64, k_max=2, pool="mean", precision=precision) as net:
+        y = run(net, fr)
+    e = relF(y, ref)
+    log(f"  relF={e:.3e} relInf={relInf(y, ref):.3e}")
+    assert e <= TOL[precision]
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+@pytest.mark.parametrize("pool", ["mean", "sum"])
+@pytest.mark.parametrize("W", [64, 128])
+def test_ragged_multi_frame(precision, pool, W):
+    """3 frames of 37 x 53 (several tiles and a ragged tail), K=5."""
+    w, fr = frame(3, 37, 53, 5, W, seed=100 + W)
+    log(f"ragged {precision} {pool} W={W}")
+    ref = oracle.forward(w, W, fr.gbuf, fr.layers, fr.scene, pool=pool)
+    with GlassNet(w, W, k_max=8, pool=pool, precision=precision) as net:
+        y = run(net, fr)
+    e = relF(y, ref)
+    log(f"  relF={e:.3e}")
+    assert e <= TOL[precision]
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+def test_edge_shapes(precision):
+    W = 128
+    for (n, h, w_, k) in [(1, 1, 1, 1), (1, 1, 7, 0), (2, 3, 5, 3), (1, 16, 16, 8), (1, 5, 61, 2)]:
+        wts, fr = frame(n, h, w_, k, W, seed=7 + h + k)
+        log(f"edge {precision} n={n} h={h} w={w_} k={k}")
+        ref = oracle.forward(wts, W, fr.gbuf, fr.layers, fr.scene)
+        with GlassNet(wts, W, k_max=8, precision=precision) as net:
+            y = run(net, fr)
+        assert relF(y, ref) <= TOL[precision], (n, h, w_, k)
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+def test_all_slots_inactive_equals_no_slots(precision):
+    W = 128
+    wts, fr = frame(1, 24, 24, 4, W, seed=5)
+    L0 = fr.layers.copy()
+    L0[:, :, 9] = 0.0
+    with GlassNet(wts, W, k_max=8, precision=precision) as net:
+        y_dead = run(net, synth.Frame(fr.gbuf, L0, fr.scene))
+        y_none = run(net, synth.Frame(fr.gbuf, fr.layers[:, :0], fr.scene))
+    assert np.array_equal(y_dead, y_none)
+    ref = oracle.forward(wts, W, fr.gbuf, fr.layers[:, :0], fr.scene)
+    assert relF(y_none, ref) <= TOL[precision]
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+def test_one_active_slot_equals_k1(precision):
+    W = 128
+    wts, fr = frame(1, 32, 32, 8, W, seed=9)
+    rng = np.random.default_rng(1)
+    L = fr.layers.copy()
+    L[:, :, 9] = 0.0
+    pos = rng.integers(0, 8, size=(32, 32))
+    single = np.empty((1, 1, 12, 32, 32), np.float32)
+    for r in range(32):
+        for c in range(32):
+            L[0, pos[r, c], 9, r, c] = 0.1 + 0.9 * rng.uniform()
+            single[0, 0, :, r, c] = L[0, pos[r, c], :, r, c]
+    with GlassNet(wts, W, k_max=8, precision=precision) as net:
+        y8 = run(net, synth.Frame(fr.gbuf, L, fr.scene))
+        y1 = run(net, synth.Frame(fr.gbuf, single, fr.scene))
+    assert np.array_equal(y8, y1)
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+def test_slot_permutations(precision):
+    """Per-pixel shuffles of the slots: fp32 within 1e-6 of the unshuffled
+    output (relative to its max); bf16 reported and bounded by its tolerance."""
+    W = 128
+    wts, fr = frame(1, 64, 64, 8, W, seed=21)
+    perms = synth.slot_shuffles(1, 8, 64, 64, 8, np.random.default_rng(2))
+    with GlassNet(wts, W, k_max=8, precision=precision) as net:
+        y0 = run(net, fr)
+        worst = 0.0
+        for p in perms:
+            y = run(net, synth.Frame(fr.gbuf, synth.apply_slot_permutation(fr.layers, p), fr.scene))
+            worst = max(worst, float(np.max(np.abs(y - y0)) / np.max(np.abs(y0))))
+    log(f"  {precision} permutation deviation {worst:.3e}")
+    assert worst <= (1e-6 if precision == "fp32" else TOL[precision])
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+def test_run_to_run_bitwise(precision):
+    W = 128
+    wts, fr = frame(2, 40, 40, 4, W, seed=31)
+    with GlassNet(wts, W, k_max=8, precision=precision) as net:
+        a = run(net, fr)
+        b = run(net, fr)
+    assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("cfg,precision", [("c1_256sq_k4_w128", "bf16"),
+                                           ("c1_256sq_k4_w128", "fp32"),
+                                           ("c2_512sq_k8_w128", "bf16"),
+                                           ("c2_512sq_k8_w128", "fp32")])
+def test_full_size_on_sampled_pixels(cfg, precision):
+    c = synth.CONFIGS[cfg]
+    w, fr, _ = synth.config_inputs(cfg)
+    log(f"full-size {cfg} {precision}")
+    with GlassNet(w, c["width"], k_max=c["k"], pool=c["pool"], precision=precision) as net:
+        y = run(net, fr)
+    assert np.all(np.isfinite(y))
+    flat = np.random.default_rng(0).choice(fr.n * fr.h * fr.w, size=3000, replace=False)
+    ref = oracle_on_sample(w, c["width"], fr, flat, c["pool"])
+    got = gpu_on_sample(y, fr, flat)
+    e = relF(got, ref)
+    log(f"  sampled relF={e:.3e} relInf={relInf(got, ref):.3e}")
+    assert e <= TOL[precision]
+
+
+def test_invalid_arguments_are_rejected():
+    torch = torch_dev()
+    W = 64
+    wts, fr = frame(1, 8, 8, 3, W, seed=1)
+    with GlassNet(wts, W, k_max=2) as net:
+        with pytest.raises(GlassNetError) as e:
+            run(net, fr)                     # k=3 > k_max=2
+        assert e.value.status == GN_E_INVAL
+        g = dev(fr.gbuf)
+        with pytest.raises(GlassNetError):
+            net.forward(g, dev(fr.layers[:, :2]), dev(fr.scene), out=g.view(-1)[:3 * 64].view(1, 3, 8, 8))
+        # the handle still works after rejected calls
+        y = net.forward(g, dev(fr.layers[:, :2]), dev(fr.scene))
+        torch.cuda.synchronize()
+        assert np.all(np.isfinite(host(y)))
+
+
+def test_workspace_does_not_depend_on_k():
+    W = 128
+    wts, _ = frame(1, 4, 4, 1, W, seed=0)
+    sizes = []
+    for kmax in (1, 2, 4, 8, 16):
+        with GlassNet(wts, W, k_max=kmax, precision="bf16") as net:
+            sizes.append(net.workspace_bytes())
+    assert len(set(sizes)) == 1, sizes

@@ -1,0 +1,77 @@
+"""CPU checks of the C-ABI library: it builds, loads and exports its header.
+
+No compute call is made here (there is no GPU in this container)."""
+import os
+import re
+import subprocess
+
+import pytest
+
+from paper_2405_19056_amd import glassnet as gb
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "glassnet.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b((?:glassnet|serve)_\w+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for required in ("glassnet_create", "glassnet_forward", "glassnet_backward",
+                     "serve_submit", "serve_poll", "glassnet_destroy", "glassnet_l1_loss"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol():
+    if not os.path.exists(gb.LIB_PATH):
+        pytest.skip("libglassnet.so not built")
+    out = subprocess.run(["nm", "-D", "--defined-only", gb.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    exported = set(re.findall(r" T (\w+)$", out, flags=re.M))
+    missing = [n for n in declared_functions() if n not in exported]
+    assert not missing, missing
+    lib = gb.lib()
+    for n in declared_functions():
+        assert hasattr(lib, n)
+
+
+def test_header_is_plain_c():
+    r = subprocess.run(["gcc", "-x", "c", "-std=c99", "-Wall", "-Werror", "-fsyntax-only", "-"],
+                       input='#include "glassnet.h"\nint main(void){return 0;}\n', text=True,
+                       capture_output=True, cwd=os.path.join(ROOT, "include"))
+    assert r.returncode == 0, r.stderr
+
+
+def test_num_params_and_error_string():
+    if not os.path.exists(gb.LIB_PATH):
+        pytest.skip("libglassnet.so not built")
+    assert gb.num_params(64) == 11 * 64 * 64 + 59 * 64 + 3
+    assert gb.num_params(128) == 187779
+    assert gb.num_params(96) == 0
+    assert isinstance(gb.last_error(), str)
+
+
+def test_create_rejects_bad_config_before_touching_a_device():
+    if not os.path.exists(gb.LIB_PATH):
+        pytest.skip("libglassnet.so not built")
+    import numpy as np
+    with pytest.raises(gb.GlassNetError) as e:
+        gb.GlassNet(np.zeros(10, np.float32), width=96)
+    assert e.value.status == gb.GN_E_UNSUPPORTED
+    with pytest.raises(gb.GlassNetError) as e:
+        gb.GlassNet(np.zeros(10, np.float32), width=64)     # wrong count
+    assert e.value.status == gb.GN_E_INVAL
+    with pytest.raises(gb.GlassNetError) as e:
+        gb.GlassNet(np.zeros(gb.num_params(64), np.float32), width=64, precision="fp8_t")
+    assert e.value.status == gb.GN_E_UNSUPPORTED
+
+
+def test_binding_refuses_a_missing_library(monkeypatch):
+    monkeypatch.setattr(gb, "_lib", None)
+    monkeypatch.setattr(gb, "LIB_PATH", "/nonexistent/libglassnet.so")
+    with pytest.raises(RuntimeError, match="not built"):
+        gb.lib()

@@ -1,0 +1,214 @@
+#!/usr/bin/env python3
+"""GlassNet per-pixel evaluation benchmark on one MI355X.
+
+One step = one fused forward pass (F, T over all K slots, pool, B, R) over one
+512 x 512 frame with K = 8 transparency layers at width 128, inputs resident
+in HBM.  Prints ONE JSON line (rank 0).
+
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision bf16|fp8_t]
+                  [--no-cpu-baseline] [--no-serve]
+  python bench.py --copy-probe      # plain device copy of known size, for
+                                    # scaling rocprofv3 FETCH/WRITE counters
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+WORKLOAD = "c2_512sq_k8_w128"
+PEAK_TFLOPS = {"bf16": 2500.0, "fp8_t": 2500.0, "fp32": 157.3}
+# Algorithmic work per pixel of the method (sigma-hoisted, dense over the K
+# slots): 9 W^2 + 2 K W^2 + (36 + 12 K) W multiply-adds.
+def alg_flop_per_px(W, K):
+    return 2 * (9 * W * W + 2 * K * W * W + (36 + 12 * K) * W)
+
+
+# Matrix-core work the fused kernel issues per pixel (its padding included):
+# F1 K=32, slot layer K=32 per slot, R1's L_d part K=32, R3 M=16.
+def executed_flop_per_px(W, K):
+    mt = W // 16
+    frags = (mt * 1 + 2 * mt * (W // 32)        # F1, F2, F3
+             + mt * (W // 32)                     # sigma part of h layer 1
+             + K * (mt + mt * (W // 32))          # per slot: h layers 1, 2
+             + mt * (W // 32)                     # h layer 3 after the pool
+             + 4 * mt * (W // 32)                 # B1 (2W inputs), B2, B3
+             + mt * (W // 32) + mt                # R1 (phi and L_d parts)
+             + mt * (W // 32) + (W // 32))        # R2, R3
+    return frags * 2 * 16 * 16 * 32 / 16          # FLOP per MFMA / 16 pixels
+
+
+# HBM bytes per pixel the method must move: fp32 inputs (14 + 12 K) read once,
+# 3 fp32 outputs written once (weights are < 1 MB per launch).
+def alg_bytes_per_px(K):
+    return 4 * (14 + 12 * K + 3)
+
+
+def kernel_source_sha():
+    p = os.path.join(ROOT, "paper_2405_19056_amd", "csrc", "fwd_mfma.hip")
+    return hashlib.sha256(open(p, "rb").read()).hexdigest()[:16]
+
+
+def load_traffic(precision):
+    """HBM bytes per launch measured by rocprofv3 counters, if they were
+    taken on the current kernel source; None otherwise."""
+    p = os.path.join(ROOT, "profiles", f"traffic_fwd_{precision}_512sq_k8.json")
+    if not os.path.exists(p):
+        return None
+    d = json.load(open(p))
+    if d.get("kernel_source_sha") != kernel_source_sha():
+        return None
+    return d.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(w, fr, W, pool, budget_s=12.0):
+    """Time the FP64 oracle (as it stands) on the host over whole rows of the
+    same frame until ~budget_s of work; returns (px/s, threads, sample)."""
+    import oracle
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max((i.get("num_threads", 1) for i in threadpool_info()), default=1)
+    except Exception:
+        threads = os.cpu_count()
+    rows_done, t_spent, r = 0, 0.0, 0
+    h = fr.h
+    while t_spent < budget_s:
+        r0, r1 = r % h, min(h, r % h + 32)
+        t0 = time.perf_counter()
+        oracle.forward(w, W, fr.gbuf[:, :, r0:r1], fr.layers[:, :, :, r0:r1], fr.scene, pool=pool)
+        t_spent += time.perf_counter() - t0
+        rows_done += r1 - r0
+        r = r1
+    px = rows_done * fr.w * fr.n
+    return px / t_spent, threads, f"{rows_done} rows x {fr.w} px of the {fr.h}x{fr.w} K={fr.k} frame ({px} px, {t_spent:.1f} s)"
+
+
+def time_forward(net, g, L, s, out, steps, warmup, torch):
+    stream = torch.cuda.current_stream()
+    for _ in range(warmup):
+        net.forward(g, L, s, out=out, stream=stream)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    for _ in range(steps):
+        net.forward(g, L, s, out=out, stream=stream)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return wall / steps, ev0.elapsed_time(ev1) / 1e3 / steps
+
+
+def copy_probe():
+    """A plain device-to-device copy of 1 GiB, for counter scaling."""
+    import torch
+    n = 1 << 28
+    a = torch.ones(n, dtype=torch.float32, device="cuda:0")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes_read": 4 * n, "copy_probe_bytes_written": 4 * n,
+                      "launches": 3}))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--precision", default="bf16", choices=["bf16", "fp8_t"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU: the per-pixel forward needs no communication and "
+              "this build runs on a single MI355X; use --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+    if args.copy_probe:
+        copy_probe()
+        return
+
+    import torch
+    from paper_2405_19056_amd import synth
+    from paper_2405_19056_amd.glassnet import GlassNet
+
+    c = synth.CONFIGS[WORKLOAD]
+    W, K, H, Wd = c["width"], c["k"], c["h"], c["w"]
+    w, fr, _ = synth.config_inputs(WORKLOAD)
+    d = lambda a: torch.from_numpy(a).to("cuda:0")  # noqa: E731
+    g, L, s = d(fr.gbuf), d(fr.layers), d(fr.scene)
+    out = torch.empty((fr.n, 3, H, Wd), dtype=torch.float32, device="cuda:0")
+    px = fr.n * H * Wd
+
+    with GlassNet(w, W, k_max=K, pool=c["pool"], precision=args.precision) as net:
+        if args.precision == "fp8_t":
+            # static activation scale from a separate seeded calibration frame
+            cal = synth.make_frame(1, 128, 128, K, seed=999)
+            net.calibrate(d(cal.gbuf), d(cal.layers), d(cal.scene))
+        step_s, kern_s = time_forward(net, g, L, s, out, args.steps, args.warmup, torch)
+
+    fp32 = None
+    if not args.no_fp32:
+        with GlassNet(w, W, k_max=K, pool=c["pool"], precision="fp32") as net32:
+            st32, k32 = time_forward(net32, g, L, s, out, max(3, args.steps // 50), 2, torch)
+        fp32 = {"value": px / st32, "unit": "pixels/s", "ms_per_frame": st32 * 1e3}
+
+    alg = alg_flop_per_px(W, K)
+    exe = executed_flop_per_px(W, K)
+    achieved = alg * px / kern_s / 1e12
+    peak = PEAK_TFLOPS[args.precision]
+    traffic = load_traffic(args.precision)
+    res = {
+        "metric": "GlassNet pixels/sec at 512^2, K=8",
+        "value": px / step_s,
+        "unit": "pixels/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": step_s * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.precision,
+        "data": "synthetic (seeded G-buffer, 8 transparency layers, random-init weights)",
+        "config": {"workload": "512x512 frame, K=8 transparency layers (active count U{0..8}), "
+                               "width-128 F/T/B/R MLPs, mean pool",
+                   "pixels_per_step": px, "width": W, "k": K},
+        "roofline": {
+            "bound": "mfma",
+            "achieved": achieved,
+            "peak": peak,
+            "unit": "TFLOP/s",
+            "frac": achieved / peak,
+            "traffic": traffic,
+            "kernel": f"fwd_mfma_kernel<{W},{args.precision}>",
+            "kernel_ms": kern_s * 1e3,
+            "alg_flop_per_px": alg,
+            "executed_flop_per_px": exe,
+            "frac_executed": exe * px / kern_s / 1e12 / peak,
+            "alg_hbm_bytes_per_px": alg_bytes_per_px(K),
+            "hbm_frac": alg_bytes_per_px(K) * px / kern_s / 8e12,
+        },
+    }
+    if fp32:
+        res["fp32_path"] = fp32
+        res["speedup_vs_fp32_path"] = res["value"] / fp32["value"]
+    if not args.no_cpu_baseline:
+        v, thr, sample = cpu_baseline(w, fr, W, c["pool"])
+        res["cpu_baseline"] = {"value": v, "unit": "pixels/s", "cores": thr, "kind": "oracle",
+                               "sample": sample}
+    print(json.dumps(res))
+
+
+if __name__ == "__main__":
+    main()

@@ -132,6 +132,12 @@ gn_status glassnet_set_weights(gn_handle *h, const float *dev_weights, size_t n,
  * E4M3; n must be 1.  The default is derived at create time. */
 gn_status glassnet_set_act_scales(gn_handle *h, const float *scales, size_t n);
 
+/* GN_FP8_T calibration: evaluates h's first layer in fp32 over every slot of
+ * every pixel of frame and sets the activation scale to (largest value)/448,
+ * so the representative frame's range maps onto E4M3 without clipping.
+ * Synchronous (waits for hip_stream); allocates and frees its own temporaries. */
+gn_status glassnet_calibrate(gn_handle *h, const gn_frame *frame, void *hip_stream);
+
 /* Forward (Sec. 3.3-3.4): out [n][GN_NUM_OUT][h][w] fp32 device.
  * Requires 0 <= k <= k_max and n, h, w >= 1.  Out must not alias inputs. */
 gn_status glassnet_forward(gn_handle *h, const gn_frame *frame, float *out, void *hip_stream);

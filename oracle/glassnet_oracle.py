@@ -255,10 +255,22 @@ def grad(w, W, gbuf, layers, scene, target, pool="mean", chunk=16384):
     The transparency mask alpha > 0 is a hard selection (no gradient flows
     through it); gradients flow into sigma through every active slot's h.
     """
+    return _backprop(w, W, gbuf, layers, scene, pool, chunk, target=target)
+
+
+def grad_from_dy(w, W, gbuf, layers, scene, dy, pool="mean", chunk=16384):
+    """dL/dw for a given dL/dy [n][3][h][w] (the vector-Jacobian product)."""
+    return _backprop(w, W, gbuf, layers, scene, pool, chunk, dy=dy)[1]
+
+
+def _backprop(w, W, gbuf, layers, scene, pool, chunk, target=None, dy=None):
     P = unpack(w, W)
     G, L, S, (n, h, wd) = _pixels(gbuf, layers, scene)
-    t = np.asarray(target, dtype=np.float64)
-    T = np.moveaxis(t, 1, 0).reshape(NOUT, -1)
+    if target is not None:
+        t = np.asarray(target, dtype=np.float64)
+        T = np.moveaxis(t, 1, 0).reshape(NOUT, -1)
+    else:
+        DY = np.moveaxis(np.asarray(dy, dtype=np.float64), 1, 0).reshape(NOUT, -1)
     npx = G.shape[1]
     total = NOUT * npx
     grads = {net: [[np.zeros_like(A), np.zeros_like(c)] for A, c in P[net]] for net in NETS}
@@ -286,10 +298,13 @@ def grad(w, W, gbuf, layers, scene, target, pool="mean", chunk=16384):
             tau = Ssum * scale[None, :]
         phi, cB = _mlp_fwd_keep(P["B"], np.concatenate([sigma, tau], axis=0))
         y, cR = _mlp_fwd_keep(P["R"], np.concatenate([phi, Gc[11:14]], axis=0))
-        diff = y - T[:, a0:b0]
-        loss += np.abs(diff).sum()
-        dy = np.sign(diff) / total
-        dR_in = _mlp_bwd(P["R"], cR, dy, grads["R"])
+        if target is not None:
+            diff = y - T[:, a0:b0]
+            loss += np.abs(diff).sum()
+            dyc = np.sign(diff) / total
+        else:
+            dyc = DY[:, a0:b0]
+        dR_in = _mlp_bwd(P["R"], cR, dyc, grads["R"])
         dphi = dR_in[:W]
         dB_in = _mlp_bwd(P["B"], cB, dphi, grads["B"])
         dsigma = dB_in[:W].copy()

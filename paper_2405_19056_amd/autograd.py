@@ -1,0 +1,63 @@
+"""torch.autograd integration of the library's forward, L1 loss and backward.
+
+    y = GlassNetFunction.apply(net, gbuf, layers, scene, w)
+    loss = L1Function.apply(net, y, target)
+    loss.backward()          # w.grad <- the library's hand-written backward
+
+Argument marshalling only: the forward, the loss and its gradient and the
+backward all run in libglassnet's kernels (Sec. 3.5: the four networks are
+trained jointly, end to end; the L1 term of the loss).  Gradients with
+respect to the buffers are not produced (they are rasterizer outputs).
+"""
+from __future__ import annotations
+
+import torch
+
+from .glassnet import GlassNet
+
+
+class GlassNetFunction(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, net: GlassNet, gbuf, layers, scene, w):
+        net.set_weights(w.detach())
+        out = net.forward(gbuf, layers, scene)
+        ctx.net = net
+        ctx.save_for_backward(gbuf, layers, scene)
+        return out
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        gbuf, layers, scene = ctx.saved_tensors
+        gw = ctx.net.backward(gbuf, layers, scene, grad_out.contiguous())
+        return None, None, None, None, gw
+
+
+class L1Function(torch.autograd.Function):
+    """mean |y - t| and its subgradient, both from the library's loss kernel."""
+
+    @staticmethod
+    def forward(ctx, net: GlassNet, y, target):
+        grad = torch.empty_like(y)
+        loss = net.l1_loss(y.detach().contiguous(), target.contiguous(), grad_out=grad)
+        ctx.save_for_backward(grad)
+        return loss
+
+    @staticmethod
+    def backward(ctx, g):
+        (grad,) = ctx.saved_tensors
+        if g.numel() == 1 and float(g) == 1.0:
+            return None, grad, None
+        return None, grad * g, None     # non-unit upstream gradient: scale the seed
+
+
+def train_step(net: GlassNet, gbuf, layers, scene, target, w, grad_w=None, stream=None):
+    """One step without autograd: forward with weights w, L1 loss, backward.
+
+    Returns (loss tensor, grad_w tensor); everything stays on the device.
+    """
+    net.set_weights(w, stream=stream)
+    y = net.forward(gbuf, layers, scene, stream=stream)
+    dy = torch.empty_like(y)
+    loss = net.l1_loss(y, target, grad_out=dy, stream=stream)
+    gw = net.backward(gbuf, layers, scene, dy, grad_w=grad_w, stream=stream)
+    return loss, gw

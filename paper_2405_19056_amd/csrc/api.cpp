@@ -237,6 +237,41 @@ gn_status glassnet_set_act_scales(gn_handle *h, const float *scales, size_t n) {
   return GN_OK;
 }
 
+gn_status glassnet_calibrate(gn_handle *h, const gn_frame *frame, void *hip_stream) {
+  gn_status st = precheck(h);
+  if (st != GN_OK) return st;
+  st = gn_validate_frame(h, frame, nullptr);
+  if (st != GN_OK) return st;
+  DeviceGuard dg(h->device);
+  hipStream_t s = (hipStream_t)hip_stream;
+  const int64_t hw = (int64_t)frame->h * frame->w;
+  float *scratch = h->d_scratch, *out = nullptr;
+  unsigned *amax = nullptr;
+  const bool own_scratch = scratch == nullptr;
+  hipError_t e = hipSuccess;
+  if (own_scratch)
+    e = hipMalloc((void **)&scratch, sizeof(float) * 4 * (size_t)h->W * h->scratch_threads);
+  if (e == hipSuccess) e = hipMalloc((void **)&out, sizeof(float) * gn::kNOUT * frame->n * hw);
+  if (e == hipSuccess) e = hipMalloc((void **)&amax, sizeof(unsigned));
+  if (e == hipSuccess) e = hipMemsetAsync(amax, 0, sizeof(unsigned), s);
+  if (e == hipSuccess) {
+    gn::FwdBatch b{frame->gbuf, frame->layers, frame->scene, out, frame->n, (int32_t)hw, frame->k};
+    e = gn::launch_fwd_fp32(h->W, h->cfg.pool, h->d_master, h->d_master_t, b, scratch,
+                            h->scratch_threads, s, amax);
+  }
+  unsigned bits = 0;
+  if (e == hipSuccess) e = hipMemcpyAsync(&bits, amax, sizeof bits, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (own_scratch) (void)hipFree(scratch);
+  (void)hipFree(out);
+  (void)hipFree(amax);
+  if (e != hipSuccess) return gn_check_device(h, e, "calibration");
+  float m;
+  memcpy(&m, &bits, sizeof m);
+  if (m > 0.0f && m < 1e30f) h->act_scale = m / 448.0f;
+  return GN_OK;
+}
+
 gn_status glassnet_workspace_bytes(gn_handle *h, uint64_t *bytes) {
   if (!h || !bytes) return fail(GN_E_INVAL, "NULL argument");
   *bytes = h->bytes_held + gn_bwd_bytes(h);

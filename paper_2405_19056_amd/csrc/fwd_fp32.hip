@@ -13,69 +13,23 @@
 //     and the sigma part is computed once per pixel instead of once per slot;
 //   * h's last layer is affine, so the masked sum over slots moves in front of
 //     it: sum_i m_i (A3 a_i + c3) = A3 (sum_i m_i a_i) + (sum_i m_i) c3.
-#include "gn_internal.h"
+#include "valu_mlp.h"
 
 namespace gn {
 namespace {
+
+using namespace valu;
 
 constexpr int kThreads = 256;
 constexpr int kOB = 64;   // outputs per register block
 
 struct Fp32Args {
   FwdBatch b;
+  unsigned *amax;                // optional: max of h's first-layer activation (as bits)
   float *__restrict__ scr;       // [4][W][nthr]
   int nthr;
   int pool;
 };
-
-__device__ __forceinline__ float relu(float x) { return fmaxf(x, 0.0f); }
-
-// Weights are read through the constant address space: the kernel never
-// writes them, and wave-uniform loads from it go through the scalar cache.
-typedef const float __attribute__((address_space(4))) cfloat;
-
-// acc[o] (o < NB) += sum_k Wt[col0+k][row0+o] * src[k] for k < NIN, where Wt is
-// a layer's matrix stored transposed ([in][out]) and src is streamed from the
-// per-thread scratch with the given stride, one block of 8 ahead.
-template <int NB, int NIN>
-__device__ __forceinline__ void acc_from_scratch(float (&acc)[NB], cfloat *Wt,
-                                                 int ldo, int row0, int col0,
-                                                 const float *__restrict__ src, int stride,
-                                                 int tid) {
-  static_assert(NIN % 8 == 0, "streamed inputs come in blocks of 8");
-  float x[8], xn[8];
-#pragma unroll
-  for (int kk = 0; kk < 8; ++kk) x[kk] = src[(size_t)kk * stride + tid];
-  for (int kb = 0; kb < NIN; kb += 8) {
-    if (kb + 8 < NIN) {
-#pragma unroll
-      for (int kk = 0; kk < 8; ++kk) xn[kk] = src[(size_t)(kb + 8 + kk) * stride + tid];
-    }
-#pragma unroll
-    for (int kk = 0; kk < 8; ++kk) {
-      cfloat *wr = Wt + (size_t)(col0 + kb + kk) * ldo + row0;
-#pragma unroll
-      for (int o = 0; o < NB; ++o) acc[o] = fmaf(wr[o], x[kk], acc[o]);
-      // keep one input row's weights (NB scalars) live at a time
-      __builtin_amdgcn_sched_barrier(0);
-    }
-#pragma unroll
-    for (int kk = 0; kk < 8; ++kk) x[kk] = xn[kk];
-  }
-}
-
-template <int NB, int NIN>
-__device__ __forceinline__ void acc_from_regs(float (&acc)[NB], cfloat *Wt,
-                                              int ldo, int row0, int col0,
-                                              const float (&x)[NIN]) {
-#pragma unroll
-  for (int k = 0; k < NIN; ++k) {
-    cfloat *wr = Wt + (size_t)(col0 + k) * ldo + row0;
-#pragma unroll
-    for (int o = 0; o < NB; ++o) acc[o] = fmaf(wr[o], x[k], acc[o]);
-    __builtin_amdgcn_sched_barrier(0);
-  }
-}
 
 template <int W>
 __global__ __launch_bounds__(kThreads) void fwd_fp32_kernel(
@@ -104,6 +58,7 @@ __global__ __launch_bounds__(kThreads) void fwd_fp32_kernel(
   const int stride = a.nthr;
   const int hw = a.b.hw, K = a.b.k;
   const int64_t npx = (int64_t)a.b.n * hw;
+  float zmax = 0.0f;
 
   for (int64_t base = (int64_t)blockIdx.x * kThreads; base < npx;
        base += (int64_t)gridDim.x * kThreads) {
@@ -188,6 +143,10 @@ __global__ __launch_bounds__(kThreads) void fwd_fp32_kernel(
         acc_from_regs<kOB, kNL>(acc, wt_ + lo[L_T1].w, LDO(L_T1), ob, 0, bi);
 #pragma unroll
         for (int o = 0; o < kOB; ++o) sA[(size_t)(ob + o) * stride + tid] = relu(acc[o]);
+        if (a.amax) {
+#pragma unroll
+          for (int o = 0; o < kOB; ++o) zmax = fmaxf(zmax, relu(acc[o]));
+        }
       }
 #pragma unroll
       for (int ob = 0; ob < W; ob += kOB) {
@@ -274,16 +233,19 @@ __global__ __launch_bounds__(kThreads) void fwd_fp32_kernel(
       }
     }
   }
+  if (a.amax) atomicMax(a.amax, __float_as_uint(zmax));   // zmax >= 0: bit order = value order
 }
 
 }  // namespace
 
-int fp32_scratch_threads(int num_cus) { return num_cus * 2 * kThreads; }
+int fp32_scratch_threads(int num_cus) { return num_cus * kThreads; }
 
 hipError_t launch_fwd_fp32(int W, int pool, const float *master, const float *master_t,
                            const FwdBatch &b,
-                           float *scratch, int scratch_threads, hipStream_t stream) {
+                           float *scratch, int scratch_threads, hipStream_t stream,
+                           unsigned *amax) {
   Fp32Args a;
+  a.amax = amax;
   a.b = b;
   a.scr = scratch;
   a.nthr = scratch_threads;

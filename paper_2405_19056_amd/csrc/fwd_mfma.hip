@@ -84,6 +84,19 @@ __device__ __forceinline__ uint32_t relu_bf16x2(uint32_t x) {
   return __builtin_bit_cast(uint32_t, v);
 }
 
+// Four non-negative floats -> four OCP E4M3 bytes (round to nearest even).
+// Values are clamped to the format's largest finite magnitude first.
+__device__ __forceinline__ int pack_fp8x4(f32x4 v) {
+  const float M = 448.0f;
+  int r = __builtin_amdgcn_cvt_pk_fp8_f32(fminf(v.x, M), fminf(v.y, M), 0, false);
+  return __builtin_amdgcn_cvt_pk_fp8_f32(fminf(v.z, M), fminf(v.w, M), r, true);
+}
+
+// 16x16x128 E4M3 x E4M3 -> fp32 on the gfx950 matrix cores, unit block scales.
+__device__ __forceinline__ f32x4 mma_fp8(i32x8 a, i32x8 b, f32x4 c) {
+  return __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(a, b, c, 0, 0, 0, 127, 0, 127);
+}
+
 __device__ __forceinline__ void wait_vm() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
 
 // Copy `bytes` (a multiple of 1 KiB) from global to LDS: each wave moves whole
@@ -99,6 +112,11 @@ __device__ __forceinline__ void lds_fill(uint8_t *dst, const uint8_t *src, int64
 
 __device__ __forceinline__ u32x4 ld_frag(const uint8_t *chunk, int idx, int lane) {
   return *(const u32x4 *)(chunk + (size_t)idx * kFrag + lane * 16);
+}
+
+// One fp8 A fragment of the 16x16x128 instruction: 64 lanes x 32 bytes.
+__device__ __forceinline__ i32x8 ld_frag8(const uint8_t *chunk, int idx, int lane) {
+  return *(const i32x8 *)(chunk + (size_t)idx * 2 * kFrag + lane * 32);
 }
 
 // acc[t][mt] += A(chunk) . in[t]   over the chunk's KS_ K-steps.
@@ -206,14 +224,27 @@ __global__ __launch_bounds__(kThreads) void fwd_mfma_kernel(MfmaArgs a) {
     lds_fill(stage_buf(s), a.packed + a.stage_off[s], a.stage_off[s + 1] - a.stage_off[s], wave,
              lane0);
   };
-  lds_fill(L_res, a.packed + a.res_off, res_bytes, wave, lane0);
+  // bf16: [T1A | T2 (bf16)]; fp8: [T1A | T2 (fp8, 2 KiB fragments) | T2 row scales]
+  constexpr bool kFp8 = PREC == GN_FP8_T;
+  if (kFp8) {
+    lds_fill(L_res, a.packed + a.res_off, (int64_t)MT * kFrag, wave, lane0);
+    lds_fill(L_res + MT * kFrag, a.packed + a.t2q_off, res_bytes - MT * kFrag, wave, lane0);
+  } else {
+    lds_fill(L_res, a.packed + a.res_off, res_bytes, wave, lane0);
+  }
   lds_fill((uint8_t *)L_bias, a.packed + a.bias_off, Shape<W>::kBiasBytes, wave, lane0);
   if ((int)blockIdx.x < a.ntiles) fill_stage0(0);
   wait_vm();
   __syncthreads();
 
   const uint8_t *T1A = L_res;
-  const uint8_t *T2 = L_res + MT * kFrag;
+  const uint8_t *T2 = L_res + MT * kFrag;                       // bf16 form
+  float *T2scale = (float *)(L_res + MT * kFrag + MT * 2 * kFrag);  // fp8 form
+  if (kFp8) {
+    // dequantisation factor of the fp8 layer: weight row scale x activation scale
+    if ((int)threadIdx.x < W) T2scale[threadIdx.x] *= a.sa;
+    __syncthreads();
+  }
   const float *bF1 = L_bias + L_F1 * W, *bF2 = L_bias + L_F2 * W, *bF3 = L_bias + L_F3 * W;
   const float *bT1 = L_bias + L_T1 * W, *bT2 = L_bias + L_T2 * W, *bT3 = L_bias + L_T3 * W;
   const float *bB1 = L_bias + L_B1 * W, *bB2 = L_bias + L_B2 * W, *bB3 = L_bias + L_B3 * W;
@@ -330,6 +361,38 @@ __global__ __launch_bounds__(kThreads) void fwd_mfma_kernel(MfmaArgs a) {
           bi[t][0] = u32x4{pk_bf16(v[0], v[1]), pk_bf16(v[2], v[3]), pk_bf16(v[4], v[5]),
                            pk_bf16(v[6], v[7])};
         }
+        if constexpr (kFp8) {
+        // h layer 1 (bf16 MFMA), output quantised to E4M3 with the static
+        // activation scale: lane byte 4*mt + r holds row 16*mt + 4*g + r, the
+        // order the fp8 weights of layer 2 were packed in.
+        i32x8 zq[kNT];
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) {
+          const u32x4 w = ld_frag(T1A, mt, lane);
+#pragma unroll
+          for (int t = 0; t < kNT; ++t) {
+            const f32x4 v = mma(w, bi[t][0],
+                                unpk_bf16(u[t][mt >> 1][2 * (mt & 1)], u[t][mt >> 1][2 * (mt & 1) + 1]));
+            zq[t][mt] = pack_fp8x4(relu4(v) * a.inv_sa);
+          }
+        }
+        // h layer 2 on the fp8 matrix cores (K = 128 in one instruction),
+        // dequantised per output row, then the masked running sum.
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) {
+          const i32x8 w = ld_frag8(T2, mt, lane);
+          const f32x4 sc = *(const f32x4 *)(T2scale + 16 * mt + 4 * g);
+          const f32x4 b = *(const f32x4 *)(bT2 + 16 * mt + 4 * g);
+#pragma unroll
+          for (int t = 0; t < kNT; ++t) {
+            const f32x4 acc = mma_fp8(w, zq[t], f32x4{0.f, 0.f, 0.f, 0.f});
+            Z[t][mt].x = fmaf(m[t], fmaxf(fmaf(acc.x, sc.x, b.x), 0.f), Z[t][mt].x);
+            Z[t][mt].y = fmaf(m[t], fmaxf(fmaf(acc.y, sc.y, b.y), 0.f), Z[t][mt].y);
+            Z[t][mt].z = fmaf(m[t], fmaxf(fmaf(acc.z, sc.z, b.z), 0.f), Z[t][mt].z);
+            Z[t][mt].w = fmaf(m[t], fmaxf(fmaf(acc.w, sc.w, b.w), 0.f), Z[t][mt].w);
+          }
+        }
+        } else {
         // h layer 1: z1 = relu(W1b b_i + u)
         u32x4 z1[kNT][KS];
 #pragma unroll
@@ -366,6 +429,7 @@ __global__ __launch_bounds__(kThreads) void fwd_mfma_kernel(MfmaArgs a) {
             Z[t][mt].z = fmaf(m[t], r.z, Z[t][mt].z);
             Z[t][mt].w = fmaf(m[t], r.w, Z[t][mt].w);
           }
+        }
         }
 #pragma unroll
         for (int t = 0; t < kNT; ++t) cnt[t] += m[t];
@@ -515,6 +579,32 @@ __global__ void pack_bf16_kernel(PackArgs p) {
   ((__bf16 *)(p.packed + d.offset))[e] = h;
 }
 
+// fp8 copy of h's second layer (the layer that runs once per slot): per output
+// row n a scale s_n = max_k |A2[n][k]| / 448 and bytes E4M3(A2[n][k] / s_n),
+// stored as MT fragments of 64 lanes x 32 bytes.  Lane 16 g + (n & 15) of
+// fragment n >> 4 holds, at byte 4 q + r, input k = 16 q + 4 g + r.
+// One block per output row, one thread per input.
+__global__ void pack_fp8_t2_kernel(PackArgs p, uint8_t *q8, float *scale) {
+  __shared__ float red[256];
+  const int n = blockIdx.x, k = threadIdx.x, W = p.W;
+  const LayerOff lo = p.lo[L_T2];
+  const float v = k < W ? p.master[lo.w + (int64_t)n * W + k] : 0.0f;
+  red[k] = fabsf(v);
+  __syncthreads();
+  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+    if (k < w) red[k] = fmaxf(red[k], red[k + w]);
+    __syncthreads();
+  }
+  const float s = red[0] > 0.0f ? red[0] / 448.0f : 1.0f;
+  if (k == 0) scale[n] = s;
+  if (k >= W) return;
+  const float x = fminf(fmaxf(v / s, -448.0f), 448.0f);
+  const uint8_t b = (uint8_t)(__builtin_amdgcn_cvt_pk_fp8_f32(x, 0.0f, 0, false) & 0xff);
+  const int g = (k & 15) >> 2, j = 4 * (k >> 4) + (k & 3);
+  const int lane = 16 * g + (n & 15);
+  q8[(size_t)(n >> 4) * 2048 + lane * 32 + j] = b;
+}
+
 __global__ void pack_bias_kernel(PackArgs p) {
   const int l = blockIdx.x, o = threadIdx.x;
   if (o >= p.W) return;
@@ -566,14 +656,24 @@ hipError_t launch_pack_weights(const float *master, uint8_t *packed, const Packe
   hipLaunchKernelGGL(pack_bf16_kernel, dim3((unsigned)((maxn + 255) / 256), kNumChunks), dim3(256),
                      0, stream, p);
   hipLaunchKernelGGL(pack_bias_kernel, dim3(kNumLayers), dim3(pl.W), 0, stream, p);
+  hipLaunchKernelGGL(pack_fp8_t2_kernel, dim3(pl.W), dim3(pl.W), 0, stream, p,
+                     packed + pl.t2q_off, (float *)(packed + pl.t2scale_off));
   return hipGetLastError();
 }
 
-static size_t mfma_lds_bytes(const PackedLayout &pl) {
+// Resident LDS bytes of the slot loop's weights for a precision.
+static int64_t resident_bytes(const PackedLayout &pl, int precision) {
+  const int MT = pl.W / 16;
+  if (precision == GN_FP8_T) return (int64_t)MT * kFrag + (pl.t2scale_off - pl.t2q_off) +
+                                    (pl.total_bytes - pl.t2scale_off);
+  return pl.resident_bytes;
+}
+
+static size_t mfma_lds_bytes(const PackedLayout &pl, int precision) {
   int64_t stage_max = 0;
   for (int s = 0; s < kNumStages; ++s)
     stage_max = std::max<int64_t>(stage_max, pl.stage_off[s + 1] - pl.stage_off[s]);
-  return (size_t)(pl.resident_bytes + (int64_t)kNumLayers * pl.W * 4 + 2 * stage_max);
+  return (size_t)(resident_bytes(pl, precision) + (int64_t)kNumLayers * pl.W * 4 + 2 * stage_max);
 }
 
 template <int W, int PREC>
@@ -597,7 +697,7 @@ hipError_t launch_fwd_mfma(int W, int precision, int pool, const uint8_t *packed
   a.packed = packed;
   for (int s = 0; s <= kNumStages; ++s) a.stage_off[s] = pl.stage_off[s];
   a.res_off = pl.resident_off;
-  a.res_bytes = pl.resident_bytes;
+  a.res_bytes = resident_bytes(pl, precision);
   a.bias_off = pl.bias_off;
   a.t2q_off = pl.t2q_off;
   a.t2s_off = pl.t2scale_off;
@@ -616,11 +716,12 @@ hipError_t launch_fwd_mfma(int W, int precision, int pool, const uint8_t *packed
   a.inv_sa = 1.0f / fp8_act_scale;
   if (ntiles <= 0) return hipSuccess;
   grid = std::max(1, std::min(grid, ntiles));
-  const size_t lds = mfma_lds_bytes(pl);
+  const size_t lds = mfma_lds_bytes(pl, precision);
   if (precision == GN_BF16) {
     if (W == 64) return launch_one<64, GN_BF16>(a, grid, lds, stream);
     if (W == 128) return launch_one<128, GN_BF16>(a, grid, lds, stream);
   }
+  if (precision == GN_FP8_T && W == 128) return launch_one<128, GN_FP8_T>(a, grid, lds, stream);
   return hipErrorInvalidValue;
 }
 

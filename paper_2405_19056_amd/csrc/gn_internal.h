@@ -97,7 +97,8 @@ hipError_t launch_pack_weights(const float *master, uint8_t *packed, const Packe
 // master_t: each layer's matrix transposed to [in][out] at the master offsets.
 hipError_t launch_fwd_fp32(int W, int pool, const float *master, const float *master_t,
                            const FwdBatch &b,
-                           float *scratch, int scratch_threads, hipStream_t stream);
+                           float *scratch, int scratch_threads, hipStream_t stream,
+                           unsigned *amax = nullptr);
 int fp32_scratch_threads(int num_cus);
 
 hipError_t launch_fwd_mfma(int W, int precision, int pool, const uint8_t *packed,

@@ -58,6 +58,7 @@ _SIGS = {
     "glassnet_l1_loss": (c_int32, [c_void_p, c_void_p, c_void_p, c_uint64, c_void_p, c_void_p,
                                    c_void_p]),
     "glassnet_workspace_bytes": (c_int32, [c_void_p, POINTER(c_uint64)]),
+    "glassnet_calibrate": (c_int32, [c_void_p, POINTER(GnFrame), c_void_p]),
     "serve_submit": (c_int32, [c_void_p, POINTER(GnFrame), c_void_p, POINTER(c_uint64)]),
     "serve_poll": (c_int32, [c_void_p, c_uint64, POINTER(c_int32), POINTER(GnTiming)]),
     "serve_drain": (c_int32, [c_void_p]),
@@ -175,6 +176,10 @@ class GlassNet:
     def set_act_scale(self, scale: float):
         s = (c_float * 1)(scale)
         _check(lib().glassnet_set_act_scales(self._h, s, 1))
+
+    def calibrate(self, gbuf, layers, scene, stream=None):
+        fr = make_frame(gbuf, layers, scene)
+        _check(lib().glassnet_calibrate(self._h, byref(fr), _stream(stream)))
 
     def workspace_bytes(self) -> int:
         b = c_uint64()

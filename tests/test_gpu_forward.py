@@ -16,7 +16,7 @@ from gpu_util import dev, gpu_on_sample, host, log, oracle_on_sample, relF, relI
 
 pytestmark = pytest.mark.gpu
 
-TOL = {"fp32": 1e-4, "bf16": 2e-2}
+TOL = {"fp32": 1e-4, "bf16": 2e-2, "fp8_t": 6e-2}
 
 
 def frame(n, h, w, k, W, seed, alpha_mode="uniform_count"):
@@ -26,6 +26,12 @@ def frame(n, h, w, k, W, seed, alpha_mode="uniform_count"):
                      synth.make_layers(n, k, h, w, s["slots"], s["active"], alpha_mode),
                      synth.make_scene(n, s["gbuf"]))
     return wts, fr
+
+
+def calibrate(net, W, k, seed=999):
+    """FP8 activation scale from a separate seeded calibration frame."""
+    _, cal = frame(1, 64, 64, k, W, seed=seed)
+    net.calibrate(dev(cal.gbuf), dev(cal.layers) if k else None, dev(cal.scene))
 
 
 def run(net, fr):
@@ -179,3 +185,49 @@ def test_workspace_does_not_depend_on_k():
         with GlassNet(wts, W, k_max=kmax, precision="bf16") as net:
             sizes.append(net.workspace_bytes())
     assert len(set(sizes)) == 1, sizes
+
+
+# ------------------------------------------------------------------ fp8 form
+def test_fp8_small_frames_elementwise():
+    W = 128
+    for (n, h, w_, k, pool) in [(1, 37, 53, 8, "mean"), (2, 16, 40, 4, "sum"), (1, 5, 7, 0, "mean")]:
+        wts, fr = frame(n, h, w_, k, W, seed=50 + k)
+        log(f"fp8 n={n} h={h} w={w_} k={k} {pool}")
+        ref = oracle.forward(wts, W, fr.gbuf, fr.layers, fr.scene, pool=pool)
+        with GlassNet(wts, W, k_max=8, pool=pool, precision="fp8_t") as net:
+            calibrate(net, W, max(k, 1))
+            y = run(net, fr)
+        e = relF(y, ref)
+        log(f"  relF={e:.3e}")
+        assert e <= TOL["fp8_t"]
+
+
+def test_fp8_full_size_on_sampled_pixels_and_permutations():
+    cfg = "c2_512sq_k8_w128"
+    c = synth.CONFIGS[cfg]
+    w, fr, st = synth.config_inputs(cfg)
+    with GlassNet(w, 128, k_max=8, pool=c["pool"], precision="fp8_t") as net:
+        calibrate(net, 128, 8)
+        y = run(net, fr)
+        flat = np.random.default_rng(0).choice(fr.n * fr.h * fr.w, size=3000, replace=False)
+        ref = oracle_on_sample(w, 128, fr, flat, c["pool"])
+        e = relF(gpu_on_sample(y, fr, flat), ref)
+        log(f"  fp8 512^2 K=8 sampled relF={e:.3e}")
+        assert e <= TOL["fp8_t"]
+        perms = synth.slot_shuffles(1, 8, fr.h, fr.w, 4, st["shuffles"])
+        worst = 0.0
+        for p in perms:
+            yp = run(net, synth.Frame(fr.gbuf, synth.apply_slot_permutation(fr.layers, p), fr.scene))
+            worst = max(worst, float(np.max(np.abs(yp - y)) / np.max(np.abs(y))))
+        log(f"  fp8 permutation deviation {worst:.3e}")
+        assert worst <= TOL["fp8_t"]
+
+
+def test_fp8_calibration_sets_a_positive_scale_and_rejects_bad_scales():
+    W = 128
+    wts, fr = frame(1, 8, 8, 2, W, seed=3)
+    with GlassNet(wts, W, k_max=8, precision="fp8_t") as net:
+        calibrate(net, W, 2)
+        net.set_act_scale(0.02)
+        with pytest.raises(GlassNetError):
+            net.set_act_scale(-1.0)

@@ -6,7 +6,7 @@ One step = one fused forward pass (F, T over all K slots, pool, B, R) over one
 in HBM.  Prints ONE JSON line (rank 0).
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision bf16|fp8_t]
-                  [--no-cpu-baseline] [--no-serve]
+                  [--no-cpu-baseline] [--serve-seconds S]
   python bench.py --copy-probe      # plain device copy of known size, for
                                     # scaling rocprofv3 FETCH/WRITE counters
 """
@@ -107,6 +107,62 @@ def time_forward(net, g, L, s, out, steps, warmup, torch):
     return wall / steps, ev0.elapsed_time(ev1) / 1e3 / steps
 
 
+def serve_phase(w, W, precision, seconds, torch, rate=200.0, seed=4):
+    """Poisson arrivals at `rate` for `seconds`; resolution from the four
+    serving sizes, K ~ U{2..8}; inputs resident; returns latency/throughput."""
+    from paper_2405_19056_amd import synth
+    from paper_2405_19056_amd.glassnet import GlassNet
+    st = synth.streams(seed)
+    arrivals = synth.poisson_arrivals(rate, seconds, st["arrivals"])
+    pick = st["slots"]
+    d = lambda a: torch.from_numpy(a).to("cuda:0")  # noqa: E731
+    res = synth.SERVE_RESOLUTIONS
+    inputs, outs = {}, {}
+    for j, (h, wd) in enumerate(res):
+        fr = synth.make_frame(1, h, wd, 8, seed=100 + j)
+        inputs[(h, wd)] = (d(fr.gbuf), d(fr.layers), d(fr.scene))
+        outs[(h, wd)] = [torch.empty((1, 3, h, wd), device="cuda:0") for _ in range(64)]
+    torch.cuda.synchronize()
+    owner = {}
+    with GlassNet(w, W, k_max=8, precision=precision) as net:
+        if precision == "fp8_t":
+            cal = synth.make_frame(1, 128, 128, 8, seed=999)
+            net.calibrate(d(cal.gbuf), d(cal.layers), d(cal.scene))
+        for r in res:                                  # warm-up
+            g, L, s = inputs[r]
+            net.serve_submit(g, L, s, outs[r][0])
+        net.serve_drain()
+        tickets, pixels = [], 0
+        t0 = time.perf_counter()
+        for i, ta in enumerate(arrivals):
+            while True:
+                dt = ta - (time.perf_counter() - t0)
+                if dt <= 0:
+                    break
+                time.sleep(min(dt, 2e-4))
+            r = res[int(pick.integers(len(res)))]
+            k = int(pick.integers(2, 9))
+            o = outs[r][i % 64]
+            prev = owner.get(id(o))
+            while prev is not None and not net.serve_poll(prev)[0]:
+                time.sleep(5e-5)
+            g, L, s = inputs[r]
+            t = net.serve_submit(g, L[:, :k], s, o)
+            owner[id(o)] = t
+            tickets.append(t)
+            pixels += r[0] * r[1]
+        net.serve_drain()
+        elapsed = time.perf_counter() - t0
+        lat = sorted(net.serve_poll(t)[1]["t_done"] - net.serve_poll(t)[1]["t_submit"]
+                     for t in tickets)
+    q = lambda f: lat[min(len(lat) - 1, int(f * len(lat)))] * 1e3  # noqa: E731
+    return {"rate_hz": rate, "seconds": seconds, "requests": len(tickets),
+            "resolutions": [f"{h}x{wd}" for h, wd in res], "k": "U{2..8}",
+            "precision": precision, "pixels_per_s": pixels / elapsed,
+            "p50_ms": q(0.50), "p99_ms": q(0.99), "max_ms": lat[-1] * 1e3,
+            "hbm_budget": "64 GiB"}
+
+
 def copy_probe():
     """A plain device-to-device copy of 1 GiB, for counter scaling."""
     import torch
@@ -129,6 +185,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--copy-probe", action="store_true")
+    ap.add_argument("--serve-seconds", type=float, default=5.0)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the per-pixel forward needs no communication and "
@@ -203,6 +260,9 @@ def main():
     if fp32:
         res["fp32_path"] = fp32
         res["speedup_vs_fp32_path"] = res["value"] / fp32["value"]
+    if args.serve_seconds > 0:
+        res["serve"] = serve_phase(w, W, args.precision, args.serve_seconds, torch)
+        res["p99_frame_latency_ms"] = res["serve"]["p99_ms"]
     if not args.no_cpu_baseline:
         v, thr, sample = cpu_baseline(w, fr, W, c["pool"])
         res["cpu_baseline"] = {"value": v, "unit": "pixels/s", "cores": thr, "kind": "oracle",

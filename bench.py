@@ -163,6 +163,63 @@ def serve_phase(w, W, precision, seconds, torch, rate=200.0, seed=4):
             "hbm_budget": "64 GiB"}
 
 
+def k_sweep(w, W, fr, pool, precision, torch, ks=(0, 1, 2, 4, 8), steps=50):
+    """Kernel time vs slot count on the same 512^2 frame (first k slots), with
+    a least-squares line: the per-object cost is linear (Sec. 4.4)."""
+    from paper_2405_19056_amd.glassnet import GlassNet
+    d = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")  # noqa: E731
+    g, s = d(fr.gbuf), d(fr.scene)
+    out = torch.empty((fr.n, 3, fr.h, fr.w), dtype=torch.float32, device="cuda:0")
+    times = []
+    with GlassNet(w, W, k_max=max(ks), pool=pool, precision=precision) as net:
+        if precision == "fp8_t":
+            from paper_2405_19056_amd import synth
+            cal = synth.make_frame(1, 128, 128, 8, seed=999)
+            net.calibrate(d(cal.gbuf), d(cal.layers), d(cal.scene))
+        for k in ks:
+            L = d(fr.layers[:, :k]) if k else None
+            _, kern = time_forward(net, g, L, s, out, steps, 5, torch)
+            times.append(kern * 1e3)
+    A = np.vstack([np.array(ks, float), np.ones(len(ks))]).T
+    (slope, icpt), *_ = np.linalg.lstsq(A, np.array(times), rcond=None)
+    pred = A @ np.array([slope, icpt])
+    r2 = 1 - np.sum((np.array(times) - pred) ** 2) / np.sum((np.array(times) - np.mean(times)) ** 2)
+    return {"k": list(ks), "kernel_ms": times, "ms_per_slot": slope, "ms_fixed": icpt, "r2": r2}
+
+
+def train_phase(torch, steps=10, precision="bf16"):
+    """One training step of the 16 x 128^2, K=4, W=128 workload: forward with
+    the current weights, L1 against teacher output + N(0, 0.01) noise, and
+    the hand-written backward to dL/dw.  Returns ms per step."""
+    from paper_2405_19056_amd import synth
+    from paper_2405_19056_amd.autograd import train_step
+    from paper_2405_19056_amd.glassnet import GlassNet
+    name = "c3_train_16x128sq_k4_w128"
+    c = synth.CONFIGS[name]
+    w, fr, st = synth.config_inputs(name)
+    d = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")  # noqa: E731
+    g, L, s = d(fr.gbuf), d(fr.layers), d(fr.scene)
+    with GlassNet(synth.make_weights(c["width"], st["teacher"]), c["width"], k_max=c["k"],
+                  pool=c["pool"], precision="fp32") as teacher:
+        t = teacher.forward(g, L, s)
+        t += d(synth.noise(tuple(t.shape), 0.01, st["noise"]))
+    wd = d(w)
+    gw = torch.empty_like(wd)
+    with GlassNet(w, c["width"], k_max=c["k"], pool=c["pool"], precision=precision) as net:
+        for _ in range(2):
+            train_step(net, g, L, s, t, wd, grad_w=gw)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            loss, _ = train_step(net, g, L, s, t, wd, grad_w=gw)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) / steps * 1e3
+    px = fr.n * fr.h * fr.w
+    return {"workload": "16 crops 128x128, K=4, W=128, L1 vs teacher + N(0,0.01)",
+            "forward": precision, "backward": "fp32", "ms_per_step": ms,
+            "pixels_per_s": px / ms * 1e3, "loss": float(loss.cpu())}
+
+
 def copy_probe():
     """A plain device-to-device copy of 1 GiB, for counter scaling."""
     import torch
@@ -186,6 +243,8 @@ def main():
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--copy-probe", action="store_true")
     ap.add_argument("--serve-seconds", type=float, default=5.0)
+    ap.add_argument("--k-sweep", action="store_true")
+    ap.add_argument("--no-train", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the per-pixel forward needs no communication and "
@@ -260,6 +319,10 @@ def main():
     if fp32:
         res["fp32_path"] = fp32
         res["speedup_vs_fp32_path"] = res["value"] / fp32["value"]
+    if not args.no_train:
+        res["train_step"] = train_phase(torch)
+    if args.k_sweep:
+        res["k_sweep"] = k_sweep(w, W, fr, c["pool"], args.precision, torch)
     if args.serve_seconds > 0:
         res["serve"] = serve_phase(w, W, args.precision, args.serve_seconds, torch)
         res["p99_frame_latency_ms"] = res["serve"]["p99_ms"]

@@ -155,6 +155,10 @@ gn_status glassnet_create(const gn_config *cfg, const float *host_weights, size_
   if (e == hipSuccess && cfg->precision == GN_FP32)
     e = hipMalloc((void **)&h->d_scratch, scratch_bytes);
   if (e == hipSuccess) e = hipMalloc((void **)&h->d_l1_partials, sizeof(float) * h->l1_npart);
+  const size_t sig_bytes = gn::mfma_sig_scratch_bytes(h->W, h->num_cus);
+  if (cfg->precision != GN_FP32)
+    for (int i = 0; i < 2 && e == hipSuccess; ++i)
+      e = hipMalloc((void **)&h->d_sig_scratch[i], sig_bytes);
   if (e == hipSuccess) e = hipMemcpy(h->d_master, host_weights, wbytes, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemset(h->d_packed, 0, (size_t)h->pl.total_bytes);
   if (e != hipSuccess) {
@@ -165,7 +169,7 @@ gn_status glassnet_create(const gn_config *cfg, const float *host_weights, size_
     return st;
   }
   h->bytes_held = 2 * wbytes + (size_t)h->pl.total_bytes + sizeof(float) * h->l1_npart +
-                  (cfg->precision == GN_FP32 ? scratch_bytes : 0);
+                  (cfg->precision == GN_FP32 ? scratch_bytes : 2 * sig_bytes);
   gn_status st = gn_prepare_weights(h, nullptr);
   if (st == GN_OK) {
     e = hipDeviceSynchronize();
@@ -197,6 +201,8 @@ gn_status glassnet_destroy(gn_handle *h) {
   (void)hipFree(h->d_packed);
   (void)hipFree(h->d_scratch);
   (void)hipFree(h->d_l1_partials);
+  (void)hipFree(h->d_sig_scratch[0]);
+  (void)hipFree(h->d_sig_scratch[1]);
   delete h;
   return GN_OK;
 }
@@ -301,7 +307,7 @@ gn_status glassnet_forward(gn_handle *h, const gn_frame *frame, float *out, void
   } else {
     const int tpf = (b.hw + gn::kTilePx - 1) / gn::kTilePx;
     e = gn::launch_fwd_mfma(h->W, h->cfg.precision, h->cfg.pool, h->d_packed, h->pl, &b, nullptr,
-                            nullptr, b.n * tpf, h->act_scale, h->num_cus, s);
+                            nullptr, b.n * tpf, h->act_scale, h->num_cus, h->d_sig_scratch[0], s);
   }
   return gn_check_device(h, e, "forward launch");
 }

@@ -52,26 +52,33 @@ struct MfmaArgs {
   int tiles_per_frame;
   int pool;
   float sa, inv_sa;                    // fp8 activation scale and its inverse
+  uint8_t *sig_scratch;                // per (workgroup, wave): sigma fragments, stage 1 -> 3
 };
 
+// Two floats -> packed bf16 pair (round to nearest even), one v_cvt_pk_bf16_f32.
 __device__ __forceinline__ uint32_t pk_bf16(float a, float b) {
-  bf16x2 v = {(__bf16)a, (__bf16)b};
-  return __builtin_bit_cast(uint32_t, v);
+  typedef float f32x2 __attribute__((ext_vector_type(2)));
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector(f32x2{a, b}, bf16x2));
 }
+
+// max(x, 0) in one v_med3_f32 (fmaxf on a matrix-core result would first
+// canonicalise its operand, costing a second instruction).
+__device__ __forceinline__ float relu1(float x) { return __builtin_amdgcn_fmed3f(x, 0.0f, 3.402823466e+38f); }
 
 __device__ __forceinline__ f32x4 mma(u32x4 a, u32x4 b, f32x4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a),
                                                  __builtin_bit_cast(bf16x8, b), c, 0, 0, 0);
 }
 
-__device__ __forceinline__ f32x4 relu4(f32x4 v) {
-  return f32x4{fmaxf(v.x, 0.f), fmaxf(v.y, 0.f), fmaxf(v.z, 0.f), fmaxf(v.w, 0.f)};
+// 16x16x16 bf16 MFMA: lane group g supplies inputs 4g..4g+3.
+__device__ __forceinline__ f32x4 mma16(uint2 a, uint2 b, f32x4 c) {
+  typedef short s16x4 __attribute__((ext_vector_type(4)));
+  return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(__builtin_bit_cast(s16x4, a),
+                                                   __builtin_bit_cast(s16x4, b), c, 0, 0, 0);
 }
 
-// bf16 pairs back to fp32 (exact: bf16 is the top half of an fp32).
-__device__ __forceinline__ f32x4 unpk_bf16(uint32_t a, uint32_t b) {
-  return f32x4{__uint_as_float(a << 16), __uint_as_float(a & 0xffff0000u),
-               __uint_as_float(b << 16), __uint_as_float(b & 0xffff0000u)};
+__device__ __forceinline__ f32x4 relu4(f32x4 v) {
+  return f32x4{relu1(v.x), relu1(v.y), relu1(v.z), relu1(v.w)};
 }
 
 // ReLU of two packed bf16: sign-magnitude values order like signed 16-bit
@@ -114,6 +121,11 @@ __device__ __forceinline__ u32x4 ld_frag(const uint8_t *chunk, int idx, int lane
   return *(const u32x4 *)(chunk + (size_t)idx * kFrag + lane * 16);
 }
 
+// One A fragment of the 16x16x16 bf16 instruction: 64 lanes x 8 bytes.
+__device__ __forceinline__ uint2 ld_frag16(const uint8_t *chunk, int idx, int lane) {
+  return *(const uint2 *)(chunk + (size_t)idx * 512 + lane * 8);
+}
+
 // One fp8 A fragment of the 16x16x128 instruction: 64 lanes x 32 bytes.
 __device__ __forceinline__ i32x8 ld_frag8(const uint8_t *chunk, int idx, int lane) {
   return *(const i32x8 *)(chunk + (size_t)idx * 2 * kFrag + lane * 32);
@@ -151,9 +163,14 @@ __device__ __forceinline__ void to_frags(const f32x4 (&acc)[kNT][MT_], u32x4 (&o
   for (int t = 0; t < kNT; ++t) {
 #pragma unroll
     for (int mt = 0; mt < MT_; ++mt) {
-      const f32x4 v = RELU ? relu4(acc[t][mt]) : acc[t][mt];
-      out[t][mt >> 1][2 * (mt & 1)] = pk_bf16(v.x, v.y);
-      out[t][mt >> 1][2 * (mt & 1) + 1] = pk_bf16(v.z, v.w);
+      const f32x4 v = acc[t][mt];
+      uint32_t lo = pk_bf16(v.x, v.y), hi = pk_bf16(v.z, v.w);
+      if (RELU) {
+        lo = relu_bf16x2(lo);
+        hi = relu_bf16x2(hi);
+      }
+      out[t][mt >> 1][2 * (mt & 1)] = lo;
+      out[t][mt >> 1][2 * (mt & 1) + 1] = hi;
     }
   }
 }
@@ -187,9 +204,14 @@ __device__ __forceinline__ void layer(u32x4 (&out)[kNT][MT_ / 2], const uint8_t 
     for (int t = 0; t < kNT; ++t) {
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
-        const f32x4 v = RELU ? relu4(acc[t][h]) : acc[t][h];
-        out[t][p][2 * h] = pk_bf16(v.x, v.y);
-        out[t][p][2 * h + 1] = pk_bf16(v.z, v.w);
+        const f32x4 v = acc[t][h];
+        uint32_t lo = pk_bf16(v.x, v.y), hi = pk_bf16(v.z, v.w);
+        if (RELU) {
+          lo = relu_bf16x2(lo);
+          hi = relu_bf16x2(hi);
+        }
+        out[t][p][2 * h] = lo;
+        out[t][p][2 * h + 1] = hi;
       }
     }
   }
@@ -227,8 +249,9 @@ __global__ __launch_bounds__(kThreads) void fwd_mfma_kernel(MfmaArgs a) {
   // bf16: [T1A | T2 (bf16)]; fp8: [T1A | T2 (fp8, 2 KiB fragments) | T2 row scales]
   constexpr bool kFp8 = PREC == GN_FP8_T;
   if (kFp8) {
-    lds_fill(L_res, a.packed + a.res_off, (int64_t)MT * kFrag, wave, lane0);
-    lds_fill(L_res + MT * kFrag, a.packed + a.t2q_off, res_bytes - MT * kFrag, wave, lane0);
+    constexpr int64_t t1a = (MT * 512 + 1023) & ~1023;
+    lds_fill(L_res, a.packed + a.res_off, t1a, wave, lane0);
+    lds_fill(L_res + t1a, a.packed + a.t2q_off, res_bytes - t1a, wave, lane0);
   } else {
     lds_fill(L_res, a.packed + a.res_off, res_bytes, wave, lane0);
   }
@@ -237,9 +260,10 @@ __global__ __launch_bounds__(kThreads) void fwd_mfma_kernel(MfmaArgs a) {
   wait_vm();
   __syncthreads();
 
+  constexpr int kT1ABytes = (MT * 512 + 1023) & ~1023;          // K=16 fragments of 512 B
   const uint8_t *T1A = L_res;
-  const uint8_t *T2 = L_res + MT * kFrag;                       // bf16 form
-  float *T2scale = (float *)(L_res + MT * kFrag + MT * 2 * kFrag);  // fp8 form
+  const uint8_t *T2 = L_res + kT1ABytes;                           // bf16 form
+  float *T2scale = (float *)(L_res + kT1ABytes + MT * 2 * kFrag);  // fp8 form
   if (kFp8) {
     // dequantisation factor of the fp8 layer: weight row scale x activation scale
     if ((int)threadIdx.x < W) T2scale[threadIdx.x] *= a.sa;
@@ -320,8 +344,15 @@ __global__ __launch_bounds__(kThreads) void fwd_mfma_kernel(MfmaArgs a) {
 
     // ================= stage 1: F layer 3 -> sigma =================
     fill_stage(2);
-    u32x4 sig[kNT][KS];
+    u32x4 sig[kNT][KS];   // live in stage 1 only; reloaded in stage 3
     layer<MT, KS, false>(sig, stage_buf(1), h2, bF3, g, lane);
+    // sigma is needed again only by B's first layer: park it in this wave's
+    // scratch instead of holding 32 registers through the slot loop
+    uint8_t *sig_slot = a.sig_scratch + ((size_t)blockIdx.x * kWaves + wave) * (kNT * KS * kFrag);
+#pragma unroll
+    for (int t = 0; t < kNT; ++t)
+#pragma unroll
+      for (int k = 0; k < KS; ++k) *(u32x4 *)(sig_slot + (t * KS + k) * kFrag + lane * 16) = sig[t][k];
     wait_vm();
     __syncthreads();
 
@@ -330,16 +361,22 @@ __global__ __launch_bounds__(kThreads) void fwd_mfma_kernel(MfmaArgs a) {
     f32x4 Z[kNT][MT];
     float cnt[kNT];
     {
-      // u = W1s sigma + c1, kept as packed bf16 in the accumulator layout
-      u32x4 u[kNT][KS];
-      layer<MT, KS, false>(u, stage_buf(2), sig, bT1, g, lane);
+      // u = W1s sigma + c1 in fp32 accumulator layout: the C operand of h's
+      // first layer for every slot
+      f32x4 u[kNT][MT];
+      bias_init(u, bT1, g);
+      mm<MT, KS>(u, stage_buf(2), sig, lane);
 #pragma unroll
       for (int t = 0; t < kNT; ++t) {
         cnt[t] = 0.0f;
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt) Z[t][mt] = f32x4{0.f, 0.f, 0.f, 0.f};
       }
-      for (int i = 0; i < K; ++i) {
+      // Slot inputs: lane group g < 3 carries planes 4g..4g+3 of its pixel (the
+      // K=16 operand of h's first layer); the next slot's planes are loaded
+      // one slot ahead so their latency overlaps the current slot's work.
+      float nxt[kNT][4];
+      auto load_slot = [&](int i) {
         const float *Li = Lp + (size_t)i * kNL * hw;
         int qs[kNT];
 #pragma unroll
@@ -347,19 +384,29 @@ __global__ __launch_bounds__(kThreads) void fwd_mfma_kernel(MfmaArgs a) {
           qs[t] = qc[t];
           asm volatile("" : "+v"(qs[t]));   // per-slot addresses stay in the loop body
         }
-        u32x4 bi[kNT][1];
+#pragma unroll
+        for (int t = 0; t < kNT; ++t)
+#pragma unroll
+          for (int j = 0; j < 4; ++j)
+            nxt[t][j] = g < 3 ? Li[(size_t)(4 * g + j) * hw + qs[t]] : 0.0f;
+      };
+      if (K > 0) load_slot(0);
+      for (int i = 0; i < K; ++i) {
+        float cur[kNT][4];
+#pragma unroll
+        for (int t = 0; t < kNT; ++t)
+#pragma unroll
+          for (int j = 0; j < 4; ++j) cur[t][j] = nxt[t][j];
+        if (i + 1 < K) load_slot(i + 1);
+        uint2 bi[kNT];
         float m[kNT];
 #pragma unroll
         for (int t = 0; t < kNT; ++t) {
-          float v[8];
-#pragma unroll
-          for (int j = 0; j < 8; ++j) {
-            const int c = 8 * g + j;
-            v[j] = c < kNL ? Li[(size_t)c * hw + qs[t]] : 0.0f;
-          }
-          m[t] = Li[(size_t)kAlpha * hw + qs[t]] > 0.0f ? 1.0f : 0.0f;
-          bi[t][0] = u32x4{pk_bf16(v[0], v[1]), pk_bf16(v[2], v[3]), pk_bf16(v[4], v[5]),
-                           pk_bf16(v[6], v[7])};
+          bi[t] = uint2{pk_bf16(cur[t][0], cur[t][1]), pk_bf16(cur[t][2], cur[t][3])};
+          // alpha (plane 9) sits in lane group 2 at position 1: broadcast it
+          const float al = __int_as_float(
+              __builtin_amdgcn_ds_bpermute((col + 32) * 4, __float_as_int(cur[t][1])));
+          m[t] = al > 0.0f ? 1.0f : 0.0f;
         }
         if constexpr (kFp8) {
         // h layer 1 (bf16 MFMA), output quantised to E4M3 with the static
@@ -368,11 +415,10 @@ __global__ __launch_bounds__(kThreads) void fwd_mfma_kernel(MfmaArgs a) {
         i32x8 zq[kNT];
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt) {
-          const u32x4 w = ld_frag(T1A, mt, lane);
+          const uint2 w = ld_frag16(T1A, mt, lane);
 #pragma unroll
           for (int t = 0; t < kNT; ++t) {
-            const f32x4 v = mma(w, bi[t][0],
-                                unpk_bf16(u[t][mt >> 1][2 * (mt & 1)], u[t][mt >> 1][2 * (mt & 1) + 1]));
+            const f32x4 v = mma16(w, bi[t], u[t][mt]);
             zq[t][mt] = pack_fp8x4(relu4(v) * a.inv_sa);
           }
         }
@@ -386,10 +432,10 @@ __global__ __launch_bounds__(kThreads) void fwd_mfma_kernel(MfmaArgs a) {
 #pragma unroll
           for (int t = 0; t < kNT; ++t) {
             const f32x4 acc = mma_fp8(w, zq[t], f32x4{0.f, 0.f, 0.f, 0.f});
-            Z[t][mt].x = fmaf(m[t], fmaxf(fmaf(acc.x, sc.x, b.x), 0.f), Z[t][mt].x);
-            Z[t][mt].y = fmaf(m[t], fmaxf(fmaf(acc.y, sc.y, b.y), 0.f), Z[t][mt].y);
-            Z[t][mt].z = fmaf(m[t], fmaxf(fmaf(acc.z, sc.z, b.z), 0.f), Z[t][mt].z);
-            Z[t][mt].w = fmaf(m[t], fmaxf(fmaf(acc.w, sc.w, b.w), 0.f), Z[t][mt].w);
+            Z[t][mt].x = fmaf(m[t], relu1(fmaf(acc.x, sc.x, b.x)), Z[t][mt].x);
+            Z[t][mt].y = fmaf(m[t], relu1(fmaf(acc.y, sc.y, b.y)), Z[t][mt].y);
+            Z[t][mt].z = fmaf(m[t], relu1(fmaf(acc.z, sc.z, b.z)), Z[t][mt].z);
+            Z[t][mt].w = fmaf(m[t], relu1(fmaf(acc.w, sc.w, b.w)), Z[t][mt].w);
           }
         }
         } else {
@@ -399,10 +445,10 @@ __global__ __launch_bounds__(kThreads) void fwd_mfma_kernel(MfmaArgs a) {
         for (int p = 0; p < KS; ++p) {
 #pragma unroll
           for (int h = 0; h < 2; ++h) {
-            const u32x4 w = ld_frag(T1A, 2 * p + h, lane);
+            const uint2 w = ld_frag16(T1A, 2 * p + h, lane);
 #pragma unroll
             for (int t = 0; t < kNT; ++t) {
-              const f32x4 v = mma(w, bi[t][0], unpk_bf16(u[t][p][2 * h], u[t][p][2 * h + 1]));
+              const f32x4 v = mma16(w, bi[t], u[t][2 * p + h]);
               z1[t][p][2 * h] = relu_bf16x2(pk_bf16(v.x, v.y));
               z1[t][p][2 * h + 1] = relu_bf16x2(pk_bf16(v.z, v.w));
             }
@@ -423,7 +469,7 @@ __global__ __launch_bounds__(kThreads) void fwd_mfma_kernel(MfmaArgs a) {
           }
 #pragma unroll
           for (int t = 0; t < kNT; ++t) {
-            const f32x4 r = relu4(acc[t]);
+            const f32x4 r = relu4(acc[t]);    // one v_med3 each
             Z[t][mt].x = fmaf(m[t], r.x, Z[t][mt].x);
             Z[t][mt].y = fmaf(m[t], r.y, Z[t][mt].y);
             Z[t][mt].z = fmaf(m[t], r.z, Z[t][mt].z);
@@ -440,6 +486,12 @@ __global__ __launch_bounds__(kThreads) void fwd_mfma_kernel(MfmaArgs a) {
 
     // ================= stage 3: pool and h layer 3 -> tau =================
     fill_stage(4);
+    u32x4 sig2[kNT][KS];
+#pragma unroll
+    for (int t = 0; t < kNT; ++t)
+#pragma unroll
+      for (int k = 0; k < KS; ++k)
+        sig2[t][k] = *(const u32x4 *)(sig_slot + (t * KS + k) * kFrag + lane * 16);
     u32x4 tau[kNT][KS];
     {
       u32x4 zs[kNT][KS];
@@ -467,7 +519,7 @@ __global__ __launch_bounds__(kThreads) void fwd_mfma_kernel(MfmaArgs a) {
     fill_stage(5);
     f32x4 accB[kNT][MT];
     bias_init(accB, bB1, g);
-    mm<MT, KS>(accB, stage_buf(4), sig, lane);
+    mm<MT, KS>(accB, stage_buf(4), sig2, lane);
     wait_vm();
     __syncthreads();
 
@@ -562,16 +614,19 @@ __device__ __forceinline__ int chain_col(int ks, int g, int j) {
 // One thread per bf16 element of one chunk (blockIdx.y = chunk).
 __global__ void pack_bf16_kernel(PackArgs p) {
   const ChunkDesc d = p.chunk[blockIdx.y];
-  const int64_t n = (int64_t)d.mt * d.ks * 64 * 8;
+  const int lg = d.kmap == KMAP_MEM16 ? 2 : 3;       // log2 of elements per lane
+  const int64_t n = (int64_t)d.mt * d.ks * 64 << lg;
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= n) return;
-  const int j = (int)(e & 7);
-  const int lane = (int)((e >> 3) & 63);
-  const int fragi = (int)(e >> 9);
+  const int j = (int)(e & ((1 << lg) - 1));
+  const int lane = (int)((e >> lg) & 63);
+  const int fragi = (int)(e >> (lg + 6));
   const int mt = fragi / d.ks, ks = fragi - mt * d.ks;
   const int row = 16 * mt + (lane & 15);
   const int g = lane >> 4;
-  const int k = d.kmap == KMAP_MEM ? 32 * ks + 8 * g + j : chain_col(ks, g, j);
+  const int k = d.kmap == KMAP_MEM     ? 32 * ks + 8 * g + j
+                : d.kmap == KMAP_MEM16 ? 16 * ks + 4 * g + j
+                                       : chain_col(ks, g, j);
   const LayerOff lo = p.lo[d.layer];
   float v = 0.0f;
   if (row < d.nrows && k < d.ncols) v = p.master[lo.w + (int64_t)row * lo.in + d.col0 + k];
@@ -640,6 +695,10 @@ hipError_t launch_transpose_master(int W, const float *master, float *master_t,
   return hipGetLastError();
 }
 
+size_t mfma_sig_scratch_bytes(int W, int grid) {
+  return (size_t)grid * kWaves * kNT * (W / 32) * kFrag;
+}
+
 hipError_t launch_pack_weights(const float *master, uint8_t *packed, const PackedLayout &pl,
                                float fp8_act_scale, hipStream_t stream) {
   (void)fp8_act_scale;
@@ -664,8 +723,9 @@ hipError_t launch_pack_weights(const float *master, uint8_t *packed, const Packe
 // Resident LDS bytes of the slot loop's weights for a precision.
 static int64_t resident_bytes(const PackedLayout &pl, int precision) {
   const int MT = pl.W / 16;
-  if (precision == GN_FP8_T) return (int64_t)MT * kFrag + (pl.t2scale_off - pl.t2q_off) +
-                                    (pl.total_bytes - pl.t2scale_off);
+  if (precision == GN_FP8_T)
+    return (((int64_t)MT * 512 + 1023) & ~(int64_t)1023) + (pl.t2scale_off - pl.t2q_off) +
+           (pl.total_bytes - pl.t2scale_off);
   return pl.resident_bytes;
 }
 
@@ -692,8 +752,10 @@ static hipError_t launch_one(const MfmaArgs &a, int grid, size_t lds, hipStream_
 hipError_t launch_fwd_mfma(int W, int precision, int pool, const uint8_t *packed,
                            const PackedLayout &pl, const FwdBatch *batch,
                            const FrameDesc *frames, const TileRef *tiles, int ntiles,
-                           float fp8_act_scale, int grid, hipStream_t stream) {
+                           float fp8_act_scale, int grid, uint8_t *sig_scratch,
+                           hipStream_t stream) {
   MfmaArgs a;
+  a.sig_scratch = sig_scratch;
   a.packed = packed;
   for (int s = 0; s <= kNumStages; ++s) a.stage_off[s] = pl.stage_off[s];
   a.res_off = pl.resident_off;
@@ -715,7 +777,7 @@ hipError_t launch_fwd_mfma(int W, int precision, int pool, const uint8_t *packed
   a.sa = fp8_act_scale;
   a.inv_sa = 1.0f / fp8_act_scale;
   if (ntiles <= 0) return hipSuccess;
-  grid = std::max(1, std::min(grid, ntiles));
+  grid = std::max(1, std::min(grid, ntiles));   // the scratch holds `grid` workgroups
   const size_t lds = mfma_lds_bytes(pl, precision);
   if (precision == GN_BF16) {
     if (W == 64) return launch_one<64, GN_BF16>(a, grid, lds, stream);

@@ -18,6 +18,7 @@ struct gn_handle {
   uint8_t *d_packed = nullptr;    // fragment-ordered bf16/fp8 weights + biases
   gn::PackedLayout pl{};
   float *d_scratch = nullptr;     // fp32 forward: per-thread vectors
+  uint8_t *d_sig_scratch[2] = {nullptr, nullptr};  // MFMA forward: caller streams, serving
   int scratch_threads = 0;
   float *d_l1_partials = nullptr;
   int l1_npart = 0;

@@ -53,7 +53,9 @@ enum Chunk {
   C_T1A, C_T2,            // resident in LDS through the slot loop
   kNumChunks
 };
-enum KMap { KMAP_CHAIN = 0, KMAP_MEM = 1 };
+// KMAP_MEM16: a 16-deep K-step of v_mfma_f32_16x16x16bf16_1k, lane group g
+// holding inputs 4g..4g+3 (fragments of 64 lanes x 8 bytes).
+enum KMap { KMAP_CHAIN = 0, KMAP_MEM = 1, KMAP_MEM16 = 2 };
 
 struct ChunkDesc {
   int32_t layer;     // Layer
@@ -101,10 +103,14 @@ hipError_t launch_fwd_fp32(int W, int pool, const float *master, const float *ma
                            unsigned *amax = nullptr);
 int fp32_scratch_threads(int num_cus);
 
+// sig_scratch: mfma_sig_scratch_bytes(W, grid) bytes private to this launch
+// (launches that may overlap need different scratch buffers).
 hipError_t launch_fwd_mfma(int W, int precision, int pool, const uint8_t *packed,
                            const PackedLayout &pl, const FwdBatch *batch,
                            const FrameDesc *frames, const TileRef *tiles, int ntiles,
-                           float fp8_act_scale, int grid, hipStream_t stream);
+                           float fp8_act_scale, int grid, uint8_t *sig_scratch,
+                           hipStream_t stream);
+size_t mfma_sig_scratch_bytes(int W, int grid);
 constexpr int kTilePx = 256;
 
 hipError_t launch_l1(const float *out, const float *target, uint64_t count, float *loss,

@@ -52,7 +52,7 @@ void make_packed_layout(int W, PackedLayout *pl) {
   set(C_R1L, L_R1, W, 3, W, MT, 1, KMAP_MEM);
   set(C_R2, L_R2, 0, W, W, MT, KS, KMAP_CHAIN);
   set(C_R3, L_R3, 0, W, kNOUT, 1, KS, KMAP_CHAIN);
-  set(C_T1A, L_T1, 0, kNL, W, MT, 1, KMAP_MEM);
+  set(C_T1A, L_T1, 0, kNL, W, MT, 1, KMAP_MEM16);
   set(C_T2, L_T2, 0, W, W, MT, KS, KMAP_CHAIN);
 
   // Stage groups in kernel order; every fragment is 1 KiB so stages stay
@@ -74,7 +74,7 @@ void make_packed_layout(int W, PackedLayout *pl) {
   pl->stage_off[kNumStages] = off;
   pl->resident_off = off;
   pl->chunk[C_T1A].offset = off;
-  off += (int64_t)MT * 1024;
+  off += ((int64_t)MT * 512 + 1023) & ~(int64_t)1023;      // K=16 fragments: 512 B each
   pl->chunk[C_T2].offset = off;
   off += (int64_t)MT * KS * 1024;
   pl->resident_bytes = off - pl->resident_off;

@@ -131,21 +131,6 @@ __device__ __forceinline__ i32x8 ld_frag8(const uint8_t *chunk, int idx, int lan
   return *(const i32x8 *)(chunk + (size_t)idx * 2 * kFrag + lane * 32);
 }
 
-// acc[t][mt] += A(chunk) . in[t]   over the chunk's KS_ K-steps.
-template <int MT_, int KS_>
-__device__ __forceinline__ void mm(f32x4 (&acc)[kNT][MT_], const uint8_t *chunk,
-                                   const u32x4 (&in)[kNT][KS_], int lane) {
-#pragma unroll
-  for (int mt = 0; mt < MT_; ++mt) {
-#pragma unroll
-    for (int ks = 0; ks < KS_; ++ks) {
-      const u32x4 w = ld_frag(chunk, mt * KS_ + ks, lane);
-#pragma unroll
-      for (int t = 0; t < kNT; ++t) acc[t][mt] = mma(w, in[t][ks], acc[t][mt]);
-    }
-  }
-}
-
 template <int MT_>
 __device__ __forceinline__ void bias_init(f32x4 (&acc)[kNT][MT_], const float *bias, int g) {
 #pragma unroll
@@ -176,14 +161,28 @@ __device__ __forceinline__ void to_frags(const f32x4 (&acc)[kNT][MT_], u32x4 (&o
 }
 
 // One chained layer, an M-tile pair at a time: out[t][p] = pack(act(A in + bias))
-// for M-tiles 2p and 2p+1.  Keeps only 2 x kNT accumulators live.
-// bias_scale[t] multiplies the bias (1 for ordinary layers).
+// for M-tiles 2p and 2p+1.  The pair's weight fragments are read up front and
+// the next pair's are requested before this pair's MFMAs issue, so LDS
+// latency overlaps matrix-core work instead of stalling every K-step.
 template <int MT_, int KS_, bool RELU>
 __device__ __forceinline__ void layer(u32x4 (&out)[kNT][MT_ / 2], const uint8_t *chunk,
                                       const u32x4 (&in)[kNT][KS_], const float *bias, int g,
                                       int lane) {
+  u32x4 wb[2][2][KS_];
+#pragma unroll
+  for (int h = 0; h < 2; ++h)
+#pragma unroll
+    for (int ks = 0; ks < KS_; ++ks) wb[0][h][ks] = ld_frag(chunk, h * KS_ + ks, lane);
 #pragma unroll
   for (int p = 0; p < MT_ / 2; ++p) {
+    const int cur = p & 1;
+    if (p + 1 < MT_ / 2) {
+#pragma unroll
+      for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int ks = 0; ks < KS_; ++ks)
+          wb[cur ^ 1][h][ks] = ld_frag(chunk, (2 * (p + 1) + h) * KS_ + ks, lane);
+    }
     f32x4 acc[kNT][2];
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
@@ -195,9 +194,8 @@ __device__ __forceinline__ void layer(u32x4 (&out)[kNT][MT_ / 2], const uint8_t 
     for (int h = 0; h < 2; ++h) {
 #pragma unroll
       for (int ks = 0; ks < KS_; ++ks) {
-        const u32x4 w = ld_frag(chunk, (2 * p + h) * KS_ + ks, lane);
 #pragma unroll
-        for (int t = 0; t < kNT; ++t) acc[t][h] = mma(w, in[t][ks], acc[t][h]);
+        for (int t = 0; t < kNT; ++t) acc[t][h] = mma(wb[cur][h][ks], in[t][ks], acc[t][h]);
       }
     }
 #pragma unroll
@@ -214,6 +212,28 @@ __device__ __forceinline__ void layer(u32x4 (&out)[kNT][MT_ / 2], const uint8_t 
         out[t][p][2 * h + 1] = hi;
       }
     }
+  }
+}
+
+// acc[t][mt] += A(chunk) . in[t] over the chunk's KS_ K-steps, one M-tile's
+// fragments read ahead of its MFMAs and the next M-tile's requested early.
+template <int MT_, int KS_>
+__device__ __forceinline__ void mm(f32x4 (&acc)[kNT][MT_], const uint8_t *chunk,
+                                   const u32x4 (&in)[kNT][KS_], int lane) {
+  u32x4 wb[2][KS_];
+#pragma unroll
+  for (int ks = 0; ks < KS_; ++ks) wb[0][ks] = ld_frag(chunk, ks, lane);
+#pragma unroll
+  for (int mt = 0; mt < MT_; ++mt) {
+    const int cur = mt & 1;
+    if (mt + 1 < MT_) {
+#pragma unroll
+      for (int ks = 0; ks < KS_; ++ks) wb[cur ^ 1][ks] = ld_frag(chunk, (mt + 1) * KS_ + ks, lane);
+    }
+#pragma unroll
+    for (int ks = 0; ks < KS_; ++ks)
+#pragma unroll
+      for (int t = 0; t < kNT; ++t) acc[t][mt] = mma(wb[cur][ks], in[t][ks], acc[t][mt]);
   }
 }
 
@@ -277,6 +297,53 @@ __global__ __launch_bounds__(kThreads) void fwd_mfma_kernel(MfmaArgs a) {
   const int64_t r1p_bytes = (int64_t)MT * KS * kFrag;    // R1P precedes R1L in stage 8
   const int64_t r2_bytes = (int64_t)MT * KS * kFrag;     // R2 precedes R3 in stage 9
 
+  // ---- tile -> frame pointers, first pixel
+  struct TileInfo {
+    const float *G, *L, *S;
+    float *O;
+    int hw, K, q0;
+  };
+  auto resolve = [&](int tile) {
+    TileInfo ti;
+    if (a.tiles) {
+      const TileRef tr = a.tiles[tile];
+      const FrameDesc fd = a.frames[tr.frame];
+      ti.G = fd.g; ti.L = fd.L; ti.S = fd.s; ti.O = fd.out; ti.hw = fd.hw; ti.K = fd.k;
+      ti.q0 = tr.q0;
+    } else {
+      const int f = tile / a.tiles_per_frame;
+      ti.hw = a.b.hw;
+      ti.K = a.b.k;
+      ti.q0 = (tile - f * a.tiles_per_frame) * kTilePx;
+      ti.G = a.b.gbuf + (size_t)f * kNG * ti.hw;
+      ti.L = a.b.layers + (size_t)f * ti.K * kNL * ti.hw;
+      ti.S = a.b.scene + (size_t)f * kNS;
+      ti.O = a.b.out + (size_t)f * kNOUT * ti.hw;
+    }
+    return ti;
+  };
+  // F's input (G-buffer planes 0..13, scene 0..15, zero pad) of a tile: lane
+  // group g holds columns 8g..8g+7 of its pixel.  Loaded one tile ahead.
+  auto load_x = [&](const TileInfo &ti, int ln, float (&xr)[kNT][8]) {
+    const int gg = ln >> 4, cc = ln & 15;
+#pragma unroll
+    for (int t = 0; t < kNT; ++t) {
+      const int q = ti.q0 + wave * (kNT * 16) + t * 16 + cc;
+      const int qq = q < ti.hw ? q : ti.hw - 1;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int c = 8 * gg + j;
+        xr[t][j] = c < kNG ? ti.G[(size_t)c * ti.hw + qq] : (c < kNG + kNS ? ti.S[c - kNG] : 0.0f);
+      }
+    }
+  };
+  float xr[kNT][8];
+  TileInfo nti;
+  if ((int)blockIdx.x < a.ntiles) {
+    nti = resolve(blockIdx.x);
+    load_x(nti, lane0, xr);
+  }
+
   for (int tile = blockIdx.x; tile < a.ntiles; tile += gridDim.x) {
     const bool has_next = tile + (int)gridDim.x < a.ntiles;
     // Opaque per-tile copies of the lane id and the packed-weight base keep
@@ -291,24 +358,11 @@ __global__ __launch_bounds__(kThreads) void fwd_mfma_kernel(MfmaArgs a) {
       lds_fill(stage_buf(s), packed + a.stage_off[s], a.stage_off[s + 1] - a.stage_off[s], wave,
                lane);
     };
-    // ---- resolve the tile's frame
-    const float *Gp, *Lp, *Sp;
-    float *Op;
-    int hw, K, q0;
-    if (a.tiles) {
-      const TileRef tr = a.tiles[tile];
-      const FrameDesc fd = a.frames[tr.frame];
-      Gp = fd.g; Lp = fd.L; Sp = fd.s; Op = fd.out; hw = fd.hw; K = fd.k; q0 = tr.q0;
-    } else {
-      const int f = tile / a.tiles_per_frame;
-      hw = a.b.hw;
-      K = a.b.k;
-      q0 = (tile - f * a.tiles_per_frame) * kTilePx;
-      Gp = a.b.gbuf + (size_t)f * kNG * hw;
-      Lp = a.b.layers + (size_t)f * K * kNL * hw;
-      Sp = a.b.scene + (size_t)f * kNS;
-      Op = a.b.out + (size_t)f * kNOUT * hw;
-    }
+    // ---- the tile's frame (resolved one tile ahead)
+    const TileInfo ti = nti;
+    const float *Gp = ti.G, *Lp = ti.L;
+    float *Op = ti.O;
+    const int hw = ti.hw, K = ti.K, q0 = ti.q0;
     int qc[kNT];
     bool valid[kNT];
 #pragma unroll
@@ -324,16 +378,9 @@ __global__ __launch_bounds__(kThreads) void fwd_mfma_kernel(MfmaArgs a) {
     {
       u32x4 x[kNT][1];
 #pragma unroll
-      for (int t = 0; t < kNT; ++t) {
-        float v[8];
-#pragma unroll
-        for (int j = 0; j < 8; ++j) {
-          const int c = 8 * g + j;            // input column: G 0..13, scene 0..15, pad
-          v[j] = c < kNG ? Gp[(size_t)c * hw + qc[t]] : (c < kNG + kNS ? Sp[c - kNG] : 0.0f);
-        }
-        x[t][0] = u32x4{pk_bf16(v[0], v[1]), pk_bf16(v[2], v[3]), pk_bf16(v[4], v[5]),
-                        pk_bf16(v[6], v[7])};
-      }
+      for (int t = 0; t < kNT; ++t)
+        x[t][0] = u32x4{pk_bf16(xr[t][0], xr[t][1]), pk_bf16(xr[t][2], xr[t][3]),
+                        pk_bf16(xr[t][4], xr[t][5]), pk_bf16(xr[t][6], xr[t][7])};
       const uint8_t *S = stage_buf(0);
       u32x4 h1[kNT][KS];
       layer<MT, 1, true>(h1, S, x, bF1, g, lane);
@@ -532,6 +579,12 @@ __global__ __launch_bounds__(kThreads) void fwd_mfma_kernel(MfmaArgs a) {
 
     // ================= stage 6: B layer 2 =================
     fill_stage(7);
+    // L_d for R's first layer (stage 8), requested two stages early
+    float ldr[kNT][3];
+#pragma unroll
+    for (int t = 0; t < kNT; ++t)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) ldr[t][c] = g == 0 ? Gp[(size_t)(11 + c) * hw + qc[t]] : 0.0f;
     {
       u32x4 hb2[kNT][KS];
       layer<MT, KS, true>(hb2, stage_buf(6), hb, bB2, g, lane);
@@ -556,16 +609,8 @@ __global__ __launch_bounds__(kThreads) void fwd_mfma_kernel(MfmaArgs a) {
     {
       u32x4 ld[kNT][1];
 #pragma unroll
-      for (int t = 0; t < kNT; ++t) {
-        float v[8];
-#pragma unroll
-        for (int j = 0; j < 8; ++j) {
-          const int c = 8 * g + j;
-          v[j] = c < 3 ? Gp[(size_t)(11 + c) * hw + qc[t]] : 0.0f;
-        }
-        ld[t][0] = u32x4{pk_bf16(v[0], v[1]), pk_bf16(v[2], v[3]), pk_bf16(v[4], v[5]),
-                         pk_bf16(v[6], v[7])};
-      }
+      for (int t = 0; t < kNT; ++t)
+        ld[t][0] = u32x4{pk_bf16(ldr[t][0], ldr[t][1]), pk_bf16(ldr[t][2], 0.0f), 0u, 0u};
       f32x4 acc[kNT][MT];
       bias_init(acc, bR1, g);
       mm<MT, KS>(acc, stage_buf(8), phi, lane);
@@ -576,7 +621,11 @@ __global__ __launch_bounds__(kThreads) void fwd_mfma_kernel(MfmaArgs a) {
     __syncthreads();
 
     // ================= stage 9: R layers 2-3 -> radiance =================
-    if (has_next) fill_stage(0);
+    if (has_next) {
+      fill_stage(0);
+      nti = resolve(tile + gridDim.x);
+      load_x(nti, lane, xr);
+    }
     {
       u32x4 hr2[kNT][KS];
       layer<MT, KS, true>(hr2, stage_buf(9), hr, bR2, g, lane);

@@ -146,7 +146,9 @@ gn_status glassnet_forward(gn_handle *h, const gn_frame *frame, float *out, void
  * grad_out is dL/d(out), device, shaped like out.  grad_w (device, n_params
  * floats) is overwritten with dL/dw in the flat layout.  Per-slot activations
  * of h are recomputed, never stored for all k.  The transparency mask is a
- * hard selection: no gradient flows through alpha's threshold. */
+ * hard selection: no gradient flows through alpha's threshold.  At most
+ * 3 * 2^20 pixels (n * h * w) per call (GN_E_INVAL beyond).  The library keeps
+ * a workspace of about 14.5 KB per pixel (W = 128) between calls. */
 gn_status glassnet_backward(gn_handle *h, const gn_frame *frame, const float *grad_out,
                             float *grad_w, void *hip_stream);
 

@@ -5,4 +5,4 @@ package.  It shares no code with the HIP library and never imports it.
 """
 from .glassnet_oracle import (alpha_blend, all_slot_orders, forward,  # noqa: F401
                               forward_bruteforce, grad, grad_from_dy, l1_loss, n_params, pack,
-                              relu_signature, unpack)
+                              relu_margins, relu_signature, unpack)

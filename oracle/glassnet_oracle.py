@@ -351,6 +351,49 @@ def relu_signature(w, W, gbuf, layers, scene, target, pool="mean"):
     return np.concatenate([s.ravel() for s in sig])
 
 
+def relu_margins(w, W, gbuf, layers, scene, pool="mean"):
+    """Per pixel, how far every ReLU input lies from the kink at 0.
+
+    For each hidden pre-activation z = a . x + c of F, of h for every active
+    slot, of B and of R, the ratio |z| / (|a| . |x| + |c|) is the relative
+    distance from the kink measured against the absolute-value sum that
+    bounds the rounding error of evaluating z.  Returns the minimum ratio per
+    pixel, shape [n, h, w].  Where it is of the order of the working
+    precision's unit roundoff, a lower-precision evaluation may take the other
+    branch of ReLU' (a different but equally valid subgradient choice), so
+    gradient parity is only meaningful away from such pixels.
+    """
+    P = unpack(w, W)
+    G, L, S, (n, h, wd) = _pixels(gbuf, layers, scene)
+    marg = np.full(G.shape[1], np.inf)
+
+    def run(name, x, active=None):
+        nonlocal marg
+        (A1, c1), (A2, c2), (A3, c3) = P[name]
+        z1 = A1 @ x + c1[:, None]
+        a1 = _relu(z1)
+        z2 = A2 @ a1 + c2[:, None]
+        for z, A, c, v in ((z1, A1, c1, x), (z2, A2, c2, a1)):
+            r = (np.abs(z) / (np.abs(A) @ np.abs(v) + np.abs(c)[:, None] + 1e-300)).min(axis=0)
+            if active is not None:
+                r = np.where(active, r, np.inf)
+            marg = np.minimum(marg, r)
+        return A3 @ _relu(z2) + c3[:, None]
+
+    sigma = run("F", np.concatenate([G, S], axis=0))
+    Ssum = np.zeros_like(sigma)
+    cnt = np.zeros(sigma.shape[1])
+    for i in range(L.shape[0]):
+        m = L[i][9] > 0.0
+        hi = run("T", np.concatenate([L[i], sigma], axis=0), active=m)
+        Ssum += m * hi
+        cnt += m
+    tau = Ssum if pool == "sum" else Ssum / np.maximum(cnt, 1.0)
+    phi = run("B", np.concatenate([sigma, tau], axis=0))
+    run("R", np.concatenate([phi, G[11:14]], axis=0))
+    return marg.reshape(n, h, wd)
+
+
 def alpha_blend(colors, alphas):
     """Order-dependent alpha compositing of Eqs. (3)-(4), front-to-back.
 

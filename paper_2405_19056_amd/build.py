@@ -41,10 +41,17 @@ def common_flags():
     ]
 
 
+# Per-source extra flags.  The backward's fp32 plane GEMMs keep their
+# accumulators in VGPRs: in the default accumulator-register form the
+# allocator rotates them through copies every K group, at half the occupancy.
+EXTRA = {"bwd.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"]}
+
+
 def _compile(src: str) -> str:
     obj = os.path.join(BUILD, os.path.basename(src) + ".o")
-    lang = ["-x", "hip"] if src.endswith(".hip") else ["-x", "hip"]
-    cmd = [hipcc()] + common_flags() + lang + ["-c", os.path.join(CSRC, src), "-o", obj]
+    lang = ["-x", "hip"]
+    cmd = ([hipcc()] + common_flags() + EXTRA.get(src, []) + lang
+           + ["-c", os.path.join(CSRC, src), "-o", obj])
     r = subprocess.run(cmd, capture_output=True, text=True)
     noise = "is not a recognized feature for this target"
     msg = "\n".join(l for l in (r.stdout + r.stderr).splitlines() if noise not in l)

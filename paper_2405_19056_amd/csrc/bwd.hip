@@ -1,29 +1,36 @@
 // Hand-written backward of GlassNet's per-pixel evaluation (Sec. 3.5 trains
-// F, T, B and R jointly end to end; this is dL/dw for a given dL/dy).
+// F, T, B and R jointly end to end; this computes dL/dw for a given dL/dy).
 //
-// Data flow (all fp32):
-//   1. fwd_save:  recompute the forward per pixel and keep every per-pixel
-//                 activation the gradient needs as a plane [row][pixel]
-//                 (G/scene inputs, F's hidden layers, sigma, u, the pooled
-//                 Z/max(c,1), tau, B's and R's hidden layers).  The per-slot
-//                 activations of h are NOT kept.
-//   2. head:      dy -> R -> B -> (dsigma from B, dtau) -> dZ through h's
-//                 last layer and the pool.
-//   3. slot i:    one transparency layer at a time, recompute z1_i, z2_i from
-//                 (b_i, u), backprop through h's layers 2 and 1, add into du,
-//                 and accumulate dW of those two layers over pixels.  Only one
-//                 slot's activations exist at any time, so memory does not
-//                 grow with the slot count (the streaming sum of Eq. (5)).
-//   4. tail:      dsigma += A1s^T du, then F's layers.
-//   5. dW:        each layer's weight gradient sum_p delta_p a_p^T is a GEMM
-//                 with K = pixels on the fp32 matrix cores (16x16x4), split
-//                 over pixel chunks; partials are reduced in a fixed order
+// Every per-pixel quantity lives in a plane [row][pixel] of fp32 in HBM, and
+// every linear map of the forward recompute and of the backward is one plane
+// GEMM on the fp32 matrix cores,
+//     out[m][p] = epilogue( sum_k A[m][k] X[k][p] ),
+// with A a weight matrix (or its transpose) and X a block of planes.  The
+// epilogues fuse what sits between two linear maps: bias, ReLU, the ReLU
+// derivative mask, the alpha mask and pool of Eq. (5) and per-pixel scales.
+//
+//   1. prep:      gather G, the scene vector, L_d, the active-slot count and
+//                 dL/dy into planes.
+//   2. forward:   F; u = W_T1,sigma sigma + b_T1 (the sigma-hoist); per slot
+//                 z1_i and z2_i with the masked pool accumulated in the
+//                 epilogue; T3; B; R's hidden layers.  The slot activations
+//                 are overwritten slot by slot, never kept for all slots.
+//   3. head:      R^T, B^T -> (dsigma_B, dtau) -> dZ through T3 and the pool.
+//   4. slot i:    recompute z1_i, then dz2_i (z2_i's ReLU mask in the
+//                 epilogue), dz1_i, du += dz1_i, and accumulate dW of T2 and
+//                 of T1's slot columns.
+//   5. tail:      dsigma += W_T1,sigma^T du, then F^T.
+//   6. dW:        each layer's sum_p delta_p a_p^T on the matrix cores, split
+//                 over pixel chunks, partials reduced in a fixed order
 //                 (deterministic, no atomics).  Bias gradients come from a row
 //                 of ones appended to each activation block.
+#include <string.h>
+
 #include "gn_api_state.h"
-#include "valu_mlp.h"
 
 namespace gn {
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 struct BwdWorkspace {
   int W = 0;
@@ -31,374 +38,400 @@ struct BwdWorkspace {
   int64_t stride = -1;       // row length the constant rows were written for
   float *planes = nullptr;
   size_t plane_bytes = 0;
-  float *part = nullptr;     // generic GEMM partials
-  float *part_t2 = nullptr;  // h layer 2 partials (accumulated over slots)
-  float *part_t1 = nullptr;  // h layer 1, slot part (accumulated over slots)
+  f32x4 *frag = nullptr;     // weight fragments of every plane GEMM
+  size_t frag_bytes = 0;
+  float *part = nullptr;     // generic dW partials
+  float *part_t2 = nullptr;  // T2 partials (accumulated over slots)
+  float *part_t1 = nullptr;  // T1 slot-column partials (accumulated over slots)
   size_t part_bytes = 0, part_t2_bytes = 0, part_t1_bytes = 0;
   int max_chunks = 0;
 };
 
 namespace {
 
-using namespace valu;
-
 constexpr int kThreads = 256;
-constexpr int kOB = 64;
 constexpr int kChunkPx = 4096;      // pixels per split-K chunk of the dW GEMMs
+// Operand loads use 32-bit byte offsets within a plane block (up to 288 rows
+// plus a 16-row tile): this bounds the pixels of one backward call.
+constexpr int64_t kMaxPx = (int64_t)3 << 20;
 
 inline int rup(int x, int m) { return (x + m - 1) / m * m; }
 
 // Row offsets of every plane block.  Activation blocks end with a row of
 // ones (bias gradients) and are padded with zero rows to a multiple of 32.
 struct Blocks {
-  int xb, a1, a2, st, zs, d1, d2, pl, g1, g2, z1, bi, u, cnt;
-  int dy, dg2, dg1, dphi, dd2, dd1, dtau, dzin, du, dsig, da2, da1, dz2, dz1;
+  int xb, a1, a2, st, u, zs, d1, d2, pl, g1, g2, z1, bi, px;
+  int dy, dg2, dg1, dphi, dd2, dd1, dsig, dtau, dzin, du, da2, da1, dz2, dz1;
   int rows;
 };
+enum { PX_INV = 0, PX_M = 1 };     // rows of the per-pixel scalar block
 
 Blocks make_blocks(int W) {
   Blocks b;
   int r = 0;
   auto take = [&](int n) { int o = r; r += n; return o; };
   const int RW = rup(W + 1, 32);
-  b.xb = take(32);               // G 0..13, scene 14..29, ones 30
+  b.xb = take(32);                   // G 0..13, scene 14..29, ones 30
   b.a1 = take(RW);
   b.a2 = take(RW);
   b.st = take(rup(2 * W + 1, 32));   // sigma, tau, ones
-  b.zs = take(RW);               // Z / max(c,1), then the bias scale of h's last layer
+  b.u = take(W);
+  b.zs = take(RW);                   // pooled Z / max(c,1); row W: bias scale of T3
   b.d1 = take(RW);
   b.d2 = take(RW);
-  b.pl = take(rup(W + 4, 32));   // phi, L_d (3), ones
+  b.pl = take(rup(W + 4, 32));       // phi, L_d (3), ones
   b.g1 = take(RW);
   b.g2 = take(RW);
-  b.z1 = take(RW);               // slot i: z1, ones
-  b.bi = take(32);               // slot i: b_i (12), ones at 12
-  b.u = take(W);
-  b.cnt = take(1);
+  b.z1 = take(RW);                   // slot i: z1, ones
+  b.bi = take(32);                   // slot i: b_i (12), ones at 12
+  b.px = take(32);                   // 1/max(c,1) (mean) or 1; slot mask m_i
   b.dy = take(32);
   b.dg2 = take(W); b.dg1 = take(W); b.dphi = take(W); b.dd2 = take(W); b.dd1 = take(W);
-  b.dtau = take(W); b.dzin = take(W); b.du = take(W); b.dsig = take(W); b.da2 = take(W);
-  b.da1 = take(W); b.dz2 = take(W); b.dz1 = take(W);
+  b.dsig = take(W); b.dtau = take(W);    // adjacent: B1^T writes both at once
+  b.dzin = take(W); b.du = take(W); b.da2 = take(W); b.da1 = take(W);
+  b.dz2 = take(W); b.dz1 = take(W);
   b.rows = r;
   return b;
 }
 
-struct BwdArgs {
+// ---- weight fragments of the plane GEMMs ------------------------------------
+// Op o multiplies A (M x K) into planes.  A[m][k] = W[m][col0 + k] of a layer
+// (trans = 0) or W[k][col0 + m] (trans = 1, the backward maps).  Fragments are
+// stored [mt][q][lane] as f32x4: element j of lane l holds
+// A[16 mt + (l & 15)][16 q + 4 j + (l >> 4)], the operand lane l presents to
+// v_mfma_f32_16x16x4f32 in K-step 4q + j; zero outside M x K.  The group
+// count is even, so every input block has at least 32 * ceil(K / 32) rows
+// (zero rows beyond the data, or the ones row, meet zero weights).
+enum Op {
+  O_F1, O_F2, O_F3, O_T1S, O_T1A, O_T2, O_T3, O_B1, O_B2, O_B3, O_R1, O_R2,
+  O_R3T, O_R2T, O_R1T, O_B3T, O_B2T, O_B1T, O_T3T, O_T2T, O_T1ST, O_F3T, O_F2T, kNumOps
+};
+
+struct OpDesc {
+  int64_t woff;      // float offset of the layer's matrix in the master vector
+  int64_t off;       // f32x4 offset of the fragments
+  int32_t ld;        // the layer's input count (master row length)
+  int32_t trans, col0, M, K, mt, kq, pad;
+};
+
+struct OpTable {
+  OpDesc op[kNumOps];
+  int64_t total;     // f32x4 count
+};
+
+OpTable make_ops(int W) {
+  LayerOff lo[kNumLayers];
+  layer_offsets(W, lo);
+  struct S { Op o; Layer l; int trans, col0, M, K; };
+  const S s[kNumOps] = {
+      {O_F1, L_F1, 0, 0, W, kNG + kNS}, {O_F2, L_F2, 0, 0, W, W},  {O_F3, L_F3, 0, 0, W, W},
+      {O_T1S, L_T1, 0, kNL, W, W},      {O_T1A, L_T1, 0, 0, W, kNL}, {O_T2, L_T2, 0, 0, W, W},
+      {O_T3, L_T3, 0, 0, W, W},         {O_B1, L_B1, 0, 0, W, 2 * W}, {O_B2, L_B2, 0, 0, W, W},
+      {O_B3, L_B3, 0, 0, W, W},         {O_R1, L_R1, 0, 0, W, W + 3}, {O_R2, L_R2, 0, 0, W, W},
+      {O_R3T, L_R3, 1, 0, W, kNOUT},    {O_R2T, L_R2, 1, 0, W, W},  {O_R1T, L_R1, 1, 0, W, W},
+      {O_B3T, L_B3, 1, 0, W, W},        {O_B2T, L_B2, 1, 0, W, W},  {O_B1T, L_B1, 1, 0, 2 * W, W},
+      {O_T3T, L_T3, 1, 0, W, W},        {O_T2T, L_T2, 1, 0, W, W},  {O_T1ST, L_T1, 1, kNL, W, W},
+      {O_F3T, L_F3, 1, 0, W, W},        {O_F2T, L_F2, 1, 0, W, W}};
+  OpTable t;
+  int64_t off = 0;
+  for (int i = 0; i < kNumOps; ++i) {
+    OpDesc &d = t.op[s[i].o];
+    d.woff = lo[s[i].l].w;
+    d.ld = lo[s[i].l].in;
+    d.trans = s[i].trans;
+    d.col0 = s[i].col0;
+    d.M = s[i].M;
+    d.K = s[i].K;
+    d.mt = (d.M + 15) / 16;
+    d.kq = (d.K + 31) / 32 * 2;     // even: the GEMM consumes groups in pairs
+    d.pad = 0;
+    d.off = off;
+    off += (int64_t)d.mt * d.kq * 64;
+  }
+  t.total = off;
+  return t;
+}
+
+__global__ __launch_bounds__(kThreads) void pack_ops_kernel(const float *__restrict__ master,
+                                                            OpTable t, f32x4 *__restrict__ frag) {
+  const int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (e >= t.total) return;
+  int o = 0;
+  while (o + 1 < kNumOps && e >= t.op[o + 1].off) ++o;
+  const OpDesc d = t.op[o];
+  const int64_t r = e - d.off;
+  const int lane = (int)(r & 63);
+  const int64_t fq = r >> 6;
+  const int mt = (int)(fq / d.kq), q = (int)(fq % d.kq);
+  const int m = 16 * mt + (lane & 15);
+  f32x4 v;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int k = 16 * q + 4 * j + (lane >> 4);
+    float x = 0.0f;
+    if (m < d.M && k < d.K)
+      x = d.trans ? master[d.woff + (int64_t)k * d.ld + d.col0 + m]
+                  : master[d.woff + (int64_t)m * d.ld + d.col0 + k];
+    v[j] = x;
+  }
+  frag[e] = v;
+}
+
+// ---- the plane GEMM ----------------------------------------------------------
+// A wave owns 64 pixels and 16*MT rows.  Pixel tile t (0..3) of the wave
+// presents pixel p0 + 4n + t as MFMA column n, so lane l reads and writes four
+// consecutive pixels of a row (16-byte accesses, 256 contiguous bytes per 16
+// lanes) and holds, after the K loop, rows 16 mt + 4 (l >> 4) + r of them.
+enum { EP_FWD = 0, EP_DZ2 = 1, EP_BWD = 2 };
+
+struct PgArgs {
+  const f32x4 *frag;     // the op's fragments
+  int kq;                // 16-deep K groups
+  int64_t stride;        // plane row length
+  const float *x;        // first row of the input block
+  float *out;            // first output row
+  const float *bias;     // [M], or null
+  const float *bscale;   // per-pixel row multiplying the bias, or null
+  const float *add;      // block added to the result (EP_DZ2: the gradient selected)
+  const float *mask;     // block: result kept where mask > 0, or null
+  const float *pscale;   // per-pixel row multiplying the result, or null
+  const float *post;     // per-pixel row multiplying after accumulation, or null
+  float *out2;           // EP_BWD: second block that receives (or accumulates) the result
+  int relu, accumulate, accumulate2;
+};
+
+__device__ __forceinline__ f32x4 ld4(const float *p) { return *(const f32x4 *)p; }
+
+// Operand loads go through buffer resources: one 32-bit per-lane byte offset
+// plus a wave-uniform offset per row, instead of a 64-bit address per row.
+// Raw addressing over 4 GiB from the base; word 3 selects 32-bit data.
+typedef __amdgpu_buffer_rsrc_t rsrc_t;
+__device__ __forceinline__ rsrc_t make_rsrc(const void *base) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, -1, 0x00020000);
+}
+__device__ __forceinline__ f32x4 bld4(rsrc_t r, uint32_t voff, uint32_t soff) {
+  return __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
+}
+__device__ __forceinline__ void st4(float *p, f32x4 v) { *(f32x4 *)p = v; }
+
+template <int MT, int EP>
+__global__ __launch_bounds__(kThreads) void plane_gemm_kernel(PgArgs a) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int n = lane & 15, g = lane >> 4;
+  const int64_t pq = ((int64_t)blockIdx.x * 4 + wave) * 64 + 4 * n;
+  const int mt0 = blockIdx.y * MT;
+  const int64_t st = a.stride;
+  f32x4 acc[MT][4];
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+    for (int t = 0; t < 4; ++t) acc[mt][t] = f32x4{0.f, 0.f, 0.f, 0.f};
+  const uint32_t fstride = (uint32_t)a.kq * 64 * 16;        // bytes per fragment row
+  const uint32_t row = (uint32_t)st * 4;                      // bytes per plane row
+  const rsrc_t xr = make_rsrc(a.x), frr = make_rsrc(a.frag + (size_t)mt0 * a.kq * 64);
+  const uint32_t xoff = (uint32_t)(((size_t)g * st + pq) * 4), foff = (uint32_t)lane * 16;
+  // Two operand sets in flight: the loads of group q + 1 are issued before
+  // the MFMAs of group q (loads of a clamped group past the end are harmless
+  // re-reads).
+  f32x4 xa[4], wa[MT], xb[4], wb[MT];
+  auto load = [&](int q, f32x4 (&x)[4], f32x4 (&w)[MT]) {
+    q = q < a.kq ? q : a.kq - 1;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) x[j] = bld4(xr, xoff, (uint32_t)(16 * q + 4 * j) * row);
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) w[mt] = bld4(frr, foff, mt * fstride + (uint32_t)q * 1024);
+  };
+  auto mfma = [&](const f32x4 (&x)[4], const f32x4 (&w)[MT]) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+          acc[mt][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(w[mt][j], x[j][t], acc[mt][t], 0, 0, 0);
+  };
+  load(0, xa, wa);
+  // The scheduling barriers keep each group's loads ahead of the previous
+  // group's MFMAs (left alone, the scheduler sinks them next to their use).
+  for (int q = 0; q < a.kq; q += 2) {      // kq is even
+    load(q + 1, xb, wb);
+    __builtin_amdgcn_sched_barrier(0);
+    mfma(xa, wa);
+    __builtin_amdgcn_sched_barrier(0);
+    load(q + 2, xa, wa);
+    __builtin_amdgcn_sched_barrier(0);
+    mfma(xb, wb);
+    __builtin_amdgcn_sched_barrier(0);
+  }
+  const f32x4 one = {1.f, 1.f, 1.f, 1.f};
+  const f32x4 bsc = a.bscale ? ld4(a.bscale + pq) : one;
+  const f32x4 psc = a.pscale ? ld4(a.pscale + pq) : one;
+  const f32x4 pst = a.post ? ld4(a.post + pq) : one;
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int m = 16 * (mt0 + mt) + 4 * g + r;
+      const size_t ix = (size_t)m * st + pq;
+      f32x4 v = {acc[mt][0][r], acc[mt][1][r], acc[mt][2][r], acc[mt][3][r]};
+      if (EP == EP_FWD) {
+        if (a.bias) v += a.bias[m] * bsc;
+        if (a.add) v += ld4(a.add + ix);
+        if (a.relu) {
+#pragma unroll
+          for (int t = 0; t < 4; ++t) v[t] = fmaxf(v[t], 0.0f);
+        }
+        v *= psc;
+        if (a.accumulate) v += ld4(a.out + ix);
+        v *= pst;
+      } else if (EP == EP_DZ2) {
+        const f32x4 z = v + a.bias[m];
+        const f32x4 d = ld4(a.add + ix);
+#pragma unroll
+        for (int t = 0; t < 4; ++t) v[t] = z[t] > 0.0f ? psc[t] * d[t] : 0.0f;
+      } else {
+        v *= psc;
+        if (a.add) v += ld4(a.add + ix);
+        if (a.mask) {
+          const f32x4 mk = ld4(a.mask + ix);
+#pragma unroll
+          for (int t = 0; t < 4; ++t) v[t] = mk[t] > 0.0f ? v[t] : 0.0f;
+        }
+      }
+      st4(a.out + ix, v);
+      if (EP == EP_BWD && a.out2) {
+        if (a.accumulate2) v += ld4(a.out2 + ix);
+        st4(a.out2 + ix, v);
+      }
+    }
+}
+
+// ---- gathers into planes -------------------------------------------------------
+struct PrepArgs {
   const float *gbuf, *layers, *scene, *grad_out;
-  int hw, k, pool;
-  int64_t npx;
+  int hw, k, pool, W;
+  int64_t npx, stride;
   float *planes;
-  int stride;
   Blocks bl;
 };
 
-__device__ __forceinline__ void layer_offsets_dev(int W, LayerOff (&lo)[kNumLayers]) {
-  int64_t off = 0;
-  const int outs[kNumLayers] = {W, W, W, W, W, W, W, W, W, W, W, kNOUT};
-  const int ins[kNumLayers] = {kNG + kNS, W, W, kNL + W, W, W, 2 * W, W, W, W + 3, W, W};
-#pragma unroll
-  for (int l = 0; l < kNumLayers; ++l) {
-    lo[l].w = off;
-    off += (int64_t)outs[l] * ins[l];
-    lo[l].b = off;
-    off += outs[l];
-    lo[l].out = outs[l];
-    lo[l].in = ins[l];
-  }
-}
-
 #define ROW(r) (a.planes + (size_t)(r) * a.stride)
 
-// out rows = act(bias + W[:, col0:col0+NIN] . in rows), NOUT outputs.
-template <int NOUT, int NIN, bool RELU>
-__device__ __forceinline__ void fwd_layer(cfloat *wm, cfloat *wt, const LayerOff &lo, int col0,
-                                          const float *in, float *out, int stride, int p) {
-  for (int ob = 0; ob < NOUT; ob += kOB) {
-    float acc[kOB];
-#pragma unroll
-    for (int o = 0; o < kOB; ++o) acc[o] = wm[lo.b + ob + o];
-    acc_from_scratch<kOB, NIN>(acc, wt + lo.w, lo.out, ob, col0, in, stride, p);
-#pragma unroll
-    for (int o = 0; o < kOB; ++o) out[(size_t)(ob + o) * stride + p] = RELU ? relu(acc[o]) : acc[o];
-  }
-}
-
-// out rows i in [0, NI) = mask_i * scale * sum_o W[o][col0 + i] d[o]  (o < NO),
-// mask_i = [act_i > 0] when act != nullptr.  `init` rows are added if given.
-template <int NI, int NO>
-__device__ __forceinline__ void bwd_layer(cfloat *wm, const LayerOff &lo, int col0,
-                                          const float *d, float *out, const float *act,
-                                          const float *init, float scale, int stride, int p) {
-  for (int ib = 0; ib < NI; ib += kOB) {
-    float acc[kOB];
-#pragma unroll
-    for (int o = 0; o < kOB; ++o) acc[o] = 0.0f;
-    acc_from_scratch<kOB, NO>(acc, wm + lo.w, lo.in, col0 + ib, 0, d, stride, p);
-#pragma unroll
-    for (int o = 0; o < kOB; ++o) {
-      const size_t ix = (size_t)(ib + o) * stride + p;
-      float v = acc[o] * scale;
-      if (init) v += init[ix];
-      if (act) v = act[ix] > 0.0f ? v : 0.0f;
-      out[ix] = v;
-    }
-  }
-}
-
-// ---- 1. forward recompute, saving the planes -------------------------------
-template <int W>
-__global__ __launch_bounds__(kThreads) void fwd_save_kernel(const float *__restrict__ wm_,
-                                                            const float *__restrict__ wt_,
-                                                            BwdArgs a) {
-  cfloat *wm = (cfloat *)wm_;
-  cfloat *wt = (cfloat *)wt_;
-  LayerOff lo[kNumLayers];
-  layer_offsets_dev(W, lo);
-  const int p = blockIdx.x * kThreads + threadIdx.x;
-  const int64_t pc = p < a.npx ? p : a.npx - 1;
-  const int f = (int)(pc / a.hw), q = (int)(pc - (int64_t)f * a.hw), hw = a.hw, K = a.k;
-  const float *G = a.gbuf + (size_t)f * kNG * hw + q;
-  const float *S = a.scene + (size_t)f * kNS;
-  const float *Ls = a.layers + (size_t)f * K * kNL * hw + q;
-  const Blocks &B = a.bl;
-  const int st = a.stride;
-  {
-    float x[kNG + kNS];
-#pragma unroll
-    for (int c = 0; c < kNG; ++c) x[c] = G[(size_t)c * hw];
-#pragma unroll
-    for (int c = 0; c < kNS; ++c) x[kNG + c] = S[c];
-#pragma unroll
-    for (int c = 0; c < kNG + kNS; ++c) ROW(B.xb + c)[p] = x[c];
-    for (int ob = 0; ob < W; ob += kOB) {
-      float acc[kOB];
-#pragma unroll
-      for (int o = 0; o < kOB; ++o) acc[o] = wm[lo[L_F1].b + ob + o];
-      acc_from_regs<kOB, kNG + kNS>(acc, wt + lo[L_F1].w, W, ob, 0, x);
-#pragma unroll
-      for (int o = 0; o < kOB; ++o) ROW(B.a1 + ob + o)[p] = relu(acc[o]);
-    }
-  }
-  fwd_layer<W, W, true>(wm, wt, lo[L_F2], 0, ROW(B.a1), ROW(B.a2), st, p);
-  fwd_layer<W, W, false>(wm, wt, lo[L_F3], 0, ROW(B.a2), ROW(B.st), st, p);       // sigma
-  fwd_layer<W, W, false>(wm, wt, lo[L_T1], kNL, ROW(B.st), ROW(B.u), st, p);      // u
-  // slot loop: Z = sum_i m_i relu(A2 relu(W1b b_i + u) + c2); z1 goes through the z1 rows
-  float Z[W];
-#pragma unroll
-  for (int o = 0; o < W; ++o) Z[o] = 0.0f;
-  float cnt = 0.0f;
-  for (int i = 0; i < K; ++i) {
-    float bi[kNL];
-#pragma unroll
-    for (int c = 0; c < kNL; ++c) bi[c] = Ls[((size_t)i * kNL + c) * hw];
-    const float m = bi[kAlpha] > 0.0f ? 1.0f : 0.0f;
-    for (int ob = 0; ob < W; ob += kOB) {
-      float acc[kOB];
-#pragma unroll
-      for (int o = 0; o < kOB; ++o) acc[o] = ROW(B.u + ob + o)[p];
-      acc_from_regs<kOB, kNL>(acc, wt + lo[L_T1].w, lo[L_T1].out, ob, 0, bi);
-#pragma unroll
-      for (int o = 0; o < kOB; ++o) ROW(B.z1 + ob + o)[p] = relu(acc[o]);
-    }
-#pragma unroll
-    for (int ob = 0; ob < W; ob += kOB) {
-      float acc[kOB];
-#pragma unroll
-      for (int o = 0; o < kOB; ++o) acc[o] = wm[lo[L_T2].b + ob + o];
-      acc_from_scratch<kOB, W>(acc, wt + lo[L_T2].w, W, ob, 0, ROW(B.z1), st, p);
-#pragma unroll
-      for (int o = 0; o < kOB; ++o) Z[ob + o] = fmaf(m, relu(acc[o]), Z[ob + o]);
-    }
-    cnt += m;
-  }
-  const bool mean = a.pool == GN_POOL_MEAN;
-  const float inv = mean ? 1.0f / fmaxf(cnt, 1.0f) : 1.0f;
-  const float bs = mean ? (cnt > 0.0f ? 1.0f : 0.0f) : cnt;
-#pragma unroll
-  for (int o = 0; o < W; ++o) ROW(B.zs + o)[p] = Z[o] * inv;
-  ROW(B.zs + W)[p] = bs;
-  ROW(B.cnt)[p] = cnt;
-  for (int ob = 0; ob < W; ob += kOB) {                                            // tau
-    float acc[kOB];
-#pragma unroll
-    for (int o = 0; o < kOB; ++o) acc[o] = bs * wm[lo[L_T3].b + ob + o];
-    acc_from_scratch<kOB, W>(acc, wt + lo[L_T3].w, W, ob, 0, ROW(B.zs), st, p);
-#pragma unroll
-    for (int o = 0; o < kOB; ++o) ROW(B.st + W + ob + o)[p] = acc[o];
-  }
-  fwd_layer<W, 2 * W, true>(wm, wt, lo[L_B1], 0, ROW(B.st), ROW(B.d1), st, p);
-  fwd_layer<W, W, true>(wm, wt, lo[L_B2], 0, ROW(B.d1), ROW(B.d2), st, p);
-  fwd_layer<W, W, false>(wm, wt, lo[L_B3], 0, ROW(B.d2), ROW(B.pl), st, p);       // phi
-#pragma unroll
-  for (int c = 0; c < 3; ++c) ROW(B.pl + W + c)[p] = G[(size_t)(11 + c) * hw];   // L_d
-  for (int ob = 0; ob < W; ob += kOB) {
-    float acc[kOB];
-    float ld[3];
-#pragma unroll
-    for (int c = 0; c < 3; ++c) ld[c] = ROW(B.pl + W + c)[p];
-#pragma unroll
-    for (int o = 0; o < kOB; ++o) acc[o] = wm[lo[L_R1].b + ob + o];
-    acc_from_scratch<kOB, W>(acc, wt + lo[L_R1].w, W, ob, 0, ROW(B.pl), st, p);
-    acc_from_regs<kOB, 3>(acc, wt + lo[L_R1].w, W, ob, W, ld);
-#pragma unroll
-    for (int o = 0; o < kOB; ++o) ROW(B.g1 + ob + o)[p] = relu(acc[o]);
-  }
-  fwd_layer<W, W, true>(wm, wt, lo[L_R2], 0, ROW(B.g1), ROW(B.g2), st, p);
-}
-
-// ---- 2. head: dy -> R -> B -> dsigma_B, dtau -> dZ ---------------------------
-template <int W>
-__global__ __launch_bounds__(kThreads) void head_kernel(const float *__restrict__ wm_, BwdArgs a) {
-  cfloat *wm = (cfloat *)wm_;
-  LayerOff lo[kNumLayers];
-  layer_offsets_dev(W, lo);
-  const int p = blockIdx.x * kThreads + threadIdx.x;
+// G and the scene vector (F's input), L_d (R's), the mean's 1/max(c,1), T3's
+// bias scale and dL/dy.  Padding pixels repeat the last pixel with dL/dy = 0,
+// so every gradient they could carry is zero.
+__global__ __launch_bounds__(kThreads) void prep_kernel(PrepArgs a) {
+  const int64_t p = (int64_t)blockIdx.x * kThreads + threadIdx.x;
   const bool valid = p < a.npx;
   const int64_t pc = valid ? p : a.npx - 1;
-  const int f = (int)(pc / a.hw), q = (int)(pc - (int64_t)f * a.hw);
+  const int f = (int)(pc / a.hw), q = (int)(pc - (int64_t)f * a.hw), hw = a.hw, W = a.W;
+  const float *G = a.gbuf + (size_t)f * kNG * hw + q;
   const Blocks &B = a.bl;
-  const int st = a.stride;
-  float dy[kNOUT];
-#pragma unroll
-  for (int c = 0; c < kNOUT; ++c) {
-    dy[c] = valid ? a.grad_out[((size_t)f * kNOUT + c) * a.hw + q] : 0.0f;  // pad pixels: 0
-    ROW(B.dy + c)[p] = dy[c];
-  }
-  for (int ib = 0; ib < W; ib += kOB) {                                          // R3^T
-    float acc[kOB];
-#pragma unroll
-    for (int o = 0; o < kOB; ++o) acc[o] = 0.0f;
-    acc_from_regs<kOB, kNOUT>(acc, wm + lo[L_R3].w, W, ib, 0, dy);
-#pragma unroll
-    for (int o = 0; o < kOB; ++o)
-      ROW(B.dg2 + ib + o)[p] = ROW(B.g2 + ib + o)[p] > 0.0f ? acc[o] : 0.0f;
-  }
-  bwd_layer<W, W>(wm, lo[L_R2], 0, ROW(B.dg2), ROW(B.dg1), ROW(B.g1), nullptr, 1.0f, st, p);
-  bwd_layer<W, W>(wm, lo[L_R1], 0, ROW(B.dg1), ROW(B.dphi), nullptr, nullptr, 1.0f, st, p);
-  bwd_layer<W, W>(wm, lo[L_B3], 0, ROW(B.dphi), ROW(B.dd2), ROW(B.d2), nullptr, 1.0f, st, p);
-  bwd_layer<W, W>(wm, lo[L_B2], 0, ROW(B.dd2), ROW(B.dd1), ROW(B.d1), nullptr, 1.0f, st, p);
-  bwd_layer<W, W>(wm, lo[L_B1], 0, ROW(B.dd1), ROW(B.dsig), nullptr, nullptr, 1.0f, st, p);
-  bwd_layer<W, W>(wm, lo[L_B1], W, ROW(B.dd1), ROW(B.dtau), nullptr, nullptr, 1.0f, st, p);
-  const float c = ROW(B.cnt)[p];
-  const float inv = a.pool == GN_POOL_MEAN ? 1.0f / fmaxf(c, 1.0f) : 1.0f;
-  bwd_layer<W, W>(wm, lo[L_T3], 0, ROW(B.dtau), ROW(B.dzin), nullptr, nullptr, inv, st, p);
+  for (int c = 0; c < kNG; ++c) ROW(B.xb + c)[p] = G[(size_t)c * hw];
+  for (int c = 0; c < kNS; ++c) ROW(B.xb + kNG + c)[p] = a.scene[(size_t)f * kNS + c];
+  for (int c = 0; c < 3; ++c) ROW(B.pl + W + c)[p] = G[(size_t)(11 + c) * hw];
+  float cnt = 0.0f;
+  const float *Lf = a.layers + (size_t)f * a.k * kNL * hw + q;
+  for (int i = 0; i < a.k; ++i) cnt += Lf[((size_t)i * kNL + kAlpha) * hw] > 0.0f ? 1.0f : 0.0f;
+  const bool mean = a.pool == GN_POOL_MEAN;
+  ROW(B.px + PX_INV)[p] = mean ? 1.0f / fmaxf(cnt, 1.0f) : 1.0f;
+  ROW(B.zs + W)[p] = mean ? (cnt > 0.0f ? 1.0f : 0.0f) : cnt;
+  for (int c = 0; c < kNOUT; ++c)
+    ROW(B.dy + c)[p] = valid ? a.grad_out[((size_t)f * kNOUT + c) * hw + q] : 0.0f;
 }
 
-// ---- 3. one slot: recompute h's layers 1-2, backprop, accumulate du --------
-template <int W>
-__global__ __launch_bounds__(kThreads) void slot_kernel(const float *__restrict__ wm_,
-                                                        const float *__restrict__ wt_, BwdArgs a,
-                                                        int slot, int first) {
-  cfloat *wm = (cfloat *)wm_;
-  cfloat *wt = (cfloat *)wt_;
-  LayerOff lo[kNumLayers];
-  layer_offsets_dev(W, lo);
-  const int p = blockIdx.x * kThreads + threadIdx.x;
+// Slot i's 12 channels and its mask m_i = [alpha > 0].
+__global__ __launch_bounds__(kThreads) void slot_gather_kernel(PrepArgs a, int slot) {
+  const int64_t p = (int64_t)blockIdx.x * kThreads + threadIdx.x;
   const int64_t pc = p < a.npx ? p : a.npx - 1;
   const int f = (int)(pc / a.hw), q = (int)(pc - (int64_t)f * a.hw), hw = a.hw;
-  const Blocks &B = a.bl;
-  const int st = a.stride;
   const float *Li = a.layers + ((size_t)f * a.k + slot) * kNL * hw + q;
-  float bi[kNL];
-#pragma unroll
-  for (int c = 0; c < kNL; ++c) {
-    bi[c] = Li[(size_t)c * hw];
-    ROW(B.bi + c)[p] = bi[c];
-  }
-  const float m = bi[kAlpha] > 0.0f ? 1.0f : 0.0f;
-  for (int ob = 0; ob < W; ob += kOB) {                                          // z1
-    float acc[kOB];
-#pragma unroll
-    for (int o = 0; o < kOB; ++o) acc[o] = ROW(B.u + ob + o)[p];
-    acc_from_regs<kOB, kNL>(acc, wt + lo[L_T1].w, lo[L_T1].out, ob, 0, bi);
-#pragma unroll
-    for (int o = 0; o < kOB; ++o) ROW(B.z1 + ob + o)[p] = relu(acc[o]);
-  }
-  for (int ob = 0; ob < W; ob += kOB) {                                          // dz2
-    float acc[kOB];
-#pragma unroll
-    for (int o = 0; o < kOB; ++o) acc[o] = wm[lo[L_T2].b + ob + o];
-    acc_from_scratch<kOB, W>(acc, wt + lo[L_T2].w, W, ob, 0, ROW(B.z1), st, p);
-#pragma unroll
-    for (int o = 0; o < kOB; ++o)
-      ROW(B.dz2 + ob + o)[p] = acc[o] > 0.0f ? m * ROW(B.dzin + ob + o)[p] : 0.0f;
-  }
-  for (int ib = 0; ib < W; ib += kOB) {                                          // dz1, du
-    float acc[kOB];
-#pragma unroll
-    for (int o = 0; o < kOB; ++o) acc[o] = 0.0f;
-    acc_from_scratch<kOB, W>(acc, wm + lo[L_T2].w, W, ib, 0, ROW(B.dz2), st, p);
-#pragma unroll
-    for (int o = 0; o < kOB; ++o) {
-      const float v = ROW(B.z1 + ib + o)[p] > 0.0f ? acc[o] : 0.0f;
-      ROW(B.dz1 + ib + o)[p] = v;
-      float *du = ROW(B.du + ib + o) + p;
-      *du = first ? v : *du + v;
-    }
-  }
-}
-
-// ---- 4. tail: dsigma += A1s^T du, then F ------------------------------------
-template <int W>
-__global__ __launch_bounds__(kThreads) void tail_kernel(const float *__restrict__ wm_, BwdArgs a,
-                                                        int have_slots) {
-  cfloat *wm = (cfloat *)wm_;
-  LayerOff lo[kNumLayers];
-  layer_offsets_dev(W, lo);
-  const int p = blockIdx.x * kThreads + threadIdx.x;
   const Blocks &B = a.bl;
-  const int st = a.stride;
-  if (have_slots)
-    bwd_layer<W, W>(wm, lo[L_T1], kNL, ROW(B.du), ROW(B.dsig), nullptr, ROW(B.dsig), 1.0f, st, p);
-  bwd_layer<W, W>(wm, lo[L_F3], 0, ROW(B.dsig), ROW(B.da2), ROW(B.a2), nullptr, 1.0f, st, p);
-  bwd_layer<W, W>(wm, lo[L_F2], 0, ROW(B.da2), ROW(B.da1), ROW(B.a1), nullptr, 1.0f, st, p);
+  for (int c = 0; c < kNL; ++c) ROW(B.bi + c)[p] = Li[(size_t)c * hw];
+  ROW(B.px + PX_M)[p] = Li[(size_t)kAlpha * hw] > 0.0f ? 1.0f : 0.0f;
 }
 
-// ---- 5. weight gradients: sum over pixels on the fp32 matrix cores ---------
-typedef float f32x4 __attribute__((ext_vector_type(4)));
+#undef ROW
 
-// part[chunk][o][i] (+)= sum_{p in chunk} D[o][p] * A[i][p] for a 32 x 32 tile
-// per wave.  Lane l feeds row (l & 15) and pixels 4 (l >> 4) + j of each
-// 16-pixel step to both operands, so every pixel meets itself exactly once.
-__global__ __launch_bounds__(64) void dw_gemm_kernel(const float *__restrict__ D,
-                                                     const float *__restrict__ A, int stride,
-                                                     int64_t npx_pad, float *__restrict__ part,
-                                                     int o_pad, int i_pad, int accumulate) {
-  const int lane = threadIdx.x;
-  const int i0 = blockIdx.x * 32, o0 = blockIdx.y * 32, chunk = blockIdx.z;
+// ---- weight gradients: sums over pixels on the fp32 matrix cores -----------
+// part[chunk][o][i] (+)= sum_{p in chunk} D[o][p] A[i][p] for the
+// (16 MO) x (16 MI) tile (blockIdx.y, blockIdx.x).  Lane l feeds row (l & 15)
+// and pixels 4 (l >> 4) + j of a 16-pixel step to both operands, so every
+// pixel meets itself exactly once.  The four waves of a workgroup take
+// interleaved 16-pixel steps of the chunk and are summed in LDS in a fixed
+// order (deterministic).
+template <int MO, int MI>
+__global__ __launch_bounds__(kThreads) void dw_gemm_kernel(const float *__restrict__ D,
+                                                           const float *__restrict__ A,
+                                                           int64_t stride, float *__restrict__ part,
+                                                           int o_pad, int i_pad, int accumulate) {
+  __shared__ f32x4 red[3][MO * MI][64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int r = lane & 15, kq = lane >> 4;
-  const int64_t p_begin = (int64_t)chunk * kChunkPx;
-  const int64_t p_end = std::min<int64_t>(p_begin + kChunkPx, npx_pad);
-  f32x4 acc[2][2];
+  const int i0 = blockIdx.x * 16 * MI, o0 = blockIdx.y * 16 * MO, chunk = blockIdx.z;
+  f32x4 acc[MO][MI];
 #pragma unroll
-  for (int mi = 0; mi < 2; ++mi)
+  for (int mo = 0; mo < MO; ++mo)
 #pragma unroll
-    for (int ni = 0; ni < 2; ++ni) acc[mi][ni] = f32x4{0.f, 0.f, 0.f, 0.f};
-  const float *d0 = D + (size_t)(o0 + r) * stride + 4 * kq;
-  const float *d1 = d0 + (size_t)16 * stride;
-  const float *a0 = A + (size_t)(i0 + r) * stride + 4 * kq;
-  const float *a1 = a0 + (size_t)16 * stride;
-  for (int64_t p = p_begin; p < p_end; p += 16) {
-    const f32x4 da = *(const f32x4 *)(d0 + p), db = *(const f32x4 *)(d1 + p);
-    const f32x4 aa = *(const f32x4 *)(a0 + p), ab = *(const f32x4 *)(a1 + p);
+    for (int mi = 0; mi < MI; ++mi) acc[mo][mi] = f32x4{0.f, 0.f, 0.f, 0.f};
+  const int64_t pbase = (int64_t)chunk * kChunkPx + 16 * wave + 4 * kq;
+  const rsrc_t dr = make_rsrc(D + (size_t)o0 * stride), ar = make_rsrc(A + (size_t)i0 * stride);
+  const uint32_t voff = (uint32_t)(((size_t)r * stride + pbase) * 4);
+  const uint32_t row16 = (uint32_t)stride * 64;               // bytes of 16 plane rows
+  f32x4 da[MO], aa[MI], db[MO], ab[MI];
+  auto load = [&](int s, f32x4 (&d)[MO], f32x4 (&x)[MI]) {
+    s = s < kChunkPx / 64 ? s : kChunkPx / 64 - 1;
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      acc[0][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(da[j], aa[j], acc[0][0], 0, 0, 0);
-      acc[0][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(da[j], ab[j], acc[0][1], 0, 0, 0);
-      acc[1][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(db[j], aa[j], acc[1][0], 0, 0, 0);
-      acc[1][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(db[j], ab[j], acc[1][1], 0, 0, 0);
-    }
+    for (int mo = 0; mo < MO; ++mo) d[mo] = bld4(dr, voff, mo * row16 + 256 * s);
+#pragma unroll
+    for (int mi = 0; mi < MI; ++mi) x[mi] = bld4(ar, voff, mi * row16 + 256 * s);
+  };
+  auto mfma = [&](const f32x4 (&d)[MO], const f32x4 (&x)[MI]) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int mo = 0; mo < MO; ++mo)
+#pragma unroll
+        for (int mi = 0; mi < MI; ++mi)
+          acc[mo][mi] = __builtin_amdgcn_mfma_f32_16x16x4f32(d[mo][j], x[mi][j], acc[mo][mi], 0, 0, 0);
+  };
+  load(0, da, aa);
+  for (int s = 0; s < kChunkPx / 64; s += 2) {
+    load(s + 1, db, ab);
+    __builtin_amdgcn_sched_barrier(0);
+    mfma(da, aa);
+    __builtin_amdgcn_sched_barrier(0);
+    load(s + 2, da, aa);
+    __builtin_amdgcn_sched_barrier(0);
+    mfma(db, ab);
+    __builtin_amdgcn_sched_barrier(0);
   }
+  if (wave > 0) {
+#pragma unroll
+    for (int mo = 0; mo < MO; ++mo)
+#pragma unroll
+      for (int mi = 0; mi < MI; ++mi) red[wave - 1][mo * MI + mi][lane] = acc[mo][mi];
+  }
+  __syncthreads();
+  if (wave != 0) return;
+#pragma unroll
+  for (int w = 0; w < 3; ++w)
+#pragma unroll
+    for (int mo = 0; mo < MO; ++mo) {
+#pragma unroll
+      for (int mi = 0; mi < MI; ++mi) acc[mo][mi] += red[w][mo * MI + mi][lane];
+      __builtin_amdgcn_sched_barrier(0);     // bounds the LDS reads in flight
+    }
   float *P = part + (size_t)chunk * o_pad * i_pad;
 #pragma unroll
-  for (int mi = 0; mi < 2; ++mi)
+  for (int mo = 0; mo < MO; ++mo)
 #pragma unroll
-    for (int ni = 0; ni < 2; ++ni)
+    for (int mi = 0; mi < MI; ++mi)
 #pragma unroll
       for (int rr = 0; rr < 4; ++rr) {
-        const int o = o0 + 16 * mi + 4 * kq + rr, i = i0 + 16 * ni + r;
+        const int o = o0 + 16 * mo + 4 * kq + rr, i = i0 + 16 * mi + r;
         float *dst = P + (size_t)o * i_pad + i;
-        *dst = accumulate ? *dst + acc[mi][ni][rr] : acc[mi][ni][rr];
+        *dst = accumulate ? *dst + acc[mo][mi][rr] : acc[mo][mi][rr];
       }
 }
 
@@ -419,10 +452,9 @@ __global__ void dw_reduce_kernel(const float *__restrict__ part, int nchunks, in
     gw[lo.b + o] = s;
 }
 
-__global__ void fill_rows_kernel(float *rows, int stride, int64_t n, float v) {
+__global__ void fill_kernel(float *dst, int64_t n, float v) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e < n) rows[e] = v;
-  (void)stride;
+  if (e < n) dst[e] = v;
 }
 
 }  // namespace
@@ -434,6 +466,7 @@ using namespace gn;
 void gn_bwd_free(gn_handle *h) {
   if (!h->bwd) return;
   (void)hipFree(h->bwd->planes);
+  (void)hipFree(h->bwd->frag);
   (void)hipFree(h->bwd->part);
   (void)hipFree(h->bwd->part_t2);
   (void)hipFree(h->bwd->part_t1);
@@ -443,7 +476,8 @@ void gn_bwd_free(gn_handle *h) {
 
 size_t gn_bwd_bytes(gn_handle *h) {
   if (!h->bwd) return 0;
-  return h->bwd->plane_bytes + h->bwd->part_bytes + h->bwd->part_t2_bytes + h->bwd->part_t1_bytes;
+  return h->bwd->plane_bytes + h->bwd->frag_bytes + h->bwd->part_bytes + h->bwd->part_t2_bytes +
+         h->bwd->part_t1_bytes;
 }
 
 static hipError_t ensure_workspace(gn_handle *h, int64_t npx_pad) {
@@ -453,38 +487,43 @@ static hipError_t ensure_workspace(gn_handle *h, int64_t npx_pad) {
   ws = new BwdWorkspace();
   h->bwd = ws;
   const Blocks bl = make_blocks(h->W);
+  const OpTable ops = make_ops(h->W);
   ws->W = h->W;
   ws->cap_px = npx_pad;
   ws->plane_bytes = sizeof(float) * (size_t)bl.rows * npx_pad;
+  ws->frag_bytes = sizeof(f32x4) * (size_t)ops.total;
   ws->max_chunks = (int)((npx_pad + kChunkPx - 1) / kChunkPx);
   const int W = h->W;
   ws->part_bytes = sizeof(float) * (size_t)ws->max_chunks * W * rup(2 * W + 1, 32);
   ws->part_t2_bytes = sizeof(float) * (size_t)ws->max_chunks * W * rup(W + 1, 32);
   ws->part_t1_bytes = sizeof(float) * (size_t)ws->max_chunks * W * 32;
   hipError_t e = hipMalloc((void **)&ws->planes, ws->plane_bytes);
+  if (e == hipSuccess) e = hipMalloc((void **)&ws->frag, ws->frag_bytes);
   if (e == hipSuccess) e = hipMalloc((void **)&ws->part, ws->part_bytes);
   if (e == hipSuccess) e = hipMalloc((void **)&ws->part_t2, ws->part_t2_bytes);
   if (e == hipSuccess) e = hipMalloc((void **)&ws->part_t1, ws->part_t1_bytes);
-  if (e == hipSuccess) e = hipMemset(ws->planes, 0, ws->plane_bytes);
   if (e != hipSuccess) gn_bwd_free(h);
   return e;
 }
 
-// Rows of ones (bias gradients) for a given plane row length.
+static hipError_t fill(float *dst, int64_t n, float v, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(fill_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, dst, n, v);
+  return hipGetLastError();
+}
+
+// Zero every plane (padding rows are read as zero K rows by the GEMMs) and
+// write the rows of ones, for a given plane row length.
 static hipError_t init_constant_rows(gn_handle *h, int64_t stride, hipStream_t s) {
   BwdWorkspace *ws = h->bwd;
   if (ws->stride == stride) return hipSuccess;
   const Blocks bl = make_blocks(h->W);
   const int W = h->W;
-  hipError_t e = hipMemsetAsync(ws->planes, 0, ws->plane_bytes, s);
+  hipError_t e = fill(ws->planes, (int64_t)bl.rows * stride, 0.0f, s);
   const int ones[] = {bl.xb + kNG + kNS, bl.a1 + W, bl.a2 + W, bl.st + 2 * W, bl.d1 + W,
                       bl.d2 + W, bl.pl + W + 3, bl.g1 + W, bl.g2 + W, bl.z1 + W, bl.bi + kNL};
-  for (int r : ones) {
-    if (e != hipSuccess) break;
-    hipLaunchKernelGGL(fill_rows_kernel, dim3((unsigned)((stride + 255) / 256)), dim3(256), 0, s,
-                       ws->planes + (size_t)r * stride, (int)stride, stride, 1.0f);
-    e = hipGetLastError();
-  }
+  for (int r : ones)
+    if (e == hipSuccess) e = fill(ws->planes + (size_t)r * stride, stride, 1.0f, s);
   if (e == hipSuccess) ws->stride = stride;
   return e;
 }
@@ -511,6 +550,10 @@ extern "C" gn_status glassnet_backward(gn_handle *h, const gn_frame *frame,
   const int64_t hw = (int64_t)frame->h * frame->w;
   const int64_t npx = (int64_t)frame->n * hw;
   const int64_t npx_pad = (npx + kChunkPx - 1) / kChunkPx * kChunkPx;
+  if (npx_pad > kMaxPx) {
+    if (prev >= 0) (void)hipSetDevice(prev);
+    return gn_set_error(GN_E_INVAL, "backward: more than 3 * 2^20 pixels in one call");
+  }
   hipError_t e = ensure_workspace(h, npx_pad);
   if (e == hipSuccess) e = init_constant_rows(h, npx_pad, s);
   if (e != hipSuccess) {
@@ -519,70 +562,175 @@ extern "C" gn_status glassnet_backward(gn_handle *h, const gn_frame *frame,
   }
   BwdWorkspace *ws = h->bwd;
   const Blocks bl = make_blocks(W);
-  BwdArgs a;
-  a.gbuf = frame->gbuf;
-  a.layers = frame->layers;
-  a.scene = frame->scene;
-  a.grad_out = grad_out;
-  a.hw = (int)hw;
-  a.k = frame->k;
-  a.pool = h->cfg.pool;
-  a.npx = npx;
-  a.planes = ws->planes;
-  a.stride = (int)npx_pad;
-  a.bl = bl;
-  const dim3 grid((unsigned)(npx_pad / kThreads)), block(kThreads);
-  const float *wm = h->d_master, *wt = h->d_master_t;
+  const OpTable ops = make_ops(W);
+  const float *wm = h->d_master;
   LayerOff lo[kNumLayers];
   layer_offsets(W, lo);
-  const int nchunks = (int)(npx_pad / kChunkPx);
+  const int K = frame->k;
+  const bool mean = h->cfg.pool == GN_POOL_MEAN;
   auto plane = [&](int r) { return ws->planes + (size_t)r * npx_pad; };
-  auto gemm = [&](const GemmJob &j, float *part, int accumulate) {
-    hipLaunchKernelGGL(dw_gemm_kernel, dim3(j.i_pad / 32, j.o_pad / 32, nchunks), dim3(64), 0, s,
-                       plane(j.dblock), plane(j.ablock), (int)npx_pad, npx_pad, part, j.o_pad,
-                       j.i_pad, accumulate);
+
+  PrepArgs pa;
+  pa.gbuf = frame->gbuf;
+  pa.layers = frame->layers;
+  pa.scene = frame->scene;
+  pa.grad_out = grad_out;
+  pa.hw = (int)hw;
+  pa.k = K;
+  pa.pool = h->cfg.pool;
+  pa.W = W;
+  pa.npx = npx;
+  pa.stride = npx_pad;
+  pa.planes = ws->planes;
+  pa.bl = bl;
+  const dim3 pgrid((unsigned)(npx_pad / kThreads)), block(kThreads);
+
+  hipLaunchKernelGGL(pack_ops_kernel, dim3((unsigned)((ops.total + kThreads - 1) / kThreads)),
+                     block, 0, s, wm, ops, ws->frag);
+  hipLaunchKernelGGL(prep_kernel, pgrid, block, 0, s, pa);
+
+  // One plane GEMM: op `o` from block `xrow` into block `orow`.
+  auto gemm = [&](Op o, int ep, int xrow, int orow, PgArgs a) {
+    const OpDesc &d = ops.op[o];
+    a.frag = ws->frag + d.off;
+    a.kq = d.kq;
+    a.stride = npx_pad;
+    a.x = plane(xrow);
+    a.out = plane(orow);
+    const int mtl = d.mt >= 8 ? 8 : 4;
+    const dim3 grid((unsigned)(npx_pad / kThreads), (unsigned)(d.mt / mtl));
+#define PG(MT, EP) hipLaunchKernelGGL((plane_gemm_kernel<MT, EP>), grid, block, 0, s, a)
+    if (mtl == 8) {
+      if (ep == EP_FWD) PG(8, EP_FWD); else if (ep == EP_DZ2) PG(8, EP_DZ2); else PG(8, EP_BWD);
+    } else {
+      if (ep == EP_FWD) PG(4, EP_FWD); else if (ep == EP_DZ2) PG(4, EP_DZ2); else PG(4, EP_BWD);
+    }
+#undef PG
   };
-  auto reduce = [&](const GemmJob &j, const float *part) {
+  auto args = []() { PgArgs a; memset(&a, 0, sizeof a); return a; };
+  auto fwd = [&](Op o, int xrow, int orow, Layer l, bool relu) {
+    PgArgs a = args();
+    a.bias = wm + lo[l].b;
+    a.relu = relu;
+    gemm(o, EP_FWD, xrow, orow, a);
+  };
+  auto bwd = [&](Op o, int xrow, int orow, int maskrow) {
+    PgArgs a = args();
+    if (maskrow >= 0) a.mask = plane(maskrow);
+    gemm(o, EP_BWD, xrow, orow, a);
+  };
+  auto z1 = [&]() {                                  // z1_i = relu(W_T1,b b_i + u)
+    PgArgs a = args();
+    a.add = plane(bl.u);
+    a.relu = 1;
+    gemm(O_T1A, EP_FWD, bl.bi, bl.z1, a);
+  };
+
+  // ---- forward recompute
+  fwd(O_F1, bl.xb, bl.a1, L_F1, true);
+  fwd(O_F2, bl.a1, bl.a2, L_F2, true);
+  fwd(O_F3, bl.a2, bl.st, L_F3, false);                     // sigma
+  fwd(O_T1S, bl.st, bl.u, L_T1, false);                     // u
+  for (int i = 0; i < K; ++i) {
+    hipLaunchKernelGGL(slot_gather_kernel, pgrid, block, 0, s, pa, i);
+    z1();
+    PgArgs a = args();                                      // Z (+)= m_i relu(W_T2 z1 + b)
+    a.bias = wm + lo[L_T2].b;
+    a.relu = 1;
+    a.pscale = plane(bl.px + PX_M);
+    a.accumulate = i > 0;
+    if (i == K - 1 && mean) a.post = plane(bl.px + PX_INV);
+    gemm(O_T2, EP_FWD, bl.z1, bl.zs, a);
+  }
+  if (K == 0 && e == hipSuccess) e = fill(plane(bl.zs), (int64_t)W * npx_pad, 0.0f, s);
+  {
+    PgArgs a = args();                                      // tau = W_T3 zs + bs b_T3
+    a.bias = wm + lo[L_T3].b;
+    a.bscale = plane(bl.zs + W);
+    gemm(O_T3, EP_FWD, bl.zs, bl.st + W, a);
+  }
+  fwd(O_B1, bl.st, bl.d1, L_B1, true);
+  fwd(O_B2, bl.d1, bl.d2, L_B2, true);
+  fwd(O_B3, bl.d2, bl.pl, L_B3, false);                     // phi
+  fwd(O_R1, bl.pl, bl.g1, L_R1, true);
+  fwd(O_R2, bl.g1, bl.g2, L_R2, true);
+
+  // ---- head
+  bwd(O_R3T, bl.dy, bl.dg2, bl.g2);
+  bwd(O_R2T, bl.dg2, bl.dg1, bl.g1);
+  bwd(O_R1T, bl.dg1, bl.dphi, -1);
+  bwd(O_B3T, bl.dphi, bl.dd2, bl.d2);
+  bwd(O_B2T, bl.dd2, bl.dd1, bl.d1);
+  bwd(O_B1T, bl.dd1, bl.dsig, -1);                          // dsigma_B and dtau
+  {
+    PgArgs a = args();                                      // dZ = W_T3^T dtau / max(c,1)
+    if (mean) a.pscale = plane(bl.px + PX_INV);
+    gemm(O_T3T, EP_BWD, bl.dtau, bl.dzin, a);
+  }
+
+  // ---- slot loop
+  const int nchunks = (int)(npx_pad / kChunkPx);
+  auto dw_gemm = [&](const GemmJob &j, float *part, int accumulate) {
+    // tile: 16 MO output rows x 16 MI input rows, dividing o_pad and i_pad
+    const int mo = j.o_pad % 64 == 0 ? 4 : 2;
+    const int ti = j.i_pad / 16;
+    const int mi = ti % 6 == 0 ? 6 : ti % 5 == 0 ? 5 : ti % 4 == 0 ? 4 : 2;
+    const dim3 grid((unsigned)(ti / mi), (unsigned)(j.o_pad / (16 * mo)), (unsigned)nchunks);
+    const float *D = plane(j.dblock), *Ap = plane(j.ablock);
+#define DW(MO, MI)                                                                              \
+  hipLaunchKernelGGL((dw_gemm_kernel<MO, MI>), grid, block, 0, s, D, Ap, npx_pad, part, j.o_pad, \
+                     j.i_pad, accumulate)
+    if (mo == 4) {
+      if (mi == 6) DW(4, 6); else if (mi == 5) DW(4, 5); else if (mi == 4) DW(4, 4); else DW(4, 2);
+    } else {
+      if (mi == 6) DW(2, 6); else if (mi == 5) DW(2, 5); else if (mi == 4) DW(2, 4); else DW(2, 2);
+    }
+#undef DW
+  };
+  auto reduce = [&](const GemmJob &j, const float *part, int nch) {
     const int n = j.n_out * (j.n_in + (j.has_bias ? 1 : 0));
-    hipLaunchKernelGGL(dw_reduce_kernel, dim3((n + 255) / 256), dim3(256), 0, s, part, nchunks,
+    hipLaunchKernelGGL(dw_reduce_kernel, dim3((n + 255) / 256), dim3(256), 0, s, part, nch,
                        j.o_pad, j.i_pad, j.n_out, j.n_in, j.has_bias, grad_w, lo[j.layer], j.col0);
   };
   const int RW = rup(W + 1, 32);
-
-  if (W == 64) {
-    hipLaunchKernelGGL(fwd_save_kernel<64>, grid, block, 0, s, wm, wt, a);
-    hipLaunchKernelGGL(head_kernel<64>, grid, block, 0, s, wm, a);
-  } else {
-    hipLaunchKernelGGL(fwd_save_kernel<128>, grid, block, 0, s, wm, wt, a);
-    hipLaunchKernelGGL(head_kernel<128>, grid, block, 0, s, wm, a);
-  }
-  // slot loop: recompute, backprop, accumulate dW of h's layers 1 (slot part) and 2
   const GemmJob jT2{bl.dz2, W, bl.z1, RW, L_T2, W, W, 1, 0};
   const GemmJob jT1a{bl.dz1, W, bl.bi, 32, L_T1, W, kNL, 1, 0};
-  for (int i = 0; i < frame->k; ++i) {
-    if (W == 64)
-      hipLaunchKernelGGL(slot_kernel<64>, grid, block, 0, s, wm, wt, a, i, i == 0);
-    else
-      hipLaunchKernelGGL(slot_kernel<128>, grid, block, 0, s, wm, wt, a, i, i == 0);
-    gemm(jT2, ws->part_t2, i > 0);
-    gemm(jT1a, ws->part_t1, i > 0);
+  for (int i = 0; i < K; ++i) {
+    hipLaunchKernelGGL(slot_gather_kernel, pgrid, block, 0, s, pa, i);
+    z1();
+    {
+      PgArgs a = args();                                    // dz2 = [z2 > 0] m_i dZ
+      a.bias = wm + lo[L_T2].b;
+      a.add = plane(bl.dzin);
+      a.pscale = plane(bl.px + PX_M);
+      gemm(O_T2, EP_DZ2, bl.z1, bl.dz2, a);
+    }
+    {
+      PgArgs a = args();                                    // dz1 = [z1 > 0] W_T2^T dz2; du += dz1
+      a.mask = plane(bl.z1);
+      a.out2 = plane(bl.du);
+      a.accumulate2 = i > 0;
+      gemm(O_T2T, EP_BWD, bl.dz2, bl.dz1, a);
+    }
+    dw_gemm(jT2, ws->part_t2, i > 0);
+    dw_gemm(jT1a, ws->part_t1, i > 0);
   }
-  if (frame->k > 0) {
-    reduce(jT2, ws->part_t2);
-    reduce(jT1a, ws->part_t1);
-  } else {
-    // no slot: h's layers 1 (slot part and bias) and 2 get zero gradient
-    e = hipMemsetAsync(grad_w + lo[L_T2].w, 0, sizeof(float) * (size_t)(W * W + W), s);
-    for (int o = 0; o < W && e == hipSuccess; ++o)
-      e = hipMemsetAsync(grad_w + lo[L_T1].w + (int64_t)o * lo[L_T1].in, 0, sizeof(float) * kNL, s);
-    if (e == hipSuccess) e = hipMemsetAsync(grad_w + lo[L_T1].b, 0, sizeof(float) * W, s);
-    if (e == hipSuccess) e = hipMemsetAsync(plane(bl.du), 0, sizeof(float) * W * npx_pad, s);
-  }
-  if (W == 64)
-    hipLaunchKernelGGL(tail_kernel<64>, grid, block, 0, s, wm, a, frame->k > 0);
-  else
-    hipLaunchKernelGGL(tail_kernel<128>, grid, block, 0, s, wm, a, frame->k > 0);
+  // with no slot, T2 and T1's slot columns and bias get zero gradient (no chunks)
+  reduce(jT2, ws->part_t2, K > 0 ? nchunks : 0);
+  reduce(jT1a, ws->part_t1, K > 0 ? nchunks : 0);
 
+  // ---- tail
+  if (K > 0) {
+    PgArgs a = args();                                      // dsigma += W_T1,sigma^T du
+    a.add = plane(bl.dsig);
+    gemm(O_T1ST, EP_BWD, bl.du, bl.dsig, a);
+  } else if (e == hipSuccess) {
+    e = fill(plane(bl.du), (int64_t)W * npx_pad, 0.0f, s);
+  }
+  bwd(O_F3T, bl.dsig, bl.da2, bl.a2);
+  bwd(O_F2T, bl.da2, bl.da1, bl.a1);
+
+  // ---- weight gradients
   const GemmJob jobs[] = {
       {bl.dy, 32, bl.g2, RW, L_R3, kNOUT, W, 1, 0},
       {bl.dg2, W, bl.g1, RW, L_R2, W, W, 1, 0},
@@ -591,14 +739,14 @@ extern "C" gn_status glassnet_backward(gn_handle *h, const gn_frame *frame,
       {bl.dd2, W, bl.d1, RW, L_B2, W, W, 1, 0},
       {bl.dd1, W, bl.st, rup(2 * W + 1, 32), L_B1, W, 2 * W, 1, 0},
       {bl.dtau, W, bl.zs, RW, L_T3, W, W, 1, 0},
-      {bl.du, W, bl.st, rup(W, 32), L_T1, W, W, 0, kNL},
+      {bl.du, W, bl.st, W, L_T1, W, W, 0, kNL},
       {bl.dsig, W, bl.a2, RW, L_F3, W, W, 1, 0},
       {bl.da2, W, bl.a1, RW, L_F2, W, W, 1, 0},
       {bl.da1, W, bl.xb, 32, L_F1, W, kNG + kNS, 1, 0},
   };
   for (const GemmJob &j : jobs) {
-    gemm(j, ws->part, 0);
-    reduce(j, ws->part);
+    dw_gemm(j, ws->part, 0);
+    reduce(j, ws->part, nchunks);
   }
   if (e == hipSuccess) e = hipGetLastError();
   if (prev >= 0) (void)hipSetDevice(prev);

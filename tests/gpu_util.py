@@ -67,3 +67,26 @@ def gpu_on_sample(y_dev_np, fr: synth.Frame, flat):
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
+
+
+# A ReLU input closer to its kink than this fraction of the absolute-value sum
+# that bounds its rounding error may take the other branch in fp32 than in
+# the fp64 oracle (fp32 evaluation errors measure about 1e-6 of that sum).
+# Gradient parity is compared on pixels away from such kinks.
+KINK = 1e-5
+
+
+def kink_free(w, W, fr: synth.Frame, pool, flat=None):
+    """Boolean mask of pixels (all [n][h][w], or the sampled `flat` indices)
+    whose every ReLU input is at least KINK away from its kink."""
+    if flat is None:
+        return oracle.relu_margins(w, W, fr.gbuf, fr.layers, fr.scene, pool=pool) >= KINK
+    hw = fr.h * fr.w
+    ok = np.empty(len(flat), dtype=bool)
+    for f in np.unique(flat // hw):
+        at = flat // hw == f
+        sel = flat[at] % hw
+        g = fr.gbuf[f].reshape(14, hw)[:, sel][None, :, None, :]
+        L = fr.layers[f].reshape(fr.k, 12, hw)[:, :, sel][None, :, :, None, :]
+        ok[at] = oracle.relu_margins(w, W, g, L, fr.scene[f:f + 1], pool=pool).ravel() >= KINK
+    return ok

@@ -332,6 +332,43 @@ def test_gradient_is_zero_for_inactive_only_slot_weights():
     assert any(np.any(A != 0) for A, c in P["F"])
 
 
+# ------------------------------------------------------------- kink margins
+def test_relu_margin_vanishes_at_a_planted_kink():
+    """One hidden unit of F gets the bias that puts its input exactly at the
+    kink for one pixel (fp64 weights): that pixel's margin drops to rounding
+    level while every other pixel keeps a margin far above it."""
+    W = 8
+    wts, fr = tiny(n=1, h=3, w=2, k=2, W=W)
+    P = oracle.unpack(wts, W)
+    G = fr.gbuf.reshape(14, -1).astype(np.float64)
+    x = np.concatenate([G, np.repeat(fr.scene.reshape(16, 1).astype(np.float64), G.shape[1], 1)])
+    base = oracle.relu_margins(wts, W, fr.gbuf, fr.layers, fr.scene).ravel()
+    assert np.all((base > 0) & (base <= 1.0))
+    p, j = 4, 3
+    A1, c1 = P["F"][0]
+    c1 = c1.copy()
+    c1[j] = -(A1[j] @ x[:, p])
+    P["F"][0] = (A1, c1)
+    m = oracle.relu_margins(oracle.pack(P), W, fr.gbuf, fr.layers, fr.scene).ravel()
+    assert m[p] < 1e-14
+    assert np.all(np.delete(m, p) > 1e-9)
+
+
+def test_relu_margin_ignores_inactive_slots():
+    """A slot with alpha = 0 never reaches the output, so its h units cannot
+    set a pixel's margin: with every alpha zeroed the margins equal those of
+    the same frame without slots."""
+    W = 8
+    wts, fr = tiny(n=1, h=3, w=3, k=3, W=W)
+    L = fr.layers.copy()
+    L[:, :, 9] = 0.0
+    a = oracle.relu_margins(wts, W, fr.gbuf, L, fr.scene)
+    b = oracle.relu_margins(wts, W, fr.gbuf, L[:, :0], fr.scene)
+    assert np.array_equal(a, b)
+    c = oracle.relu_margins(wts, W, fr.gbuf, fr.layers, fr.scene)
+    assert not np.array_equal(a, c)
+
+
 # ------------------------------------------------------ the paper's own table
 def test_order_inversion_table():
     """Tab. OrderLoss: inverting the transparency-buffer order leaves the MAE

@@ -187,6 +187,49 @@ def k_sweep(w, W, fr, pool, precision, torch, ks=(0, 1, 2, 4, 8), steps=50):
     return {"k": list(ks), "kernel_ms": times, "ms_per_slot": slope, "ms_fixed": icpt, "r2": r2}
 
 
+def bwd_executed_flop_per_px(W, K):
+    """MFMA FLOP per pixel that one backward call executes: the plane GEMMs of
+    the forward recompute and of the backward (M x K operand shapes as padded
+    by the kernels: K rounded up to 32) and the dW GEMMs (o_pad x i_pad)."""
+    r32 = lambda x: (x + 31) // 32 * 32  # noqa: E731
+    RW = r32(W + 1)
+    # F1 F2 F3 T1s T3 B1 B2 B3 R1 R2; per slot T1 (slot columns), T2
+    fwd = 2 * W * (32 + W + W + W + W + 2 * W + W + W + r32(W + 3) + W) + K * 2 * W * (32 + W)
+    # R3^T R2^T R1^T B3^T B2^T B1^T T3^T T1s^T F3^T F2^T; per slot z1, dz2, dz1
+    bwd = 2 * W * (32 + 4 * W + 2 * W + W + W + 2 * W) + K * 2 * W * (32 + 2 * W)
+    # dW of R3; R2 B3 B2 T3 F3 F2; R1; B1; T1s; F1; per slot T2, T1 slot columns
+    dw = 2 * (32 * RW + W * (6 * RW + r32(W + 4) + r32(2 * W + 1) + W + 32)) + K * 2 * W * (RW + 32)
+    return fwd + bwd + dw
+
+
+def time_backward(torch, calls=10):
+    """Backward alone on the training workload (16 x 128^2, K=4, W=128), dL/dy
+    ~ N(0,1): ms per call from HIP events on the stream the calls run on."""
+    from paper_2405_19056_amd import synth
+    from paper_2405_19056_amd.glassnet import GlassNet
+    name = "c3_train_16x128sq_k4_w128"
+    c = synth.CONFIGS[name]
+    w, fr, _ = synth.config_inputs(name)
+    d = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")  # noqa: E731
+    g, L, s = d(fr.gbuf), d(fr.layers), d(fr.scene)
+    dy = d(np.random.default_rng(0).normal(size=(fr.n, 3, fr.h, fr.w)).astype(np.float32))
+    with GlassNet(w, c["width"], k_max=c["k"], pool=c["pool"], precision="bf16") as net:
+        gw = net.backward(g, L, s, dy)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(calls):
+            net.backward(g, L, s, dy, grad_w=gw)
+        e1.record()
+        torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / calls
+    px = fr.n * fr.h * fr.w
+    flop = bwd_executed_flop_per_px(c["width"], c["k"]) * px
+    return {"workload": "16 crops 128x128, K=4, W=128", "ms_per_call": ms,
+            "executed_mfma_flop": flop, "tflops": flop / ms / 1e9,
+            "frac_fp32_mfma_peak": flop / ms / 1e9 / PEAK_TFLOPS["fp32"]}
+
+
 def train_phase(torch, steps=10, precision="bf16"):
     """One training step of the 16 x 128^2, K=4, W=128 workload: forward with
     the current weights, L1 against teacher output + N(0, 0.01) noise, and
@@ -217,7 +260,8 @@ def train_phase(torch, steps=10, precision="bf16"):
     px = fr.n * fr.h * fr.w
     return {"workload": "16 crops 128x128, K=4, W=128, L1 vs teacher + N(0,0.01)",
             "forward": precision, "backward": "fp32", "ms_per_step": ms,
-            "pixels_per_s": px / ms * 1e3, "loss": float(loss.cpu())}
+            "pixels_per_s": px / ms * 1e3, "loss": float(loss.cpu()),
+            "backward_alone": time_backward(torch)}
 
 
 def copy_probe():
@@ -245,6 +289,8 @@ def main():
     ap.add_argument("--serve-seconds", type=float, default=5.0)
     ap.add_argument("--k-sweep", action="store_true")
     ap.add_argument("--no-train", action="store_true")
+    ap.add_argument("--backward-calls", type=int, default=0,
+                    help="only time this many backward calls of the training workload")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the per-pixel forward needs no communication and "
@@ -252,6 +298,10 @@ def main():
         sys.exit(2)
     if args.copy_probe:
         copy_probe()
+        return
+    if args.backward_calls > 0:
+        import torch
+        print(json.dumps({"backward": time_backward(torch, args.backward_calls)}))
         return
 
     import torch

@@ -214,12 +214,14 @@ __device__ __forceinline__ f32x4 bld4(rsrc_t r, uint32_t voff, uint32_t soff) {
 }
 __device__ __forceinline__ void st4(float *p, f32x4 v) { *(f32x4 *)p = v; }
 
-template <int MT, int EP>
+template <int MT, int EP, int RS>
 __global__ __launch_bounds__(kThreads) void plane_gemm_kernel(PgArgs a) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int n = lane & 15, g = lane >> 4;
-  const int64_t pq = ((int64_t)blockIdx.x * 4 + wave) * 64 + 4 * n;
-  const int mt0 = blockIdx.y * MT;
+  // RS waves share 64 pixels and split the workgroup's 16 MT RS rows
+  const int pgrp = wave / RS, rs = wave - pgrp * RS;
+  const int64_t pq = ((int64_t)blockIdx.x * (4 / RS) + pgrp) * 64 + 4 * n;
+  const int mt0 = (blockIdx.y * RS + rs) * MT;
   const int64_t st = a.stride;
   f32x4 acc[MT][4];
 #pragma unroll
@@ -364,11 +366,18 @@ template <int MO, int MI>
 __global__ __launch_bounds__(kThreads) void dw_gemm_kernel(const float *__restrict__ D,
                                                            const float *__restrict__ A,
                                                            int64_t stride, float *__restrict__ part,
-                                                           int o_pad, int i_pad, int accumulate) {
+                                                           int o_pad, int i_pad, int accumulate,
+                                                           int ti_n, int ntile, int nchunks) {
   __shared__ f32x4 red[3][MO * MI][64];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int r = lane & 15, kq = lane >> 4;
-  const int i0 = blockIdx.x * 16 * MI, o0 = blockIdx.y * 16 * MO, chunk = blockIdx.z;
+  // Workgroups are dealt to the 8 XCDs round robin by linear id; the tiles
+  // of one chunk are numbered so that they share an XCD (and its L2), which
+  // then reads the chunk's D and A rows from HBM once.
+  const int b = blockIdx.x, xcd = b & 7, rr = b >> 3;
+  const int chunk = 8 * (rr / ntile) + xcd, tile = rr % ntile;
+  if (chunk >= nchunks) return;
+  const int i0 = (tile % ti_n) * 16 * MI, o0 = (tile / ti_n) * 16 * MO;
   f32x4 acc[MO][MI];
 #pragma unroll
   for (int mo = 0; mo < MO; ++mo)
@@ -597,13 +606,14 @@ extern "C" gn_status glassnet_backward(gn_handle *h, const gn_frame *frame,
     a.stride = npx_pad;
     a.x = plane(xrow);
     a.out = plane(orow);
-    const int mtl = d.mt >= 8 ? 8 : 4;
-    const dim3 grid((unsigned)(npx_pad / kThreads), (unsigned)(d.mt / mtl));
-#define PG(MT, EP) hipLaunchKernelGGL((plane_gemm_kernel<MT, EP>), grid, block, 0, s, a)
-    if (mtl == 8) {
-      if (ep == EP_FWD) PG(8, EP_FWD); else if (ep == EP_DZ2) PG(8, EP_DZ2); else PG(8, EP_BWD);
+    // 64-row waves; two waves share a pixel group when the op has 128+ rows
+    const int rsplit = d.mt >= 8 ? 2 : 1;
+    const dim3 grid((unsigned)(npx_pad / (kThreads / rsplit)), (unsigned)(d.mt / (4 * rsplit)));
+#define PG(EP, RS) hipLaunchKernelGGL((plane_gemm_kernel<4, EP, RS>), grid, block, 0, s, a)
+    if (rsplit == 2) {
+      if (ep == EP_FWD) PG(EP_FWD, 2); else if (ep == EP_DZ2) PG(EP_DZ2, 2); else PG(EP_BWD, 2);
     } else {
-      if (ep == EP_FWD) PG(4, EP_FWD); else if (ep == EP_DZ2) PG(4, EP_DZ2); else PG(4, EP_BWD);
+      if (ep == EP_FWD) PG(EP_FWD, 1); else if (ep == EP_DZ2) PG(EP_DZ2, 1); else PG(EP_BWD, 1);
     }
 #undef PG
   };
@@ -675,11 +685,12 @@ extern "C" gn_status glassnet_backward(gn_handle *h, const gn_frame *frame,
     const int mo = j.o_pad % 64 == 0 ? 4 : 2;
     const int ti = j.i_pad / 16;
     const int mi = ti % 6 == 0 ? 6 : ti % 5 == 0 ? 5 : ti % 4 == 0 ? 4 : 2;
-    const dim3 grid((unsigned)(ti / mi), (unsigned)(j.o_pad / (16 * mo)), (unsigned)nchunks);
+    const int ti_n = ti / mi, ntile = ti_n * (j.o_pad / (16 * mo));
+    const dim3 grid((unsigned)(8 * ntile * ((nchunks + 7) / 8)));
     const float *D = plane(j.dblock), *Ap = plane(j.ablock);
 #define DW(MO, MI)                                                                              \
   hipLaunchKernelGGL((dw_gemm_kernel<MO, MI>), grid, block, 0, s, D, Ap, npx_pad, part, j.o_pad, \
-                     j.i_pad, accumulate)
+                     j.i_pad, accumulate, ti_n, ntile, nchunks)
     if (mo == 4) {
       if (mi == 6) DW(4, 6); else if (mi == 5) DW(4, 5); else if (mi == 4) DW(4, 4); else DW(4, 2);
     } else {

@@ -36,7 +36,7 @@ typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 typedef int i32x8 __attribute__((ext_vector_type(8)));
 
 constexpr int kWaves = 8;
-constexpr int kNT = 2;                 // N-tiles of 16 pixels per wave
+constexpr int kNT = 2;                // N-tiles of 16 pixels per wave
 constexpr int kThreads = kWaves * 64;
 static_assert(kWaves * kNT * 16 == kTilePx, "tile = waves x N-tiles x 16 pixels");
 constexpr int kFrag = 1024;            // one bf16 A fragment: 64 lanes x 16 B

@@ -34,6 +34,8 @@ typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 typedef int i32x8 __attribute__((ext_vector_type(8)));
+typedef const float __attribute__((address_space(1))) gcfloat;
+typedef float __attribute__((address_space(1))) gfloat;
 
 constexpr int kWaves = 8;
 constexpr int kNT = 2;                // N-tiles of 16 pixels per wave
@@ -105,6 +107,15 @@ __device__ __forceinline__ f32x4 mma_fp8(i32x8 a, i32x8 b, f32x4 c) {
 }
 
 __device__ __forceinline__ void wait_vm() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
+
+// Stage boundary that leaves the newest N vector-memory operations in flight:
+// N global stores issued after the next stage's LDS fill, whose completion
+// nothing in the workgroup waits for.  The fill itself (older) has landed in
+// LDS once vmcnt <= N; LDS traffic is drained and every wave has arrived.
+template <int N>
+__device__ __forceinline__ void stage_sync_after_stores() {
+  asm volatile("s_waitcnt vmcnt(%0)\n\ts_waitcnt lgkmcnt(0)\n\ts_barrier" ::"n"(N) : "memory");
+}
 
 // Copy `bytes` (a multiple of 1 KiB) from global to LDS: each wave moves whole
 // 1 KiB blocks, lane i writing bytes [16 i, 16 i + 16) of its block.
@@ -298,9 +309,14 @@ __global__ __launch_bounds__(kThreads) void fwd_mfma_kernel(MfmaArgs a) {
   const int64_t r2_bytes = (int64_t)MT * KS * kFrag;     // R2 precedes R3 in stage 9
 
   // ---- tile -> frame pointers, first pixel
+  // Frame pointers in the global address space: loads and stores through
+  // them are global (vector-memory counter only).  Through generic pointers
+  // they would be flat operations, which also count against the LDS counter,
+  // so every wait for an LDS fragment would also wait for the HBM loads in
+  // flight (the prefetched slot inputs among them).
   struct TileInfo {
-    const float *G, *L, *S;
-    float *O;
+    gcfloat *G, *L, *S;
+    gfloat *O;
     int hw, K, q0;
   };
   auto resolve = [&](int tile) {
@@ -308,17 +324,18 @@ __global__ __launch_bounds__(kThreads) void fwd_mfma_kernel(MfmaArgs a) {
     if (a.tiles) {
       const TileRef tr = a.tiles[tile];
       const FrameDesc fd = a.frames[tr.frame];
-      ti.G = fd.g; ti.L = fd.L; ti.S = fd.s; ti.O = fd.out; ti.hw = fd.hw; ti.K = fd.k;
+      ti.G = (gcfloat *)fd.g; ti.L = (gcfloat *)fd.L; ti.S = (gcfloat *)fd.s;
+      ti.O = (gfloat *)fd.out; ti.hw = fd.hw; ti.K = fd.k;
       ti.q0 = tr.q0;
     } else {
       const int f = tile / a.tiles_per_frame;
       ti.hw = a.b.hw;
       ti.K = a.b.k;
       ti.q0 = (tile - f * a.tiles_per_frame) * kTilePx;
-      ti.G = a.b.gbuf + (size_t)f * kNG * ti.hw;
-      ti.L = a.b.layers + (size_t)f * ti.K * kNL * ti.hw;
-      ti.S = a.b.scene + (size_t)f * kNS;
-      ti.O = a.b.out + (size_t)f * kNOUT * ti.hw;
+      ti.G = (gcfloat *)(a.b.gbuf + (size_t)f * kNG * ti.hw);
+      ti.L = (gcfloat *)(a.b.layers + (size_t)f * ti.K * kNL * ti.hw);
+      ti.S = (gcfloat *)(a.b.scene + (size_t)f * kNS);
+      ti.O = (gfloat *)(a.b.out + (size_t)f * kNOUT * ti.hw);
     }
     return ti;
   };
@@ -360,8 +377,8 @@ __global__ __launch_bounds__(kThreads) void fwd_mfma_kernel(MfmaArgs a) {
     };
     // ---- the tile's frame (resolved one tile ahead)
     const TileInfo ti = nti;
-    const float *Gp = ti.G, *Lp = ti.L;
-    float *Op = ti.O;
+    gcfloat *Gp = ti.G, *Lp = ti.L;
+    gfloat *Op = ti.O;
     const int hw = ti.hw, K = ti.K, q0 = ti.q0;
     int qc[kNT];
     bool valid[kNT];
@@ -400,8 +417,9 @@ __global__ __launch_bounds__(kThreads) void fwd_mfma_kernel(MfmaArgs a) {
     for (int t = 0; t < kNT; ++t)
 #pragma unroll
       for (int k = 0; k < KS; ++k) *(u32x4 *)(sig_slot + (t * KS + k) * kFrag + lane * 16) = sig[t][k];
-    wait_vm();
-    __syncthreads();
+    // the kNT x KS stores above stay in flight; the same wave reads them back
+    // in stage 3, after stage 2's full wait
+    stage_sync_after_stores<kNT * KS>();
 
     // ================= stage 2: u = W1s sigma + c1, then the slot loop =======
     fill_stage(3);
@@ -424,7 +442,7 @@ __global__ __launch_bounds__(kThreads) void fwd_mfma_kernel(MfmaArgs a) {
       // one slot ahead so their latency overlaps the current slot's work.
       float nxt[kNT][4];
       auto load_slot = [&](int i) {
-        const float *Li = Lp + (size_t)i * kNL * hw;
+        gcfloat *Li = Lp + (size_t)i * kNL * hw;
         int qs[kNT];
 #pragma unroll
         for (int t = 0; t < kNT; ++t) {
@@ -632,17 +650,19 @@ __global__ __launch_bounds__(kThreads) void fwd_mfma_kernel(MfmaArgs a) {
       f32x4 y[kNT][1];
       bias_init(y, bR3, g);
       mm<1, KS>(y, stage_buf(9) + r2_bytes, hr2, lane);
+      // Lane group 0 holds rows 0..2.  Tail lanes store the value of pixel
+      // hw - 1 they recomputed (bitwise the same as that pixel's own lane),
+      // so exactly 3 kNT store instructions issue, with a non-empty mask.
 #pragma unroll
       for (int t = 0; t < kNT; ++t) {
-        if (g == 0 && valid[t]) {
+        if (g == 0) {
           Op[qc[t]] = y[t][0].x;
           Op[(size_t)hw + qc[t]] = y[t][0].y;
           Op[(size_t)2 * hw + qc[t]] = y[t][0].z;
         }
       }
     }
-    wait_vm();
-    __syncthreads();
+    stage_sync_after_stores<3 * kNT>();
   }
 }
 

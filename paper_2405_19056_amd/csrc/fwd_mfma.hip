@@ -55,6 +55,7 @@ struct MfmaArgs {
   int pool;
   float sa, inv_sa;                    // fp8 activation scale and its inverse
   uint8_t *sig_scratch;                // per (workgroup, wave): sigma fragments, stage 1 -> 3
+  int sig_lds_waves;                   // waves 0 .. n-1 park sigma in LDS instead
 };
 
 // Two floats -> packed bf16 pair (round to nearest even), one v_cvt_pk_bf16_f32.
@@ -412,14 +413,29 @@ __global__ __launch_bounds__(kThreads) void fwd_mfma_kernel(MfmaArgs a) {
     layer<MT, KS, false>(sig, stage_buf(1), h2, bF3, g, lane);
     // sigma is needed again only by B's first layer: park it in this wave's
     // scratch instead of holding 32 registers through the slot loop
-    uint8_t *sig_slot = a.sig_scratch + ((size_t)blockIdx.x * kWaves + wave) * (kNT * KS * kFrag);
+    // (LDS left free by the weights holds it for the first sig_lds_waves
+    // waves; the others use a per-wave slot in HBM)
+    constexpr int kSigBytes = kNT * KS * kFrag;
+    const bool sig_in_lds = wave < a.sig_lds_waves;
+    uint8_t *sig_lds = L_stage1 + stage_max + (size_t)wave * kSigBytes;
+    uint8_t *sig_slot = a.sig_scratch + ((size_t)blockIdx.x * kWaves + wave) * kSigBytes;
+    if (sig_in_lds) {
 #pragma unroll
-    for (int t = 0; t < kNT; ++t)
+      for (int t = 0; t < kNT; ++t)
 #pragma unroll
-      for (int k = 0; k < KS; ++k) *(u32x4 *)(sig_slot + (t * KS + k) * kFrag + lane * 16) = sig[t][k];
+        for (int k = 0; k < KS; ++k) *(u32x4 *)(sig_lds + (t * KS + k) * kFrag + lane * 16) = sig[t][k];
+    } else {
+#pragma unroll
+      for (int t = 0; t < kNT; ++t)
+#pragma unroll
+        for (int k = 0; k < KS; ++k) *(u32x4 *)(sig_slot + (t * KS + k) * kFrag + lane * 16) = sig[t][k];
+    }
     // the kNT x KS stores above stay in flight; the same wave reads them back
     // in stage 3, after stage 2's full wait
-    stage_sync_after_stores<kNT * KS>();
+    if (sig_in_lds)
+      stage_sync_after_stores<0>();
+    else
+      stage_sync_after_stores<kNT * KS>();
 
     // ================= stage 2: u = W1s sigma + c1, then the slot loop =======
     fill_stage(3);
@@ -556,7 +572,8 @@ __global__ __launch_bounds__(kThreads) void fwd_mfma_kernel(MfmaArgs a) {
     for (int t = 0; t < kNT; ++t)
 #pragma unroll
       for (int k = 0; k < KS; ++k)
-        sig2[t][k] = *(const u32x4 *)(sig_slot + (t * KS + k) * kFrag + lane * 16);
+        sig2[t][k] = sig_in_lds ? *(const u32x4 *)(sig_lds + (t * KS + k) * kFrag + lane * 16)
+                                : *(const u32x4 *)(sig_slot + (t * KS + k) * kFrag + lane * 16);
     u32x4 tau[kNT][KS];
     {
       u32x4 zs[kNT][KS];
@@ -798,11 +815,25 @@ static int64_t resident_bytes(const PackedLayout &pl, int precision) {
   return pl.resident_bytes;
 }
 
-static size_t mfma_lds_bytes(const PackedLayout &pl, int precision) {
+static size_t mfma_base_lds_bytes(const PackedLayout &pl, int precision) {
   int64_t stage_max = 0;
   for (int s = 0; s < kNumStages; ++s)
     stage_max = std::max<int64_t>(stage_max, pl.stage_off[s + 1] - pl.stage_off[s]);
   return (size_t)(resident_bytes(pl, precision) + (int64_t)kNumLayers * pl.W * 4 + 2 * stage_max);
+}
+
+// Waves whose sigma fits in the LDS the weights leave free (160 KiB per CU).
+static int mfma_sig_lds_waves(const PackedLayout &pl, int precision) {
+  constexpr size_t kLdsMax = 160 * 1024;
+  const size_t per_wave = (size_t)kNT * (pl.W / 32) * kFrag;
+  const size_t base = mfma_base_lds_bytes(pl, precision);
+  if (base >= kLdsMax) return 0;
+  return (int)std::min<size_t>(kWaves, (kLdsMax - base) / per_wave);
+}
+
+static size_t mfma_lds_bytes(const PackedLayout &pl, int precision) {
+  return mfma_base_lds_bytes(pl, precision) +
+         (size_t)mfma_sig_lds_waves(pl, precision) * kNT * (pl.W / 32) * kFrag;
 }
 
 template <int W, int PREC>
@@ -825,6 +856,7 @@ hipError_t launch_fwd_mfma(int W, int precision, int pool, const uint8_t *packed
                            hipStream_t stream) {
   MfmaArgs a;
   a.sig_scratch = sig_scratch;
+  a.sig_lds_waves = mfma_sig_lds_waves(pl, precision);
   a.packed = packed;
   for (int s = 0; s <= kNumStages; ++s) a.stage_off[s] = pl.stage_off[s];
   a.res_off = pl.resident_off;

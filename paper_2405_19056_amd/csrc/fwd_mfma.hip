@@ -55,7 +55,9 @@ struct MfmaArgs {
   int pool;
   float sa, inv_sa;                    // fp8 activation scale and its inverse
   uint8_t *sig_scratch;                // per (workgroup, wave): sigma fragments, stage 1 -> 3
-  int sig_lds_waves;                   // waves 0 .. n-1 park sigma in LDS instead
+  int sig_lds_waves;                   // waves 0 .. n-1 park sigma in LDS instead:
+  int sig_tail_waves;                  // the first n - t after the stage buffers, the
+                                       // last t in the stage buffers' idle tails
 };
 
 // Two floats -> packed bf16 pair (round to nearest even), one v_cvt_pk_bf16_f32.
@@ -416,8 +418,13 @@ __global__ __launch_bounds__(kThreads) void fwd_mfma_kernel(MfmaArgs a) {
     // (LDS left free by the weights holds it for the first sig_lds_waves
     // waves; the others use a per-wave slot in HBM)
     constexpr int kSigBytes = kNT * KS * kFrag;
+    // Both stage buffers hold only stages 1-4's fragments (stage_max bytes or
+    // fewer) while sigma is parked, so their tails serve the last waves.
     const bool sig_in_lds = wave < a.sig_lds_waves;
-    uint8_t *sig_lds = L_stage1 + stage_max + (size_t)wave * kSigBytes;
+    const int nfree = a.sig_lds_waves - a.sig_tail_waves;
+    uint8_t *sig_lds = wave < nfree ? L_stage1 + stage_max + (size_t)wave * kSigBytes
+                                    : ((wave - nfree) & 1 ? L_stage1 : L_stage0) + stage_max -
+                                          (size_t)(1 + (wave - nfree) / 2) * kSigBytes;
     uint8_t *sig_slot = a.sig_scratch + ((size_t)blockIdx.x * kWaves + wave) * kSigBytes;
     if (sig_in_lds) {
 #pragma unroll
@@ -822,18 +829,42 @@ static size_t mfma_base_lds_bytes(const PackedLayout &pl, int precision) {
   return (size_t)(resident_bytes(pl, precision) + (int64_t)kNumLayers * pl.W * 4 + 2 * stage_max);
 }
 
-// Waves whose sigma fits in the LDS the weights leave free (160 KiB per CU).
-static int mfma_sig_lds_waves(const PackedLayout &pl, int precision) {
+// Waves whose sigma fits in the LDS the weights leave free (160 KiB per CU),
+// and how many of them sit in the stage buffers' tails: from stage 1 to stage
+// 4 buffer 1 holds stages 1 and 3, buffer 0 stages 2 and 4.
+static void mfma_sig_lds(const PackedLayout &pl, int precision, int *nlds, int *ntail) {
   constexpr size_t kLdsMax = 160 * 1024;
   const size_t per_wave = (size_t)kNT * (pl.W / 32) * kFrag;
   const size_t base = mfma_base_lds_bytes(pl, precision);
-  if (base >= kLdsMax) return 0;
-  return (int)std::min<size_t>(kWaves, (kLdsMax - base) / per_wave);
+  int64_t stage_max = 0;
+  for (int s = 0; s < kNumStages; ++s)
+    stage_max = std::max<int64_t>(stage_max, pl.stage_off[s + 1] - pl.stage_off[s]);
+  auto size = [&](int s) { return pl.stage_off[s + 1] - pl.stage_off[s]; };
+  const int64_t tail1 = stage_max - std::max(size(1), size(3));
+  const int64_t tail0 = stage_max - std::max(size(2), size(4));
+  const int free_waves = base >= kLdsMax ? 0 : (int)((kLdsMax - base) / per_wave);
+  int t = 0;
+  // tails are used alternately (buffer 0, buffer 1, buffer 0, ...)
+  for (int64_t used0 = 0, used1 = 0;; ++t) {
+    int64_t &u = (t & 1) ? used1 : used0;
+    const int64_t cap = (t & 1) ? tail1 : tail0;
+    if (u + (int64_t)per_wave > cap) break;
+    u += per_wave;
+  }
+  const int n = std::min(kWaves, free_waves + t);
+  *ntail = std::max(0, n - free_waves);
+  *nlds = n;
+}
+
+static int mfma_sig_free_waves(const PackedLayout &pl, int precision) {
+  int n, t;
+  mfma_sig_lds(pl, precision, &n, &t);
+  return n - t;
 }
 
 static size_t mfma_lds_bytes(const PackedLayout &pl, int precision) {
   return mfma_base_lds_bytes(pl, precision) +
-         (size_t)mfma_sig_lds_waves(pl, precision) * kNT * (pl.W / 32) * kFrag;
+         (size_t)mfma_sig_free_waves(pl, precision) * kNT * (pl.W / 32) * kFrag;
 }
 
 template <int W, int PREC>
@@ -856,7 +887,7 @@ hipError_t launch_fwd_mfma(int W, int precision, int pool, const uint8_t *packed
                            hipStream_t stream) {
   MfmaArgs a;
   a.sig_scratch = sig_scratch;
-  a.sig_lds_waves = mfma_sig_lds_waves(pl, precision);
+  mfma_sig_lds(pl, precision, &a.sig_lds_waves, &a.sig_tail_waves);
   a.packed = packed;
   for (int s = 0; s <= kNumStages; ++s) a.stage_off[s] = pl.stage_off[s];
   a.res_off = pl.resident_off;

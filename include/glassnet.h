@@ -57,7 +57,11 @@ typedef int32_t gn_status;
 #define GN_E_BUSY (-6)         /* serving: pending queue full */
 
 /* Arithmetic of the forward pass.
- *   GN_FP32    fp32 weights and activations on the vector ALUs.
+ *   GN_FP32    fp32 weights and activations on the fp32 matrix cores, layer by
+ *              layer through a workspace of fp32 planes (about 14.5 KB per
+ *              pixel at W = 128, kept by the handle and shared with the
+ *              backward: FP32 forward and backward calls on different
+ *              streams must be ordered by the caller).
  *   GN_BF16    bf16 weights/activations on MFMA, fp32 accumulation, fp32 pool.
  *   GN_FP8_T   the per-slot hidden layer of h in FP8-E4M3 (per-output-channel
  *              fp32 weight scales, static activation scale), the rest as GN_BF16.
@@ -139,7 +143,8 @@ gn_status glassnet_set_act_scales(gn_handle *h, const float *scales, size_t n);
 gn_status glassnet_calibrate(gn_handle *h, const gn_frame *frame, void *hip_stream);
 
 /* Forward (Sec. 3.3-3.4): out [n][GN_NUM_OUT][h][w] fp32 device.
- * Requires 0 <= k <= k_max and n, h, w >= 1.  Out must not alias inputs. */
+ * Requires 0 <= k <= k_max and n, h, w >= 1.  Out must not alias inputs.
+ * GN_FP32: at most 3 * 2^20 pixels (n * h * w) per call (GN_E_INVAL beyond). */
 gn_status glassnet_forward(gn_handle *h, const gn_frame *frame, float *out, void *hip_stream);
 
 /* Backward of the forward above with respect to the weights (Sec. 3.5), fp32.

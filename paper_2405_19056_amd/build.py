@@ -20,7 +20,7 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libglassnet.so")
 ARCH = "gfx950"
 
-SOURCES = ["api.cpp", "layout.cpp", "serve.cpp", "fwd_fp32.hip", "fwd_mfma.hip", "bwd.hip",
+SOURCES = ["api.cpp", "layout.cpp", "serve.cpp", "fwd_mfma.hip", "planes.hip",
            "loss.hip"]
 
 
@@ -44,7 +44,7 @@ def common_flags():
 # Per-source extra flags.  The backward's fp32 plane GEMMs keep their
 # accumulators in VGPRs: in the default accumulator-register form the
 # allocator rotates them through copies every K group, at half the occupancy.
-EXTRA = {"bwd.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"]}
+EXTRA = {"planes.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"]}
 
 
 def _compile(src: str) -> str:

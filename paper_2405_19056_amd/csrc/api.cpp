@@ -91,8 +91,7 @@ static gn_status precheck(gn_handle *h) {
 }
 
 gn_status gn_prepare_weights(gn_handle *h, hipStream_t stream) {
-  hipError_t e = gn::launch_transpose_master(h->W, h->d_master, h->d_master_t, stream);
-  if (e == hipSuccess) e = gn::launch_pack_weights(h->d_master, h->d_packed, h->pl, h->act_scale, stream);
+  hipError_t e = gn::launch_pack_weights(h->d_master, h->d_packed, h->pl, h->act_scale, stream);
   return gn_check_device(h, e, "weight packing");
 }
 
@@ -143,17 +142,12 @@ gn_status glassnet_create(const gn_config *cfg, const float *host_weights, size_
   }
   h->num_cus = prop.multiProcessorCount;
   gn::make_packed_layout(h->W, &h->pl);
-  h->scratch_threads = gn::fp32_scratch_threads(h->num_cus);
   h->l1_npart = 4 * h->num_cus;
 
   const size_t wbytes = sizeof(float) * np;
-  const size_t scratch_bytes = sizeof(float) * 4 * (size_t)h->W * h->scratch_threads;
   hipError_t e = hipSuccess;
   if (e == hipSuccess) e = hipMalloc((void **)&h->d_master, wbytes);
-  if (e == hipSuccess) e = hipMalloc((void **)&h->d_master_t, wbytes);
   if (e == hipSuccess) e = hipMalloc((void **)&h->d_packed, (size_t)h->pl.total_bytes);
-  if (e == hipSuccess && cfg->precision == GN_FP32)
-    e = hipMalloc((void **)&h->d_scratch, scratch_bytes);
   if (e == hipSuccess) e = hipMalloc((void **)&h->d_l1_partials, sizeof(float) * h->l1_npart);
   const size_t sig_bytes = gn::mfma_sig_scratch_bytes(h->W, h->num_cus);
   if (cfg->precision != GN_FP32)
@@ -168,8 +162,8 @@ gn_status glassnet_create(const gn_config *cfg, const float *host_weights, size_
     glassnet_destroy(h);
     return st;
   }
-  h->bytes_held = 2 * wbytes + (size_t)h->pl.total_bytes + sizeof(float) * h->l1_npart +
-                  (cfg->precision == GN_FP32 ? scratch_bytes : 2 * sig_bytes);
+  h->bytes_held = wbytes + (size_t)h->pl.total_bytes + sizeof(float) * h->l1_npart +
+                  (cfg->precision == GN_FP32 ? 0 : 2 * sig_bytes);
   gn_status st = gn_prepare_weights(h, nullptr);
   if (st == GN_OK) {
     e = hipDeviceSynchronize();
@@ -197,9 +191,7 @@ gn_status glassnet_destroy(gn_handle *h) {
   gn_bwd_free(h);
   if (!h->poisoned) (void)hipDeviceSynchronize();
   (void)hipFree(h->d_master);
-  (void)hipFree(h->d_master_t);
   (void)hipFree(h->d_packed);
-  (void)hipFree(h->d_scratch);
   (void)hipFree(h->d_l1_partials);
   (void)hipFree(h->d_sig_scratch[0]);
   (void)hipFree(h->d_sig_scratch[1]);
@@ -250,28 +242,22 @@ gn_status glassnet_calibrate(gn_handle *h, const gn_frame *frame, void *hip_stre
   if (st != GN_OK) return st;
   DeviceGuard dg(h->device);
   hipStream_t s = (hipStream_t)hip_stream;
-  const int64_t hw = (int64_t)frame->h * frame->w;
-  float *scratch = h->d_scratch, *out = nullptr;
   unsigned *amax = nullptr;
-  const bool own_scratch = scratch == nullptr;
-  hipError_t e = hipSuccess;
-  if (own_scratch)
-    e = hipMalloc((void **)&scratch, sizeof(float) * 4 * (size_t)h->W * h->scratch_threads);
-  if (e == hipSuccess) e = hipMalloc((void **)&out, sizeof(float) * gn::kNOUT * frame->n * hw);
-  if (e == hipSuccess) e = hipMalloc((void **)&amax, sizeof(unsigned));
+  hipError_t e = hipMalloc((void **)&amax, sizeof(unsigned));
   if (e == hipSuccess) e = hipMemsetAsync(amax, 0, sizeof(unsigned), s);
-  if (e == hipSuccess) {
-    gn::FwdBatch b{frame->gbuf, frame->layers, frame->scene, out, frame->n, (int32_t)hw, frame->k};
-    e = gn::launch_fwd_fp32(h->W, h->cfg.pool, h->d_master, h->d_master_t, b, scratch,
-                            h->scratch_threads, s, amax);
+  if (e != hipSuccess) {
+    (void)hipFree(amax);
+    return gn_check_device(h, e, "calibration");
   }
+  st = gn_planes_calibrate(h, frame, amax, s);
   unsigned bits = 0;
-  if (e == hipSuccess) e = hipMemcpyAsync(&bits, amax, sizeof bits, hipMemcpyDeviceToHost, s);
-  if (e == hipSuccess) e = hipStreamSynchronize(s);
-  if (own_scratch) (void)hipFree(scratch);
-  (void)hipFree(out);
+  if (st == GN_OK) {
+    e = hipMemcpyAsync(&bits, amax, sizeof bits, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    st = gn_check_device(h, e, "calibration");
+  }
   (void)hipFree(amax);
-  if (e != hipSuccess) return gn_check_device(h, e, "calibration");
+  if (st != GN_OK) return st;
   float m;
   memcpy(&m, &bits, sizeof m);
   if (m > 0.0f && m < 1e30f) h->act_scale = m / 448.0f;
@@ -300,15 +286,11 @@ gn_status glassnet_forward(gn_handle *h, const gn_frame *frame, float *out, void
   b.n = frame->n;
   b.hw = frame->h * frame->w;
   b.k = frame->k;
-  hipError_t e;
-  if (h->cfg.precision == GN_FP32) {
-    e = gn::launch_fwd_fp32(h->W, h->cfg.pool, h->d_master, h->d_master_t, b, h->d_scratch,
-                            h->scratch_threads, s);
-  } else {
-    const int tpf = (b.hw + gn::kTilePx - 1) / gn::kTilePx;
-    e = gn::launch_fwd_mfma(h->W, h->cfg.precision, h->cfg.pool, h->d_packed, h->pl, &b, nullptr,
-                            nullptr, b.n * tpf, h->act_scale, h->num_cus, h->d_sig_scratch[0], s);
-  }
+  if (h->cfg.precision == GN_FP32) return gn_planes_forward(h, frame, out, s);
+  const int tpf = (b.hw + gn::kTilePx - 1) / gn::kTilePx;
+  const hipError_t e = gn::launch_fwd_mfma(h->W, h->cfg.precision, h->cfg.pool, h->d_packed, h->pl,
+                                           &b, nullptr, nullptr, b.n * tpf, h->act_scale,
+                                           h->num_cus, h->d_sig_scratch[0], s);
   return gn_check_device(h, e, "forward launch");
 }
 

@@ -761,32 +761,7 @@ __global__ void pack_bias_kernel(PackArgs p) {
   ((float *)(p.packed + p.bias_off))[(int64_t)l * p.W + o] = v;
 }
 
-// Transposed copy of every layer matrix ([out][in] -> [in][out]) for the fp32 path.
-__global__ void transpose_kernel(const float *master, float *mt, LayerOff lo) {
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t n = (int64_t)lo.out * lo.in;
-  if (e >= n) return;
-  const int r = (int)(e / lo.in), c = (int)(e - (int64_t)r * lo.in);
-  mt[lo.w + (int64_t)c * lo.out + r] = master[lo.w + e];
-}
-
 }  // namespace
-
-hipError_t launch_transpose_master(int W, const float *master, float *master_t,
-                                   hipStream_t stream) {
-  LayerOff lo[kNumLayers];
-  layer_offsets(W, lo);
-  for (int l = 0; l < kNumLayers; ++l) {
-    const int64_t n = (int64_t)lo[l].out * lo[l].in;
-    hipLaunchKernelGGL(transpose_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream,
-                       master, master_t, lo[l]);
-    // biases keep their place so both copies share offsets
-    hipError_t e = hipMemcpyAsync(master_t + lo[l].b, master + lo[l].b,
-                                  sizeof(float) * lo[l].out, hipMemcpyDeviceToDevice, stream);
-    if (e != hipSuccess) return e;
-  }
-  return hipGetLastError();
-}
 
 size_t mfma_sig_scratch_bytes(int W, int grid) {
   return (size_t)grid * kWaves * kNT * (W / 32) * kFrag;

@@ -14,12 +14,9 @@ struct gn_handle {
   int num_cus = 0;
   size_t nparams = 0;
   float *d_master = nullptr;      // fp32 master weights (flat layout)
-  float *d_master_t = nullptr;    // same, every matrix transposed (fp32 forward)
   uint8_t *d_packed = nullptr;    // fragment-ordered bf16/fp8 weights + biases
   gn::PackedLayout pl{};
-  float *d_scratch = nullptr;     // fp32 forward: per-thread vectors
   uint8_t *d_sig_scratch[2] = {nullptr, nullptr};  // MFMA forward: caller streams, serving
-  int scratch_threads = 0;
   float *d_l1_partials = nullptr;
   int l1_npart = 0;
   float act_scale = 0.0f;         // fp8 activation scale
@@ -37,4 +34,8 @@ gn_status gn_prepare_weights(gn_handle *h, hipStream_t stream);
 gn_status gn_serve_init(gn_handle *h);
 void gn_serve_shutdown(gn_handle *h);
 void gn_bwd_free(gn_handle *h);
+// The fp32 plane pipeline (planes.hip): the FP32 forward and the FP8
+// calibration (amax: device float bits of the largest h-layer-1 activation).
+gn_status gn_planes_forward(gn_handle *h, const gn_frame *frame, float *out, hipStream_t s);
+gn_status gn_planes_calibrate(gn_handle *h, const gn_frame *frame, unsigned *amax, hipStream_t s);
 size_t gn_bwd_bytes(gn_handle *h);

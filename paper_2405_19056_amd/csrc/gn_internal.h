@@ -84,6 +84,7 @@ struct PackedLayout {
 void make_packed_layout(int W, PackedLayout *pl);
 
 // ---- launches (all asynchronous on `stream`) --------------------------------
+struct BwdWorkspace;
 struct FwdBatch {
   // Arithmetic mode: n frames of equal hw/k laid out as in gn_frame.
   const float *gbuf, *layers, *scene;
@@ -91,17 +92,9 @@ struct FwdBatch {
   int32_t n, hw, k;
 };
 
-hipError_t launch_transpose_master(int W, const float *master, float *master_t,
-                                  hipStream_t stream);
 hipError_t launch_pack_weights(const float *master, uint8_t *packed, const PackedLayout &pl,
                                float fp8_act_scale, hipStream_t stream);
 
-// master_t: each layer's matrix transposed to [in][out] at the master offsets.
-hipError_t launch_fwd_fp32(int W, int pool, const float *master, const float *master_t,
-                           const FwdBatch &b,
-                           float *scratch, int scratch_threads, hipStream_t stream,
-                           unsigned *amax = nullptr);
-int fp32_scratch_threads(int num_cus);
 
 // sig_scratch: mfma_sig_scratch_bytes(W, grid) bytes private to this launch
 // (launches that may overlap need different scratch buffers).
@@ -116,9 +109,5 @@ constexpr int kTilePx = 256;
 hipError_t launch_l1(const float *out, const float *target, uint64_t count, float *loss,
                      float *grad, float *partials, int npart, hipStream_t stream);
 
-struct BwdWorkspace;
-hipError_t launch_backward(int W, int pool, const float *master, const FwdBatch &b,
-                           const float *grad_out, float *grad_w, BwdWorkspace *ws,
-                           hipStream_t stream);
 
 }  // namespace gn

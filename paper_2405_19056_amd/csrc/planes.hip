@@ -1,9 +1,10 @@
-// Hand-written backward of GlassNet's per-pixel evaluation (Sec. 3.5 trains
-// F, T, B and R jointly end to end; this computes dL/dw for a given dL/dy).
+// The fp32 plane pipeline: GlassNet's FP32 forward (Sec. 3.3-3.4), the FP8
+// calibration pass, and the hand-written backward (Sec. 3.5 trains F, T, B
+// and R jointly end to end; dL/dw for a given dL/dy).
 //
 // Every per-pixel quantity lives in a plane [row][pixel] of fp32 in HBM, and
-// every linear map of the forward recompute and of the backward is one plane
-// GEMM on the fp32 matrix cores,
+// every linear map of the forward and of the backward is one plane GEMM on
+// the fp32 matrix cores,
 //     out[m][p] = epilogue( sum_k A[m][k] X[k][p] ),
 // with A a weight matrix (or its transpose) and X a block of planes.  The
 // epilogues fuse what sits between two linear maps: bias, ReLU, the ReLU
@@ -15,6 +16,8 @@
 //                 z1_i and z2_i with the masked pool accumulated in the
 //                 epilogue; T3; B; R's hidden layers.  The slot activations
 //                 are overwritten slot by slot, never kept for all slots.
+//                 The FP32 forward ends with R's last layer into the output;
+//                 the calibration stops after h's first layer of every slot.
 //   3. head:      R^T, B^T -> (dsigma_B, dtau) -> dZ through T3 and the pool.
 //   4. slot i:    recompute z1_i, then dz2_i (z2_i's ReLU mask in the
 //                 epilogue), dz1_i, du += dz1_i, and accumulate dW of T2 and
@@ -60,7 +63,7 @@ inline int rup(int x, int m) { return (x + m - 1) / m * m; }
 // Row offsets of every plane block.  Activation blocks end with a row of
 // ones (bias gradients) and are padded with zero rows to a multiple of 32.
 struct Blocks {
-  int xb, a1, a2, st, u, zs, d1, d2, pl, g1, g2, z1, bi, px;
+  int xb, a1, a2, st, u, zs, d1, d2, pl, g1, g2, z1, bi, px, y;
   int dy, dg2, dg1, dphi, dd2, dd1, dsig, dtau, dzin, du, da2, da1, dz2, dz1;
   int rows;
 };
@@ -85,6 +88,7 @@ Blocks make_blocks(int W) {
   b.z1 = take(RW);                   // slot i: z1, ones
   b.bi = take(32);                   // slot i: b_i (12), ones at 12
   b.px = take(32);                   // 1/max(c,1) (mean) or 1; slot mask m_i
+  b.y = take(32);                    // R's 3 outputs (16-row GEMM tile), forward only
   b.dy = take(32);
   b.dg2 = take(W); b.dg1 = take(W); b.dphi = take(W); b.dd2 = take(W); b.dd1 = take(W);
   b.dsig = take(W); b.dtau = take(W);    // adjacent: B1^T writes both at once
@@ -103,7 +107,7 @@ Blocks make_blocks(int W) {
 // count is even, so every input block has at least 32 * ceil(K / 32) rows
 // (zero rows beyond the data, or the ones row, meet zero weights).
 enum Op {
-  O_F1, O_F2, O_F3, O_T1S, O_T1A, O_T2, O_T3, O_B1, O_B2, O_B3, O_R1, O_R2,
+  O_F1, O_F2, O_F3, O_T1S, O_T1A, O_T2, O_T3, O_B1, O_B2, O_B3, O_R1, O_R2, O_R3,
   O_R3T, O_R2T, O_R1T, O_B3T, O_B2T, O_B1T, O_T3T, O_T2T, O_T1ST, O_F3T, O_F2T, kNumOps
 };
 
@@ -128,6 +132,7 @@ OpTable make_ops(int W) {
       {O_T1S, L_T1, 0, kNL, W, W},      {O_T1A, L_T1, 0, 0, W, kNL}, {O_T2, L_T2, 0, 0, W, W},
       {O_T3, L_T3, 0, 0, W, W},         {O_B1, L_B1, 0, 0, W, 2 * W}, {O_B2, L_B2, 0, 0, W, W},
       {O_B3, L_B3, 0, 0, W, W},         {O_R1, L_R1, 0, 0, W, W + 3}, {O_R2, L_R2, 0, 0, W, W},
+      {O_R3, L_R3, 0, 0, kNOUT, W},
       {O_R3T, L_R3, 1, 0, W, kNOUT},    {O_R2T, L_R2, 1, 0, W, W},  {O_R1T, L_R1, 1, 0, W, W},
       {O_B3T, L_B3, 1, 0, W, W},        {O_B2T, L_B2, 1, 0, W, W},  {O_B1T, L_B1, 1, 0, 2 * W, W},
       {O_T3T, L_T3, 1, 0, W, W},        {O_T2T, L_T2, 1, 0, W, W},  {O_T1ST, L_T1, 1, kNL, W, W},
@@ -339,7 +344,7 @@ __global__ __launch_bounds__(kThreads) void prep_kernel(PrepArgs a) {
   ROW(B.px + PX_INV)[p] = mean ? 1.0f / fmaxf(cnt, 1.0f) : 1.0f;
   ROW(B.zs + W)[p] = mean ? (cnt > 0.0f ? 1.0f : 0.0f) : cnt;
   for (int c = 0; c < kNOUT; ++c)
-    ROW(B.dy + c)[p] = valid ? a.grad_out[((size_t)f * kNOUT + c) * hw + q] : 0.0f;
+    ROW(B.dy + c)[p] = valid && a.grad_out ? a.grad_out[((size_t)f * kNOUT + c) * hw + q] : 0.0f;
 }
 
 // Slot i's 12 channels and its mask m_i = [alpha > 0].
@@ -466,6 +471,37 @@ __global__ void fill_kernel(float *dst, int64_t n, float v) {
   if (e < n) dst[e] = v;
 }
 
+// R's 3 output rows (plus their biases) into the caller's [n][3][hw] layout.
+__global__ __launch_bounds__(kThreads) void scatter_out_kernel(const float *__restrict__ y,
+                                                               int64_t stride, int64_t npx, int hw,
+                                                               const float *__restrict__ b3,
+                                                               float *__restrict__ out) {
+  const int64_t p = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (p >= npx) return;
+  const int f = (int)(p / hw), q = (int)(p - (int64_t)f * hw);
+  for (int c = 0; c < kNOUT; ++c)
+    out[((size_t)f * kNOUT + c) * hw + q] = y[(size_t)c * stride + p] + b3[c];
+}
+
+// max over rows [0, n) and pixels [0, npx) of a non-negative plane block, as
+// float bits (for non-negative floats the bit order is the value order).
+__global__ __launch_bounds__(kThreads) void amax_kernel(const float *__restrict__ rows, int n,
+                                                        int64_t stride, int64_t npx,
+                                                        unsigned *amax) {
+  __shared__ float red[kThreads];
+  const int64_t p = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  float m = 0.0f;
+  if (p < npx)
+    for (int r = 0; r < n; ++r) m = fmaxf(m, rows[(size_t)r * stride + p]);
+  red[threadIdx.x] = m;
+  __syncthreads();
+  for (int w = kThreads / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + w]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) atomicMax(amax, __float_as_uint(red[0]));
+}
+
 }  // namespace
 
 }  // namespace gn
@@ -543,6 +579,312 @@ struct GemmJob {
   int n_out, n_in, has_bias, col0;
 };
 
+// One call of the plane pipeline over a frame batch.  begin() validates the
+// size, prepares the workspace and operand fragments and gathers the inputs;
+// the phases enqueue their launches on the call's stream in order.
+class Pipeline {
+ public:
+  Pipeline(gn_handle *h, hipStream_t s)
+      : h_(h), s_(s), W_(h->W), bl_(make_blocks(h->W)), ops_(make_ops(h->W)) {
+    layer_offsets(W_, lo_);
+  }
+
+  gn_status begin(const gn_frame *f, const float *grad_out, const char *what) {
+    const int64_t hw = (int64_t)f->h * f->w;
+    npx_ = (int64_t)f->n * hw;
+    npx_pad_ = (npx_ + kChunkPx - 1) / kChunkPx * kChunkPx;
+    if (npx_pad_ > kMaxPx) return gn_set_error(GN_E_INVAL, "more than 3 * 2^20 pixels in one call");
+    hw_ = (int)hw;
+    K_ = f->k;
+    e_ = ensure_workspace(h_, npx_pad_);
+    if (e_ == hipSuccess) e_ = init_constant_rows(h_, npx_pad_, s_);
+    if (e_ != hipSuccess) return gn_check_device(h_, e_, what);
+    ws_ = h_->bwd;
+    wm_ = h_->d_master;
+    pa_.gbuf = f->gbuf;
+    pa_.layers = f->layers;
+    pa_.scene = f->scene;
+    pa_.grad_out = grad_out;
+    pa_.hw = hw_;
+    pa_.k = K_;
+    pa_.pool = h_->cfg.pool;
+    pa_.W = W_;
+    pa_.npx = npx_;
+    pa_.stride = npx_pad_;
+    pa_.planes = ws_->planes;
+    pa_.bl = bl_;
+    hipLaunchKernelGGL(pack_ops_kernel, dim3((unsigned)((ops_.total + kThreads - 1) / kThreads)),
+                       dim3(kThreads), 0, s_, wm_, ops_, ws_->frag);
+    hipLaunchKernelGGL(prep_kernel, pgrid(), dim3(kThreads), 0, s_, pa_);
+    return GN_OK;
+  }
+
+  // F, then u = W_T1,sigma sigma + b_T1 (the sigma-hoist).
+  void trunk() {
+    fwd(O_F1, bl_.xb, bl_.a1, L_F1, true);
+    fwd(O_F2, bl_.a1, bl_.a2, L_F2, true);
+    fwd(O_F3, bl_.a2, bl_.st, L_F3, false);                  // sigma
+    fwd(O_T1S, bl_.st, bl_.u, L_T1, false);                  // u
+  }
+
+  // Z = sum_i m_i relu(W_T2 z1_i + b_T2), then / max(c, 1) for the mean.
+  void slots() {
+    const bool mean = h_->cfg.pool == GN_POOL_MEAN;
+    for (int i = 0; i < K_; ++i) {
+      gather(i);
+      z1();
+      PgArgs a = args();
+      a.bias = wm_ + lo_[L_T2].b;
+      a.relu = 1;
+      a.pscale = plane(bl_.px + PX_M);
+      a.accumulate = i > 0;
+      if (i == K_ - 1 && mean) a.post = plane(bl_.px + PX_INV);
+      gemm(O_T2, EP_FWD, bl_.z1, bl_.zs, a);
+    }
+    if (K_ == 0) fill_rows(bl_.zs, W_);
+  }
+
+  // T3 (tau), B (phi) and R's hidden layers.
+  void head() {
+    PgArgs a = args();                                       // tau = W_T3 zs + bs b_T3
+    a.bias = wm_ + lo_[L_T3].b;
+    a.bscale = plane(bl_.zs + W_);
+    gemm(O_T3, EP_FWD, bl_.zs, bl_.st + W_, a);
+    fwd(O_B1, bl_.st, bl_.d1, L_B1, true);
+    fwd(O_B2, bl_.d1, bl_.d2, L_B2, true);
+    fwd(O_B3, bl_.d2, bl_.pl, L_B3, false);                  // phi
+    fwd(O_R1, bl_.pl, bl_.g1, L_R1, true);
+    fwd(O_R2, bl_.g1, bl_.g2, L_R2, true);
+  }
+
+  // R's last layer (no bias in the GEMM: its 3 biases are added while the
+  // rows are scattered into the caller's [n][3][h][w] output).
+  void output(float *out) {
+    gemm(O_R3, EP_FWD, bl_.g2, bl_.y, args());
+    hipLaunchKernelGGL(scatter_out_kernel, pgrid(), dim3(kThreads), 0, s_, plane(bl_.y),
+                       npx_pad_, npx_, hw_, wm_ + lo_[L_R3].b, out);
+  }
+
+  // FP8 calibration: the largest first-layer activation of h over every slot
+  // of every pixel, as float bits (non-negative, so bit order = value order).
+  void calibrate(unsigned *amax) {
+    for (int i = 0; i < K_; ++i) {
+      gather(i);
+      z1();
+      hipLaunchKernelGGL(amax_kernel, pgrid(), dim3(kThreads), 0, s_, plane(bl_.z1), W_,
+                         npx_pad_, npx_, amax);
+    }
+  }
+
+  // dL/dw given the forward planes (trunk, slots, head) and dL/dy (begin).
+  void backward(float *grad_w) {
+    const bool mean = h_->cfg.pool == GN_POOL_MEAN;
+    const int W = W_;
+    // ---- head: R^T, B^T -> (dsigma_B, dtau) -> dZ
+    bwd(O_R3T, bl_.dy, bl_.dg2, bl_.g2);
+    bwd(O_R2T, bl_.dg2, bl_.dg1, bl_.g1);
+    bwd(O_R1T, bl_.dg1, bl_.dphi, -1);
+    bwd(O_B3T, bl_.dphi, bl_.dd2, bl_.d2);
+    bwd(O_B2T, bl_.dd2, bl_.dd1, bl_.d1);
+    bwd(O_B1T, bl_.dd1, bl_.dsig, -1);                        // dsigma_B and dtau
+    {
+      PgArgs a = args();                                      // dZ = W_T3^T dtau / max(c,1)
+      if (mean) a.pscale = plane(bl_.px + PX_INV);
+      gemm(O_T3T, EP_BWD, bl_.dtau, bl_.dzin, a);
+    }
+    // ---- slot loop
+    const int RW = rup(W + 1, 32);
+    const GemmJob jT2{bl_.dz2, W, bl_.z1, RW, L_T2, W, W, 1, 0};
+    const GemmJob jT1a{bl_.dz1, W, bl_.bi, 32, L_T1, W, kNL, 1, 0};
+    for (int i = 0; i < K_; ++i) {
+      gather(i);
+      z1();
+      {
+        PgArgs a = args();                                    // dz2 = [z2 > 0] m_i dZ
+        a.bias = wm_ + lo_[L_T2].b;
+        a.add = plane(bl_.dzin);
+        a.pscale = plane(bl_.px + PX_M);
+        gemm(O_T2, EP_DZ2, bl_.z1, bl_.dz2, a);
+      }
+      {
+        PgArgs a = args();                                    // dz1 = [z1 > 0] W_T2^T dz2; du += dz1
+        a.mask = plane(bl_.z1);
+        a.out2 = plane(bl_.du);
+        a.accumulate2 = i > 0;
+        gemm(O_T2T, EP_BWD, bl_.dz2, bl_.dz1, a);
+      }
+      dw_gemm(jT2, ws_->part_t2, i > 0);
+      dw_gemm(jT1a, ws_->part_t1, i > 0);
+    }
+    // with no slot, T2 and T1's slot columns and bias get zero gradient (no chunks)
+    reduce(jT2, ws_->part_t2, K_ > 0 ? nchunks() : 0, grad_w);
+    reduce(jT1a, ws_->part_t1, K_ > 0 ? nchunks() : 0, grad_w);
+    // ---- tail
+    if (K_ > 0) {
+      PgArgs a = args();                                      // dsigma += W_T1,sigma^T du
+      a.add = plane(bl_.dsig);
+      gemm(O_T1ST, EP_BWD, bl_.du, bl_.dsig, a);
+    } else {
+      fill_rows(bl_.du, W);
+    }
+    bwd(O_F3T, bl_.dsig, bl_.da2, bl_.a2);
+    bwd(O_F2T, bl_.da2, bl_.da1, bl_.a1);
+    // ---- weight gradients
+    const GemmJob jobs[] = {
+        {bl_.dy, 32, bl_.g2, RW, L_R3, kNOUT, W, 1, 0},
+        {bl_.dg2, W, bl_.g1, RW, L_R2, W, W, 1, 0},
+        {bl_.dg1, W, bl_.pl, rup(W + 4, 32), L_R1, W, W + 3, 1, 0},
+        {bl_.dphi, W, bl_.d2, RW, L_B3, W, W, 1, 0},
+        {bl_.dd2, W, bl_.d1, RW, L_B2, W, W, 1, 0},
+        {bl_.dd1, W, bl_.st, rup(2 * W + 1, 32), L_B1, W, 2 * W, 1, 0},
+        {bl_.dtau, W, bl_.zs, RW, L_T3, W, W, 1, 0},
+        {bl_.du, W, bl_.st, W, L_T1, W, W, 0, kNL},
+        {bl_.dsig, W, bl_.a2, RW, L_F3, W, W, 1, 0},
+        {bl_.da2, W, bl_.a1, RW, L_F2, W, W, 1, 0},
+        {bl_.da1, W, bl_.xb, 32, L_F1, W, kNG + kNS, 1, 0},
+    };
+    for (const GemmJob &j : jobs) {
+      dw_gemm(j, ws_->part, 0);
+      reduce(j, ws_->part, nchunks(), grad_w);
+    }
+  }
+
+  gn_status finish(const char *what) {
+    if (e_ == hipSuccess) e_ = hipGetLastError();
+    return gn_check_device(h_, e_, what);
+  }
+
+ private:
+  dim3 pgrid() const { return dim3((unsigned)(npx_pad_ / kThreads)); }
+  int nchunks() const { return (int)(npx_pad_ / kChunkPx); }
+  float *plane(int r) const { return ws_->planes + (size_t)r * npx_pad_; }
+  static PgArgs args() {
+    PgArgs a;
+    memset(&a, 0, sizeof a);
+    return a;
+  }
+  void fill_rows(int row, int n) {
+    if (e_ == hipSuccess) e_ = fill(plane(row), (int64_t)n * npx_pad_, 0.0f, s_);
+  }
+  void gather(int i) {
+    hipLaunchKernelGGL(slot_gather_kernel, pgrid(), dim3(kThreads), 0, s_, pa_, i);
+  }
+
+  // One plane GEMM: op `o` from block `xrow` into block `orow`.
+  void gemm(Op o, int ep, int xrow, int orow, PgArgs a) {
+    const OpDesc &d = ops_.op[o];
+    a.frag = ws_->frag + d.off;
+    a.kq = d.kq;
+    a.stride = npx_pad_;
+    a.x = plane(xrow);
+    a.out = plane(orow);
+    const dim3 block(kThreads);
+    if (d.mt < 4) {             // R3: one 16-row tile, 64-pixel waves
+      const dim3 grid((unsigned)(npx_pad_ / kThreads), 1);
+      hipLaunchKernelGGL((plane_gemm_kernel<1, EP_FWD, 1>), grid, block, 0, s_, a);
+      return;
+    }
+    // 64-row waves; two waves share a pixel group when the op has 128+ rows
+    const int rsplit = d.mt >= 8 ? 2 : 1;
+    const dim3 grid((unsigned)(npx_pad_ / (kThreads / rsplit)), (unsigned)(d.mt / (4 * rsplit)));
+#define PG(EP, RS) hipLaunchKernelGGL((plane_gemm_kernel<4, EP, RS>), grid, block, 0, s_, a)
+    if (rsplit == 2) {
+      if (ep == EP_FWD) PG(EP_FWD, 2); else if (ep == EP_DZ2) PG(EP_DZ2, 2); else PG(EP_BWD, 2);
+    } else {
+      if (ep == EP_FWD) PG(EP_FWD, 1); else if (ep == EP_DZ2) PG(EP_DZ2, 1); else PG(EP_BWD, 1);
+    }
+#undef PG
+  }
+  void fwd(Op o, int xrow, int orow, Layer l, bool relu) {
+    PgArgs a = args();
+    a.bias = wm_ + lo_[l].b;
+    a.relu = relu;
+    gemm(o, EP_FWD, xrow, orow, a);
+  }
+  void bwd(Op o, int xrow, int orow, int maskrow) {
+    PgArgs a = args();
+    if (maskrow >= 0) a.mask = plane(maskrow);
+    gemm(o, EP_BWD, xrow, orow, a);
+  }
+  void z1() {                                                // z1_i = relu(W_T1,b b_i + u)
+    PgArgs a = args();
+    a.add = plane(bl_.u);
+    a.relu = 1;
+    gemm(O_T1A, EP_FWD, bl_.bi, bl_.z1, a);
+  }
+  void dw_gemm(const GemmJob &j, float *part, int accumulate) {
+    // tile: 16 MO output rows x 16 MI input rows, dividing o_pad and i_pad
+    const int mo = j.o_pad % 64 == 0 ? 4 : 2;
+    const int ti = j.i_pad / 16;
+    const int mi = ti % 6 == 0 ? 6 : ti % 5 == 0 ? 5 : ti % 4 == 0 ? 4 : 2;
+    const int ti_n = ti / mi, ntile = ti_n * (j.o_pad / (16 * mo)), nch = nchunks();
+    const dim3 grid((unsigned)(8 * ntile * ((nch + 7) / 8))), block(kThreads);
+    const float *D = plane(j.dblock), *Ap = plane(j.ablock);
+#define DW(MO, MI)                                                                       \
+  hipLaunchKernelGGL((dw_gemm_kernel<MO, MI>), grid, block, 0, s_, D, Ap, npx_pad_, part, \
+                     j.o_pad, j.i_pad, accumulate, ti_n, ntile, nch)
+    if (mo == 4) {
+      if (mi == 6) DW(4, 6); else if (mi == 5) DW(4, 5); else if (mi == 4) DW(4, 4); else DW(4, 2);
+    } else {
+      if (mi == 6) DW(2, 6); else if (mi == 5) DW(2, 5); else if (mi == 4) DW(2, 4); else DW(2, 2);
+    }
+#undef DW
+  }
+  void reduce(const GemmJob &j, const float *part, int nch, float *grad_w) {
+    const int n = j.n_out * (j.n_in + (j.has_bias ? 1 : 0));
+    hipLaunchKernelGGL(dw_reduce_kernel, dim3((n + 255) / 256), dim3(256), 0, s_, part, nch,
+                       j.o_pad, j.i_pad, j.n_out, j.n_in, j.has_bias, grad_w, lo_[j.layer], j.col0);
+  }
+
+  gn_handle *h_;
+  hipStream_t s_;
+  int W_;
+  Blocks bl_;
+  OpTable ops_;
+  LayerOff lo_[kNumLayers];
+  BwdWorkspace *ws_ = nullptr;
+  const float *wm_ = nullptr;
+  PrepArgs pa_{};
+  int64_t npx_ = 0, npx_pad_ = 0;
+  int hw_ = 0, K_ = 0;
+  hipError_t e_ = hipSuccess;
+};
+
+// Runs fn(pipeline) on the handle's device; restores the caller's device.
+template <class Fn>
+static gn_status with_device(gn_handle *h, Fn fn) {
+  int prev = -1;
+  (void)hipGetDevice(&prev);
+  if (hipSetDevice(h->device) != hipSuccess) return gn_set_error(GN_E_DEVICE, "hipSetDevice failed");
+  const gn_status st = fn();
+  if (prev >= 0) (void)hipSetDevice(prev);
+  return st;
+}
+
+gn_status gn_planes_forward(gn_handle *h, const gn_frame *frame, float *out, hipStream_t s) {
+  return with_device(h, [&]() {
+    Pipeline p(h, s);
+    gn_status st = p.begin(frame, nullptr, "fp32 forward");
+    if (st != GN_OK) return st;
+    p.trunk();
+    p.slots();
+    p.head();
+    p.output(out);
+    return p.finish("fp32 forward");
+  });
+}
+
+gn_status gn_planes_calibrate(gn_handle *h, const gn_frame *frame, unsigned *amax, hipStream_t s) {
+  return with_device(h, [&]() {
+    Pipeline p(h, s);
+    gn_status st = p.begin(frame, nullptr, "calibration");
+    if (st != GN_OK) return st;
+    p.trunk();
+    p.calibrate(amax);
+    return p.finish("calibration");
+  });
+}
+
 extern "C" gn_status glassnet_backward(gn_handle *h, const gn_frame *frame,
                                        const float *grad_out, float *grad_w, void *hip_stream) {
   if (!h) return gn_set_error(GN_E_INVAL, "handle is NULL");
@@ -551,215 +893,14 @@ extern "C" gn_status glassnet_backward(gn_handle *h, const gn_frame *frame,
     return gn_set_error(GN_E_INVAL, "grad_out and grad_w must be non-NULL, 4-byte aligned");
   gn_status st = gn_validate_frame(h, frame, nullptr);
   if (st != GN_OK) return st;
-  int prev = -1;
-  (void)hipGetDevice(&prev);
-  if (hipSetDevice(h->device) != hipSuccess) return gn_set_error(GN_E_DEVICE, "hipSetDevice failed");
-  hipStream_t s = (hipStream_t)hip_stream;
-  const int W = h->W;
-  const int64_t hw = (int64_t)frame->h * frame->w;
-  const int64_t npx = (int64_t)frame->n * hw;
-  const int64_t npx_pad = (npx + kChunkPx - 1) / kChunkPx * kChunkPx;
-  if (npx_pad > kMaxPx) {
-    if (prev >= 0) (void)hipSetDevice(prev);
-    return gn_set_error(GN_E_INVAL, "backward: more than 3 * 2^20 pixels in one call");
-  }
-  hipError_t e = ensure_workspace(h, npx_pad);
-  if (e == hipSuccess) e = init_constant_rows(h, npx_pad, s);
-  if (e != hipSuccess) {
-    if (prev >= 0) (void)hipSetDevice(prev);
-    return gn_check_device(h, e, "backward workspace");
-  }
-  BwdWorkspace *ws = h->bwd;
-  const Blocks bl = make_blocks(W);
-  const OpTable ops = make_ops(W);
-  const float *wm = h->d_master;
-  LayerOff lo[kNumLayers];
-  layer_offsets(W, lo);
-  const int K = frame->k;
-  const bool mean = h->cfg.pool == GN_POOL_MEAN;
-  auto plane = [&](int r) { return ws->planes + (size_t)r * npx_pad; };
-
-  PrepArgs pa;
-  pa.gbuf = frame->gbuf;
-  pa.layers = frame->layers;
-  pa.scene = frame->scene;
-  pa.grad_out = grad_out;
-  pa.hw = (int)hw;
-  pa.k = K;
-  pa.pool = h->cfg.pool;
-  pa.W = W;
-  pa.npx = npx;
-  pa.stride = npx_pad;
-  pa.planes = ws->planes;
-  pa.bl = bl;
-  const dim3 pgrid((unsigned)(npx_pad / kThreads)), block(kThreads);
-
-  hipLaunchKernelGGL(pack_ops_kernel, dim3((unsigned)((ops.total + kThreads - 1) / kThreads)),
-                     block, 0, s, wm, ops, ws->frag);
-  hipLaunchKernelGGL(prep_kernel, pgrid, block, 0, s, pa);
-
-  // One plane GEMM: op `o` from block `xrow` into block `orow`.
-  auto gemm = [&](Op o, int ep, int xrow, int orow, PgArgs a) {
-    const OpDesc &d = ops.op[o];
-    a.frag = ws->frag + d.off;
-    a.kq = d.kq;
-    a.stride = npx_pad;
-    a.x = plane(xrow);
-    a.out = plane(orow);
-    // 64-row waves; two waves share a pixel group when the op has 128+ rows
-    const int rsplit = d.mt >= 8 ? 2 : 1;
-    const dim3 grid((unsigned)(npx_pad / (kThreads / rsplit)), (unsigned)(d.mt / (4 * rsplit)));
-#define PG(EP, RS) hipLaunchKernelGGL((plane_gemm_kernel<4, EP, RS>), grid, block, 0, s, a)
-    if (rsplit == 2) {
-      if (ep == EP_FWD) PG(EP_FWD, 2); else if (ep == EP_DZ2) PG(EP_DZ2, 2); else PG(EP_BWD, 2);
-    } else {
-      if (ep == EP_FWD) PG(EP_FWD, 1); else if (ep == EP_DZ2) PG(EP_DZ2, 1); else PG(EP_BWD, 1);
-    }
-#undef PG
-  };
-  auto args = []() { PgArgs a; memset(&a, 0, sizeof a); return a; };
-  auto fwd = [&](Op o, int xrow, int orow, Layer l, bool relu) {
-    PgArgs a = args();
-    a.bias = wm + lo[l].b;
-    a.relu = relu;
-    gemm(o, EP_FWD, xrow, orow, a);
-  };
-  auto bwd = [&](Op o, int xrow, int orow, int maskrow) {
-    PgArgs a = args();
-    if (maskrow >= 0) a.mask = plane(maskrow);
-    gemm(o, EP_BWD, xrow, orow, a);
-  };
-  auto z1 = [&]() {                                  // z1_i = relu(W_T1,b b_i + u)
-    PgArgs a = args();
-    a.add = plane(bl.u);
-    a.relu = 1;
-    gemm(O_T1A, EP_FWD, bl.bi, bl.z1, a);
-  };
-
-  // ---- forward recompute
-  fwd(O_F1, bl.xb, bl.a1, L_F1, true);
-  fwd(O_F2, bl.a1, bl.a2, L_F2, true);
-  fwd(O_F3, bl.a2, bl.st, L_F3, false);                     // sigma
-  fwd(O_T1S, bl.st, bl.u, L_T1, false);                     // u
-  for (int i = 0; i < K; ++i) {
-    hipLaunchKernelGGL(slot_gather_kernel, pgrid, block, 0, s, pa, i);
-    z1();
-    PgArgs a = args();                                      // Z (+)= m_i relu(W_T2 z1 + b)
-    a.bias = wm + lo[L_T2].b;
-    a.relu = 1;
-    a.pscale = plane(bl.px + PX_M);
-    a.accumulate = i > 0;
-    if (i == K - 1 && mean) a.post = plane(bl.px + PX_INV);
-    gemm(O_T2, EP_FWD, bl.z1, bl.zs, a);
-  }
-  if (K == 0 && e == hipSuccess) e = fill(plane(bl.zs), (int64_t)W * npx_pad, 0.0f, s);
-  {
-    PgArgs a = args();                                      // tau = W_T3 zs + bs b_T3
-    a.bias = wm + lo[L_T3].b;
-    a.bscale = plane(bl.zs + W);
-    gemm(O_T3, EP_FWD, bl.zs, bl.st + W, a);
-  }
-  fwd(O_B1, bl.st, bl.d1, L_B1, true);
-  fwd(O_B2, bl.d1, bl.d2, L_B2, true);
-  fwd(O_B3, bl.d2, bl.pl, L_B3, false);                     // phi
-  fwd(O_R1, bl.pl, bl.g1, L_R1, true);
-  fwd(O_R2, bl.g1, bl.g2, L_R2, true);
-
-  // ---- head
-  bwd(O_R3T, bl.dy, bl.dg2, bl.g2);
-  bwd(O_R2T, bl.dg2, bl.dg1, bl.g1);
-  bwd(O_R1T, bl.dg1, bl.dphi, -1);
-  bwd(O_B3T, bl.dphi, bl.dd2, bl.d2);
-  bwd(O_B2T, bl.dd2, bl.dd1, bl.d1);
-  bwd(O_B1T, bl.dd1, bl.dsig, -1);                          // dsigma_B and dtau
-  {
-    PgArgs a = args();                                      // dZ = W_T3^T dtau / max(c,1)
-    if (mean) a.pscale = plane(bl.px + PX_INV);
-    gemm(O_T3T, EP_BWD, bl.dtau, bl.dzin, a);
-  }
-
-  // ---- slot loop
-  const int nchunks = (int)(npx_pad / kChunkPx);
-  auto dw_gemm = [&](const GemmJob &j, float *part, int accumulate) {
-    // tile: 16 MO output rows x 16 MI input rows, dividing o_pad and i_pad
-    const int mo = j.o_pad % 64 == 0 ? 4 : 2;
-    const int ti = j.i_pad / 16;
-    const int mi = ti % 6 == 0 ? 6 : ti % 5 == 0 ? 5 : ti % 4 == 0 ? 4 : 2;
-    const int ti_n = ti / mi, ntile = ti_n * (j.o_pad / (16 * mo));
-    const dim3 grid((unsigned)(8 * ntile * ((nchunks + 7) / 8)));
-    const float *D = plane(j.dblock), *Ap = plane(j.ablock);
-#define DW(MO, MI)                                                                              \
-  hipLaunchKernelGGL((dw_gemm_kernel<MO, MI>), grid, block, 0, s, D, Ap, npx_pad, part, j.o_pad, \
-                     j.i_pad, accumulate, ti_n, ntile, nchunks)
-    if (mo == 4) {
-      if (mi == 6) DW(4, 6); else if (mi == 5) DW(4, 5); else if (mi == 4) DW(4, 4); else DW(4, 2);
-    } else {
-      if (mi == 6) DW(2, 6); else if (mi == 5) DW(2, 5); else if (mi == 4) DW(2, 4); else DW(2, 2);
-    }
-#undef DW
-  };
-  auto reduce = [&](const GemmJob &j, const float *part, int nch) {
-    const int n = j.n_out * (j.n_in + (j.has_bias ? 1 : 0));
-    hipLaunchKernelGGL(dw_reduce_kernel, dim3((n + 255) / 256), dim3(256), 0, s, part, nch,
-                       j.o_pad, j.i_pad, j.n_out, j.n_in, j.has_bias, grad_w, lo[j.layer], j.col0);
-  };
-  const int RW = rup(W + 1, 32);
-  const GemmJob jT2{bl.dz2, W, bl.z1, RW, L_T2, W, W, 1, 0};
-  const GemmJob jT1a{bl.dz1, W, bl.bi, 32, L_T1, W, kNL, 1, 0};
-  for (int i = 0; i < K; ++i) {
-    hipLaunchKernelGGL(slot_gather_kernel, pgrid, block, 0, s, pa, i);
-    z1();
-    {
-      PgArgs a = args();                                    // dz2 = [z2 > 0] m_i dZ
-      a.bias = wm + lo[L_T2].b;
-      a.add = plane(bl.dzin);
-      a.pscale = plane(bl.px + PX_M);
-      gemm(O_T2, EP_DZ2, bl.z1, bl.dz2, a);
-    }
-    {
-      PgArgs a = args();                                    // dz1 = [z1 > 0] W_T2^T dz2; du += dz1
-      a.mask = plane(bl.z1);
-      a.out2 = plane(bl.du);
-      a.accumulate2 = i > 0;
-      gemm(O_T2T, EP_BWD, bl.dz2, bl.dz1, a);
-    }
-    dw_gemm(jT2, ws->part_t2, i > 0);
-    dw_gemm(jT1a, ws->part_t1, i > 0);
-  }
-  // with no slot, T2 and T1's slot columns and bias get zero gradient (no chunks)
-  reduce(jT2, ws->part_t2, K > 0 ? nchunks : 0);
-  reduce(jT1a, ws->part_t1, K > 0 ? nchunks : 0);
-
-  // ---- tail
-  if (K > 0) {
-    PgArgs a = args();                                      // dsigma += W_T1,sigma^T du
-    a.add = plane(bl.dsig);
-    gemm(O_T1ST, EP_BWD, bl.du, bl.dsig, a);
-  } else if (e == hipSuccess) {
-    e = fill(plane(bl.du), (int64_t)W * npx_pad, 0.0f, s);
-  }
-  bwd(O_F3T, bl.dsig, bl.da2, bl.a2);
-  bwd(O_F2T, bl.da2, bl.da1, bl.a1);
-
-  // ---- weight gradients
-  const GemmJob jobs[] = {
-      {bl.dy, 32, bl.g2, RW, L_R3, kNOUT, W, 1, 0},
-      {bl.dg2, W, bl.g1, RW, L_R2, W, W, 1, 0},
-      {bl.dg1, W, bl.pl, rup(W + 4, 32), L_R1, W, W + 3, 1, 0},
-      {bl.dphi, W, bl.d2, RW, L_B3, W, W, 1, 0},
-      {bl.dd2, W, bl.d1, RW, L_B2, W, W, 1, 0},
-      {bl.dd1, W, bl.st, rup(2 * W + 1, 32), L_B1, W, 2 * W, 1, 0},
-      {bl.dtau, W, bl.zs, RW, L_T3, W, W, 1, 0},
-      {bl.du, W, bl.st, W, L_T1, W, W, 0, kNL},
-      {bl.dsig, W, bl.a2, RW, L_F3, W, W, 1, 0},
-      {bl.da2, W, bl.a1, RW, L_F2, W, W, 1, 0},
-      {bl.da1, W, bl.xb, 32, L_F1, W, kNG + kNS, 1, 0},
-  };
-  for (const GemmJob &j : jobs) {
-    dw_gemm(j, ws->part, 0);
-    reduce(j, ws->part, nchunks);
-  }
-  if (e == hipSuccess) e = hipGetLastError();
-  if (prev >= 0) (void)hipSetDevice(prev);
-  return gn_check_device(h, e, "backward launch");
+  return with_device(h, [&]() {
+    Pipeline p(h, (hipStream_t)hip_stream);
+    gn_status st2 = p.begin(frame, grad_out, "backward workspace");
+    if (st2 != GN_OK) return st2;
+    p.trunk();
+    p.slots();
+    p.head();
+    p.backward(grad_w);
+    return p.finish("backward launch");
+  });
 }

@@ -139,7 +139,8 @@ gn_status glassnet_set_act_scales(gn_handle *h, const float *scales, size_t n);
 /* GN_FP8_T calibration: evaluates h's first layer in fp32 over every slot of
  * every pixel of frame and sets the activation scale to (largest value)/448,
  * so the representative frame's range maps onto E4M3 without clipping.
- * Synchronous (waits for hip_stream); allocates and frees its own temporaries. */
+ * Runs the fp32 plane pipeline of GN_FP32 (same workspace, same pixel limit).
+ * Synchronous (waits for hip_stream). */
 gn_status glassnet_calibrate(gn_handle *h, const gn_frame *frame, void *hip_stream);
 
 /* Forward (Sec. 3.3-3.4): out [n][GN_NUM_OUT][h][w] fp32 device.

@@ -177,6 +177,46 @@ def test_invalid_arguments_are_rejected():
         assert np.all(np.isfinite(host(y)))
 
 
+def test_fp32_plane_workspace_reused_across_sizes_and_with_backward():
+    """One fp32 handle: a small frame, a larger one (the plane workspace grows),
+    the small one again (planes re-zeroed for the shorter rows), then a backward
+    on a third size and the small forward once more: every result matches the
+    oracle, and the repeated small forwards are bitwise equal."""
+    torch = torch_dev()
+    W = 64
+    wts, fr_a = frame(2, 19, 23, 3, W, seed=61)
+    _, fr_b = frame(1, 80, 80, 5, W, seed=62)
+    _, fr_c = frame(1, 30, 33, 2, W, seed=63)
+    with GlassNet(wts, W, k_max=8, precision="fp32") as net:
+        ya = run(net, fr_a)
+        yb = run(net, fr_b)
+        ya2 = run(net, fr_a)
+        dy = np.random.default_rng(3).normal(size=(1, 3, 30, 33)).astype(np.float32)
+        g = net.backward(dev(fr_c.gbuf), dev(fr_c.layers), dev(fr_c.scene), dev(dy))
+        torch.cuda.synchronize()
+        ya3 = run(net, fr_a)
+    for y, fr in ((ya, fr_a), (yb, fr_b)):
+        assert relF(y, oracle.forward(wts, W, fr.gbuf, fr.layers, fr.scene)) <= TOL["fp32"]
+    assert np.array_equal(ya, ya2) and np.array_equal(ya, ya3)
+    assert np.all(np.isfinite(host(g)))
+
+
+def test_fp32_forward_rejects_more_pixels_than_it_addresses():
+    """The fp32 plane pipeline covers at most 3 * 2^20 pixels per call; beyond
+    that the forward is an argument error raised before any launch."""
+    torch = torch_dev()
+    W, n, h, w = 64, 1, 1025, 3072
+    wts = synth.make_weights(W, np.random.default_rng(0))
+    g = torch.zeros((n, 14, h, w), device="cuda:0")
+    sc = torch.zeros((n, 16), device="cuda:0")
+    with GlassNet(wts, W, k_max=2, precision="fp32") as net:
+        with pytest.raises(GlassNetError) as e:
+            net.forward(g, None, sc)
+        assert e.value.status == GN_E_INVAL
+    del g
+    torch.cuda.empty_cache()
+
+
 def test_workspace_does_not_depend_on_k():
     W = 128
     wts, _ = frame(1, 4, 4, 1, W, seed=0)

@@ -168,6 +168,49 @@ gn_status glassnet_l1_loss(gn_handle *h, const float *out, const float *target,
  * workspaces.  Independent of the slot count k (the pool is a running sum). */
 gn_status glassnet_workspace_bytes(gn_handle *h, uint64_t *bytes);
 
+/* Object streaming (Sec. 3.3, Eq. (5); Sec. 4.4.2 and Fig. "MemUsage"): tau
+ * is a sum over transparency buffers, so each object's buffer can be
+ * evaluated on its own and added to a running sum, and device memory stays
+ * constant in the number of transparent objects.  A frame batch is evaluated
+ * as begin (F -> sigma), then any number of accumulate calls (k >= 0 objects
+ * each), then finish (pool, T3, B, R -> out).  The result is bitwise the
+ * glassnet_forward result of the same handle over all accumulated slots in
+ * call order (same arithmetic, same order).  finish may follow any accumulate
+ * call (a progressive result) and accumulation may continue after it.
+ *
+ * The state is caller-owned device memory of glassnet_stream_state_bytes
+ * bytes (772 bytes per pixel at W = 128, 388 at W = 64, whatever the number
+ * of objects): sigma in bf16, the fp32 running sum of h's hidden layer and
+ * the active-slot count, in a layout private to the library.  Calls on one
+ * state are ordered on the hip_stream each passes; calls on different streams
+ * must be ordered by the caller.  GN_BF16 and GN_FP8_T handles only (GN_FP32:
+ * GN_E_UNSUPPORTED). */
+gn_status glassnet_stream_state_bytes(gn_handle *h, int32_t n, int32_t hgt, int32_t wid,
+                                      uint64_t *bytes);
+
+/* Start a frame batch: evaluate F on frame->gbuf and frame->scene into state
+ * (frame->k and frame->layers are ignored).  state: 16-byte aligned device
+ * memory of state_bytes >= glassnet_stream_state_bytes(n, h, w) bytes; a
+ * state begun earlier that overlaps this memory is forgotten. */
+gn_status glassnet_stream_begin(gn_handle *h, const gn_frame *frame, void *state,
+                                uint64_t state_bytes, void *hip_stream);
+
+/* Add frame->k objects, frame->layers [n][k][GN_NUM_L][h][w], to the state's
+ * running sum (gbuf and scene are ignored).  n, h, w must be those of the
+ * begin call; 0 <= k <= k_max, and k = 0 is a no-op.  GN_E_INVAL for a state
+ * not begun on this handle. */
+gn_status glassnet_stream_accumulate(gn_handle *h, const gn_frame *frame, void *state,
+                                     void *hip_stream);
+
+/* Pool the objects accumulated so far (none: an empty pool) and evaluate T3,
+ * B and R: out [n][GN_NUM_OUT][h][w] fp32 device, L_d read from frame->gbuf
+ * (layers, scene and k are ignored).  The state is left unchanged. */
+gn_status glassnet_stream_finish(gn_handle *h, const gn_frame *frame, void *state, float *out,
+                                 void *hip_stream);
+
+/* Forget a begun state (its memory stays the caller's).  GN_E_INVAL if unknown. */
+gn_status glassnet_stream_release(gn_handle *h, void *state);
+
 /* Serving (continuous batching).  serve_submit enqueues a frame batch whose
  * device buffers the library may read until serve_poll reports done; out is
  * written then.  Frames are admitted while the bytes of admitted-but-unfinished

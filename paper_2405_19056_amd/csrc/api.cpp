@@ -294,6 +294,159 @@ gn_status glassnet_forward(gn_handle *h, const gn_frame *frame, float *out, void
   return gn_check_device(h, e, "forward launch");
 }
 
+// ---- object streaming ---------------------------------------------------------
+
+static gn_status stream_geometry(gn_handle *h, int32_t n, int32_t hgt, int32_t wid,
+                                 uint64_t *bytes) {
+  if (h->cfg.precision == GN_FP32)
+    return fail(GN_E_UNSUPPORTED, "object streaming runs on the matrix-core forward (GN_BF16, GN_FP8_T)");
+  if (n < 1 || hgt < 1 || wid < 1)
+    return fail(GN_E_INVAL, "frame shape n=%d h=%d w=%d must be >= 1", n, hgt, wid);
+  const int64_t hw = (int64_t)hgt * wid;
+  if (hw * gn::kNG > INT32_MAX || (int64_t)n * hw > INT32_MAX)
+    return fail(GN_E_INVAL, "frame too large (%d x %d x %d)", n, hgt, wid);
+  const uint64_t tiles = (uint64_t)n * (uint64_t)((hw + gn::kTilePx - 1) / gn::kTilePx);
+  *bytes = tiles * gn::stream_state_tile_bytes(h->W);
+  return GN_OK;
+}
+
+// The record of a begun state whose geometry matches the frame (caller holds stream_mu).
+static gn_status stream_lookup(gn_handle *h, const gn_frame *f, const void *state,
+                               GnStreamRec **rec) {
+  auto it = h->streams.find((uintptr_t)state);
+  if (it == h->streams.end())
+    return fail(GN_E_INVAL, "state %p was not begun with glassnet_stream_begin", state);
+  const GnStreamRec &r = it->second;
+  if (f->n != r.n || f->h != r.hgt || f->w != r.wid)
+    return fail(GN_E_INVAL, "frame %d x %d x %d does not match the state's %d x %d x %d", f->n,
+                f->h, f->w, r.n, r.hgt, r.wid);
+  *rec = &it->second;
+  return GN_OK;
+}
+
+static gn::FwdBatch stream_batch(const gn_frame *f) {
+  gn::FwdBatch b;
+  b.gbuf = f->gbuf;
+  b.layers = f->layers;
+  b.scene = f->scene;
+  b.out = nullptr;
+  b.n = f->n;
+  b.hw = f->h * f->w;
+  b.k = f->k;
+  return b;
+}
+
+gn_status glassnet_stream_state_bytes(gn_handle *h, int32_t n, int32_t hgt, int32_t wid,
+                                      uint64_t *bytes) {
+  if (!h || !bytes) return fail(GN_E_INVAL, "NULL argument");
+  return stream_geometry(h, n, hgt, wid, bytes);
+}
+
+gn_status glassnet_stream_begin(gn_handle *h, const gn_frame *frame, void *state,
+                                uint64_t state_bytes, void *hip_stream) {
+  gn_status st = precheck(h);
+  if (st != GN_OK) return st;
+  if (!frame || !state) return fail(GN_E_INVAL, "frame and state must be non-NULL");
+  uint64_t need = 0;
+  st = stream_geometry(h, frame->n, frame->h, frame->w, &need);
+  if (st != GN_OK) return st;
+  if (state_bytes < need)
+    return fail(GN_E_INVAL, "state holds %llu bytes, the frame needs %llu",
+                (unsigned long long)state_bytes, (unsigned long long)need);
+  if (((uintptr_t)state & 15u) != 0) return fail(GN_E_INVAL, "state must be 16-byte aligned");
+  if (!frame->gbuf || !frame->scene) return fail(GN_E_INVAL, "gbuf and scene must be non-NULL");
+  if (!aligned4(frame->gbuf) || !aligned4(frame->scene))
+    return fail(GN_E_INVAL, "device pointers must be 4-byte aligned");
+  const size_t hw = (size_t)frame->h * frame->w;
+  if (overlaps(state, need, frame->gbuf, sizeof(float) * frame->n * gn::kNG * hw) ||
+      overlaps(state, need, frame->scene, sizeof(float) * frame->n * gn::kNS))
+    return fail(GN_E_INVAL, "state aliases an input buffer");
+  DeviceGuard dg(h->device);
+  {
+    std::lock_guard<std::mutex> lk(h->stream_mu);
+    // a state that reuses (part of) the memory of earlier ones replaces them
+    for (auto it = h->streams.begin(); it != h->streams.end();) {
+      if (overlaps((const void *)it->first, it->second.bytes, state, need))
+        it = h->streams.erase(it);
+      else
+        ++it;
+    }
+    h->streams[(uintptr_t)state] = GnStreamRec{frame->n, frame->h, frame->w, need, true};
+  }
+  gn::FwdBatch b = stream_batch(frame);
+  b.layers = nullptr;     // BEGIN reads the G-buffer and the scene vector only
+  b.k = 0;
+  const hipError_t e = gn::launch_fwd_stream(h->W, h->cfg.precision, h->cfg.pool, h->d_packed,
+                                             h->pl, b, h->act_scale, h->num_cus, gn::FWD_BEGIN,
+                                             (uint8_t *)state, 0, (hipStream_t)hip_stream);
+  return gn_check_device(h, e, "stream begin launch");
+}
+
+gn_status glassnet_stream_accumulate(gn_handle *h, const gn_frame *frame, void *state,
+                                     void *hip_stream) {
+  gn_status st = precheck(h);
+  if (st != GN_OK) return st;
+  if (!frame || !state) return fail(GN_E_INVAL, "frame and state must be non-NULL");
+  if (frame->k < 0 || frame->k > h->cfg.k_max)
+    return fail(GN_E_INVAL, "k=%d outside [0, k_max=%d]", frame->k, h->cfg.k_max);
+  if (frame->k > 0 && !frame->layers) return fail(GN_E_INVAL, "layers is NULL with k=%d", frame->k);
+  if (!aligned4(frame->layers)) return fail(GN_E_INVAL, "device pointers must be 4-byte aligned");
+  std::lock_guard<std::mutex> lk(h->stream_mu);
+  GnStreamRec *rec = nullptr;
+  st = stream_lookup(h, frame, state, &rec);
+  if (st != GN_OK) return st;
+  if (frame->k == 0) return GN_OK;
+  const size_t hw = (size_t)frame->h * frame->w;
+  if (overlaps(state, rec->bytes, frame->layers, sizeof(float) * frame->n * frame->k * gn::kNL * hw))
+    return fail(GN_E_INVAL, "state aliases the layers buffer");
+  DeviceGuard dg(h->device);
+  const gn::FwdBatch b = stream_batch(frame);
+  const hipError_t e = gn::launch_fwd_stream(h->W, h->cfg.precision, h->cfg.pool, h->d_packed,
+                                             h->pl, b, h->act_scale, h->num_cus, gn::FWD_ACC,
+                                             (uint8_t *)state, rec->fresh ? 0 : 1,
+                                             (hipStream_t)hip_stream);
+  rec->fresh = false;
+  return gn_check_device(h, e, "stream accumulate launch");
+}
+
+gn_status glassnet_stream_finish(gn_handle *h, const gn_frame *frame, void *state, float *out,
+                                 void *hip_stream) {
+  gn_status st = precheck(h);
+  if (st != GN_OK) return st;
+  if (!frame || !state || !out) return fail(GN_E_INVAL, "frame, state and out must be non-NULL");
+  if (!frame->gbuf) return fail(GN_E_INVAL, "gbuf must be non-NULL");
+  if (!aligned4(frame->gbuf) || !aligned4(out))
+    return fail(GN_E_INVAL, "device pointers must be 4-byte aligned");
+  std::lock_guard<std::mutex> lk(h->stream_mu);
+  GnStreamRec *rec = nullptr;
+  st = stream_lookup(h, frame, state, &rec);
+  if (st != GN_OK) return st;
+  const size_t hw = (size_t)frame->h * frame->w;
+  const size_t ob = sizeof(float) * frame->n * gn::kNOUT * hw;
+  if (overlaps(out, ob, frame->gbuf, sizeof(float) * frame->n * gn::kNG * hw) ||
+      overlaps(out, ob, state, rec->bytes))
+    return fail(GN_E_INVAL, "out aliases gbuf or the state");
+  DeviceGuard dg(h->device);
+  gn::FwdBatch b = stream_batch(frame);
+  b.layers = nullptr;     // FINISH reads L_d from the G-buffer and the state only
+  b.scene = nullptr;
+  b.k = 0;
+  b.out = out;
+  const hipError_t e = gn::launch_fwd_stream(h->W, h->cfg.precision, h->cfg.pool, h->d_packed,
+                                             h->pl, b, h->act_scale, h->num_cus, gn::FWD_FINISH,
+                                             (uint8_t *)state, rec->fresh ? 0 : 1,
+                                             (hipStream_t)hip_stream);
+  return gn_check_device(h, e, "stream finish launch");
+}
+
+gn_status glassnet_stream_release(gn_handle *h, void *state) {
+  if (!h || !state) return fail(GN_E_INVAL, "NULL argument");
+  std::lock_guard<std::mutex> lk(h->stream_mu);
+  if (!h->streams.erase((uintptr_t)state))
+    return fail(GN_E_INVAL, "state %p was not begun with glassnet_stream_begin", state);
+  return GN_OK;
+}
+
 gn_status glassnet_l1_loss(gn_handle *h, const float *out, const float *target, uint64_t count,
                            float *loss, float *grad_out, void *hip_stream) {
   gn_status st = precheck(h);

@@ -36,6 +36,8 @@ typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 typedef int i32x8 __attribute__((ext_vector_type(8)));
 typedef const float __attribute__((address_space(1))) gcfloat;
 typedef float __attribute__((address_space(1))) gfloat;
+typedef u32x4 __attribute__((address_space(1))) gu32x4;
+typedef f32x4 __attribute__((address_space(1))) gf32x4;
 
 constexpr int kWaves = 8;
 constexpr int kNT = 2;                // N-tiles of 16 pixels per wave
@@ -58,6 +60,8 @@ struct MfmaArgs {
   int sig_lds_waves;                   // waves 0 .. n-1 park sigma in LDS instead:
   int sig_tail_waves;                  // the first n - t after the stage buffers, the
                                        // last t in the stage buffers' idle tails
+  uint8_t *state;                      // object streaming: per-tile state (modes other than FULL)
+  int state_load;                      // 1: the state holds a running sum to continue from
 };
 
 // Two floats -> packed bf16 pair (round to nearest even), one v_cvt_pk_bf16_f32.
@@ -257,9 +261,28 @@ struct Shape {
   static constexpr int kBiasBytes = kNumLayers * W * 4;
 };
 
-template <int W, int PREC>
+// Object-streaming state of one tile (modes other than FWD_FULL): sigma as
+// bf16 B fragments [wave][t][ks][lane], the running masked sum Z of h's hidden
+// layer as fp32 accumulator rows [wave][t][mt][lane], the active-slot count
+// [wave][t][pixel column].  Every access is a whole 16-byte lane vector.
+template <int W>
+struct StreamTile {
+  static constexpr int64_t kSig = (int64_t)kWaves * kNT * (W / 32) * kFrag;
+  static constexpr int64_t kZ = (int64_t)kWaves * kNT * (W / 16) * kFrag;
+  static constexpr int64_t kCnt = (int64_t)kWaves * kNT * 16 * 4;
+  static constexpr int64_t kBytes = kSig + kZ + kCnt;
+};
+
+// MODE selects the part of the path one launch runs: FWD_FULL the whole
+// forward; FWD_BEGIN stages 0-1 (sigma into the state); FWD_ACC stage 2 (the
+// slot loop, continuing the state's running sum); FWD_FINISH stages 3-9 from
+// the state.  FWD_FULL compiles to the code it had before the modes existed.
+template <int W, int PREC, int MODE>
 __global__ __launch_bounds__(kThreads) void fwd_mfma_kernel(MfmaArgs a) {
   constexpr int MT = Shape<W>::MT, KS = Shape<W>::KS;
+  constexpr bool kSlots = MODE == FWD_FULL || MODE == FWD_ACC;     // runs the slot loop
+  constexpr bool kTrunk = MODE == FWD_FULL || MODE == FWD_BEGIN;   // runs F
+  constexpr bool kHead = MODE == FWD_FULL || MODE == FWD_FINISH;   // runs T3, B, R
   extern __shared__ __attribute__((aligned(1024))) uint8_t lds[];
   const int wave = threadIdx.x >> 6;
 
@@ -273,7 +296,10 @@ __global__ __launch_bounds__(kThreads) void fwd_mfma_kernel(MfmaArgs a) {
     stage_max = max(stage_max, a.stage_off[s + 1] - a.stage_off[s]);
   uint8_t *L_stage0 = lds + res_bytes + Shape<W>::kBiasBytes;
   uint8_t *L_stage1 = L_stage0 + stage_max;
-  auto stage_buf = [&](int s) { return (s & 1) ? L_stage1 : L_stage0; };
+  // FWD_FINISH runs an odd number of stages per tile, so its buffer parity
+  // flips from one tile to the next (par); every other mode keeps par = 0.
+  int par = 0;
+  auto stage_buf = [&](int s) { return ((s + par) & 1) ? L_stage1 : L_stage0; };
   // resident weights of the slot loop and all biases, once per workgroup
   const int lane0 = threadIdx.x & 63;
   auto fill_stage0 = [&](int s) {
@@ -282,15 +308,27 @@ __global__ __launch_bounds__(kThreads) void fwd_mfma_kernel(MfmaArgs a) {
   };
   // bf16: [T1A | T2 (bf16)]; fp8: [T1A | T2 (fp8, 2 KiB fragments) | T2 row scales]
   constexpr bool kFp8 = PREC == GN_FP8_T;
-  if (kFp8) {
-    constexpr int64_t t1a = (MT * 512 + 1023) & ~1023;
-    lds_fill(L_res, a.packed + a.res_off, t1a, wave, lane0);
-    lds_fill(L_res + t1a, a.packed + a.t2q_off, res_bytes - t1a, wave, lane0);
-  } else {
-    lds_fill(L_res, a.packed + a.res_off, res_bytes, wave, lane0);
+  if constexpr (kSlots) {
+    if (kFp8) {
+      constexpr int64_t t1a = (MT * 512 + 1023) & ~1023;
+      lds_fill(L_res, a.packed + a.res_off, t1a, wave, lane0);
+      lds_fill(L_res + t1a, a.packed + a.t2q_off, res_bytes - t1a, wave, lane0);
+    } else {
+      lds_fill(L_res, a.packed + a.res_off, res_bytes, wave, lane0);
+    }
   }
   lds_fill((uint8_t *)L_bias, a.packed + a.bias_off, Shape<W>::kBiasBytes, wave, lane0);
-  if ((int)blockIdx.x < a.ntiles) fill_stage0(0);
+  if ((int)blockIdx.x < a.ntiles) {
+    // FULL streams every stage; BEGIN and ACC keep their few stages resident
+    // for the whole launch; FINISH starts its pipeline at stage 3.
+    if constexpr (MODE == FWD_FULL) fill_stage0(0);
+    if constexpr (MODE == FWD_BEGIN) {
+      fill_stage0(0);
+      fill_stage0(1);
+    }
+    if constexpr (MODE == FWD_ACC) fill_stage0(2);
+    if constexpr (MODE == FWD_FINISH) fill_stage0(3);
+  }
   wait_vm();
   __syncthreads();
 
@@ -298,7 +336,7 @@ __global__ __launch_bounds__(kThreads) void fwd_mfma_kernel(MfmaArgs a) {
   const uint8_t *T1A = L_res;
   const uint8_t *T2 = L_res + kT1ABytes;                           // bf16 form
   float *T2scale = (float *)(L_res + kT1ABytes + MT * 2 * kFrag);  // fp8 form
-  if (kFp8) {
+  if (kFp8 && kSlots) {
     // dequantisation factor of the fp8 layer: weight row scale x activation scale
     if ((int)threadIdx.x < W) T2scale[threadIdx.x] *= a.sa;
     __syncthreads();
@@ -361,7 +399,7 @@ __global__ __launch_bounds__(kThreads) void fwd_mfma_kernel(MfmaArgs a) {
   TileInfo nti;
   if ((int)blockIdx.x < a.ntiles) {
     nti = resolve(blockIdx.x);
-    load_x(nti, lane0, xr);
+    if constexpr (kTrunk) load_x(nti, lane0, xr);
   }
 
   for (int tile = blockIdx.x; tile < a.ntiles; tile += gridDim.x) {
@@ -391,29 +429,16 @@ __global__ __launch_bounds__(kThreads) void fwd_mfma_kernel(MfmaArgs a) {
       valid[t] = q < hw;
       qc[t] = valid[t] ? q : hw - 1;          // tail lanes recompute a real pixel
     }
+    // this wave's part of the tile's streaming state
+    uint8_t *st = a.state + (size_t)tile * StreamTile<W>::kBytes;
+    gu32x4 *st_sig = (gu32x4 *)(st + (size_t)wave * (kNT * KS * kFrag)) + lane;
+    gf32x4 *st_z = (gf32x4 *)(st + StreamTile<W>::kSig + (size_t)wave * (kNT * MT * kFrag)) + lane;
+    gfloat *st_cnt = (gfloat *)(st + StreamTile<W>::kSig + StreamTile<W>::kZ) + wave * (kNT * 16) + col;
+    u32x4 sig[kNT][KS];   // sigma: from F (FULL, BEGIN) or from the state (ACC)
+    f32x4 Z[kNT][MT];     // running masked sum of h's hidden layer, and
+    float cnt[kNT];       // the number of active slots it holds
 
-    // ================= stage 0: F layers 1-2 =================
-    fill_stage(1);
-    u32x4 h2[kNT][KS];
-    {
-      u32x4 x[kNT][1];
-#pragma unroll
-      for (int t = 0; t < kNT; ++t)
-        x[t][0] = u32x4{pk_bf16(xr[t][0], xr[t][1]), pk_bf16(xr[t][2], xr[t][3]),
-                        pk_bf16(xr[t][4], xr[t][5]), pk_bf16(xr[t][6], xr[t][7])};
-      const uint8_t *S = stage_buf(0);
-      u32x4 h1[kNT][KS];
-      layer<MT, 1, true>(h1, S, x, bF1, g, lane);
-      layer<MT, KS, true>(h2, S + f1_bytes, h1, bF2, g, lane);
-    }
-    wait_vm();
-    __syncthreads();
-
-    // ================= stage 1: F layer 3 -> sigma =================
-    fill_stage(2);
-    u32x4 sig[kNT][KS];   // live in stage 1 only; reloaded in stage 3
-    layer<MT, KS, false>(sig, stage_buf(1), h2, bF3, g, lane);
-    // sigma is needed again only by B's first layer: park it in this wave's
+    // FULL: sigma is needed again only by B's first layer: park it in this wave's
     // scratch instead of holding 32 registers through the slot loop
     // (LDS left free by the weights holds it for the first sig_lds_waves
     // waves; the others use a per-wave slot in HBM)
@@ -426,267 +451,356 @@ __global__ __launch_bounds__(kThreads) void fwd_mfma_kernel(MfmaArgs a) {
                                     : ((wave - nfree) & 1 ? L_stage1 : L_stage0) + stage_max -
                                           (size_t)(1 + (wave - nfree) / 2) * kSigBytes;
     uint8_t *sig_slot = a.sig_scratch + ((size_t)blockIdx.x * kWaves + wave) * kSigBytes;
-    if (sig_in_lds) {
-#pragma unroll
-      for (int t = 0; t < kNT; ++t)
-#pragma unroll
-        for (int k = 0; k < KS; ++k) *(u32x4 *)(sig_lds + (t * KS + k) * kFrag + lane * 16) = sig[t][k];
-    } else {
-#pragma unroll
-      for (int t = 0; t < kNT; ++t)
-#pragma unroll
-        for (int k = 0; k < KS; ++k) *(u32x4 *)(sig_slot + (t * KS + k) * kFrag + lane * 16) = sig[t][k];
-    }
-    // the kNT x KS stores above stay in flight; the same wave reads them back
-    // in stage 3, after stage 2's full wait
-    if (sig_in_lds)
-      stage_sync_after_stores<0>();
-    else
-      stage_sync_after_stores<kNT * KS>();
 
-    // ================= stage 2: u = W1s sigma + c1, then the slot loop =======
-    fill_stage(3);
-    f32x4 Z[kNT][MT];
-    float cnt[kNT];
-    {
-      // u = W1s sigma + c1 in fp32 accumulator layout: the C operand of h's
-      // first layer for every slot
-      f32x4 u[kNT][MT];
-      bias_init(u, bT1, g);
-      mm<MT, KS>(u, stage_buf(2), sig, lane);
+    if constexpr (kTrunk) {
+      // ================= stage 0: F layers 1-2 =================
+      if constexpr (MODE == FWD_FULL) fill_stage(1);
+      u32x4 h2[kNT][KS];
+      {
+        u32x4 x[kNT][1];
 #pragma unroll
-      for (int t = 0; t < kNT; ++t) {
-        cnt[t] = 0.0f;
-#pragma unroll
-        for (int mt = 0; mt < MT; ++mt) Z[t][mt] = f32x4{0.f, 0.f, 0.f, 0.f};
+        for (int t = 0; t < kNT; ++t)
+          x[t][0] = u32x4{pk_bf16(xr[t][0], xr[t][1]), pk_bf16(xr[t][2], xr[t][3]),
+                          pk_bf16(xr[t][4], xr[t][5]), pk_bf16(xr[t][6], xr[t][7])};
+        const uint8_t *S = stage_buf(0);
+        u32x4 h1[kNT][KS];
+        layer<MT, 1, true>(h1, S, x, bF1, g, lane);
+        layer<MT, KS, true>(h2, S + f1_bytes, h1, bF2, g, lane);
       }
-      // Slot inputs: lane group g < 3 carries planes 4g..4g+3 of its pixel (the
-      // K=16 operand of h's first layer); the next slot's planes are loaded
-      // one slot ahead so their latency overlaps the current slot's work.
-      float nxt[kNT][4];
-      auto load_slot = [&](int i) {
-        gcfloat *Li = Lp + (size_t)i * kNL * hw;
-        int qs[kNT];
-#pragma unroll
-        for (int t = 0; t < kNT; ++t) {
-          qs[t] = qc[t];
-          asm volatile("" : "+v"(qs[t]));   // per-slot addresses stay in the loop body
-        }
+      if constexpr (MODE == FWD_FULL) {
+        wait_vm();
+        __syncthreads();
+      }
+
+      // ================= stage 1: F layer 3 -> sigma =================
+      if constexpr (MODE == FWD_FULL) fill_stage(2);
+      layer<MT, KS, false>(sig, stage_buf(1), h2, bF3, g, lane);
+      if constexpr (MODE == FWD_BEGIN) {
+        // sigma goes to the streaming state; the next tile's F input is requested
 #pragma unroll
         for (int t = 0; t < kNT; ++t)
 #pragma unroll
-          for (int j = 0; j < 4; ++j)
-            nxt[t][j] = g < 3 ? Li[(size_t)(4 * g + j) * hw + qs[t]] : 0.0f;
-      };
-      if (K > 0) load_slot(0);
-      for (int i = 0; i < K; ++i) {
-        float cur[kNT][4];
-#pragma unroll
-        for (int t = 0; t < kNT; ++t)
-#pragma unroll
-          for (int j = 0; j < 4; ++j) cur[t][j] = nxt[t][j];
-        if (i + 1 < K) load_slot(i + 1);
-        uint2 bi[kNT];
-        float m[kNT];
-#pragma unroll
-        for (int t = 0; t < kNT; ++t) {
-          bi[t] = uint2{pk_bf16(cur[t][0], cur[t][1]), pk_bf16(cur[t][2], cur[t][3])};
-          // alpha (plane 9) sits in lane group 2 at position 1: broadcast it
-          const float al = __int_as_float(
-              __builtin_amdgcn_ds_bpermute((col + 32) * 4, __float_as_int(cur[t][1])));
-          m[t] = al > 0.0f ? 1.0f : 0.0f;
+          for (int k = 0; k < KS; ++k) st_sig[(t * KS + k) * 64] = sig[t][k];
+        if (has_next) {
+          nti = resolve(tile + gridDim.x);
+          load_x(nti, lane, xr);
         }
-        if constexpr (kFp8) {
-        // h layer 1 (bf16 MFMA), output quantised to E4M3 with the static
-        // activation scale: lane byte 4*mt + r holds row 16*mt + 4*g + r, the
-        // order the fp8 weights of layer 2 were packed in.
-        i32x8 zq[kNT];
+      } else {
+        if (sig_in_lds) {
 #pragma unroll
-        for (int mt = 0; mt < MT; ++mt) {
-          const uint2 w = ld_frag16(T1A, mt, lane);
+          for (int t = 0; t < kNT; ++t)
 #pragma unroll
-          for (int t = 0; t < kNT; ++t) {
-            const f32x4 v = mma16(w, bi[t], u[t][mt]);
-            zq[t][mt] = pack_fp8x4(relu4(v) * a.inv_sa);
-          }
-        }
-        // h layer 2 on the fp8 matrix cores (K = 128 in one instruction),
-        // dequantised per output row, then the masked running sum.
-#pragma unroll
-        for (int mt = 0; mt < MT; ++mt) {
-          const i32x8 w = ld_frag8(T2, mt, lane);
-          const f32x4 sc = *(const f32x4 *)(T2scale + 16 * mt + 4 * g);
-          const f32x4 b = *(const f32x4 *)(bT2 + 16 * mt + 4 * g);
-#pragma unroll
-          for (int t = 0; t < kNT; ++t) {
-            const f32x4 acc = mma_fp8(w, zq[t], f32x4{0.f, 0.f, 0.f, 0.f});
-            Z[t][mt].x = fmaf(m[t], relu1(fmaf(acc.x, sc.x, b.x)), Z[t][mt].x);
-            Z[t][mt].y = fmaf(m[t], relu1(fmaf(acc.y, sc.y, b.y)), Z[t][mt].y);
-            Z[t][mt].z = fmaf(m[t], relu1(fmaf(acc.z, sc.z, b.z)), Z[t][mt].z);
-            Z[t][mt].w = fmaf(m[t], relu1(fmaf(acc.w, sc.w, b.w)), Z[t][mt].w);
-          }
-        }
+            for (int k = 0; k < KS; ++k) *(u32x4 *)(sig_lds + (t * KS + k) * kFrag + lane * 16) = sig[t][k];
         } else {
-        // h layer 1: z1 = relu(W1b b_i + u)
-        u32x4 z1[kNT][KS];
 #pragma unroll
-        for (int p = 0; p < KS; ++p) {
+          for (int t = 0; t < kNT; ++t)
 #pragma unroll
-          for (int h = 0; h < 2; ++h) {
-            const uint2 w = ld_frag16(T1A, 2 * p + h, lane);
+            for (int k = 0; k < KS; ++k) *(u32x4 *)(sig_slot + (t * KS + k) * kFrag + lane * 16) = sig[t][k];
+        }
+        // the kNT x KS stores above stay in flight; the same wave reads them back
+        // in stage 3, after stage 2's full wait
+        if (sig_in_lds)
+          stage_sync_after_stores<0>();
+        else
+          stage_sync_after_stores<kNT * KS>();
+      }
+    }
+
+    if constexpr (kSlots) {
+      // ================= stage 2: u = W1s sigma + c1, then the slot loop =======
+      if constexpr (MODE == FWD_FULL) fill_stage(3);
+      if constexpr (MODE == FWD_ACC) {
+#pragma unroll
+        for (int t = 0; t < kNT; ++t)
+#pragma unroll
+          for (int k = 0; k < KS; ++k) sig[t][k] = st_sig[(t * KS + k) * 64];
+      }
+      {
+        // u = W1s sigma + c1 in fp32 accumulator layout: the C operand of h's
+        // first layer for every slot
+        f32x4 u[kNT][MT];
+        bias_init(u, bT1, g);
+        mm<MT, KS>(u, stage_buf(2), sig, lane);
+#pragma unroll
+        for (int t = 0; t < kNT; ++t) {
+          cnt[t] = 0.0f;
+#pragma unroll
+          for (int mt = 0; mt < MT; ++mt) Z[t][mt] = f32x4{0.f, 0.f, 0.f, 0.f};
+        }
+        if constexpr (MODE == FWD_ACC) {
+          if (a.state_load) {     // continue the running sum of earlier calls
 #pragma unroll
             for (int t = 0; t < kNT; ++t) {
-              const f32x4 v = mma16(w, bi[t], u[t][2 * p + h]);
-              z1[t][p][2 * h] = relu_bf16x2(pk_bf16(v.x, v.y));
-              z1[t][p][2 * h + 1] = relu_bf16x2(pk_bf16(v.z, v.w));
+              cnt[t] = st_cnt[t * 16];
+#pragma unroll
+              for (int mt = 0; mt < MT; ++mt) Z[t][mt] = st_z[(t * MT + mt) * 64];
             }
           }
         }
-        // h layer 2 and the masked running sum: Z += m * relu(A2 z1 + c2)
-#pragma unroll
-        for (int mt = 0; mt < MT; ++mt) {
-          const f32x4 b = *(const f32x4 *)(bT2 + 16 * mt + 4 * g);
-          f32x4 acc[kNT];
-#pragma unroll
-          for (int t = 0; t < kNT; ++t) acc[t] = b;
-#pragma unroll
-          for (int ks = 0; ks < KS; ++ks) {
-            const u32x4 w = ld_frag(T2, mt * KS + ks, lane);
-#pragma unroll
-            for (int t = 0; t < kNT; ++t) acc[t] = mma(w, z1[t][ks], acc[t]);
-          }
+        // Slot inputs: lane group g < 3 carries planes 4g..4g+3 of its pixel (the
+        // K=16 operand of h's first layer); the next slot's planes are loaded
+        // one slot ahead so their latency overlaps the current slot's work.
+        float nxt[kNT][4];
+        auto load_slot = [&](int i) {
+          gcfloat *Li = Lp + (size_t)i * kNL * hw;
+          int qs[kNT];
 #pragma unroll
           for (int t = 0; t < kNT; ++t) {
-            const f32x4 r = relu4(acc[t]);    // one v_med3 each
-            Z[t][mt].x = fmaf(m[t], r.x, Z[t][mt].x);
-            Z[t][mt].y = fmaf(m[t], r.y, Z[t][mt].y);
-            Z[t][mt].z = fmaf(m[t], r.z, Z[t][mt].z);
-            Z[t][mt].w = fmaf(m[t], r.w, Z[t][mt].w);
+            qs[t] = qc[t];
+            asm volatile("" : "+v"(qs[t]));   // per-slot addresses stay in the loop body
+          }
+#pragma unroll
+          for (int t = 0; t < kNT; ++t)
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+              nxt[t][j] = g < 3 ? Li[(size_t)(4 * g + j) * hw + qs[t]] : 0.0f;
+        };
+        if (K > 0) load_slot(0);
+        for (int i = 0; i < K; ++i) {
+          float cur[kNT][4];
+#pragma unroll
+          for (int t = 0; t < kNT; ++t)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) cur[t][j] = nxt[t][j];
+          if (i + 1 < K) load_slot(i + 1);
+          uint2 bi[kNT];
+          float m[kNT];
+#pragma unroll
+          for (int t = 0; t < kNT; ++t) {
+            bi[t] = uint2{pk_bf16(cur[t][0], cur[t][1]), pk_bf16(cur[t][2], cur[t][3])};
+            // alpha (plane 9) sits in lane group 2 at position 1: broadcast it
+            const float al = __int_as_float(
+                __builtin_amdgcn_ds_bpermute((col + 32) * 4, __float_as_int(cur[t][1])));
+            m[t] = al > 0.0f ? 1.0f : 0.0f;
+          }
+          if constexpr (kFp8) {
+          // h layer 1 (bf16 MFMA), output quantised to E4M3 with the static
+          // activation scale: lane byte 4*mt + r holds row 16*mt + 4*g + r, the
+          // order the fp8 weights of layer 2 were packed in.
+          i32x8 zq[kNT];
+#pragma unroll
+          for (int mt = 0; mt < MT; ++mt) {
+            const uint2 w = ld_frag16(T1A, mt, lane);
+#pragma unroll
+            for (int t = 0; t < kNT; ++t) {
+              const f32x4 v = mma16(w, bi[t], u[t][mt]);
+              zq[t][mt] = pack_fp8x4(relu4(v) * a.inv_sa);
+            }
+          }
+          // h layer 2 on the fp8 matrix cores (K = 128 in one instruction),
+          // dequantised per output row, then the masked running sum.
+#pragma unroll
+          for (int mt = 0; mt < MT; ++mt) {
+            const i32x8 w = ld_frag8(T2, mt, lane);
+            const f32x4 sc = *(const f32x4 *)(T2scale + 16 * mt + 4 * g);
+            const f32x4 b = *(const f32x4 *)(bT2 + 16 * mt + 4 * g);
+#pragma unroll
+            for (int t = 0; t < kNT; ++t) {
+              const f32x4 acc = mma_fp8(w, zq[t], f32x4{0.f, 0.f, 0.f, 0.f});
+              Z[t][mt].x = fmaf(m[t], relu1(fmaf(acc.x, sc.x, b.x)), Z[t][mt].x);
+              Z[t][mt].y = fmaf(m[t], relu1(fmaf(acc.y, sc.y, b.y)), Z[t][mt].y);
+              Z[t][mt].z = fmaf(m[t], relu1(fmaf(acc.z, sc.z, b.z)), Z[t][mt].z);
+              Z[t][mt].w = fmaf(m[t], relu1(fmaf(acc.w, sc.w, b.w)), Z[t][mt].w);
+            }
+          }
+          } else {
+          // h layer 1: z1 = relu(W1b b_i + u)
+          u32x4 z1[kNT][KS];
+#pragma unroll
+          for (int p = 0; p < KS; ++p) {
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+              const uint2 w = ld_frag16(T1A, 2 * p + h, lane);
+#pragma unroll
+              for (int t = 0; t < kNT; ++t) {
+                const f32x4 v = mma16(w, bi[t], u[t][2 * p + h]);
+                z1[t][p][2 * h] = relu_bf16x2(pk_bf16(v.x, v.y));
+                z1[t][p][2 * h + 1] = relu_bf16x2(pk_bf16(v.z, v.w));
+              }
+            }
+          }
+          // h layer 2 and the masked running sum: Z += m * relu(A2 z1 + c2).
+          // The fragments stream one K-step ahead of the MFMAs that use them.
+          u32x4 wnext = ld_frag(T2, 0, lane);
+#pragma unroll
+          for (int mt = 0; mt < MT; ++mt) {
+            const f32x4 b = *(const f32x4 *)(bT2 + 16 * mt + 4 * g);
+            f32x4 acc[kNT];
+#pragma unroll
+            for (int t = 0; t < kNT; ++t) acc[t] = b;
+#pragma unroll
+            for (int ks = 0; ks < KS; ++ks) {
+              const u32x4 w = wnext;
+              if (mt * KS + ks + 1 < MT * KS) wnext = ld_frag(T2, mt * KS + ks + 1, lane);
+#pragma unroll
+              for (int t = 0; t < kNT; ++t) acc[t] = mma(w, z1[t][ks], acc[t]);
+            }
+#pragma unroll
+            for (int t = 0; t < kNT; ++t) {
+              const f32x4 r = relu4(acc[t]);    // one v_med3 each
+              Z[t][mt].x = fmaf(m[t], r.x, Z[t][mt].x);
+              Z[t][mt].y = fmaf(m[t], r.y, Z[t][mt].y);
+              Z[t][mt].z = fmaf(m[t], r.z, Z[t][mt].z);
+              Z[t][mt].w = fmaf(m[t], r.w, Z[t][mt].w);
+            }
+          }
+          }
+#pragma unroll
+          for (int t = 0; t < kNT; ++t) cnt[t] += m[t];
+        }
+      }
+      if constexpr (MODE == FWD_ACC) {
+#pragma unroll
+        for (int t = 0; t < kNT; ++t) {
+          if (g == 0) st_cnt[t * 16] = cnt[t];
+#pragma unroll
+          for (int mt = 0; mt < MT; ++mt) st_z[(t * MT + mt) * 64] = Z[t][mt];
+        }
+        if (has_next) nti = resolve(tile + gridDim.x);
+      } else {
+        wait_vm();
+        __syncthreads();
+      }
+    }
+
+    if constexpr (kHead) {
+      // ================= stage 3: pool and h layer 3 -> tau =================
+      fill_stage(4);
+      u32x4 sig2[kNT][KS];
+      if constexpr (MODE == FWD_FINISH) {
+        // the pool state and sigma come from the streaming state
+#pragma unroll
+        for (int t = 0; t < kNT; ++t) {
+          cnt[t] = a.state_load ? st_cnt[t * 16] : 0.0f;
+#pragma unroll
+          for (int mt = 0; mt < MT; ++mt)
+            Z[t][mt] = a.state_load ? st_z[(t * MT + mt) * 64] : f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+          for (int k = 0; k < KS; ++k) sig2[t][k] = st_sig[(t * KS + k) * 64];
+        }
+      } else {
+#pragma unroll
+        for (int t = 0; t < kNT; ++t)
+#pragma unroll
+          for (int k = 0; k < KS; ++k)
+            sig2[t][k] = sig_in_lds ? *(const u32x4 *)(sig_lds + (t * KS + k) * kFrag + lane * 16)
+                                    : *(const u32x4 *)(sig_slot + (t * KS + k) * kFrag + lane * 16);
+      }
+      u32x4 tau[kNT][KS];
+      {
+        u32x4 zs[kNT][KS];
+        f32x4 acc[kNT][MT];
+#pragma unroll
+        for (int t = 0; t < kNT; ++t) {
+          const bool mean = a.pool == GN_POOL_MEAN;
+          const float inv = mean ? 1.0f / fmaxf(cnt[t], 1.0f) : 1.0f;
+          const float bs = mean ? (cnt[t] > 0.0f ? 1.0f : 0.0f) : cnt[t];
+#pragma unroll
+          for (int mt = 0; mt < MT; ++mt) {
+            const f32x4 v = Z[t][mt] * inv;
+            zs[t][mt >> 1][2 * (mt & 1)] = pk_bf16(v.x, v.y);
+            zs[t][mt >> 1][2 * (mt & 1) + 1] = pk_bf16(v.z, v.w);
+            acc[t][mt] = *(const f32x4 *)(bT3 + 16 * mt + 4 * g) * bs;
           }
         }
-        }
-#pragma unroll
-        for (int t = 0; t < kNT; ++t) cnt[t] += m[t];
+        mm<MT, KS>(acc, stage_buf(3), zs, lane);
+        to_frags<MT, false>(acc, tau);
       }
-    }
-    wait_vm();
-    __syncthreads();
+      wait_vm();
+      __syncthreads();
 
-    // ================= stage 3: pool and h layer 3 -> tau =================
-    fill_stage(4);
-    u32x4 sig2[kNT][KS];
-#pragma unroll
-    for (int t = 0; t < kNT; ++t)
-#pragma unroll
-      for (int k = 0; k < KS; ++k)
-        sig2[t][k] = sig_in_lds ? *(const u32x4 *)(sig_lds + (t * KS + k) * kFrag + lane * 16)
-                                : *(const u32x4 *)(sig_slot + (t * KS + k) * kFrag + lane * 16);
-    u32x4 tau[kNT][KS];
-    {
-      u32x4 zs[kNT][KS];
-      f32x4 acc[kNT][MT];
-#pragma unroll
-      for (int t = 0; t < kNT; ++t) {
-        const bool mean = a.pool == GN_POOL_MEAN;
-        const float inv = mean ? 1.0f / fmaxf(cnt[t], 1.0f) : 1.0f;
-        const float bs = mean ? (cnt[t] > 0.0f ? 1.0f : 0.0f) : cnt[t];
-#pragma unroll
-        for (int mt = 0; mt < MT; ++mt) {
-          const f32x4 v = Z[t][mt] * inv;
-          zs[t][mt >> 1][2 * (mt & 1)] = pk_bf16(v.x, v.y);
-          zs[t][mt >> 1][2 * (mt & 1) + 1] = pk_bf16(v.z, v.w);
-          acc[t][mt] = *(const f32x4 *)(bT3 + 16 * mt + 4 * g) * bs;
-        }
-      }
-      mm<MT, KS>(acc, stage_buf(3), zs, lane);
-      to_frags<MT, false>(acc, tau);
-    }
-    wait_vm();
-    __syncthreads();
+      // ================= stages 4-5: B layer 1 on [sigma; tau] =================
+      fill_stage(5);
+      f32x4 accB[kNT][MT];
+      bias_init(accB, bB1, g);
+      mm<MT, KS>(accB, stage_buf(4), sig2, lane);
+      wait_vm();
+      __syncthreads();
 
-    // ================= stages 4-5: B layer 1 on [sigma; tau] =================
-    fill_stage(5);
-    f32x4 accB[kNT][MT];
-    bias_init(accB, bB1, g);
-    mm<MT, KS>(accB, stage_buf(4), sig2, lane);
-    wait_vm();
-    __syncthreads();
+      fill_stage(6);
+      u32x4 hb[kNT][KS];
+      mm<MT, KS>(accB, stage_buf(5), tau, lane);
+      to_frags<MT, true>(accB, hb);
+      wait_vm();
+      __syncthreads();
 
-    fill_stage(6);
-    u32x4 hb[kNT][KS];
-    mm<MT, KS>(accB, stage_buf(5), tau, lane);
-    to_frags<MT, true>(accB, hb);
-    wait_vm();
-    __syncthreads();
-
-    // ================= stage 6: B layer 2 =================
-    fill_stage(7);
-    // L_d for R's first layer (stage 8), requested two stages early
-    float ldr[kNT][3];
-#pragma unroll
-    for (int t = 0; t < kNT; ++t)
-#pragma unroll
-      for (int c = 0; c < 3; ++c) ldr[t][c] = g == 0 ? Gp[(size_t)(11 + c) * hw + qc[t]] : 0.0f;
-    {
-      u32x4 hb2[kNT][KS];
-      layer<MT, KS, true>(hb2, stage_buf(6), hb, bB2, g, lane);
+      // ================= stage 6: B layer 2 =================
+      fill_stage(7);
+      // L_d for R's first layer (stage 8), requested two stages early
+      float ldr[kNT][3];
 #pragma unroll
       for (int t = 0; t < kNT; ++t)
 #pragma unroll
-        for (int k = 0; k < KS; ++k) hb[t][k] = hb2[t][k];
-    }
-    wait_vm();
-    __syncthreads();
-
-    // ================= stage 7: B layer 3 -> phi =================
-    fill_stage(8);
-    u32x4 phi[kNT][KS];
-    layer<MT, KS, false>(phi, stage_buf(7), hb, bB3, g, lane);
-    wait_vm();
-    __syncthreads();
-
-    // ================= stage 8: R layer 1 on [phi; L_d] =================
-    fill_stage(9);
-    u32x4 hr[kNT][KS];
-    {
-      u32x4 ld[kNT][1];
+        for (int c = 0; c < 3; ++c) ldr[t][c] = g == 0 ? Gp[(size_t)(11 + c) * hw + qc[t]] : 0.0f;
+      {
+        u32x4 hb2[kNT][KS];
+        layer<MT, KS, true>(hb2, stage_buf(6), hb, bB2, g, lane);
 #pragma unroll
-      for (int t = 0; t < kNT; ++t)
-        ld[t][0] = u32x4{pk_bf16(ldr[t][0], ldr[t][1]), pk_bf16(ldr[t][2], 0.0f), 0u, 0u};
-      f32x4 acc[kNT][MT];
-      bias_init(acc, bR1, g);
-      mm<MT, KS>(acc, stage_buf(8), phi, lane);
-      mm<MT, 1>(acc, stage_buf(8) + r1p_bytes, ld, lane);
-      to_frags<MT, true>(acc, hr);
-    }
-    wait_vm();
-    __syncthreads();
-
-    // ================= stage 9: R layers 2-3 -> radiance =================
-    if (has_next) {
-      fill_stage(0);
-      nti = resolve(tile + gridDim.x);
-      load_x(nti, lane, xr);
-    }
-    {
-      u32x4 hr2[kNT][KS];
-      layer<MT, KS, true>(hr2, stage_buf(9), hr, bR2, g, lane);
-      f32x4 y[kNT][1];
-      bias_init(y, bR3, g);
-      mm<1, KS>(y, stage_buf(9) + r2_bytes, hr2, lane);
-      // Lane group 0 holds rows 0..2.  Tail lanes store the value of pixel
-      // hw - 1 they recomputed (bitwise the same as that pixel's own lane),
-      // so exactly 3 kNT store instructions issue, with a non-empty mask.
+        for (int t = 0; t < kNT; ++t)
 #pragma unroll
-      for (int t = 0; t < kNT; ++t) {
-        if (g == 0) {
-          Op[qc[t]] = y[t][0].x;
-          Op[(size_t)hw + qc[t]] = y[t][0].y;
-          Op[(size_t)2 * hw + qc[t]] = y[t][0].z;
+          for (int k = 0; k < KS; ++k) hb[t][k] = hb2[t][k];
+      }
+      wait_vm();
+      __syncthreads();
+
+      // ================= stage 7: B layer 3 -> phi =================
+      fill_stage(8);
+      u32x4 phi[kNT][KS];
+      layer<MT, KS, false>(phi, stage_buf(7), hb, bB3, g, lane);
+      wait_vm();
+      __syncthreads();
+
+      // ================= stage 8: R layer 1 on [phi; L_d] =================
+      fill_stage(9);
+      u32x4 hr[kNT][KS];
+      {
+        u32x4 ld[kNT][1];
+#pragma unroll
+        for (int t = 0; t < kNT; ++t)
+          ld[t][0] = u32x4{pk_bf16(ldr[t][0], ldr[t][1]), pk_bf16(ldr[t][2], 0.0f), 0u, 0u};
+        f32x4 acc[kNT][MT];
+        bias_init(acc, bR1, g);
+        mm<MT, KS>(acc, stage_buf(8), phi, lane);
+        mm<MT, 1>(acc, stage_buf(8) + r1p_bytes, ld, lane);
+        to_frags<MT, true>(acc, hr);
+      }
+      wait_vm();
+      __syncthreads();
+
+      // ================= stage 9: R layers 2-3 -> radiance =================
+      if (has_next) {
+        if constexpr (MODE == FWD_FULL) {
+          fill_stage(0);
+          nti = resolve(tile + gridDim.x);
+          load_x(nti, lane, xr);
+        } else {
+          // the next tile's stage 3 goes to the buffer this tile's stage 8 used
+          lds_fill(((3 + (par ^ 1)) & 1) ? L_stage1 : L_stage0, packed + a.stage_off[3],
+                   a.stage_off[4] - a.stage_off[3], wave, lane);
+          nti = resolve(tile + gridDim.x);
         }
       }
+      {
+        u32x4 hr2[kNT][KS];
+        layer<MT, KS, true>(hr2, stage_buf(9), hr, bR2, g, lane);
+        f32x4 y[kNT][1];
+        bias_init(y, bR3, g);
+        mm<1, KS>(y, stage_buf(9) + r2_bytes, hr2, lane);
+        // Lane group 0 holds rows 0..2.  Tail lanes store the value of pixel
+        // hw - 1 they recomputed (bitwise the same as that pixel's own lane),
+        // so exactly 3 kNT store instructions issue, with a non-empty mask.
+#pragma unroll
+        for (int t = 0; t < kNT; ++t) {
+          if (g == 0) {
+            Op[qc[t]] = y[t][0].x;
+            Op[(size_t)hw + qc[t]] = y[t][0].y;
+            Op[(size_t)2 * hw + qc[t]] = y[t][0].z;
+          }
+        }
+      }
+      stage_sync_after_stores<3 * kNT>();
+      if constexpr (MODE == FWD_FINISH) par ^= 1;
     }
-    stage_sync_after_stores<3 * kNT>();
   }
 }
 
@@ -842,26 +956,44 @@ static size_t mfma_lds_bytes(const PackedLayout &pl, int precision) {
          (size_t)mfma_sig_free_waves(pl, precision) * kNT * (pl.W / 32) * kFrag;
 }
 
-template <int W, int PREC>
+template <int W, int PREC, int MODE>
 static hipError_t launch_one(const MfmaArgs &a, int grid, size_t lds, hipStream_t stream) {
   static bool attr_set = false;     // per process; the attribute is per function
   if (!attr_set) {
-    hipError_t e = hipFuncSetAttribute((const void *)fwd_mfma_kernel<W, PREC>,
+    hipError_t e = hipFuncSetAttribute((const void *)fwd_mfma_kernel<W, PREC, MODE>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     attr_set = true;
   }
-  hipLaunchKernelGGL((fwd_mfma_kernel<W, PREC>), dim3(grid), dim3(kThreads), lds, stream, a);
+  hipLaunchKernelGGL((fwd_mfma_kernel<W, PREC, MODE>), dim3(grid), dim3(kThreads), lds, stream, a);
   return hipGetLastError();
 }
 
-hipError_t launch_fwd_mfma(int W, int precision, int pool, const uint8_t *packed,
-                           const PackedLayout &pl, const FwdBatch *batch,
-                           const FrameDesc *frames, const TileRef *tiles, int ntiles,
-                           float fp8_act_scale, int grid, uint8_t *sig_scratch,
-                           hipStream_t stream) {
+template <int W, int PREC>
+static hipError_t launch_mode(int mode, const MfmaArgs &a, int grid, size_t lds,
+                              hipStream_t stream) {
+  switch (mode) {
+    case FWD_FULL: return launch_one<W, PREC, FWD_FULL>(a, grid, lds, stream);
+    case FWD_BEGIN: return launch_one<W, PREC, FWD_BEGIN>(a, grid, lds, stream);
+    case FWD_ACC: return launch_one<W, PREC, FWD_ACC>(a, grid, lds, stream);
+    case FWD_FINISH: return launch_one<W, PREC, FWD_FINISH>(a, grid, lds, stream);
+  }
+  return hipErrorInvalidValue;
+}
+
+size_t stream_state_tile_bytes(int W) {
+  return W == 64 ? (size_t)StreamTile<64>::kBytes : (size_t)StreamTile<128>::kBytes;
+}
+
+static hipError_t launch_impl(int W, int precision, int pool, const uint8_t *packed,
+                              const PackedLayout &pl, const FwdBatch *batch,
+                              const FrameDesc *frames, const TileRef *tiles, int ntiles,
+                              float fp8_act_scale, int grid, uint8_t *sig_scratch, int mode,
+                              uint8_t *state, int state_load, hipStream_t stream) {
   MfmaArgs a;
   a.sig_scratch = sig_scratch;
+  a.state = state;
+  a.state_load = state_load;
   mfma_sig_lds(pl, precision, &a.sig_lds_waves, &a.sig_tail_waves);
   a.packed = packed;
   for (int s = 0; s <= kNumStages; ++s) a.stage_off[s] = pl.stage_off[s];
@@ -887,11 +1019,31 @@ hipError_t launch_fwd_mfma(int W, int precision, int pool, const uint8_t *packed
   grid = std::max(1, std::min(grid, ntiles));   // the scratch holds `grid` workgroups
   const size_t lds = mfma_lds_bytes(pl, precision);
   if (precision == GN_BF16) {
-    if (W == 64) return launch_one<64, GN_BF16>(a, grid, lds, stream);
-    if (W == 128) return launch_one<128, GN_BF16>(a, grid, lds, stream);
+    if (W == 64) return launch_mode<64, GN_BF16>(mode, a, grid, lds, stream);
+    if (W == 128) return launch_mode<128, GN_BF16>(mode, a, grid, lds, stream);
   }
-  if (precision == GN_FP8_T && W == 128) return launch_one<128, GN_FP8_T>(a, grid, lds, stream);
+  if (precision == GN_FP8_T && W == 128)
+    return launch_mode<128, GN_FP8_T>(mode, a, grid, lds, stream);
   return hipErrorInvalidValue;
+}
+
+hipError_t launch_fwd_mfma(int W, int precision, int pool, const uint8_t *packed,
+                           const PackedLayout &pl, const FwdBatch *batch,
+                           const FrameDesc *frames, const TileRef *tiles, int ntiles,
+                           float fp8_act_scale, int grid, uint8_t *sig_scratch,
+                           hipStream_t stream) {
+  return launch_impl(W, precision, pool, packed, pl, batch, frames, tiles, ntiles, fp8_act_scale,
+                     grid, sig_scratch, FWD_FULL, nullptr, 0, stream);
+}
+
+hipError_t launch_fwd_stream(int W, int precision, int pool, const uint8_t *packed,
+                             const PackedLayout &pl, const FwdBatch &batch, float fp8_act_scale,
+                             int grid, int mode, uint8_t *state, int state_load,
+                             hipStream_t stream) {
+  if (mode == FWD_FULL || !state) return hipErrorInvalidValue;
+  const int tpf = (batch.hw + kTilePx - 1) / kTilePx;
+  return launch_impl(W, precision, pool, packed, pl, &batch, nullptr, nullptr, batch.n * tpf,
+                     fp8_act_scale, grid, nullptr, mode, state, state_load, stream);
 }
 
 }  // namespace gn

@@ -2,10 +2,21 @@
 #pragma once
 
 #include <atomic>
+#include <map>
+#include <mutex>
 
 #include "gn_internal.h"
 
 struct GnServer;
+
+// A caller-owned object-streaming state the handle knows about (begun by
+// glassnet_stream_begin): the frame geometry it was sized for, its bytes, and
+// whether any slot has been accumulated into it yet.
+struct GnStreamRec {
+  int32_t n, hgt, wid;
+  uint64_t bytes;
+  bool fresh;
+};
 
 struct gn_handle {
   gn_config cfg{};
@@ -24,6 +35,8 @@ struct gn_handle {
   size_t bytes_held = 0;          // device bytes of the forward state
   gn::BwdWorkspace *bwd = nullptr;
   GnServer *server = nullptr;
+  std::mutex stream_mu;                          // guards streams
+  std::map<uintptr_t, GnStreamRec> streams;      // keyed by state address
 };
 
 gn_status gn_set_error(gn_status code, const char *msg);

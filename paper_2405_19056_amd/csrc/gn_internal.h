@@ -106,6 +106,20 @@ hipError_t launch_fwd_mfma(int W, int precision, int pool, const uint8_t *packed
 size_t mfma_sig_scratch_bytes(int W, int grid);
 constexpr int kTilePx = 256;
 
+// Object streaming: the parts of the fused forward one launch runs.  BEGIN
+// evaluates F and stores sigma in the state; ACC runs the slot loop over the
+// batch's k slots, continuing the state's running sum when state_load is 1
+// (starting from zero otherwise); FINISH pools and runs T3, B and R from the
+// state (an empty pool when state_load is 0) and writes batch.out.  The state
+// holds stream_state_tile_bytes(W) bytes per tile of kTilePx pixels of each
+// frame (n x ceil(hw / kTilePx) tiles).
+enum FwdMode { FWD_FULL = 0, FWD_BEGIN = 1, FWD_ACC = 2, FWD_FINISH = 3 };
+size_t stream_state_tile_bytes(int W);
+hipError_t launch_fwd_stream(int W, int precision, int pool, const uint8_t *packed,
+                             const PackedLayout &pl, const FwdBatch &batch, float fp8_act_scale,
+                             int grid, int mode, uint8_t *state, int state_load,
+                             hipStream_t stream);
+
 hipError_t launch_l1(const float *out, const float *target, uint64_t count, float *loss,
                      float *grad, float *partials, int npart, hipStream_t stream);
 

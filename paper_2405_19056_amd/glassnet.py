@@ -59,6 +59,13 @@ _SIGS = {
                                    c_void_p]),
     "glassnet_workspace_bytes": (c_int32, [c_void_p, POINTER(c_uint64)]),
     "glassnet_calibrate": (c_int32, [c_void_p, POINTER(GnFrame), c_void_p]),
+    "glassnet_stream_state_bytes": (c_int32, [c_void_p, c_int32, c_int32, c_int32,
+                                              POINTER(c_uint64)]),
+    "glassnet_stream_begin": (c_int32, [c_void_p, POINTER(GnFrame), c_void_p, c_uint64, c_void_p]),
+    "glassnet_stream_accumulate": (c_int32, [c_void_p, POINTER(GnFrame), c_void_p, c_void_p]),
+    "glassnet_stream_finish": (c_int32, [c_void_p, POINTER(GnFrame), c_void_p, c_void_p,
+                                         c_void_p]),
+    "glassnet_stream_release": (c_int32, [c_void_p, c_void_p]),
     "serve_submit": (c_int32, [c_void_p, POINTER(GnFrame), c_void_p, POINTER(c_uint64)]),
     "serve_poll": (c_int32, [c_void_p, c_uint64, POINTER(c_int32), POINTER(GnTiming)]),
     "serve_drain": (c_int32, [c_void_p]),
@@ -113,6 +120,13 @@ def _stream(stream):
     torch = _torch()
     s = stream if stream is not None else torch.cuda.current_stream()
     return c_void_p(s.cuda_stream)
+
+
+def _state_ptr(t):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or not t.is_contiguous():
+        raise TypeError("state must be a contiguous device tensor")
+    return t.data_ptr(), t.numel() * t.element_size()
 
 
 def make_frame(gbuf, layers, scene) -> GnFrame:
@@ -212,6 +226,49 @@ class GlassNet:
         _check(lib().glassnet_l1_loss(self._h, _dev_ptr(out, "out"), _dev_ptr(target, "target"),
                                       out.numel(), _dev_ptr(loss, "loss"), gp, _stream(stream)))
         return loss
+
+    # -- object streaming
+    def stream_state_bytes(self, n, h, w) -> int:
+        b = c_uint64()
+        _check(lib().glassnet_stream_state_bytes(self._h, n, h, w, byref(b)))
+        return int(b.value)
+
+    def stream_state(self, n, h, w, device="cuda"):
+        """A device buffer sized for streaming n frames of h x w pixels."""
+        torch = _torch()
+        return torch.empty(self.stream_state_bytes(n, h, w), dtype=torch.uint8, device=device)
+
+    def stream_begin(self, gbuf, scene, state, stream=None):
+        n, c, h, w = gbuf.shape
+        if c != NUM_G or tuple(scene.shape) != (n, NUM_S):
+            raise ValueError("gbuf must be [n][14][h][w] and scene [n][16]")
+        fr = GnFrame(n, h, w, 0, _dev_ptr(gbuf, "gbuf"), None, _dev_ptr(scene, "scene"))
+        ptr, nbytes = _state_ptr(state)
+        _check(lib().glassnet_stream_begin(self._h, byref(fr), ptr, nbytes, _stream(stream)))
+
+    def stream_accumulate(self, layers, state, stream=None):
+        n, k, c, h, w = layers.shape
+        if c != NUM_L:
+            raise ValueError("layers must be [n][k][12][h][w]")
+        lp = _dev_ptr(layers, "layers") if k > 0 else None
+        fr = GnFrame(n, h, w, k, None, lp, None)
+        _check(lib().glassnet_stream_accumulate(self._h, byref(fr), _state_ptr(state)[0],
+                                                _stream(stream)))
+
+    def stream_finish(self, gbuf, state, out=None, stream=None):
+        torch = _torch()
+        n, c, h, w = gbuf.shape
+        if c != NUM_G:
+            raise ValueError("gbuf must be [n][14][h][w]")
+        if out is None:
+            out = torch.empty((n, NUM_OUT, h, w), dtype=torch.float32, device=gbuf.device)
+        fr = GnFrame(n, h, w, 0, _dev_ptr(gbuf, "gbuf"), None, None)
+        _check(lib().glassnet_stream_finish(self._h, byref(fr), _state_ptr(state)[0],
+                                            _dev_ptr(out, "out"), _stream(stream)))
+        return out
+
+    def stream_release(self, state):
+        _check(lib().glassnet_stream_release(self._h, _state_ptr(state)[0]))
 
     # -- serving
     def serve_submit(self, gbuf, layers, scene, out) -> int:

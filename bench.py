@@ -264,6 +264,51 @@ def train_phase(torch, steps=10, precision="bf16"):
             "backward_alone": time_backward(torch)}
 
 
+def stream_phase(net, g, L, s, out, torch, reps=30):
+    """Object streaming on the bench frame: begin, the K objects in calls of
+    one object each (and all K in one call), finish.  Also the accumulate
+    call alone, an HBM-bound kernel: per pixel it reads the state (sigma bf16
+    2W B, running sum fp32 4W B, count 4 B) and the object's 48 B and writes
+    the running sum and count back."""
+    n, K, _, H, Wd = L.shape
+    W = net.width
+    px = n * H * Wd
+    st = net.stream_state(n, H, Wd)
+    Ls = [L[:, i:i + 1].contiguous() for i in range(K)]
+
+    def frame(chunks):
+        net.stream_begin(g, s, st)
+        for c in chunks:
+            net.stream_accumulate(c, st)
+        net.stream_finish(g, st, out=out)
+
+    def timed(fn, n_rep):
+        for _ in range(3):
+            fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(n_rep):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / 1e3 / n_rep
+
+    t1 = timed(lambda: frame(Ls), reps)
+    tk = timed(lambda: frame([L]), reps)
+    ta = timed(lambda: net.stream_accumulate(Ls[0], st), 4 * reps)
+    acc_bytes = px * ((2 * W + 4 * W + 4) + 48 + (4 * W + 4))
+    net.stream_release(st)
+    return {"state_bytes_per_px": net.stream_state_bytes(n, H, Wd) / px,
+            "ms_per_frame_1_object_per_call": t1 * 1e3,
+            "ms_per_frame_all_objects_in_one_call": tk * 1e3,
+            "pixels_per_s_1_object_per_call": px / t1,
+            "accumulate_1_object_us": ta * 1e6,
+            "accumulate_alg_bytes": acc_bytes,
+            "accumulate_hbm_gbps": acc_bytes / ta / 1e9,
+            "accumulate_hbm_frac": acc_bytes / ta / 8e12}
+
+
 def copy_probe():
     """A plain device-to-device copy of 1 GiB, for counter scaling."""
     import torch
@@ -289,6 +334,8 @@ def main():
     ap.add_argument("--serve-seconds", type=float, default=5.0)
     ap.add_argument("--k-sweep", action="store_true")
     ap.add_argument("--no-train", action="store_true")
+    ap.add_argument("--no-stream", action="store_true")
+    ap.add_argument("--stream-reps", type=int, default=30)
     ap.add_argument("--backward-calls", type=int, default=0,
                     help="only time this many backward calls of the training workload")
     args = ap.parse_args()
@@ -322,6 +369,8 @@ def main():
             cal = synth.make_frame(1, 128, 128, K, seed=999)
             net.calibrate(d(cal.gbuf), d(cal.layers), d(cal.scene))
         step_s, kern_s = time_forward(net, g, L, s, out, args.steps, args.warmup, torch)
+        stream = (None if args.no_stream else
+                  stream_phase(net, g, L, s, out, torch, reps=args.stream_reps))
 
     fp32 = None
     if not args.no_fp32:
@@ -357,7 +406,7 @@ def main():
             "unit": "TFLOP/s",
             "frac": achieved / peak,
             "traffic": traffic,
-            "kernel": f"fwd_mfma_kernel<{W},{args.precision}>",
+            "kernel": f"fwd_mfma_kernel<{W},{args.precision},FULL>",
             "kernel_ms": kern_s * 1e3,
             "alg_flop_per_px": alg,
             "executed_flop_per_px": exe,
@@ -369,6 +418,8 @@ def main():
     if fp32:
         res["fp32_path"] = fp32
         res["speedup_vs_fp32_path"] = res["value"] / fp32["value"]
+    if stream:
+        res["stream"] = stream
     if not args.no_train:
         res["train_step"] = train_phase(torch)
     if args.k_sweep:

@@ -100,12 +100,15 @@ __device__ __forceinline__ uint32_t relu_bf16x2(uint32_t x) {
   return __builtin_bit_cast(uint32_t, v);
 }
 
-// Four non-negative floats -> four OCP E4M3 bytes (round to nearest even).
-// Values are clamped to the format's largest finite magnitude first.
-__device__ __forceinline__ int pack_fp8x4(f32x4 v) {
+// Four floats -> four OCP E4M3 bytes (round to nearest even) of
+// min(max(v, 0), 448): ReLU and the clamp to the format's largest finite
+// magnitude in one v_med3 each.
+__device__ __forceinline__ int relu_pack_fp8x4(f32x4 v) {
   const float M = 448.0f;
-  int r = __builtin_amdgcn_cvt_pk_fp8_f32(fminf(v.x, M), fminf(v.y, M), 0, false);
-  return __builtin_amdgcn_cvt_pk_fp8_f32(fminf(v.z, M), fminf(v.w, M), r, true);
+  const float x = __builtin_amdgcn_fmed3f(v.x, 0.0f, M), y = __builtin_amdgcn_fmed3f(v.y, 0.0f, M);
+  const float z = __builtin_amdgcn_fmed3f(v.z, 0.0f, M), w = __builtin_amdgcn_fmed3f(v.w, 0.0f, M);
+  int r = __builtin_amdgcn_cvt_pk_fp8_f32(x, y, 0, false);
+  return __builtin_amdgcn_cvt_pk_fp8_f32(z, w, r, true);
 }
 
 // 16x16x128 E4M3 x E4M3 -> fp32 on the gfx950 matrix cores, unit block scales.
@@ -337,8 +340,15 @@ __global__ __launch_bounds__(kThreads) void fwd_mfma_kernel(MfmaArgs a) {
   const uint8_t *T2 = L_res + kT1ABytes;                           // bf16 form
   float *T2scale = (float *)(L_res + kT1ABytes + MT * 2 * kFrag);  // fp8 form
   if (kFp8 && kSlots) {
-    // dequantisation factor of the fp8 layer: weight row scale x activation scale
-    if ((int)threadIdx.x < W) T2scale[threadIdx.x] *= a.sa;
+    // dequantisation factor s of the fp8 layer (weight row scale x activation
+    // scale), and that layer's bias divided by it: the slot loop sums
+    // relu(acc + c2 / s) = relu(s acc + c2) / s (s > 0) and the pool
+    // multiplies by s once
+    if ((int)threadIdx.x < W) {
+      const float sc = T2scale[threadIdx.x] * a.sa;
+      T2scale[threadIdx.x] = sc;
+      L_bias[L_T2 * W + threadIdx.x] /= sc;
+    }
     __syncthreads();
   }
   const float *bF1 = L_bias + L_F1 * W, *bF2 = L_bias + L_F2 * W, *bF3 = L_bias + L_F3 * W;
@@ -521,6 +531,14 @@ __global__ __launch_bounds__(kThreads) void fwd_mfma_kernel(MfmaArgs a) {
         f32x4 u[kNT][MT];
         bias_init(u, bT1, g);
         mm<MT, KS>(u, stage_buf(2), sig, lane);
+        if constexpr (kFp8) {
+          // fp8: h's first layer runs in units of the activation scale (its
+          // inputs b_i and u are divided by it), so its output quantises directly
+#pragma unroll
+          for (int t = 0; t < kNT; ++t)
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt) u[t][mt] *= a.inv_sa;
+        }
 #pragma unroll
         for (int t = 0; t < kNT; ++t) {
           cnt[t] = 0.0f;
@@ -567,40 +585,44 @@ __global__ __launch_bounds__(kThreads) void fwd_mfma_kernel(MfmaArgs a) {
           float m[kNT];
 #pragma unroll
           for (int t = 0; t < kNT; ++t) {
-            bi[t] = uint2{pk_bf16(cur[t][0], cur[t][1]), pk_bf16(cur[t][2], cur[t][3])};
+            if constexpr (kFp8)
+              bi[t] = uint2{pk_bf16(cur[t][0] * a.inv_sa, cur[t][1] * a.inv_sa),
+                            pk_bf16(cur[t][2] * a.inv_sa, cur[t][3] * a.inv_sa)};
+            else
+              bi[t] = uint2{pk_bf16(cur[t][0], cur[t][1]), pk_bf16(cur[t][2], cur[t][3])};
             // alpha (plane 9) sits in lane group 2 at position 1: broadcast it
             const float al = __int_as_float(
                 __builtin_amdgcn_ds_bpermute((col + 32) * 4, __float_as_int(cur[t][1])));
             m[t] = al > 0.0f ? 1.0f : 0.0f;
           }
           if constexpr (kFp8) {
-          // h layer 1 (bf16 MFMA), output quantised to E4M3 with the static
-          // activation scale: lane byte 4*mt + r holds row 16*mt + 4*g + r, the
-          // order the fp8 weights of layer 2 were packed in.
+          // h layer 1 (bf16 MFMA, in activation-scale units), quantised to
+          // E4M3: lane byte 4*mt + r holds row 16*mt + 4*g + r, the order the
+          // fp8 weights of layer 2 were packed in.
           i32x8 zq[kNT];
 #pragma unroll
           for (int mt = 0; mt < MT; ++mt) {
             const uint2 w = ld_frag16(T1A, mt, lane);
 #pragma unroll
-            for (int t = 0; t < kNT; ++t) {
-              const f32x4 v = mma16(w, bi[t], u[t][mt]);
-              zq[t][mt] = pack_fp8x4(relu4(v) * a.inv_sa);
-            }
+            for (int t = 0; t < kNT; ++t) zq[t][mt] = relu_pack_fp8x4(mma16(w, bi[t], u[t][mt]));
           }
           // h layer 2 on the fp8 matrix cores (K = 128 in one instruction),
-          // dequantised per output row, then the masked running sum.
+          // the running sum kept in units of the dequantisation factor s
+          // (applied at the pool); each M-tile's fragment is requested one
+          // M-tile ahead of its MFMAs.
+          i32x8 wn = ld_frag8(T2, 0, lane);
 #pragma unroll
           for (int mt = 0; mt < MT; ++mt) {
-            const i32x8 w = ld_frag8(T2, mt, lane);
-            const f32x4 sc = *(const f32x4 *)(T2scale + 16 * mt + 4 * g);
-            const f32x4 b = *(const f32x4 *)(bT2 + 16 * mt + 4 * g);
+            const i32x8 w = wn;
+            if (mt + 1 < MT) wn = ld_frag8(T2, mt + 1, lane);
+            const f32x4 b = *(const f32x4 *)(bT2 + 16 * mt + 4 * g);     // c2 / s
 #pragma unroll
             for (int t = 0; t < kNT; ++t) {
-              const f32x4 acc = mma_fp8(w, zq[t], f32x4{0.f, 0.f, 0.f, 0.f});
-              Z[t][mt].x = fmaf(m[t], relu1(fmaf(acc.x, sc.x, b.x)), Z[t][mt].x);
-              Z[t][mt].y = fmaf(m[t], relu1(fmaf(acc.y, sc.y, b.y)), Z[t][mt].y);
-              Z[t][mt].z = fmaf(m[t], relu1(fmaf(acc.z, sc.z, b.z)), Z[t][mt].z);
-              Z[t][mt].w = fmaf(m[t], relu1(fmaf(acc.w, sc.w, b.w)), Z[t][mt].w);
+              const f32x4 r = relu4(mma_fp8(w, zq[t], b));
+              Z[t][mt].x = fmaf(m[t], r.x, Z[t][mt].x);
+              Z[t][mt].y = fmaf(m[t], r.y, Z[t][mt].y);
+              Z[t][mt].z = fmaf(m[t], r.z, Z[t][mt].z);
+              Z[t][mt].w = fmaf(m[t], r.w, Z[t][mt].w);
             }
           }
           } else {
@@ -688,6 +710,19 @@ __global__ __launch_bounds__(kThreads) void fwd_mfma_kernel(MfmaArgs a) {
       }
       u32x4 tau[kNT][KS];
       {
+        // fp8: the running sum is in units of the dequantisation factor s
+        // (weight row scale x activation scale) of the slot loop's fp8 layer
+        f32x4 s8[MT];
+        if constexpr (kFp8) {
+#pragma unroll
+          for (int mt = 0; mt < MT; ++mt) {
+            if constexpr (MODE == FWD_FULL)
+              s8[mt] = *(const f32x4 *)(T2scale + 16 * mt + 4 * g);
+            else
+              s8[mt] = *(const f32x4 *)((const float *)(a.packed + a.t2s_off) + 16 * mt + 4 * g) *
+                       a.sa;
+          }
+        }
         u32x4 zs[kNT][KS];
         f32x4 acc[kNT][MT];
 #pragma unroll
@@ -697,7 +732,7 @@ __global__ __launch_bounds__(kThreads) void fwd_mfma_kernel(MfmaArgs a) {
           const float bs = mean ? (cnt[t] > 0.0f ? 1.0f : 0.0f) : cnt[t];
 #pragma unroll
           for (int mt = 0; mt < MT; ++mt) {
-            const f32x4 v = Z[t][mt] * inv;
+            const f32x4 v = kFp8 ? (Z[t][mt] * s8[mt]) * inv : Z[t][mt] * inv;
             zs[t][mt >> 1][2 * (mt & 1)] = pk_bf16(v.x, v.y);
             zs[t][mt >> 1][2 * (mt & 1) + 1] = pk_bf16(v.z, v.w);
             acc[t][mt] = *(const f32x4 *)(bT3 + 16 * mt + 4 * g) * bs;

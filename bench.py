@@ -107,9 +107,10 @@ def time_forward(net, g, L, s, out, steps, warmup, torch):
     return wall / steps, ev0.elapsed_time(ev1) / 1e3 / steps
 
 
-def serve_phase(w, W, precision, seconds, torch, rate=200.0, seed=4):
+def serve_phase(w, W, precision, seconds, torch, rate=200.0, seed=4, budget_mb=0):
     """Poisson arrivals at `rate` for `seconds`; resolution from the four
-    serving sizes, K ~ U{2..8}; inputs resident; returns latency/throughput."""
+    serving sizes, K ~ U{2..8}; inputs resident; admission budget `budget_mb`
+    (0: 64 GiB); returns latency/throughput."""
     from paper_2405_19056_amd import synth
     from paper_2405_19056_amd.glassnet import GlassNet
     st = synth.streams(seed)
@@ -124,7 +125,8 @@ def serve_phase(w, W, precision, seconds, torch, rate=200.0, seed=4):
         outs[(h, wd)] = [torch.empty((1, 3, h, wd), device="cuda:0") for _ in range(64)]
     torch.cuda.synchronize()
     owner = {}
-    with GlassNet(w, W, k_max=8, precision=precision) as net:
+    budget = int(budget_mb) << 20
+    with GlassNet(w, W, k_max=8, precision=precision, hbm_budget_bytes=budget) as net:
         if precision == "fp8_t":
             cal = synth.make_frame(1, 128, 128, 8, seed=999)
             net.calibrate(d(cal.gbuf), d(cal.layers), d(cal.scene))
@@ -160,7 +162,7 @@ def serve_phase(w, W, precision, seconds, torch, rate=200.0, seed=4):
             "resolutions": [f"{h}x{wd}" for h, wd in res], "k": "U{2..8}",
             "precision": precision, "pixels_per_s": pixels / elapsed,
             "p50_ms": q(0.50), "p99_ms": q(0.99), "max_ms": lat[-1] * 1e3,
-            "hbm_budget": "64 GiB"}
+            "hbm_budget": f"{budget_mb} MiB" if budget_mb else "64 GiB"}
 
 
 def k_sweep(w, W, fr, pool, precision, torch, ks=(0, 1, 2, 4, 8), steps=50):
@@ -332,6 +334,9 @@ def main():
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--copy-probe", action="store_true")
     ap.add_argument("--serve-seconds", type=float, default=5.0)
+    ap.add_argument("--serve-rate", type=float, default=200.0, help="Poisson arrivals per second")
+    ap.add_argument("--serve-budget-mb", type=int, default=0,
+                    help="serving admission budget in MiB (0: 64 GiB)")
     ap.add_argument("--k-sweep", action="store_true")
     ap.add_argument("--no-train", action="store_true")
     ap.add_argument("--no-stream", action="store_true")
@@ -425,7 +430,8 @@ def main():
     if args.k_sweep:
         res["k_sweep"] = k_sweep(w, W, fr, c["pool"], args.precision, torch)
     if args.serve_seconds > 0:
-        res["serve"] = serve_phase(w, W, args.precision, args.serve_seconds, torch)
+        res["serve"] = serve_phase(w, W, args.precision, args.serve_seconds, torch,
+                                   rate=args.serve_rate, budget_mb=args.serve_budget_mb)
         res["p99_frame_latency_ms"] = res["serve"]["p99_ms"]
     if not args.no_cpu_baseline:
         v, thr, sample = cpu_baseline(w, fr, W, c["pool"])

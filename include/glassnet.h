@@ -179,12 +179,13 @@ gn_status glassnet_workspace_bytes(gn_handle *h, uint64_t *bytes);
  * call (a progressive result) and accumulation may continue after it.
  *
  * The state is caller-owned device memory of glassnet_stream_state_bytes
- * bytes (772 bytes per pixel at W = 128, 388 at W = 64, whatever the number
- * of objects): sigma in bf16, the fp32 running sum of h's hidden layer and
- * the active-slot count, in a layout private to the library.  Calls on one
- * state are ordered on the hip_stream each passes; calls on different streams
- * must be ordered by the caller.  GN_BF16 and GN_FP8_T handles only (GN_FP32:
- * GN_E_UNSUPPORTED). */
+ * bytes, whatever the number of objects: sigma, the fp32 running sum of h's
+ * hidden layer and the active-slot count, in a layout private to the library
+ * (GN_BF16 / GN_FP8_T: sigma in bf16, 772 bytes per pixel at W = 128, 388 at
+ * W = 64; GN_FP32: all fp32, (2 W + 1) floats per pixel, through the plane
+ * workspace of the FP32 forward with its pixel limit).  Calls on one state
+ * are ordered on the hip_stream each passes; calls on different streams must
+ * be ordered by the caller. */
 gn_status glassnet_stream_state_bytes(gn_handle *h, int32_t n, int32_t hgt, int32_t wid,
                                       uint64_t *bytes);
 

@@ -298,16 +298,36 @@ gn_status glassnet_forward(gn_handle *h, const gn_frame *frame, float *out, void
 
 static gn_status stream_geometry(gn_handle *h, int32_t n, int32_t hgt, int32_t wid,
                                  uint64_t *bytes) {
-  if (h->cfg.precision == GN_FP32)
-    return fail(GN_E_UNSUPPORTED, "object streaming runs on the matrix-core forward (GN_BF16, GN_FP8_T)");
   if (n < 1 || hgt < 1 || wid < 1)
     return fail(GN_E_INVAL, "frame shape n=%d h=%d w=%d must be >= 1", n, hgt, wid);
   const int64_t hw = (int64_t)hgt * wid;
   if (hw * gn::kNG > INT32_MAX || (int64_t)n * hw > INT32_MAX)
     return fail(GN_E_INVAL, "frame too large (%d x %d x %d)", n, hgt, wid);
+  if (h->cfg.precision == GN_FP32) {          // plane pipeline: [sigma; Z; count] rows
+    *bytes = gn_planes_stream_bytes(h->W, (int64_t)n * hw);
+    return GN_OK;
+  }
   const uint64_t tiles = (uint64_t)n * (uint64_t)((hw + gn::kTilePx - 1) / gn::kTilePx);
   *bytes = tiles * gn::stream_state_tile_bytes(h->W);
   return GN_OK;
+}
+
+// One streaming launch: the fused kernel's mode, or the plane pipeline (GN_FP32).
+static gn_status stream_launch(gn_handle *h, const gn::FwdBatch &b, const gn_frame *f, int mode,
+                               void *state, int state_load, float *out, hipStream_t s,
+                               const char *what) {
+  if (h->cfg.precision == GN_FP32) {
+    gn_frame pf = *f;
+    pf.gbuf = b.gbuf;
+    pf.layers = b.layers;
+    pf.scene = b.scene;
+    pf.k = b.k;
+    return gn_planes_stream(h, &pf, mode, (float *)state, state_load ? 0 : 1, out, s);
+  }
+  const hipError_t e = gn::launch_fwd_stream(h->W, h->cfg.precision, h->cfg.pool, h->d_packed,
+                                             h->pl, b, h->act_scale, h->num_cus, mode,
+                                             (uint8_t *)state, state_load, s);
+  return gn_check_device(h, e, what);
 }
 
 // The record of a begun state whose geometry matches the frame (caller holds stream_mu).
@@ -376,10 +396,8 @@ gn_status glassnet_stream_begin(gn_handle *h, const gn_frame *frame, void *state
   gn::FwdBatch b = stream_batch(frame);
   b.layers = nullptr;     // BEGIN reads the G-buffer and the scene vector only
   b.k = 0;
-  const hipError_t e = gn::launch_fwd_stream(h->W, h->cfg.precision, h->cfg.pool, h->d_packed,
-                                             h->pl, b, h->act_scale, h->num_cus, gn::FWD_BEGIN,
-                                             (uint8_t *)state, 0, (hipStream_t)hip_stream);
-  return gn_check_device(h, e, "stream begin launch");
+  return stream_launch(h, b, frame, gn::FWD_BEGIN, state, 0, nullptr, (hipStream_t)hip_stream,
+                       "stream begin launch");
 }
 
 gn_status glassnet_stream_accumulate(gn_handle *h, const gn_frame *frame, void *state,
@@ -400,13 +418,13 @@ gn_status glassnet_stream_accumulate(gn_handle *h, const gn_frame *frame, void *
   if (overlaps(state, rec->bytes, frame->layers, sizeof(float) * frame->n * frame->k * gn::kNL * hw))
     return fail(GN_E_INVAL, "state aliases the layers buffer");
   DeviceGuard dg(h->device);
-  const gn::FwdBatch b = stream_batch(frame);
-  const hipError_t e = gn::launch_fwd_stream(h->W, h->cfg.precision, h->cfg.pool, h->d_packed,
-                                             h->pl, b, h->act_scale, h->num_cus, gn::FWD_ACC,
-                                             (uint8_t *)state, rec->fresh ? 0 : 1,
-                                             (hipStream_t)hip_stream);
-  rec->fresh = false;
-  return gn_check_device(h, e, "stream accumulate launch");
+  gn::FwdBatch b = stream_batch(frame);
+  b.gbuf = nullptr;       // ACC reads the objects' layers only
+  b.scene = nullptr;
+  st = stream_launch(h, b, frame, gn::FWD_ACC, state, rec->fresh ? 0 : 1, nullptr,
+                     (hipStream_t)hip_stream, "stream accumulate launch");
+  if (st == GN_OK) rec->fresh = false;
+  return st;
 }
 
 gn_status glassnet_stream_finish(gn_handle *h, const gn_frame *frame, void *state, float *out,
@@ -432,11 +450,8 @@ gn_status glassnet_stream_finish(gn_handle *h, const gn_frame *frame, void *stat
   b.scene = nullptr;
   b.k = 0;
   b.out = out;
-  const hipError_t e = gn::launch_fwd_stream(h->W, h->cfg.precision, h->cfg.pool, h->d_packed,
-                                             h->pl, b, h->act_scale, h->num_cus, gn::FWD_FINISH,
-                                             (uint8_t *)state, rec->fresh ? 0 : 1,
-                                             (hipStream_t)hip_stream);
-  return gn_check_device(h, e, "stream finish launch");
+  return stream_launch(h, b, frame, gn::FWD_FINISH, state, rec->fresh ? 0 : 1, out,
+                       (hipStream_t)hip_stream, "stream finish launch");
 }
 
 gn_status glassnet_stream_release(gn_handle *h, void *state) {

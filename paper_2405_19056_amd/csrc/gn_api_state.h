@@ -51,4 +51,9 @@ void gn_bwd_free(gn_handle *h);
 // calibration (amax: device float bits of the largest h-layer-1 activation).
 gn_status gn_planes_forward(gn_handle *h, const gn_frame *frame, float *out, hipStream_t s);
 gn_status gn_planes_calibrate(gn_handle *h, const gn_frame *frame, unsigned *amax, hipStream_t s);
+// Object streaming on the plane pipeline (GN_FP32): mode FWD_BEGIN, FWD_ACC or
+// FWD_FINISH; the state holds gn_planes_stream_bytes(W, n h w) bytes.
+size_t gn_planes_stream_bytes(int W, int64_t npx);
+gn_status gn_planes_stream(gn_handle *h, const gn_frame *frame, int mode, float *state, int fresh,
+                           float *out, hipStream_t s);
 size_t gn_bwd_bytes(gn_handle *h);

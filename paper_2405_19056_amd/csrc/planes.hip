@@ -326,17 +326,21 @@ struct PrepArgs {
 
 // G and the scene vector (F's input), L_d (R's), the mean's 1/max(c,1), T3's
 // bias scale and dL/dy.  Padding pixels repeat the last pixel with dL/dy = 0,
-// so every gradient they could carry is zero.
+// so every gradient they could carry is zero.  A null gbuf or scene (object
+// streaming calls that do not run F or R) leaves those planes untouched.
 __global__ __launch_bounds__(kThreads) void prep_kernel(PrepArgs a) {
   const int64_t p = (int64_t)blockIdx.x * kThreads + threadIdx.x;
   const bool valid = p < a.npx;
   const int64_t pc = valid ? p : a.npx - 1;
   const int f = (int)(pc / a.hw), q = (int)(pc - (int64_t)f * a.hw), hw = a.hw, W = a.W;
-  const float *G = a.gbuf + (size_t)f * kNG * hw + q;
   const Blocks &B = a.bl;
-  for (int c = 0; c < kNG; ++c) ROW(B.xb + c)[p] = G[(size_t)c * hw];
-  for (int c = 0; c < kNS; ++c) ROW(B.xb + kNG + c)[p] = a.scene[(size_t)f * kNS + c];
-  for (int c = 0; c < 3; ++c) ROW(B.pl + W + c)[p] = G[(size_t)(11 + c) * hw];
+  if (a.gbuf) {
+    const float *G = a.gbuf + (size_t)f * kNG * hw + q;
+    for (int c = 0; c < kNG; ++c) ROW(B.xb + c)[p] = G[(size_t)c * hw];
+    for (int c = 0; c < 3; ++c) ROW(B.pl + W + c)[p] = G[(size_t)(11 + c) * hw];
+  }
+  if (a.scene)
+    for (int c = 0; c < kNS; ++c) ROW(B.xb + kNG + c)[p] = a.scene[(size_t)f * kNS + c];
   float cnt = 0.0f;
   const float *Lf = a.layers + (size_t)f * a.k * kNL * hw + q;
   for (int i = 0; i < a.k; ++i) cnt += Lf[((size_t)i * kNL + kAlpha) * hw] > 0.0f ? 1.0f : 0.0f;
@@ -359,6 +363,36 @@ __global__ __launch_bounds__(kThreads) void slot_gather_kernel(PrepArgs a, int s
 }
 
 #undef ROW
+
+// Object streaming: add the call's active-slot count of every pixel to the
+// state's count row (or set it, on the first call).
+__global__ __launch_bounds__(kThreads) void stream_count_kernel(const float *__restrict__ layers,
+                                                                int k, int hw, int64_t npx,
+                                                                float *__restrict__ cnt, int fresh) {
+  const int64_t p = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (p >= npx) return;
+  const int f = (int)(p / hw), q = (int)(p - (int64_t)f * hw);
+  const float *Lf = layers + (size_t)f * k * kNL * hw + q;
+  float c = fresh ? 0.0f : cnt[p];
+  for (int i = 0; i < k; ++i) c += Lf[((size_t)i * kNL + kAlpha) * hw] > 0.0f ? 1.0f : 0.0f;
+  cnt[p] = c;
+}
+
+// Object streaming: the pool of Eq. (5) from the state, T3's input block:
+// zs[r] = Z[r] / max(c, 1) (mean) or Z[r] (sum) and T3's bias scale row, as
+// the forward's last slot epilogue and prep compute them.
+__global__ __launch_bounds__(kThreads) void stream_pool_kernel(const float *__restrict__ Z,
+                                                               const float *__restrict__ cnt,
+                                                               int64_t npx, int W, int mean,
+                                                               float *__restrict__ zs,
+                                                               int64_t stride) {
+  const int64_t p = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (p >= npx) return;
+  const float c = cnt[p];
+  const float inv = mean ? 1.0f / fmaxf(c, 1.0f) : 1.0f;
+  for (int r = 0; r < W; ++r) zs[(size_t)r * stride + p] = Z[(size_t)r * npx + p] * inv;
+  zs[(size_t)W * stride + p] = mean ? (c > 0.0f ? 1.0f : 0.0f) : c;
+}
 
 // ---- weight gradients: sums over pixels on the fp32 matrix cores -----------
 // part[chunk][o][i] (+)= sum_{p in chunk} D[o][p] A[i][p] for the
@@ -749,6 +783,46 @@ class Pipeline {
     }
   }
 
+  // ---- object streaming: the state is [sigma (W rows); Z (W rows); count]
+  // of npx floats per row.  begin: F, sigma out.  accumulate: sigma in, u,
+  // the call's slots added to Z (continued from the state unless fresh), the
+  // count.  finish: sigma and the pool in, T3, B, R.  The arithmetic and its
+  // order are the forward's.
+  void stream_begin(float *state) {
+    trunk();
+    copy_rows(state, npx_, plane(bl_.st), npx_pad_, W_);
+  }
+  void stream_accumulate(float *state, bool fresh) {
+    copy_rows(plane(bl_.st), npx_pad_, state, npx_, W_);
+    fwd(O_T1S, bl_.st, bl_.u, L_T1, false);                  // u, as in trunk()
+    if (!fresh) copy_rows(plane(bl_.zs), npx_pad_, state + (size_t)W_ * npx_, npx_, W_);
+    for (int i = 0; i < K_; ++i) {
+      gather(i);
+      z1();
+      PgArgs a = args();
+      a.bias = wm_ + lo_[L_T2].b;
+      a.relu = 1;
+      a.pscale = plane(bl_.px + PX_M);
+      a.accumulate = i > 0 || !fresh;
+      gemm(O_T2, EP_FWD, bl_.z1, bl_.zs, a);
+    }
+    copy_rows(state + (size_t)W_ * npx_, npx_, plane(bl_.zs), npx_pad_, W_);
+    hipLaunchKernelGGL(stream_count_kernel, pgrid(), dim3(kThreads), 0, s_, pa_.layers, K_, hw_,
+                       npx_, state + (size_t)2 * W_ * npx_, fresh ? 1 : 0);
+  }
+  void stream_finish(const float *state, bool fresh, float *out) {
+    copy_rows(plane(bl_.st), npx_pad_, state, npx_, W_);
+    if (fresh) {
+      fill_rows(bl_.zs, W_ + 1);           // no object: empty pool, zero bias scale
+    } else {
+      hipLaunchKernelGGL(stream_pool_kernel, pgrid(), dim3(kThreads), 0, s_,
+                         state + (size_t)W_ * npx_, state + (size_t)2 * W_ * npx_, npx_, W_,
+                         h_->cfg.pool == GN_POOL_MEAN ? 1 : 0, plane(bl_.zs), npx_pad_);
+    }
+    head();
+    output(out);
+  }
+
   gn_status finish(const char *what) {
     if (e_ == hipSuccess) e_ = hipGetLastError();
     return gn_check_device(h_, e_, what);
@@ -768,6 +842,12 @@ class Pipeline {
   }
   void gather(int i) {
     hipLaunchKernelGGL(slot_gather_kernel, pgrid(), dim3(kThreads), 0, s_, pa_, i);
+  }
+  // n rows of npx floats between row-major blocks of different row lengths
+  void copy_rows(float *dst, int64_t dst_len, const float *src, int64_t src_len, int n) {
+    if (e_ == hipSuccess)
+      e_ = hipMemcpy2DAsync(dst, sizeof(float) * dst_len, src, sizeof(float) * src_len,
+                            sizeof(float) * npx_, n, hipMemcpyDeviceToDevice, s_);
   }
 
   // One plane GEMM: op `o` from block `xrow` into block `orow`.
@@ -882,6 +962,28 @@ gn_status gn_planes_calibrate(gn_handle *h, const gn_frame *frame, unsigned *ama
     p.trunk();
     p.calibrate(amax);
     return p.finish("calibration");
+  });
+}
+
+// Object streaming on the plane pipeline (GN_FP32 handles); state holds
+// gn_planes_stream_bytes floats.
+size_t gn_planes_stream_bytes(int W, int64_t npx) {
+  return sizeof(float) * (size_t)(2 * W + 1) * (size_t)npx;
+}
+
+gn_status gn_planes_stream(gn_handle *h, const gn_frame *frame, int mode, float *state, int fresh,
+                           float *out, hipStream_t s) {
+  return with_device(h, [&]() {
+    Pipeline p(h, s);
+    gn_status st = p.begin(frame, nullptr, "fp32 stream");
+    if (st != GN_OK) return st;
+    if (mode == FWD_BEGIN)
+      p.stream_begin(state);
+    else if (mode == FWD_ACC)
+      p.stream_accumulate(state, fresh != 0);
+    else
+      p.stream_finish(state, fresh != 0, out);
+    return p.finish("fp32 stream");
   });
 }
 

@@ -155,6 +155,48 @@ def test_training_workload_with_sparse_seed():
     log(f"  training workload worst per-tensor relF {worst:.3e}")
 
 
+def test_l1_gradient_matches_central_differences_on_an_8x8_crop():
+    """The training workload's gradient check: dL/dw of the L1 loss on an 8x8
+    crop, K=4, W=128, from the library (forward, L1 kernel, fp32 backward),
+    against FP64 central differences of the oracle's loss (h = 1e-6) on 160
+    coordinates whose +-h perturbation leaves every branch (ReLU sign, L1
+    sign) unchanged.  Targets sit 0.5 from the output, so the L1 sign is the
+    same in fp32 and fp64; pixels near a ReLU kink are redrawn."""
+    torch = torch_dev()
+    W = 128
+    wts, fr, s = frame(1, 8, 8, 4, W, seed=90)
+    fr = redraw_near_kinks(wts, W, fr, "mean", s)
+    rng = np.random.default_rng(90)
+    y = oracle.forward(wts, W, fr.gbuf, fr.layers, fr.scene)
+    target = y + rng.choice([-0.5, 0.5], size=y.shape)
+    with GlassNet(wts, W, k_max=8, precision="fp32") as net:
+        gd, Ld, sd = dev(fr.gbuf), dev(fr.layers), dev(fr.scene)
+        yy = net.forward(gd, Ld, sd)
+        dy = torch.empty_like(yy)
+        net.l1_loss(yy, dev(target), grad_out=dy)
+        g = host(net.backward(gd, Ld, sd, dy)).astype(np.float64)
+        torch.cuda.synchronize()
+    w64 = wts.astype(np.float64)
+    eps, fds = 1e-6, []
+    for i in rng.choice(w64.size, size=160, replace=False):
+        wp, wm = w64.copy(), w64.copy()
+        wp[i] += eps
+        wm[i] -= eps
+        if not np.array_equal(oracle.relu_signature(wp, W, fr.gbuf, fr.layers, fr.scene, target),
+                              oracle.relu_signature(wm, W, fr.gbuf, fr.layers, fr.scene, target)):
+            continue
+        lp = oracle.l1_loss(oracle.forward(wp, W, fr.gbuf, fr.layers, fr.scene), target)[0]
+        lm = oracle.l1_loss(oracle.forward(wm, W, fr.gbuf, fr.layers, fr.scene), target)[0]
+        fds.append((i, (lp - lm) / (2 * eps)))
+    assert len(fds) >= 144
+    scale = max(abs(f) for _, f in fds)
+    # fp32 backward: ~1e-6 relative per coordinate; the loss's fp64 rounding
+    # over 2h contributes ~1e-10 absolute
+    worst = max(abs(g[i] - f) / (1e-4 * abs(f) + 1e-6 * scale) for i, f in fds)
+    log(f"  8x8 crop: {len(fds)} coordinates, worst |g - fd| / bound {worst:.3f}")
+    assert worst <= 1.0
+
+
 def test_l1_loss_kernel():
     torch = torch_dev()
     rng = np.random.default_rng(0)

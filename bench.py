@@ -346,7 +346,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the per-pixel forward needs no communication and "
-              "this build runs on a single MI355X; use --gpus 1.", file=sys.stderr)
+              "the library runs on a single MI355X; use --gpus 1.", file=sys.stderr)
         sys.exit(2)
     if args.copy_probe:
         copy_probe()

@@ -52,7 +52,7 @@ typedef int32_t gn_status;
 #define GN_E_INVAL (-1)        /* bad argument: shape, pointer, alignment, size */
 #define GN_E_NOMEM (-2)        /* device or host allocation failed */
 #define GN_E_DEVICE (-3)       /* HIP runtime or kernel error; handle poisoned */
-#define GN_E_UNSUPPORTED (-4)  /* valid request this build does not implement */
+#define GN_E_UNSUPPORTED (-4)  /* valid request the library does not implement */
 #define GN_E_AGAIN (-5)        /* serving: result not ready yet */
 #define GN_E_BUSY (-6)         /* serving: pending queue full */
 

@@ -145,7 +145,10 @@ gn_status glassnet_calibrate(gn_handle *h, const gn_frame *frame, void *hip_stre
 
 /* Forward (Sec. 3.3-3.4): out [n][GN_NUM_OUT][h][w] fp32 device.
  * Requires 0 <= k <= k_max and n, h, w >= 1.  Out must not alias inputs.
- * GN_FP32: at most 3 * 2^20 pixels (n * h * w) per call (GN_E_INVAL beyond). */
+ * GN_FP32: at most 3 * 2^20 pixels (n * h * w) per call (GN_E_INVAL beyond).
+ * Forward calls of one handle share a small device scratch (GN_BF16 /
+ * GN_FP8_T) or the plane workspace (GN_FP32): calls on different streams must
+ * be ordered by the caller.  Serving has its own. */
 gn_status glassnet_forward(gn_handle *h, const gn_frame *frame, float *out, void *hip_stream);
 
 /* Backward of the forward above with respect to the weights (Sec. 3.5), fp32.

@@ -185,8 +185,9 @@ gn_status glassnet_workspace_bytes(gn_handle *h, uint64_t *bytes);
  * bytes, whatever the number of objects: sigma, the fp32 running sum of h's
  * hidden layer and the active-slot count, in a layout private to the library
  * (GN_BF16 / GN_FP8_T: sigma in bf16, 772 bytes per pixel at W = 128, 388 at
- * W = 64; GN_FP32: all fp32, (2 W + 1) floats per pixel, through the plane
- * workspace of the FP32 forward with its pixel limit).  Calls on one state
+ * W = 64; GN_FP32: sigma and the count in fp32 and the running sum in fp64,
+ * (3 W + 1) x 4 bytes per pixel, through the plane workspace of the FP32
+ * forward with its pixel limit).  Calls on one state
  * are ordered on the hip_stream each passes; calls on different streams must
  * be ordered by the caller. */
 gn_status glassnet_stream_state_bytes(gn_handle *h, int32_t n, int32_t hgt, int32_t wid,

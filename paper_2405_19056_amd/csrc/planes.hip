@@ -65,6 +65,7 @@ inline int rup(int x, int m) { return (x + m - 1) / m * m; }
 struct Blocks {
   int xb, a1, a2, st, u, zs, d1, d2, pl, g1, g2, z1, bi, px, y;
   int dy, dg2, dg1, dphi, dd2, dd1, dsig, dtau, dzin, du, da2, da1, dz2, dz1;
+  int zd;            // fp64 running sum of the pool: W rows of doubles (2 W float rows)
   int rows;
 };
 enum { PX_INV = 0, PX_M = 1 };     // rows of the per-pixel scalar block
@@ -94,6 +95,7 @@ Blocks make_blocks(int W) {
   b.dsig = take(W); b.dtau = take(W);    // adjacent: B1^T writes both at once
   b.dzin = take(W); b.du = take(W); b.da2 = take(W); b.da1 = take(W);
   b.dz2 = take(W); b.dz1 = take(W);
+  b.zd = take(2 * W);
   b.rows = r;
   return b;
 }
@@ -202,7 +204,10 @@ struct PgArgs {
   const float *pscale;   // per-pixel row multiplying the result, or null
   const float *post;     // per-pixel row multiplying after accumulation, or null
   float *out2;           // EP_BWD: second block that receives (or accumulates) the result
+  double *acc64;         // EP_FWD: fp64 block (row length = stride) that accumulates the
+                         // result (or starts, without accumulate); out gets it rounded
   int relu, accumulate, accumulate2;
+  int skip_out;          // with acc64: leave out unwritten (an intermediate slot)
 };
 
 __device__ __forceinline__ f32x4 ld4(const float *p) { return *(const f32x4 *)p; }
@@ -289,8 +294,24 @@ __global__ __launch_bounds__(kThreads) void plane_gemm_kernel(PgArgs a) {
           for (int t = 0; t < 4; ++t) v[t] = fmaxf(v[t], 0.0f);
         }
         v *= psc;
-        if (a.accumulate) v += ld4(a.out + ix);
+        if (a.acc64) {
+          // the pool of Eq. (5) summed in fp64: exact for the terms met here,
+          // so its single rounding does not depend on the order of the slots
+          typedef double f64x2 __attribute__((ext_vector_type(2)));
+          f64x2 *zp = (f64x2 *)(a.acc64 + ix);
+          f64x2 z0 = f64x2{(double)v[0], (double)v[1]}, z1 = f64x2{(double)v[2], (double)v[3]};
+          if (a.accumulate) {
+            z0 += zp[0];
+            z1 += zp[1];
+          }
+          zp[0] = z0;
+          zp[1] = z1;
+          v = f32x4{(float)z0[0], (float)z0[1], (float)z1[0], (float)z1[1]};
+        } else if (a.accumulate) {
+          v += ld4(a.out + ix);
+        }
         v *= pst;
+        if (a.acc64 && a.skip_out) continue;
       } else if (EP == EP_DZ2) {
         const f32x4 z = v + a.bias[m];
         const f32x4 d = ld4(a.add + ix);
@@ -379,9 +400,10 @@ __global__ __launch_bounds__(kThreads) void stream_count_kernel(const float *__r
 }
 
 // Object streaming: the pool of Eq. (5) from the state, T3's input block:
-// zs[r] = Z[r] / max(c, 1) (mean) or Z[r] (sum) and T3's bias scale row, as
-// the forward's last slot epilogue and prep compute them.
-__global__ __launch_bounds__(kThreads) void stream_pool_kernel(const float *__restrict__ Z,
+// zs[r] = Z[r] / max(c, 1) (mean) or Z[r] (sum), Z rounded from fp64 first,
+// and T3's bias scale row, as the forward's last slot epilogue and prep
+// compute them.
+__global__ __launch_bounds__(kThreads) void stream_pool_kernel(const double *__restrict__ Z,
                                                                const float *__restrict__ cnt,
                                                                int64_t npx, int W, int mean,
                                                                float *__restrict__ zs,
@@ -390,7 +412,7 @@ __global__ __launch_bounds__(kThreads) void stream_pool_kernel(const float *__re
   if (p >= npx) return;
   const float c = cnt[p];
   const float inv = mean ? 1.0f / fmaxf(c, 1.0f) : 1.0f;
-  for (int r = 0; r < W; ++r) zs[(size_t)r * stride + p] = Z[(size_t)r * npx + p] * inv;
+  for (int r = 0; r < W; ++r) zs[(size_t)r * stride + p] = (float)Z[(size_t)r * npx + p] * inv;
   zs[(size_t)W * stride + p] = mean ? (c > 0.0f ? 1.0f : 0.0f) : c;
 }
 
@@ -662,7 +684,10 @@ class Pipeline {
   }
 
   // Z = sum_i m_i relu(W_T2 z1_i + b_T2), then / max(c, 1) for the mean.
-  void slots() {
+  // exact_pool: the sum in fp64, rounded once after the last slot, so the
+  // result does not depend on the slot order (the forward's outputs); the
+  // backward's recompute keeps the fp32 running sum.
+  void slots(bool exact_pool = true) {
     const bool mean = h_->cfg.pool == GN_POOL_MEAN;
     for (int i = 0; i < K_; ++i) {
       gather(i);
@@ -672,6 +697,10 @@ class Pipeline {
       a.relu = 1;
       a.pscale = plane(bl_.px + PX_M);
       a.accumulate = i > 0;
+      if (exact_pool) {
+        a.acc64 = dplane(bl_.zd);
+        a.skip_out = i < K_ - 1;
+      }
       if (i == K_ - 1 && mean) a.post = plane(bl_.px + PX_INV);
       gemm(O_T2, EP_FWD, bl_.z1, bl_.zs, a);
     }
@@ -783,8 +812,8 @@ class Pipeline {
     }
   }
 
-  // ---- object streaming: the state is [sigma (W rows); Z (W rows); count]
-  // of npx floats per row.  begin: F, sigma out.  accumulate: sigma in, u,
+  // ---- object streaming: the state is [sigma (W fp32 rows); Z (W fp64
+  // rows); count (fp32)] of npx elements per row.  begin: F, sigma out.  accumulate: sigma in, u,
   // the call's slots added to Z (continued from the state unless fresh), the
   // count.  finish: sigma and the pool in, T3, B, R.  The arithmetic and its
   // order are the forward's.
@@ -795,7 +824,8 @@ class Pipeline {
   void stream_accumulate(float *state, bool fresh) {
     copy_rows(plane(bl_.st), npx_pad_, state, npx_, W_);
     fwd(O_T1S, bl_.st, bl_.u, L_T1, false);                  // u, as in trunk()
-    if (!fresh) copy_rows(plane(bl_.zs), npx_pad_, state + (size_t)W_ * npx_, npx_, W_);
+    double *z64 = (double *)(state + (size_t)W_ * npx_);
+    if (!fresh) copy_rows(dplane(bl_.zd), npx_pad_, z64, npx_, W_);
     for (int i = 0; i < K_; ++i) {
       gather(i);
       z1();
@@ -804,11 +834,13 @@ class Pipeline {
       a.relu = 1;
       a.pscale = plane(bl_.px + PX_M);
       a.accumulate = i > 0 || !fresh;
+      a.acc64 = dplane(bl_.zd);
+      a.skip_out = 1;                                         // the state keeps the sum
       gemm(O_T2, EP_FWD, bl_.z1, bl_.zs, a);
     }
-    copy_rows(state + (size_t)W_ * npx_, npx_, plane(bl_.zs), npx_pad_, W_);
+    copy_rows(z64, npx_, dplane(bl_.zd), npx_pad_, W_);
     hipLaunchKernelGGL(stream_count_kernel, pgrid(), dim3(kThreads), 0, s_, pa_.layers, K_, hw_,
-                       npx_, state + (size_t)2 * W_ * npx_, fresh ? 1 : 0);
+                       npx_, state + (size_t)3 * W_ * npx_, fresh ? 1 : 0);
   }
   void stream_finish(const float *state, bool fresh, float *out) {
     copy_rows(plane(bl_.st), npx_pad_, state, npx_, W_);
@@ -816,7 +848,8 @@ class Pipeline {
       fill_rows(bl_.zs, W_ + 1);           // no object: empty pool, zero bias scale
     } else {
       hipLaunchKernelGGL(stream_pool_kernel, pgrid(), dim3(kThreads), 0, s_,
-                         state + (size_t)W_ * npx_, state + (size_t)2 * W_ * npx_, npx_, W_,
+                         (const double *)(state + (size_t)W_ * npx_),
+                         state + (size_t)3 * W_ * npx_, npx_, W_,
                          h_->cfg.pool == GN_POOL_MEAN ? 1 : 0, plane(bl_.zs), npx_pad_);
     }
     head();
@@ -843,12 +876,15 @@ class Pipeline {
   void gather(int i) {
     hipLaunchKernelGGL(slot_gather_kernel, pgrid(), dim3(kThreads), 0, s_, pa_, i);
   }
-  // n rows of npx floats between row-major blocks of different row lengths
-  void copy_rows(float *dst, int64_t dst_len, const float *src, int64_t src_len, int n) {
+  // n rows of npx elements between row-major blocks of different row lengths
+  template <class T>
+  void copy_rows(T *dst, int64_t dst_len, const T *src, int64_t src_len, int n) {
     if (e_ == hipSuccess)
-      e_ = hipMemcpy2DAsync(dst, sizeof(float) * dst_len, src, sizeof(float) * src_len,
-                            sizeof(float) * npx_, n, hipMemcpyDeviceToDevice, s_);
+      e_ = hipMemcpy2DAsync(dst, sizeof(T) * dst_len, src, sizeof(T) * src_len, sizeof(T) * npx_,
+                            n, hipMemcpyDeviceToDevice, s_);
   }
+  // a block of fp64 rows (two float rows each) as doubles, row length npx_pad_
+  double *dplane(int r) const { return (double *)plane(r); }
 
   // One plane GEMM: op `o` from block `xrow` into block `orow`.
   void gemm(Op o, int ep, int xrow, int orow, PgArgs a) {
@@ -968,7 +1004,7 @@ gn_status gn_planes_calibrate(gn_handle *h, const gn_frame *frame, unsigned *ama
 // Object streaming on the plane pipeline (GN_FP32 handles); state holds
 // gn_planes_stream_bytes floats.
 size_t gn_planes_stream_bytes(int W, int64_t npx) {
-  return sizeof(float) * (size_t)(2 * W + 1) * (size_t)npx;
+  return sizeof(float) * (size_t)(3 * W + 1) * (size_t)npx;   // sigma, fp64 Z, count
 }
 
 gn_status gn_planes_stream(gn_handle *h, const gn_frame *frame, int mode, float *state, int fresh,
@@ -1000,7 +1036,7 @@ extern "C" gn_status glassnet_backward(gn_handle *h, const gn_frame *frame,
     gn_status st2 = p.begin(frame, grad_out, "backward workspace");
     if (st2 != GN_OK) return st2;
     p.trunk();
-    p.slots();
+    p.slots(false);
     p.head();
     p.backward(grad_w);
     return p.finish("backward launch");

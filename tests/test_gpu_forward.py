@@ -266,13 +266,11 @@ def test_fp8_full_size_on_sampled_pixels_and_permutations():
 @pytest.mark.parametrize("precision", ["fp32", "bf16", "fp8_t"])
 def test_permutation_sweep_512sq_k8_32_shuffles(precision):
     """The 512^2, K=8 workload under 32 independent per-pixel shuffles of its
-    eight layers (Eq. (5) is symmetric in the layers).  Each shuffled output
-    is compared with the unshuffled one by relative Frobenius error, the
-    metric of every output tolerance here: fp32 <= 1e-6, bf16 and fp8_t
-    within their output tolerances.  fp32's per-element worst case over the
-    25 M outputs (the tail of summation-order rounding in the pool, measured
-    1.1e-6 of the largest output) is bounded separately by 2e-6.  The
-    shuffles are applied on the device."""
+    eight layers (Eq. (5) is symmetric in the layers).  fp32: every element
+    within 1e-6 of the largest unshuffled output (the FP32 form sums the pool
+    in fp64, so the slot order leaves no trace beyond rare roundings); bf16
+    and fp8_t: relative Frobenius error within their output tolerances, the
+    per-element deviation reported.  The shuffles are applied on the device."""
     torch = torch_dev()
     cfg = "c2_512sq_k8_w128"
     c = synth.CONFIGS[cfg]
@@ -296,9 +294,10 @@ def test_permutation_sweep_512sq_k8_32_shuffles(precision):
         torch.cuda.synchronize()
     log(f"  {precision} 512^2 K=8, 32 shuffles: worst relF {worst_rel:.3e}, "
         f"worst element {worst:.3e}")
-    assert worst_rel <= (1e-6 if precision == "fp32" else TOL[precision])
     if precision == "fp32":
-        assert worst <= 2e-6
+        assert worst <= 1e-6
+    else:
+        assert worst_rel <= TOL[precision]
 
 
 def test_fp8_calibration_sets_a_positive_scale_and_rejects_bad_scales():

@@ -188,7 +188,7 @@ def test_state_size_does_not_grow_with_objects():
                       precision="bf16") as n64:
             assert n64.stream_state_bytes(3, 7, 100) == 3 * 3 * 256 * 388
     with GlassNet(wts, 128, k_max=64, precision="fp32") as net:
-        assert net.stream_state_bytes(2, 30, 50) == 2 * 30 * 50 * (2 * 128 + 1) * 4
+        assert net.stream_state_bytes(2, 30, 50) == 2 * 30 * 50 * (3 * 128 + 1) * 4
 
 
 @pytest.mark.parametrize("precision", ["bf16", "fp8_t", "fp32"])

@@ -53,7 +53,10 @@ struct BwdWorkspace {
 namespace {
 
 constexpr int kThreads = 256;
-constexpr int kChunkPx = 4096;      // pixels per split-K chunk of the dW GEMMs
+constexpr int kChunkPx = 4096;      // plane rows hold the pixels rounded up to this
+// Plane rows are npx_pad + kRowSkew floats apart: a power-of-two pitch puts
+// the same pixel of every row on the same HBM channel.
+constexpr int kRowSkew = 1056;
 // Operand loads use 32-bit byte offsets within a plane block (up to 288 rows
 // plus a 16-row tile): this bounds the pixels of one backward call.
 constexpr int64_t kMaxPx = (int64_t)3 << 20;
@@ -417,109 +420,172 @@ __global__ __launch_bounds__(kThreads) void stream_pool_kernel(const double *__r
 }
 
 // ---- weight gradients: sums over pixels on the fp32 matrix cores -----------
-// part[chunk][o][i] (+)= sum_{p in chunk} D[o][p] A[i][p] for the
-// (16 MO) x (16 MI) tile (blockIdx.y, blockIdx.x).  Lane l feeds row (l & 15)
-// and pixels 4 (l >> 4) + j of a 16-pixel step to both operands, so every
-// pixel meets itself exactly once.  The four waves of a workgroup take
-// interleaved 16-pixel steps of the chunk and are summed in LDS in a fixed
-// order (deterministic).
+constexpr int kDwPx = 1024;     // pixels per chunk: one workgroup, one partial tile
+constexpr size_t kDwLds = 160 * 1024;   // LDS bytes per workgroup
+constexpr int kDwStep = 32;     // pixels per LDS stage: 8 chunks of 16 bytes per row
+// LDS stages of dw_lds_kernel<MO, MI>, each (MO + MI) x 32 rows of kDwStep
+// fp32: at most 4, and at least 2 for every shape with MO + MI <= 20.
+constexpr int dw_lds_stages(int MO, int MI) {
+  return (int)(kDwLds / ((size_t)(MO + MI) * 32 * kDwStep * 4)) < 4
+             ? (int)(kDwLds / ((size_t)(MO + MI) * 32 * kDwStep * 4))
+             : 4;
+}
+
+// part[chunk][o][i] (+)= sum over the chunk's pixels of D[o][p] A[i][p] for
+// the whole (32 MO) x (32 MI) tile of one weight gradient; the four waves
+// split it into 2 x 2 quadrants of (16 MO) x (16 MI) and each writes its own.
+// Every 32-pixel step of D's and A's rows is copied into LDS once, with direct
+// global->LDS loads, up to nst - 1 steps ahead of the matrix cores; row r keeps
+// its 16-byte chunk c at slot c ^ (r & 7), so the rows that 8 lanes read
+// together fall into distinct banks.  Lane l feeds row (l & 15) and the four
+// pixels of chunk 4 h + (l >> 4) of step half h to both operands, so every
+// pixel meets itself exactly once; the sums run in a fixed order.
 template <int MO, int MI>
-__global__ __launch_bounds__(kThreads) void dw_gemm_kernel(const float *__restrict__ D,
-                                                           const float *__restrict__ A,
-                                                           int64_t stride, float *__restrict__ part,
-                                                           int o_pad, int i_pad, int accumulate,
-                                                           int ti_n, int ntile, int nchunks) {
-  __shared__ f32x4 red[3][MO * MI][64];
+__global__ __launch_bounds__(kThreads) void dw_lds_kernel(const float *__restrict__ D,
+                                                         const float *__restrict__ A,
+                                                         int64_t stride, float *__restrict__ part,
+                                                         int accumulate) {
+  constexpr int nst = dw_lds_stages(MO, MI);
+  constexpr int kRows = 32 * (MO + MI);          // D's rows, then A's
+  constexpr int kStage = kRows * 8;              // 16-byte slots per stage
+  constexpr int kFills = kStage / 256;           // fill instructions per wave per stage
+  constexpr int kSteps = kDwPx / kDwStep;
+  extern __shared__ __attribute__((aligned(16))) f32x4 slab[];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int r = lane & 15, kq = lane >> 4;
-  // Workgroups are dealt to the 8 XCDs round robin by linear id; the tiles
-  // of one chunk are numbered so that they share an XCD (and its L2), which
-  // then reads the chunk's D and A rows from HBM once.
-  const int b = blockIdx.x, xcd = b & 7, rr = b >> 3;
-  const int chunk = 8 * (rr / ntile) + xcd, tile = rr % ntile;
-  if (chunk >= nchunks) return;
-  const int i0 = (tile % ti_n) * 16 * MI, o0 = (tile / ti_n) * 16 * MO;
+  const int wo = wave >> 1, wi = wave & 1;
+  const int chunk = blockIdx.x;
+  const int64_t p0 = (int64_t)chunk * kDwPx;
+  auto fill = [&](int st) {
+    f32x4 *dst = slab + (size_t)(st % nst) * kStage;
+    const int64_t px = p0 + (int64_t)st * kDwStep;
+#pragma unroll
+    for (int f = 0; f < kFills; ++f) {
+      const int base = (f * 4 + wave) * 64;
+      const int idx = base + lane, row = idx >> 3, c = (idx & 7) ^ (row & 7);
+      const float *src = row < 32 * MO ? D + (size_t)row * stride
+                                       : A + (size_t)(row - 32 * MO) * stride;
+      __builtin_amdgcn_global_load_lds((const void *)(src + px + 4 * c),
+                                       (__attribute__((address_space(3))) void *)(dst + base),
+                                       16, 0, 0);
+    }
+  };
   f32x4 acc[MO][MI];
 #pragma unroll
   for (int mo = 0; mo < MO; ++mo)
 #pragma unroll
     for (int mi = 0; mi < MI; ++mi) acc[mo][mi] = f32x4{0.f, 0.f, 0.f, 0.f};
-  const int64_t pbase = (int64_t)chunk * kChunkPx + 16 * wave + 4 * kq;
-  const rsrc_t dr = make_rsrc(D + (size_t)o0 * stride), ar = make_rsrc(A + (size_t)i0 * stride);
-  const uint32_t voff = (uint32_t)(((size_t)r * stride + pbase) * 4);
-  const uint32_t row16 = (uint32_t)stride * 64;               // bytes of 16 plane rows
-  f32x4 da[MO], aa[MI], db[MO], ab[MI];
-  auto load = [&](int s, f32x4 (&d)[MO], f32x4 (&x)[MI]) {
-    s = s < kChunkPx / 64 ? s : kChunkPx / 64 - 1;
+  const int drow = 16 * MO * wo + r, arow = 32 * MO + 16 * MI * wi + r;
+  for (int st = 0; st < nst - 1 && st < kSteps; ++st) fill(st);
+  for (int st = 0; st < kSteps; ++st) {
+    // stage st has landed once only the fills of later stages may be pending
+    const int pend = min(nst - 2, kSteps - 1 - st);
+    if (pend >= 2)
+      asm volatile("s_waitcnt vmcnt(%0)" ::"n"(2 * kFills) : "memory");
+    else if (pend == 1)
+      asm volatile("s_waitcnt vmcnt(%0)" ::"n"(kFills) : "memory");
+    else
+      asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    __syncthreads();     // stage st visible; every wave is done with stage st - 1
+    if (st + nst - 1 < kSteps) fill(st + nst - 1);     // into stage st - 1's buffer
+    const f32x4 *S = slab + (size_t)(st % nst) * kStage;
 #pragma unroll
-    for (int mo = 0; mo < MO; ++mo) d[mo] = bld4(dr, voff, mo * row16 + 256 * s);
+    for (int h = 0; h < 2; ++h) {
+      const int c = 4 * h + kq;
+      f32x4 d[MO], x[MI];
 #pragma unroll
-    for (int mi = 0; mi < MI; ++mi) x[mi] = bld4(ar, voff, mi * row16 + 256 * s);
-  };
-  auto mfma = [&](const f32x4 (&d)[MO], const f32x4 (&x)[MI]) {
+      for (int mo = 0; mo < MO; ++mo) {
+        const int row = drow + 16 * mo;
+        d[mo] = S[row * 8 + (c ^ (row & 7))];
+      }
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
+      for (int mi = 0; mi < MI; ++mi) {
+        const int row = arow + 16 * mi;
+        x[mi] = S[row * 8 + (c ^ (row & 7))];
+      }
 #pragma unroll
-      for (int mo = 0; mo < MO; ++mo)
+      for (int j = 0; j < 4; ++j)
 #pragma unroll
-        for (int mi = 0; mi < MI; ++mi)
-          acc[mo][mi] = __builtin_amdgcn_mfma_f32_16x16x4f32(d[mo][j], x[mi][j], acc[mo][mi], 0, 0, 0);
-  };
-  load(0, da, aa);
-  for (int s = 0; s < kChunkPx / 64; s += 2) {
-    load(s + 1, db, ab);
-    __builtin_amdgcn_sched_barrier(0);
-    mfma(da, aa);
-    __builtin_amdgcn_sched_barrier(0);
-    load(s + 2, da, aa);
-    __builtin_amdgcn_sched_barrier(0);
-    mfma(db, ab);
-    __builtin_amdgcn_sched_barrier(0);
-  }
-  if (wave > 0) {
+        for (int mo = 0; mo < MO; ++mo)
 #pragma unroll
-    for (int mo = 0; mo < MO; ++mo)
-#pragma unroll
-      for (int mi = 0; mi < MI; ++mi) red[wave - 1][mo * MI + mi][lane] = acc[mo][mi];
-  }
-  __syncthreads();
-  if (wave != 0) return;
-#pragma unroll
-  for (int w = 0; w < 3; ++w)
-#pragma unroll
-    for (int mo = 0; mo < MO; ++mo) {
-#pragma unroll
-      for (int mi = 0; mi < MI; ++mi) acc[mo][mi] += red[w][mo * MI + mi][lane];
-      __builtin_amdgcn_sched_barrier(0);     // bounds the LDS reads in flight
+          for (int mi = 0; mi < MI; ++mi)
+            acc[mo][mi] = __builtin_amdgcn_mfma_f32_16x16x4f32(d[mo][j], x[mi][j], acc[mo][mi],
+                                                                0, 0, 0);
     }
-  float *P = part + (size_t)chunk * o_pad * i_pad;
+  }
+  constexpr int kIPad = 32 * MI;
+  float *P = part + (size_t)chunk * (32 * MO) * kIPad;
 #pragma unroll
   for (int mo = 0; mo < MO; ++mo)
 #pragma unroll
     for (int mi = 0; mi < MI; ++mi)
 #pragma unroll
       for (int rr = 0; rr < 4; ++rr) {
-        const int o = o0 + 16 * mo + 4 * kq + rr, i = i0 + 16 * mi + r;
-        float *dst = P + (size_t)o * i_pad + i;
+        const int o = 16 * MO * wo + 16 * mo + 4 * kq + rr, i = 16 * MI * wi + 16 * mi + r;
+        float *dst = P + (size_t)o * kIPad + i;
         *dst = accumulate ? *dst + acc[mo][mi][rr] : acc[mo][mi][rr];
       }
 }
 
+template <int MO, int MI>
+static hipError_t launch_dw_lds(const float *D, const float *A, int64_t stride, float *part,
+                                int accumulate, int nchunks, hipStream_t s) {
+  constexpr int nst = dw_lds_stages(MO, MI);
+  static_assert(nst >= 2, "dw_lds_kernel needs two LDS stages");
+  constexpr size_t lds = (size_t)nst * (MO + MI) * 32 * kDwStep * 4;
+  static bool attr_set = false;     // per process; the attribute is per function
+  if (!attr_set) {
+    hipError_t e = hipFuncSetAttribute((const void *)dw_lds_kernel<MO, MI>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    attr_set = true;
+  }
+  hipLaunchKernelGGL((dw_lds_kernel<MO, MI>), dim3((unsigned)nchunks), dim3(kThreads), lds, s, D,
+                     A, stride, part, accumulate);
+  return hipGetLastError();
+}
+
 // grad_w[layer][o][col0 + i] = sum_chunks part[c][o][i] (i < n_in);
-// grad_w bias[o] = sum part[c][o][n_in] when has_bias.
-__global__ void dw_reduce_kernel(const float *__restrict__ part, int nchunks, int o_pad, int i_pad,
-                                 int n_out, int n_in, int has_bias, float *__restrict__ gw,
-                                 LayerOff lo, int col0) {
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  const int ncol = n_in + (has_bias ? 1 : 0);
-  if (e >= n_out * ncol) return;
-  const int o = e / ncol, i = e - o * ncol;
-  float s = 0.0f;
-  for (int c = 0; c < nchunks; ++c) s += part[((size_t)c * o_pad + o) * i_pad + i];
-  if (i < n_in)
-    gw[lo.w + (int64_t)o * lo.in + col0 + i] = s;
-  else
-    gw[lo.b + o] = s;
+// grad_w bias[o] = sum part[c][o][n_in] when has_bias.  A workgroup owns 16
+// float4 columns of the padded (o_pad x i_pad) tile; its thread group g sums
+// chunks g, g + 16, g + 32, ... in order and group 0 adds the 16 sums in group
+// order, so the result does not depend on the launch.
+__global__ __launch_bounds__(kThreads) void dw_reduce_kernel(const float *__restrict__ part,
+                                                             int nchunks, int o_pad, int i_pad,
+                                                             int n_out, int n_in, int has_bias,
+                                                             float *__restrict__ gw, LayerOff lo,
+                                                             int col0) {
+  __shared__ f32x4 red[16][16];
+  const int v = threadIdx.x & 15, g = threadIdx.x >> 4;
+  const int n4 = o_pad * i_pad / 4, e4 = blockIdx.x * 16 + v;
+  f32x4 s = f32x4{0.f, 0.f, 0.f, 0.f};
+  if (e4 < n4) {
+    const f32x4 *src = (const f32x4 *)part + e4;
+    int c = g;
+    for (; c + 48 < nchunks; c += 64) {
+      const f32x4 a0 = src[(size_t)c * n4], a1 = src[(size_t)(c + 16) * n4];
+      const f32x4 a2 = src[(size_t)(c + 32) * n4], a3 = src[(size_t)(c + 48) * n4];
+      s += a0;
+      s += a1;
+      s += a2;
+      s += a3;
+    }
+    for (; c < nchunks; c += 16) s += src[(size_t)c * n4];
+  }
+  red[g][v] = s;
+  __syncthreads();
+  if (g != 0 || e4 >= n4) return;
+  for (int k = 1; k < 16; ++k) s += red[k][v];
+  const int o = 4 * e4 / i_pad, i0 = 4 * e4 - o * i_pad;
+  if (o >= n_out) return;
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    const int i = i0 + t;
+    if (i < n_in)
+      gw[lo.w + (int64_t)o * lo.in + col0 + i] = s[t];
+    else if (has_bias && i == n_in)
+      gw[lo.b + o] = s[t];
+  }
 }
 
 __global__ void fill_kernel(float *dst, int64_t n, float v) {
@@ -591,9 +657,9 @@ static hipError_t ensure_workspace(gn_handle *h, int64_t npx_pad) {
   const OpTable ops = make_ops(h->W);
   ws->W = h->W;
   ws->cap_px = npx_pad;
-  ws->plane_bytes = sizeof(float) * (size_t)bl.rows * npx_pad;
+  ws->plane_bytes = sizeof(float) * (size_t)bl.rows * (npx_pad + kRowSkew);
   ws->frag_bytes = sizeof(f32x4) * (size_t)ops.total;
-  ws->max_chunks = (int)((npx_pad + kChunkPx - 1) / kChunkPx);
+  ws->max_chunks = (int)((npx_pad + kDwPx - 1) / kDwPx);
   const int W = h->W;
   ws->part_bytes = sizeof(float) * (size_t)ws->max_chunks * W * rup(2 * W + 1, 32);
   ws->part_t2_bytes = sizeof(float) * (size_t)ws->max_chunks * W * rup(W + 1, 32);
@@ -649,11 +715,12 @@ class Pipeline {
     const int64_t hw = (int64_t)f->h * f->w;
     npx_ = (int64_t)f->n * hw;
     npx_pad_ = (npx_ + kChunkPx - 1) / kChunkPx * kChunkPx;
+    ld_ = npx_pad_ + kRowSkew;
     if (npx_pad_ > kMaxPx) return gn_set_error(GN_E_INVAL, "more than 3 * 2^20 pixels in one call");
     hw_ = (int)hw;
     K_ = f->k;
     e_ = ensure_workspace(h_, npx_pad_);
-    if (e_ == hipSuccess) e_ = init_constant_rows(h_, npx_pad_, s_);
+    if (e_ == hipSuccess) e_ = init_constant_rows(h_, ld_, s_);
     if (e_ != hipSuccess) return gn_check_device(h_, e_, what);
     ws_ = h_->bwd;
     wm_ = h_->d_master;
@@ -666,7 +733,7 @@ class Pipeline {
     pa_.pool = h_->cfg.pool;
     pa_.W = W_;
     pa_.npx = npx_;
-    pa_.stride = npx_pad_;
+    pa_.stride = ld_;
     pa_.planes = ws_->planes;
     pa_.bl = bl_;
     hipLaunchKernelGGL(pack_ops_kernel, dim3((unsigned)((ops_.total + kThreads - 1) / kThreads)),
@@ -725,7 +792,7 @@ class Pipeline {
   void output(float *out) {
     gemm(O_R3, EP_FWD, bl_.g2, bl_.y, args());
     hipLaunchKernelGGL(scatter_out_kernel, pgrid(), dim3(kThreads), 0, s_, plane(bl_.y),
-                       npx_pad_, npx_, hw_, wm_ + lo_[L_R3].b, out);
+                       ld_, npx_, hw_, wm_ + lo_[L_R3].b, out);
   }
 
   // FP8 calibration: the largest first-layer activation of h over every slot
@@ -735,7 +802,7 @@ class Pipeline {
       gather(i);
       z1();
       hipLaunchKernelGGL(amax_kernel, pgrid(), dim3(kThreads), 0, s_, plane(bl_.z1), W_,
-                         npx_pad_, npx_, amax);
+                         ld_, npx_, amax);
     }
   }
 
@@ -819,13 +886,13 @@ class Pipeline {
   // order are the forward's.
   void stream_begin(float *state) {
     trunk();
-    copy_rows(state, npx_, plane(bl_.st), npx_pad_, W_);
+    copy_rows(state, npx_, plane(bl_.st), ld_, W_);
   }
   void stream_accumulate(float *state, bool fresh) {
-    copy_rows(plane(bl_.st), npx_pad_, state, npx_, W_);
+    copy_rows(plane(bl_.st), ld_, state, npx_, W_);
     fwd(O_T1S, bl_.st, bl_.u, L_T1, false);                  // u, as in trunk()
     double *z64 = (double *)(state + (size_t)W_ * npx_);
-    if (!fresh) copy_rows(dplane(bl_.zd), npx_pad_, z64, npx_, W_);
+    if (!fresh) copy_rows(dplane(bl_.zd), ld_, z64, npx_, W_);
     for (int i = 0; i < K_; ++i) {
       gather(i);
       z1();
@@ -838,19 +905,19 @@ class Pipeline {
       a.skip_out = 1;                                         // the state keeps the sum
       gemm(O_T2, EP_FWD, bl_.z1, bl_.zs, a);
     }
-    copy_rows(z64, npx_, dplane(bl_.zd), npx_pad_, W_);
+    copy_rows(z64, npx_, dplane(bl_.zd), ld_, W_);
     hipLaunchKernelGGL(stream_count_kernel, pgrid(), dim3(kThreads), 0, s_, pa_.layers, K_, hw_,
                        npx_, state + (size_t)3 * W_ * npx_, fresh ? 1 : 0);
   }
   void stream_finish(const float *state, bool fresh, float *out) {
-    copy_rows(plane(bl_.st), npx_pad_, state, npx_, W_);
+    copy_rows(plane(bl_.st), ld_, state, npx_, W_);
     if (fresh) {
       fill_rows(bl_.zs, W_ + 1);           // no object: empty pool, zero bias scale
     } else {
       hipLaunchKernelGGL(stream_pool_kernel, pgrid(), dim3(kThreads), 0, s_,
                          (const double *)(state + (size_t)W_ * npx_),
                          state + (size_t)3 * W_ * npx_, npx_, W_,
-                         h_->cfg.pool == GN_POOL_MEAN ? 1 : 0, plane(bl_.zs), npx_pad_);
+                         h_->cfg.pool == GN_POOL_MEAN ? 1 : 0, plane(bl_.zs), ld_);
     }
     head();
     output(out);
@@ -863,15 +930,15 @@ class Pipeline {
 
  private:
   dim3 pgrid() const { return dim3((unsigned)(npx_pad_ / kThreads)); }
-  int nchunks() const { return (int)(npx_pad_ / kChunkPx); }
-  float *plane(int r) const { return ws_->planes + (size_t)r * npx_pad_; }
+  int nchunks() const { return (int)(npx_pad_ / kDwPx); }
+  float *plane(int r) const { return ws_->planes + (size_t)r * ld_; }
   static PgArgs args() {
     PgArgs a;
     memset(&a, 0, sizeof a);
     return a;
   }
   void fill_rows(int row, int n) {
-    if (e_ == hipSuccess) e_ = fill(plane(row), (int64_t)n * npx_pad_, 0.0f, s_);
+    if (e_ == hipSuccess) e_ = fill(plane(row), (int64_t)n * ld_, 0.0f, s_);
   }
   void gather(int i) {
     hipLaunchKernelGGL(slot_gather_kernel, pgrid(), dim3(kThreads), 0, s_, pa_, i);
@@ -883,7 +950,7 @@ class Pipeline {
       e_ = hipMemcpy2DAsync(dst, sizeof(T) * dst_len, src, sizeof(T) * src_len, sizeof(T) * npx_,
                             n, hipMemcpyDeviceToDevice, s_);
   }
-  // a block of fp64 rows (two float rows each) as doubles, row length npx_pad_
+  // a block of fp64 rows (two float rows each) as doubles, row pitch ld_
   double *dplane(int r) const { return (double *)plane(r); }
 
   // One plane GEMM: op `o` from block `xrow` into block `orow`.
@@ -891,7 +958,7 @@ class Pipeline {
     const OpDesc &d = ops_.op[o];
     a.frag = ws_->frag + d.off;
     a.kq = d.kq;
-    a.stride = npx_pad_;
+    a.stride = ld_;
     a.x = plane(xrow);
     a.out = plane(orow);
     const dim3 block(kThreads);
@@ -929,26 +996,23 @@ class Pipeline {
     gemm(O_T1A, EP_FWD, bl_.bi, bl_.z1, a);
   }
   void dw_gemm(const GemmJob &j, float *part, int accumulate) {
-    // tile: 16 MO output rows x 16 MI input rows, dividing o_pad and i_pad
-    const int mo = j.o_pad % 64 == 0 ? 4 : 2;
-    const int ti = j.i_pad / 16;
-    const int mi = ti % 6 == 0 ? 6 : ti % 5 == 0 ? 5 : ti % 4 == 0 ? 4 : 2;
-    const int ti_n = ti / mi, ntile = ti_n * (j.o_pad / (16 * mo)), nch = nchunks();
-    const dim3 grid((unsigned)(8 * ntile * ((nch + 7) / 8))), block(kThreads);
+    // the whole (o_pad x i_pad) gradient per workgroup, operands staged in LDS
+    const int MO = j.o_pad / 32, MI = j.i_pad / 32;
     const float *D = plane(j.dblock), *Ap = plane(j.ablock);
-#define DW(MO, MI)                                                                       \
-  hipLaunchKernelGGL((dw_gemm_kernel<MO, MI>), grid, block, 0, s_, D, Ap, npx_pad_, part, \
-                     j.o_pad, j.i_pad, accumulate, ti_n, ntile, nch)
-    if (mo == 4) {
-      if (mi == 6) DW(4, 6); else if (mi == 5) DW(4, 5); else if (mi == 4) DW(4, 4); else DW(4, 2);
-    } else {
-      if (mi == 6) DW(2, 6); else if (mi == 5) DW(2, 5); else if (mi == 4) DW(2, 4); else DW(2, 2);
-    }
-#undef DW
+#define DL(A, B)                                                                       \
+  if (MO == A && MI == B) {                                                            \
+    const hipError_t e = launch_dw_lds<A, B>(D, Ap, ld_, part, accumulate, nchunks(), s_); \
+    if (e_ == hipSuccess) e_ = e;                                                      \
+    return;                                                                            \
+  }
+    DL(1, 5) DL(4, 5) DL(4, 9) DL(4, 4) DL(4, 1)     // W = 128
+    DL(1, 3) DL(2, 3) DL(2, 5) DL(2, 2) DL(2, 1)     // W = 64
+#undef DL
+    e_ = hipErrorInvalidValue;     // no other gradient shape exists for widths 64 and 128
   }
   void reduce(const GemmJob &j, const float *part, int nch, float *grad_w) {
-    const int n = j.n_out * (j.n_in + (j.has_bias ? 1 : 0));
-    hipLaunchKernelGGL(dw_reduce_kernel, dim3((n + 255) / 256), dim3(256), 0, s_, part, nch,
+    const int n4 = j.o_pad * j.i_pad / 4;
+    hipLaunchKernelGGL(dw_reduce_kernel, dim3((n4 + 15) / 16), dim3(kThreads), 0, s_, part, nch,
                        j.o_pad, j.i_pad, j.n_out, j.n_in, j.has_bias, grad_w, lo_[j.layer], j.col0);
   }
 
@@ -961,7 +1025,7 @@ class Pipeline {
   BwdWorkspace *ws_ = nullptr;
   const float *wm_ = nullptr;
   PrepArgs pa_{};
-  int64_t npx_ = 0, npx_pad_ = 0;
+  int64_t npx_ = 0, npx_pad_ = 0, ld_ = 0;   // pixels, padded pixels, plane row pitch
   int hw_ = 0, K_ = 0;
   hipError_t e_ = hipSuccess;
 };

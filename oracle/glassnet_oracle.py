@@ -25,7 +25,14 @@ Readings where the paper leaves details open (each listed in the design notes):
     no active slot gives tau = 0;
   * B takes [sigma ; tau]; R takes [phi ; L_d] with L_d = G-buffer planes 11..13;
   * L1 loss = mean |y - t| over every output element, with subgradient 0 at
-    y == t and ReLU'(0) = 0.
+    y == t and ReLU'(0) = 0;
+  * positional encoding (Sec. 3.4 encodes every input; the frequency count is
+    not given): with L levels, an input vector x becomes
+    [x; sin(pi x); cos(pi x); sin(2 pi x); cos(2 pi x); ...;
+     sin(2^(L-1) pi x); cos(2^(L-1) pi x)], blocks of the raw width in that
+    order.  It applies to F's input [G; s] and to h's slot input b_i; sigma
+    (internal) and R's L_d stay raw, and the mask reads the raw alpha.  L = 0
+    is the unencoded network of the workloads.
 
 Everything is evaluated in float64 from the float32 inputs, literally in the
 order above: no hoisting of sigma out of h, no fusion.  `forward_bruteforce`
@@ -34,6 +41,7 @@ is a scalar Python-loop twin used to pin `forward` on tiny inputs.
 from __future__ import annotations
 
 import itertools
+import math
 
 import numpy as np
 
@@ -41,27 +49,40 @@ NG, NL, NS, NOUT = 14, 12, 16, 3
 NETS = ("F", "T", "B", "R")
 
 
-def _shapes(W):
-    fan_in = {"F": (NG + NS, W, W), "T": (NL + W, W, W), "B": (2 * W, W, W),
+def encode(x, levels):
+    """Positional encoding of the rows of x [C, P] -> [(1 + 2 levels) C, P]."""
+    x = np.asarray(x, dtype=np.float64)
+    blocks = [x]
+    for k in range(levels):
+        arg = np.pi * (2.0 ** k) * x
+        blocks.append(np.sin(arg))
+        blocks.append(np.cos(arg))
+    return np.concatenate(blocks, axis=0)
+
+
+def _shapes(W, pe_levels=0):
+    e = 1 + 2 * pe_levels
+    fan_in = {"F": ((NG + NS) * e, W, W), "T": (NL * e + W, W, W), "B": (2 * W, W, W),
               "R": (W + 3, W, W)}
     fan_out = {"F": (W, W, W), "T": (W, W, W), "B": (W, W, W), "R": (W, W, NOUT)}
     return fan_in, fan_out
 
 
-def n_params(W: int) -> int:
-    fi, fo = _shapes(W)
+def n_params(W: int, pe_levels: int = 0) -> int:
+    fi, fo = _shapes(W, pe_levels)
     return sum(fo[n][j] * fi[n][j] + fo[n][j] for n in NETS for j in range(3))
 
 
-def unpack(w, W: int):
+def unpack(w, W: int, pe_levels: int = 0):
     """Flat float vector -> {net: [(A1, c1), (A2, c2), (A3, c3)]} in float64.
 
     Order: nets F, T, B, R; layers 1..3; matrix row-major [out][in], then bias.
     """
     w = np.asarray(w, dtype=np.float64).ravel()
-    if w.size != n_params(W):
-        raise ValueError(f"expected {n_params(W)} weights for W={W}, got {w.size}")
-    fi, fo = _shapes(W)
+    if w.size != n_params(W, pe_levels):
+        raise ValueError(f"expected {n_params(W, pe_levels)} weights for W={W}, "
+                         f"{pe_levels} encoding levels, got {w.size}")
+    fi, fo = _shapes(W, pe_levels)
     out, off = {}, 0
     for net in NETS:
         layers = []
@@ -111,16 +132,16 @@ def _pixels(gbuf, layers, scene):
     return G, Lp, S, (n, h, w)
 
 
-def _forward_cols(P, G, L, S, W, pool, keep=False):
+def _forward_cols(P, G, L, S, W, pool, keep=False, pe=0):
     """Column-wise forward over pixels.  P = unpacked params."""
-    x = np.concatenate([G, S], axis=0)                     # [30, P]
+    x = encode(np.concatenate([G, S], axis=0), pe)          # [30 (1 + 2 pe), P]
     sigma = _mlp(P["F"], x)                                 # [W, P]
     k = L.shape[0]
     Ssum = np.zeros_like(sigma)
     cnt = np.zeros(sigma.shape[1])
     for i in range(k):
         b = L[i]                                            # [12, P]
-        h = _mlp(P["T"], np.concatenate([b, sigma], axis=0))  # Eq. (5): h(b_i, sigma)
+        h = _mlp(P["T"], np.concatenate([encode(b, pe), sigma], axis=0))  # Eq. (5): h(b_i, sigma)
         m = (b[9] > 0.0).astype(np.float64)                 # alpha > 0
         Ssum += m[None, :] * h
         cnt += m
@@ -137,13 +158,14 @@ def _forward_cols(P, G, L, S, W, pool, keep=False):
     return y
 
 
-def forward(w, W, gbuf, layers, scene, pool="mean", chunk=16384, return_latents=False):
+def forward(w, W, gbuf, layers, scene, pool="mean", chunk=16384, return_latents=False,
+            pe_levels=0):
     """Vectorised FP64 forward.  Returns y [n][3][h][w] (float64).
 
     With return_latents=True also returns dict of sigma, tau, phi [n][W][h][w]
     and the active count [n][h][w].
     """
-    P = unpack(w, W)
+    P = unpack(w, W, pe_levels)
     G, L, S, (n, h, wd) = _pixels(gbuf, layers, scene)
     npx = G.shape[1]
     y = np.empty((NOUT, npx))
@@ -152,11 +174,12 @@ def forward(w, W, gbuf, layers, scene, pool="mean", chunk=16384, return_latents=
     for a in range(0, npx, chunk):
         b = min(npx, a + chunk)
         if return_latents:
-            yy, d = _forward_cols(P, G[:, a:b], L[:, :, a:b], S[:, a:b], W, pool, keep=True)
+            yy, d = _forward_cols(P, G[:, a:b], L[:, :, a:b], S[:, a:b], W, pool, keep=True,
+                                  pe=pe_levels)
             for key in lat:
                 lat[key][..., a:b] = d[key]
         else:
-            yy = _forward_cols(P, G[:, a:b], L[:, :, a:b], S[:, a:b], W, pool)
+            yy = _forward_cols(P, G[:, a:b], L[:, :, a:b], S[:, a:b], W, pool, pe=pe_levels)
         y[:, a:b] = yy
 
     def img(v):
@@ -170,9 +193,17 @@ def forward(w, W, gbuf, layers, scene, pool="mean", chunk=16384, return_latents=
     return out
 
 
-def forward_bruteforce(w, W, gbuf, layers, scene, pool="mean"):
+def forward_bruteforce(w, W, gbuf, layers, scene, pool="mean", pe_levels=0):
     """Scalar Python loops over pixels, slots and neurons (tiny inputs only)."""
-    P = unpack(w, W)
+    P = unpack(w, W, pe_levels)
+
+    def enc(v):
+        out = list(v)
+        for k in range(pe_levels):
+            f = math.pi * 2 ** k
+            out += [math.sin(f * t) for t in v]
+            out += [math.cos(f * t) for t in v]
+        return out
 
     def dense(layer, v, act):
         A, c = layer
@@ -199,13 +230,13 @@ def forward_bruteforce(w, W, gbuf, layers, scene, pool="mean"):
         for r in range(h):
             for c in range(wd):
                 gp = [float(g[f, ch, r, c]) for ch in range(NG)]
-                sigma = net("F", gp + [float(v) for v in s[f]])
+                sigma = net("F", enc(gp + [float(v) for v in s[f]]))
                 tau = [0.0] * W
                 active = 0
                 for i in range(k):
                     b = [float(L[f, i, ch, r, c]) for ch in range(NL)]
                     if b[9] > 0.0:
-                        hi = net("T", b + sigma)
+                        hi = net("T", enc(b) + sigma)
                         tau = [t + v for t, v in zip(tau, hi)]
                         active += 1
                 if pool == "mean" and active > 0:
@@ -249,22 +280,22 @@ def _mlp_bwd(layers, cache, dout, grads):
     return A1.T @ d
 
 
-def grad(w, W, gbuf, layers, scene, target, pool="mean", chunk=16384):
+def grad(w, W, gbuf, layers, scene, target, pool="mean", chunk=16384, pe_levels=0):
     """L1 loss and its gradient w.r.t. the flat weight vector (FP64 backprop).
 
     The transparency mask alpha > 0 is a hard selection (no gradient flows
     through it); gradients flow into sigma through every active slot's h.
     """
-    return _backprop(w, W, gbuf, layers, scene, pool, chunk, target=target)
+    return _backprop(w, W, gbuf, layers, scene, pool, chunk, target=target, pe=pe_levels)
 
 
-def grad_from_dy(w, W, gbuf, layers, scene, dy, pool="mean", chunk=16384):
+def grad_from_dy(w, W, gbuf, layers, scene, dy, pool="mean", chunk=16384, pe_levels=0):
     """dL/dw for a given dL/dy [n][3][h][w] (the vector-Jacobian product)."""
-    return _backprop(w, W, gbuf, layers, scene, pool, chunk, dy=dy)[1]
+    return _backprop(w, W, gbuf, layers, scene, pool, chunk, dy=dy, pe=pe_levels)[1]
 
 
-def _backprop(w, W, gbuf, layers, scene, pool, chunk, target=None, dy=None):
-    P = unpack(w, W)
+def _backprop(w, W, gbuf, layers, scene, pool, chunk, target=None, dy=None, pe=0):
+    P = unpack(w, W, pe)
     G, L, S, (n, h, wd) = _pixels(gbuf, layers, scene)
     if target is not None:
         t = np.asarray(target, dtype=np.float64)
@@ -278,14 +309,14 @@ def _backprop(w, W, gbuf, layers, scene, pool, chunk, target=None, dy=None):
     for a0 in range(0, npx, chunk):
         b0 = min(npx, a0 + chunk)
         Gc, Lc, Sc = G[:, a0:b0], L[:, :, a0:b0], S[:, a0:b0]
-        x = np.concatenate([Gc, Sc], axis=0)
+        x = encode(np.concatenate([Gc, Sc], axis=0), pe)
         sigma, cF = _mlp_fwd_keep(P["F"], x)
         k = Lc.shape[0]
         Ssum = np.zeros_like(sigma)
         cnt = np.zeros(sigma.shape[1])
         cT, ms = [], []
         for i in range(k):
-            hi, ci = _mlp_fwd_keep(P["T"], np.concatenate([Lc[i], sigma], axis=0))
+            hi, ci = _mlp_fwd_keep(P["T"], np.concatenate([encode(Lc[i], pe), sigma], axis=0))
             m = (Lc[i][9] > 0.0).astype(np.float64)
             Ssum += m[None, :] * hi
             cnt += m
@@ -312,19 +343,19 @@ def _backprop(w, W, gbuf, layers, scene, pool, chunk, target=None, dy=None):
         for i in range(k):
             dh = dS * ms[i][None, :]
             dv = _mlp_bwd(P["T"], cT[i], dh, grads["T"])
-            dsigma += dv[NL:]
+            dsigma += dv[NL * (1 + 2 * pe):]
         _mlp_bwd(P["F"], cF, dsigma, grads["F"])
     flat = pack({net: [(gA, gc) for gA, gc in grads[net]] for net in NETS})
     return loss / total, flat
 
 
-def relu_signature(w, W, gbuf, layers, scene, target, pool="mean"):
+def relu_signature(w, W, gbuf, layers, scene, target, pool="mean", pe_levels=0):
     """Every branch decision of the loss (ReLU signs, slot masks, L1 signs).
 
     Two parameter vectors with equal signatures lie on the same smooth piece
     of the loss, where central finite differences are valid.
     """
-    P = unpack(w, W)
+    P = unpack(w, W, pe_levels)
     G, L, S, _ = _pixels(gbuf, layers, scene)
     T = np.moveaxis(np.asarray(target, dtype=np.float64), 1, 0).reshape(NOUT, -1)
     sig = []
@@ -335,12 +366,12 @@ def relu_signature(w, W, gbuf, layers, scene, target, pool="mean"):
         sig.append(z2 > 0.0)
         return out
 
-    x = np.concatenate([G, S], axis=0)
+    x = encode(np.concatenate([G, S], axis=0), pe_levels)
     sigma = run("F", x)
     Ssum = np.zeros_like(sigma)
     cnt = np.zeros(sigma.shape[1])
     for i in range(L.shape[0]):
-        hi = run("T", np.concatenate([L[i], sigma], axis=0))
+        hi = run("T", np.concatenate([encode(L[i], pe_levels), sigma], axis=0))
         m = (L[i][9] > 0.0).astype(np.float64)
         Ssum += m * hi
         cnt += m
@@ -351,7 +382,7 @@ def relu_signature(w, W, gbuf, layers, scene, target, pool="mean"):
     return np.concatenate([s.ravel() for s in sig])
 
 
-def relu_margins(w, W, gbuf, layers, scene, pool="mean"):
+def relu_margins(w, W, gbuf, layers, scene, pool="mean", pe_levels=0):
     """Per pixel, how far every ReLU input lies from the kink at 0.
 
     For each hidden pre-activation z = a . x + c of F, of h for every active
@@ -363,7 +394,7 @@ def relu_margins(w, W, gbuf, layers, scene, pool="mean"):
     branch of ReLU' (a different but equally valid subgradient choice), so
     gradient parity is only meaningful away from such pixels.
     """
-    P = unpack(w, W)
+    P = unpack(w, W, pe_levels)
     G, L, S, (n, h, wd) = _pixels(gbuf, layers, scene)
     marg = np.full(G.shape[1], np.inf)
 
@@ -380,12 +411,12 @@ def relu_margins(w, W, gbuf, layers, scene, pool="mean"):
             marg = np.minimum(marg, r)
         return A3 @ _relu(z2) + c3[:, None]
 
-    sigma = run("F", np.concatenate([G, S], axis=0))
+    sigma = run("F", encode(np.concatenate([G, S], axis=0), pe_levels))
     Ssum = np.zeros_like(sigma)
     cnt = np.zeros(sigma.shape[1])
     for i in range(L.shape[0]):
         m = L[i][9] > 0.0
-        hi = run("T", np.concatenate([L[i], sigma], axis=0), active=m)
+        hi = run("T", np.concatenate([encode(L[i], pe_levels), sigma], axis=0), active=m)
         Ssum += m * hi
         cnt += m
     tau = Ssum if pool == "sum" else Ssum / np.maximum(cnt, 1.0)

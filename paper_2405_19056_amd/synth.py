@@ -49,19 +49,22 @@ _STREAMS = ("weights", "gbuf", "slots", "active", "shuffles", "teacher",
             "noise", "arrivals")
 
 
-def layer_shapes(width: int):
-    """(fan_out, fan_in) of the 12 linear layers in packing order."""
+def layer_shapes(width: int, pe_levels: int = 0):
+    """(fan_out, fan_in) of the 12 linear layers in packing order.  With
+    positional encoding of L levels, F's input and h's slot input are
+    (1 + 2 L) times wider."""
     W = width
+    e = 1 + 2 * pe_levels
     return [
-        (W, N_G + N_S), (W, W), (W, W),          # F
-        (W, N_L + W), (W, W), (W, W),            # T (shared per-layer MLP h)
+        (W, (N_G + N_S) * e), (W, W), (W, W),    # F
+        (W, N_L * e + W), (W, W), (W, W),        # T (shared per-layer MLP h)
         (W, 2 * W), (W, W), (W, W),              # B
         (W, W + 3), (W, W), (N_OUT, W),          # R
     ]
 
 
-def num_params(width: int) -> int:
-    return sum(o * i + o for o, i in layer_shapes(width))
+def num_params(width: int, pe_levels: int = 0) -> int:
+    return sum(o * i + o for o, i in layer_shapes(width, pe_levels))
 
 
 def streams(seed: int) -> dict:
@@ -70,9 +73,9 @@ def streams(seed: int) -> dict:
     return {name: np.random.default_rng(c) for name, c in zip(_STREAMS, children)}
 
 
-def make_weights(width: int, rng: np.random.Generator) -> np.ndarray:
+def make_weights(width: int, rng: np.random.Generator, pe_levels: int = 0) -> np.ndarray:
     parts = []
-    for fan_out, fan_in in layer_shapes(width):
+    for fan_out, fan_in in layer_shapes(width, pe_levels):
         wb = np.sqrt(6.0 / fan_in)
         bb = 1.0 / np.sqrt(fan_in)
         parts.append(rng.uniform(-wb, wb, size=fan_out * fan_in))

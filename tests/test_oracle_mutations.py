@@ -11,6 +11,7 @@ import numpy as np
 import pytest
 
 import oracle.glassnet_oracle as go
+import test_oracle_pe as pe_pins
 import test_oracle_pins as pins
 
 PIN_TESTS = [
@@ -24,20 +25,26 @@ PIN_TESTS = [
     lambda: pins.test_mean_sum_closed_forms(),
     lambda: pins.test_every_slot_order_gives_the_same_image("sum"),
     lambda: pins.test_frames_use_their_own_scene_vector(),
+    lambda: pe_pins.test_encoding_identities(),
+    lambda: pe_pins.test_encoding_exact_values(),
+    lambda: pe_pins.test_encoded_vectorised_matches_bruteforce(2, "mean"),
+    lambda: pe_pins.test_zero_encoding_columns_reduce_to_the_raw_network(1),
+    lambda: pe_pins.test_column_layout_of_the_encoded_inputs(),
 ]
 
 
-def _forward_cols_variant(P, G, L, S, W, pool, keep=False, *, cat_h=None, ld=slice(11, 14),
-                          active=lambda a: a > 0.0, sign=1.0, mean_over_k=False, cat_b=None,
-                          use_scene=True):
+def _forward_cols_variant(P, G, L, S, W, pool, keep=False, pe=0, *, cat_h=None,
+                          ld=slice(11, 14), active=lambda a: a > 0.0, sign=1.0,
+                          mean_over_k=False, cat_b=None, use_scene=True, encode_slots=True):
     relu = go._relu
-    x = np.concatenate([G, S if use_scene else 0 * S], axis=0)
+    x = go.encode(np.concatenate([G, S if use_scene else 0 * S], axis=0), pe)
     sigma = go._mlp(P["F"], x)
     Ssum = np.zeros_like(sigma)
     cnt = np.zeros(sigma.shape[1])
     for i in range(L.shape[0]):
         b = L[i]
-        inp = cat_h(b, sigma) if cat_h else np.concatenate([b, sigma], axis=0)
+        be = go.encode(b, pe) if encode_slots else np.concatenate([b] + [0 * b] * (2 * pe))
+        inp = cat_h(be, sigma) if cat_h else np.concatenate([be, sigma], axis=0)
         h = go._mlp(P["T"], inp)
         m = active(b[9]).astype(np.float64)
         Ssum += sign * m[None, :] * h
@@ -69,10 +76,24 @@ def _mlp_relu_out(layers, x):
 _orig_mlp = go._mlp
 _orig_unpack = go.unpack
 _orig_fc = go._forward_cols
+_orig_encode = go.encode
 
 
-def _unpack_transposed(w, W):
-    P = _orig_unpack(w, W)
+def _encode_variant(x, levels, *, freq=lambda k: np.pi * 2.0 ** k, cos_first=False):
+    x = np.asarray(x, dtype=np.float64)
+    blocks = [x]
+    for k in range(levels):
+        s, c = np.sin(freq(k) * x), np.cos(freq(k) * x)
+        blocks += [c, s] if cos_first else [s, c]
+    return np.concatenate(blocks, axis=0)
+
+
+def enc(**kw):
+    return lambda x, levels: _encode_variant(x, levels, **kw)
+
+
+def _unpack_transposed(w, W, pe_levels=0):
+    P = _orig_unpack(w, W, pe_levels)
     return {n: [(A.T if A.shape[0] == A.shape[1] else A, c) for A, c in layers]
             for n, layers in P.items()}
 
@@ -93,6 +114,11 @@ MUTATIONS = {
     "pool subtracts h": ("_forward_cols", fc(sign=-1.0)),
     "B input [tau; sigma]": ("_forward_cols", fc(cat_b=lambda s, t: np.concatenate([t, s], axis=0))),
     "scene vector ignored": ("_forward_cols", fc(use_scene=False)),
+    "encoding frequencies 2^k instead of pi 2^k": ("encode", enc(freq=lambda k: 2.0 ** k)),
+    "encoding frequencies pi (k + 1)": ("encode", enc(freq=lambda k: np.pi * (k + 1))),
+    "encoding frequencies 2 pi 2^k": ("encode", enc(freq=lambda k: 2 * np.pi * 2.0 ** k)),
+    "cos block before sin block": ("encode", enc(cos_first=True)),
+    "slot input left unencoded": ("_forward_cols", fc(encode_slots=False)),
 }
 
 

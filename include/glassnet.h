@@ -46,6 +46,7 @@ extern "C" {
 #define GN_NUM_OUT 3
 #define GN_ALPHA_PLANE 9
 #define GN_MAX_K 64
+#define GN_MAX_PE_LEVELS 4
 
 typedef int32_t gn_status;
 #define GN_OK 0
@@ -86,6 +87,13 @@ typedef struct gn_config {
   uint64_t hbm_budget_bytes;  /* serving admission budget; 0 = 64 GiB */
   int32_t device;             /* HIP device ordinal */
   int32_t max_pending;        /* serving: pending-queue bound; 0 = 65536 */
+  int32_t pe_levels;          /* positional encoding levels L, 0..GN_MAX_PE_LEVELS
+                                 (Sec. 3.4 encodes every network input).  With
+                                 L > 0, F's input [G; s] (30 channels) and h's
+                                 slot input b_i (12) each become 1 + 2 L blocks
+                                 of their channels: x, then sin(2^k pi x) and
+                                 cos(2^k pi x) for k = 0 .. L-1.  sigma, R's
+                                 L_d and the alpha mask stay raw.  0 = none. */
 } gn_config;
 
 typedef struct gn_handle gn_handle;
@@ -107,15 +115,18 @@ typedef struct gn_timing {
   double t_submit, t_admit, t_start, t_done;
 } gn_timing;
 
-/* Number of fp32 parameters for width W: 11 W^2 + 59 W + 3.
+/* Number of fp32 parameters for width W and L positional-encoding levels:
+ * 11 W^2 + 59 W + 3 + 84 L W.
  * Flat layout: nets F, T, B, R; layers 1, 2, 3; per layer the matrix row-major
  * [out][in] then the bias.  Input order: F [G-buffer 0..13; scene 0..15],
- * T [slot planes 0..11; sigma], B [sigma; tau], R [phi; L_d].  Returns 0 for
- * an unsupported width. */
-size_t glassnet_num_params(int32_t width);
+ * T [slot planes 0..11; sigma], B [sigma; tau], R [phi; L_d]; with L > 0 F's
+ * columns are the 1 + 2 L encoding blocks of [G; scene] in block order (raw,
+ * sin level 0, cos level 0, sin level 1, ...) and T's the blocks of the slot
+ * planes, then sigma.  Returns 0 for an unsupported width or level count. */
+size_t glassnet_num_params(int32_t width, int32_t pe_levels);
 
 /* Create a handle on cfg->device and upload host_weights (host, n floats,
- * n == glassnet_num_params(width)).  The library owns the fp32 master copy,
+ * n == glassnet_num_params(width, pe_levels)).  The library owns the fp32 master copy,
  * its bf16/fp8 packed forms and every workspace.  *out is set on GN_OK. */
 gn_status glassnet_create(const gn_config *cfg, const float *host_weights, size_t n,
                           gn_handle **out);

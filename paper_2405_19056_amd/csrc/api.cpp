@@ -97,7 +97,9 @@ gn_status gn_prepare_weights(gn_handle *h, hipStream_t stream) {
 
 extern "C" {
 
-size_t glassnet_num_params(int32_t width) { return gn::num_params(width); }
+size_t glassnet_num_params(int32_t width, int32_t pe_levels) {
+  return gn::num_params(width, pe_levels);
+}
 
 const char *glassnet_last_error(void) { return g_err.c_str(); }
 
@@ -116,8 +118,13 @@ gn_status glassnet_create(const gn_config *cfg, const float *host_weights, size_
   if (cfg->precision == GN_FP8_T && cfg->width != 128)
     return fail(GN_E_UNSUPPORTED, "GN_FP8_T needs width 128");
   if (!host_weights) return fail(GN_E_INVAL, "host_weights is NULL");
-  const size_t np = gn::num_params(cfg->width);
-  if (n != np) return fail(GN_E_INVAL, "expected %zu weights for width %d, got %zu", np, cfg->width, n);
+  if (cfg->pe_levels < 0 || cfg->pe_levels > GN_MAX_PE_LEVELS)
+    return fail(GN_E_UNSUPPORTED, "pe_levels %d outside [0, %d]", cfg->pe_levels,
+                GN_MAX_PE_LEVELS);
+  const size_t np = gn::num_params(cfg->width, cfg->pe_levels);
+  if (n != np)
+    return fail(GN_E_INVAL, "expected %zu weights for width %d and %d encoding levels, got %zu",
+                np, cfg->width, cfg->pe_levels, n);
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1)
     return fail(GN_E_DEVICE, "no HIP device available");
@@ -141,7 +148,7 @@ gn_status glassnet_create(const gn_config *cfg, const float *host_weights, size_
     return fail(GN_E_DEVICE, "hipGetDeviceProperties failed");
   }
   h->num_cus = prop.multiProcessorCount;
-  gn::make_packed_layout(h->W, &h->pl);
+  gn::make_packed_layout(h->W, cfg->pe_levels, &h->pl);
   h->l1_npart = 4 * h->num_cus;
 
   const size_t wbytes = sizeof(float) * np;

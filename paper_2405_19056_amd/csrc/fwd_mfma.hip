@@ -47,7 +47,7 @@ constexpr int kFrag = 1024;            // one bf16 A fragment: 64 lanes x 16 B
 
 struct MfmaArgs {
   const uint8_t *packed;
-  int64_t stage_off[kNumStages + 1];
+  int64_t stage_off[kMaxStages + 1];
   int64_t res_off, res_bytes, bias_off, t2q_off, t2s_off;
   FwdBatch b;
   const FrameDesc *frames;
@@ -117,6 +117,17 @@ __device__ __forceinline__ f32x4 mma_fp8(i32x8 a, i32x8 b, f32x4 c) {
 }
 
 __device__ __forceinline__ void wait_vm() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
+
+// Positional-encoding block b of x (Sec. 3.4): x for b = 0, then
+// sin(2^k pi x) for b = 2k + 1 and cos(2^k pi x) for b = 2k + 2.  The hardware
+// sine and cosine take revolutions: x 2^(k-1) (an exact scaling) is reduced
+// exactly to [0, 1) first.
+__device__ __forceinline__ float pe_enc(float x, int b) {
+  if (b == 0) return x;
+  const int k = (b - 1) >> 1;
+  const float r = __builtin_amdgcn_fractf(x * (float)(1 << k) * 0.5f);
+  return (b & 1) ? __builtin_amdgcn_sinf(r) : __builtin_amdgcn_cosf(r);
+}
 
 // Stage boundary that leaves the newest N vector-memory operations in flight:
 // N global stores issued after the next stage's LDS fill, whose completion
@@ -258,6 +269,19 @@ __device__ __forceinline__ void mm(f32x4 (&acc)[kNT][MT_], const uint8_t *chunk,
   }
 }
 
+// F's encoded input as B fragments: K-step b (of N) is encoding block B0 + b
+// of the 8 raw channels the lane holds.
+template <int B0, int N>
+__device__ __forceinline__ void enc_frags(const float (&xr)[kNT][8], u32x4 (&x)[kNT][N]) {
+#pragma unroll
+  for (int t = 0; t < kNT; ++t)
+#pragma unroll
+    for (int b = 0; b < N; ++b)
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        x[t][b][q] = pk_bf16(pe_enc(xr[t][2 * q], B0 + b), pe_enc(xr[t][2 * q + 1], B0 + b));
+}
+
 template <int W>
 struct Shape {
   static constexpr int MT = W / 16, KS = W / 32;
@@ -280,9 +304,22 @@ struct StreamTile {
 // forward; FWD_BEGIN stages 0-1 (sigma into the state); FWD_ACC stage 2 (the
 // slot loop, continuing the state's running sum); FWD_FINISH stages 3-9 from
 // the state.  FWD_FULL compiles to the code it had before the modes existed.
-template <int W, int PREC, int MODE>
+//
+// PE > 0: F's and h's inputs are positionally encoded with PE levels; F1 then
+// runs over two stages of its own (stage indices below), and h's first layer
+// takes pe_k16_steps(PE) 16-deep K-steps per slot.
+template <int W, int PREC, int MODE, int PE>
 __global__ __launch_bounds__(kThreads) void fwd_mfma_kernel(MfmaArgs a) {
   constexpr int MT = Shape<W>::MT, KS = Shape<W>::KS;
+  constexpr int kShift = stage_shift(PE), kStages = kNumStages + kShift;
+  // stage of each weight group (F1 and F2 share stage 0 without encoding)
+  constexpr int sF1 = 0, sF1B = 1, sF2 = kShift, sF3 = 1 + kShift, sT1S = 2 + kShift,
+                sT3 = 3 + kShift, sB1S = 4 + kShift, sB1T = 5 + kShift, sB2 = 6 + kShift,
+                sB3 = 7 + kShift, sR1 = 8 + kShift, sR2 = 9 + kShift;
+  constexpr int kE = pe_blocks(PE);                   // encoding blocks
+  constexpr int kF1A = PE > 0 ? (kE + 1) / 2 : 1;     // F1's blocks in stage sF1
+  constexpr int kF1B = kE - kF1A;                     // and in stage sF1B
+  constexpr int kNK16 = PE > 0 ? pe_k16_steps(PE) : 1;   // h layer 1's K=16 steps
   constexpr bool kSlots = MODE == FWD_FULL || MODE == FWD_ACC;     // runs the slot loop
   constexpr bool kTrunk = MODE == FWD_FULL || MODE == FWD_BEGIN;   // runs F
   constexpr bool kHead = MODE == FWD_FULL || MODE == FWD_FINISH;   // runs T3, B, R
@@ -295,7 +332,7 @@ __global__ __launch_bounds__(kThreads) void fwd_mfma_kernel(MfmaArgs a) {
   float *L_bias = (float *)(lds + res_bytes);
   int64_t stage_max = 0;
 #pragma unroll
-  for (int s = 0; s < kNumStages; ++s)
+  for (int s = 0; s < kStages; ++s)
     stage_max = max(stage_max, a.stage_off[s + 1] - a.stage_off[s]);
   uint8_t *L_stage0 = lds + res_bytes + Shape<W>::kBiasBytes;
   uint8_t *L_stage1 = L_stage0 + stage_max;
@@ -311,9 +348,10 @@ __global__ __launch_bounds__(kThreads) void fwd_mfma_kernel(MfmaArgs a) {
   };
   // bf16: [T1A | T2 (bf16)]; fp8: [T1A | T2 (fp8, 2 KiB fragments) | T2 row scales]
   constexpr bool kFp8 = PREC == GN_FP8_T;
+  constexpr int kT1ABytes = (MT * kNK16 * 512 + 1023) & ~1023;   // K=16 fragments of 512 B
   if constexpr (kSlots) {
     if (kFp8) {
-      constexpr int64_t t1a = (MT * 512 + 1023) & ~1023;
+      constexpr int64_t t1a = kT1ABytes;
       lds_fill(L_res, a.packed + a.res_off, t1a, wave, lane0);
       lds_fill(L_res + t1a, a.packed + a.t2q_off, res_bytes - t1a, wave, lane0);
     } else {
@@ -322,20 +360,20 @@ __global__ __launch_bounds__(kThreads) void fwd_mfma_kernel(MfmaArgs a) {
   }
   lds_fill((uint8_t *)L_bias, a.packed + a.bias_off, Shape<W>::kBiasBytes, wave, lane0);
   if ((int)blockIdx.x < a.ntiles) {
-    // FULL streams every stage; BEGIN and ACC keep their few stages resident
-    // for the whole launch; FINISH starts its pipeline at stage 3.
-    if constexpr (MODE == FWD_FULL) fill_stage0(0);
+    // FULL streams every stage; BEGIN (without encoding) and ACC keep their
+    // few stages resident for the whole launch; BEGIN with encoding streams
+    // its four stages per tile; FINISH starts its pipeline at T3's stage.
+    if constexpr (MODE == FWD_FULL) fill_stage0(sF1);
     if constexpr (MODE == FWD_BEGIN) {
-      fill_stage0(0);
-      fill_stage0(1);
+      fill_stage0(sF1);
+      if constexpr (PE == 0) fill_stage0(sF3);
     }
-    if constexpr (MODE == FWD_ACC) fill_stage0(2);
-    if constexpr (MODE == FWD_FINISH) fill_stage0(3);
+    if constexpr (MODE == FWD_ACC) fill_stage0(sT1S);
+    if constexpr (MODE == FWD_FINISH) fill_stage0(sT3);
   }
   wait_vm();
   __syncthreads();
 
-  constexpr int kT1ABytes = (MT * 512 + 1023) & ~1023;          // K=16 fragments of 512 B
   const uint8_t *T1A = L_res;
   const uint8_t *T2 = L_res + kT1ABytes;                           // bf16 form
   float *T2scale = (float *)(L_res + kT1ABytes + MT * 2 * kFrag);  // fp8 form
@@ -463,28 +501,59 @@ __global__ __launch_bounds__(kThreads) void fwd_mfma_kernel(MfmaArgs a) {
     uint8_t *sig_slot = a.sig_scratch + ((size_t)blockIdx.x * kWaves + wave) * kSigBytes;
 
     if constexpr (kTrunk) {
-      // ================= stage 0: F layers 1-2 =================
-      if constexpr (MODE == FWD_FULL) fill_stage(1);
       u32x4 h2[kNT][KS];
-      {
-        u32x4 x[kNT][1];
+      if constexpr (PE == 0) {
+        // ================= stage 0: F layers 1-2 =================
+        if constexpr (MODE == FWD_FULL) fill_stage(sF3);
+        {
+          u32x4 x[kNT][1];
 #pragma unroll
-        for (int t = 0; t < kNT; ++t)
-          x[t][0] = u32x4{pk_bf16(xr[t][0], xr[t][1]), pk_bf16(xr[t][2], xr[t][3]),
-                          pk_bf16(xr[t][4], xr[t][5]), pk_bf16(xr[t][6], xr[t][7])};
-        const uint8_t *S = stage_buf(0);
+          for (int t = 0; t < kNT; ++t)
+            x[t][0] = u32x4{pk_bf16(xr[t][0], xr[t][1]), pk_bf16(xr[t][2], xr[t][3]),
+                            pk_bf16(xr[t][4], xr[t][5]), pk_bf16(xr[t][6], xr[t][7])};
+          const uint8_t *S = stage_buf(sF1);
+          u32x4 h1[kNT][KS];
+          layer<MT, 1, true>(h1, S, x, bF1, g, lane);
+          layer<MT, KS, true>(h2, S + f1_bytes, h1, bF2, g, lane);
+        }
+        if constexpr (MODE == FWD_FULL) {
+          wait_vm();
+          __syncthreads();
+        }
+      } else {
+        // ====== stages 0-1: F layer 1 on the encoded input; stage 2: F layer 2 ======
+        fill_stage(sF1B);
+        f32x4 acc[kNT][MT];
+        bias_init(acc, bF1, g);
+        {
+          u32x4 x[kNT][kF1A];
+          enc_frags<0, kF1A>(xr, x);
+          mm<MT, kF1A>(acc, stage_buf(sF1), x, lane);
+        }
+        wait_vm();
+        __syncthreads();
+        fill_stage(sF2);
         u32x4 h1[kNT][KS];
-        layer<MT, 1, true>(h1, S, x, bF1, g, lane);
-        layer<MT, KS, true>(h2, S + f1_bytes, h1, bF2, g, lane);
-      }
-      if constexpr (MODE == FWD_FULL) {
+        {
+          u32x4 x[kNT][kF1B];
+          enc_frags<kF1A, kF1B>(xr, x);
+          mm<MT, kF1B>(acc, stage_buf(sF1B), x, lane);
+          to_frags<MT, true>(acc, h1);
+        }
+        wait_vm();
+        __syncthreads();
+        fill_stage(sF3);
+        layer<MT, KS, true>(h2, stage_buf(sF2), h1, bF2, g, lane);
         wait_vm();
         __syncthreads();
       }
 
-      // ================= stage 1: F layer 3 -> sigma =================
-      if constexpr (MODE == FWD_FULL) fill_stage(2);
-      layer<MT, KS, false>(sig, stage_buf(1), h2, bF3, g, lane);
+      // ================= F layer 3 -> sigma =================
+      if constexpr (MODE == FWD_FULL) fill_stage(sT1S);
+      if constexpr (MODE == FWD_BEGIN && PE > 0) {
+        if (has_next) fill_stage(sF1);      // the next tile's first stage
+      }
+      layer<MT, KS, false>(sig, stage_buf(sF3), h2, bF3, g, lane);
       if constexpr (MODE == FWD_BEGIN) {
         // sigma goes to the streaming state; the next tile's F input is requested
 #pragma unroll
@@ -494,6 +563,11 @@ __global__ __launch_bounds__(kThreads) void fwd_mfma_kernel(MfmaArgs a) {
         if (has_next) {
           nti = resolve(tile + gridDim.x);
           load_x(nti, lane, xr);
+        }
+        if constexpr (PE > 0) {
+          // the next tile's first stage has landed; this stage's buffer is free
+          wait_vm();
+          __syncthreads();
         }
       } else {
         if (sig_in_lds) {
@@ -518,7 +592,7 @@ __global__ __launch_bounds__(kThreads) void fwd_mfma_kernel(MfmaArgs a) {
 
     if constexpr (kSlots) {
       // ================= stage 2: u = W1s sigma + c1, then the slot loop =======
-      if constexpr (MODE == FWD_FULL) fill_stage(3);
+      if constexpr (MODE == FWD_FULL) fill_stage(sT3);
       if constexpr (MODE == FWD_ACC) {
 #pragma unroll
         for (int t = 0; t < kNT; ++t)
@@ -530,7 +604,7 @@ __global__ __launch_bounds__(kThreads) void fwd_mfma_kernel(MfmaArgs a) {
         // first layer for every slot
         f32x4 u[kNT][MT];
         bias_init(u, bT1, g);
-        mm<MT, KS>(u, stage_buf(2), sig, lane);
+        mm<MT, KS>(u, stage_buf(sT1S), sig, lane);
         if constexpr (kFp8) {
           // fp8: h's first layer runs in units of the activation scale (its
           // inputs b_i and u are divided by it), so its output quantises directly
@@ -556,9 +630,11 @@ __global__ __launch_bounds__(kThreads) void fwd_mfma_kernel(MfmaArgs a) {
           }
         }
         // Slot inputs: lane group g < 3 carries planes 4g..4g+3 of its pixel (the
-        // K=16 operand of h's first layer); the next slot's planes are loaded
-        // one slot ahead so their latency overlaps the current slot's work.
-        float nxt[kNT][4];
+        // K=16 operand of h's first layer; with encoding, lane group g carries
+        // planes 3g..3g+2 and their encodings); the next slot's planes are
+        // loaded one slot ahead so their latency overlaps the current slot's work.
+        constexpr int kRaw = PE > 0 ? 3 : 4;
+        float nxt[kNT][kRaw];
         auto load_slot = [&](int i) {
           gcfloat *Li = Lp + (size_t)i * kNL * hw;
           int qs[kNT];
@@ -570,30 +646,53 @@ __global__ __launch_bounds__(kThreads) void fwd_mfma_kernel(MfmaArgs a) {
 #pragma unroll
           for (int t = 0; t < kNT; ++t)
 #pragma unroll
-            for (int j = 0; j < 4; ++j)
-              nxt[t][j] = g < 3 ? Li[(size_t)(4 * g + j) * hw + qs[t]] : 0.0f;
+            for (int j = 0; j < kRaw; ++j) {
+              if constexpr (PE > 0)
+                nxt[t][j] = Li[(size_t)(3 * g + j) * hw + qs[t]];
+              else
+                nxt[t][j] = g < 3 ? Li[(size_t)(4 * g + j) * hw + qs[t]] : 0.0f;
+            }
         };
         if (K > 0) load_slot(0);
         for (int i = 0; i < K; ++i) {
-          float cur[kNT][4];
+          float cur[kNT][kRaw];
 #pragma unroll
           for (int t = 0; t < kNT; ++t)
 #pragma unroll
-            for (int j = 0; j < 4; ++j) cur[t][j] = nxt[t][j];
+            for (int j = 0; j < kRaw; ++j) cur[t][j] = nxt[t][j];
           if (i + 1 < K) load_slot(i + 1);
-          uint2 bi[kNT];
+          uint2 bi[kNT][kNK16];
           float m[kNT];
 #pragma unroll
           for (int t = 0; t < kNT; ++t) {
-            if constexpr (kFp8)
-              bi[t] = uint2{pk_bf16(cur[t][0] * a.inv_sa, cur[t][1] * a.inv_sa),
-                            pk_bf16(cur[t][2] * a.inv_sa, cur[t][3] * a.inv_sa)};
-            else
-              bi[t] = uint2{pk_bf16(cur[t][0], cur[t][1]), pk_bf16(cur[t][2], cur[t][3])};
-            // alpha (plane 9) sits in lane group 2 at position 1: broadcast it
-            const float al = __int_as_float(
-                __builtin_amdgcn_ds_bpermute((col + 32) * 4, __float_as_int(cur[t][1])));
-            m[t] = al > 0.0f ? 1.0f : 0.0f;
+            if constexpr (PE > 0) {
+              // value v = 4 s + j of the lane group's list: block v / 3 of raw
+              // plane 3 g + v % 3 (zero past the last block)
+              float e[4 * kNK16];
+#pragma unroll
+              for (int v = 0; v < 4 * kNK16; ++v) {
+                const float x = v / 3 < kE ? pe_enc(cur[t][v % 3], v / 3) : 0.0f;
+                e[v] = kFp8 ? x * a.inv_sa : x;
+              }
+#pragma unroll
+              for (int st = 0; st < kNK16; ++st)
+                bi[t][st] = uint2{pk_bf16(e[4 * st], e[4 * st + 1]),
+                                  pk_bf16(e[4 * st + 2], e[4 * st + 3])};
+              // alpha (plane 9) sits in lane group 3 at position 0: broadcast it
+              const float al = __int_as_float(
+                  __builtin_amdgcn_ds_bpermute((col + 48) * 4, __float_as_int(cur[t][0])));
+              m[t] = al > 0.0f ? 1.0f : 0.0f;
+            } else {
+              if constexpr (kFp8)
+                bi[t][0] = uint2{pk_bf16(cur[t][0] * a.inv_sa, cur[t][1] * a.inv_sa),
+                                 pk_bf16(cur[t][2] * a.inv_sa, cur[t][3] * a.inv_sa)};
+              else
+                bi[t][0] = uint2{pk_bf16(cur[t][0], cur[t][1]), pk_bf16(cur[t][2], cur[t][3])};
+              // alpha (plane 9) sits in lane group 2 at position 1: broadcast it
+              const float al = __int_as_float(
+                  __builtin_amdgcn_ds_bpermute((col + 32) * 4, __float_as_int(cur[t][1])));
+              m[t] = al > 0.0f ? 1.0f : 0.0f;
+            }
           }
           if constexpr (kFp8) {
           // h layer 1 (bf16 MFMA, in activation-scale units), quantised to
@@ -602,9 +701,24 @@ __global__ __launch_bounds__(kThreads) void fwd_mfma_kernel(MfmaArgs a) {
           i32x8 zq[kNT];
 #pragma unroll
           for (int mt = 0; mt < MT; ++mt) {
-            const uint2 w = ld_frag16(T1A, mt, lane);
+            if constexpr (PE > 0) {
+              f32x4 acc1[kNT];
 #pragma unroll
-            for (int t = 0; t < kNT; ++t) zq[t][mt] = relu_pack_fp8x4(mma16(w, bi[t], u[t][mt]));
+              for (int t = 0; t < kNT; ++t) acc1[t] = u[t][mt];
+#pragma unroll
+              for (int st = 0; st < kNK16; ++st) {
+                const uint2 w = ld_frag16(T1A, mt * kNK16 + st, lane);
+#pragma unroll
+                for (int t = 0; t < kNT; ++t) acc1[t] = mma16(w, bi[t][st], acc1[t]);
+              }
+#pragma unroll
+              for (int t = 0; t < kNT; ++t) zq[t][mt] = relu_pack_fp8x4(acc1[t]);
+            } else {
+              const uint2 w = ld_frag16(T1A, mt, lane);
+#pragma unroll
+              for (int t = 0; t < kNT; ++t)
+                zq[t][mt] = relu_pack_fp8x4(mma16(w, bi[t][0], u[t][mt]));
+            }
           }
           // h layer 2 on the fp8 matrix cores (K = 128 in one instruction),
           // the running sum kept in units of the dequantisation factor s
@@ -632,10 +746,24 @@ __global__ __launch_bounds__(kThreads) void fwd_mfma_kernel(MfmaArgs a) {
           for (int p = 0; p < KS; ++p) {
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
-              const uint2 w = ld_frag16(T1A, 2 * p + h, lane);
+              f32x4 acc1[kNT];
+              if constexpr (PE > 0) {
+#pragma unroll
+                for (int t = 0; t < kNT; ++t) acc1[t] = u[t][2 * p + h];
+#pragma unroll
+                for (int st = 0; st < kNK16; ++st) {
+                  const uint2 w = ld_frag16(T1A, (2 * p + h) * kNK16 + st, lane);
+#pragma unroll
+                  for (int t = 0; t < kNT; ++t) acc1[t] = mma16(w, bi[t][st], acc1[t]);
+                }
+              } else {
+                const uint2 w = ld_frag16(T1A, 2 * p + h, lane);
+#pragma unroll
+                for (int t = 0; t < kNT; ++t) acc1[t] = mma16(w, bi[t][0], u[t][2 * p + h]);
+              }
 #pragma unroll
               for (int t = 0; t < kNT; ++t) {
-                const f32x4 v = mma16(w, bi[t], u[t][2 * p + h]);
+                const f32x4 v = acc1[t];
                 z1[t][p][2 * h] = relu_bf16x2(pk_bf16(v.x, v.y));
                 z1[t][p][2 * h + 1] = relu_bf16x2(pk_bf16(v.z, v.w));
               }
@@ -687,7 +815,7 @@ __global__ __launch_bounds__(kThreads) void fwd_mfma_kernel(MfmaArgs a) {
 
     if constexpr (kHead) {
       // ================= stage 3: pool and h layer 3 -> tau =================
-      fill_stage(4);
+      fill_stage(sB1S);
       u32x4 sig2[kNT][KS];
       if constexpr (MODE == FWD_FINISH) {
         // the pool state and sigma come from the streaming state
@@ -738,29 +866,29 @@ __global__ __launch_bounds__(kThreads) void fwd_mfma_kernel(MfmaArgs a) {
             acc[t][mt] = *(const f32x4 *)(bT3 + 16 * mt + 4 * g) * bs;
           }
         }
-        mm<MT, KS>(acc, stage_buf(3), zs, lane);
+        mm<MT, KS>(acc, stage_buf(sT3), zs, lane);
         to_frags<MT, false>(acc, tau);
       }
       wait_vm();
       __syncthreads();
 
       // ================= stages 4-5: B layer 1 on [sigma; tau] =================
-      fill_stage(5);
+      fill_stage(sB1T);
       f32x4 accB[kNT][MT];
       bias_init(accB, bB1, g);
-      mm<MT, KS>(accB, stage_buf(4), sig2, lane);
+      mm<MT, KS>(accB, stage_buf(sB1S), sig2, lane);
       wait_vm();
       __syncthreads();
 
-      fill_stage(6);
+      fill_stage(sB2);
       u32x4 hb[kNT][KS];
-      mm<MT, KS>(accB, stage_buf(5), tau, lane);
+      mm<MT, KS>(accB, stage_buf(sB1T), tau, lane);
       to_frags<MT, true>(accB, hb);
       wait_vm();
       __syncthreads();
 
       // ================= stage 6: B layer 2 =================
-      fill_stage(7);
+      fill_stage(sB3);
       // L_d for R's first layer (stage 8), requested two stages early
       float ldr[kNT][3];
 #pragma unroll
@@ -769,7 +897,7 @@ __global__ __launch_bounds__(kThreads) void fwd_mfma_kernel(MfmaArgs a) {
         for (int c = 0; c < 3; ++c) ldr[t][c] = g == 0 ? Gp[(size_t)(11 + c) * hw + qc[t]] : 0.0f;
       {
         u32x4 hb2[kNT][KS];
-        layer<MT, KS, true>(hb2, stage_buf(6), hb, bB2, g, lane);
+        layer<MT, KS, true>(hb2, stage_buf(sB2), hb, bB2, g, lane);
 #pragma unroll
         for (int t = 0; t < kNT; ++t)
 #pragma unroll
@@ -779,14 +907,14 @@ __global__ __launch_bounds__(kThreads) void fwd_mfma_kernel(MfmaArgs a) {
       __syncthreads();
 
       // ================= stage 7: B layer 3 -> phi =================
-      fill_stage(8);
+      fill_stage(sR1);
       u32x4 phi[kNT][KS];
-      layer<MT, KS, false>(phi, stage_buf(7), hb, bB3, g, lane);
+      layer<MT, KS, false>(phi, stage_buf(sB3), hb, bB3, g, lane);
       wait_vm();
       __syncthreads();
 
       // ================= stage 8: R layer 1 on [phi; L_d] =================
-      fill_stage(9);
+      fill_stage(sR2);
       u32x4 hr[kNT][KS];
       {
         u32x4 ld[kNT][1];
@@ -795,8 +923,8 @@ __global__ __launch_bounds__(kThreads) void fwd_mfma_kernel(MfmaArgs a) {
           ld[t][0] = u32x4{pk_bf16(ldr[t][0], ldr[t][1]), pk_bf16(ldr[t][2], 0.0f), 0u, 0u};
         f32x4 acc[kNT][MT];
         bias_init(acc, bR1, g);
-        mm<MT, KS>(acc, stage_buf(8), phi, lane);
-        mm<MT, 1>(acc, stage_buf(8) + r1p_bytes, ld, lane);
+        mm<MT, KS>(acc, stage_buf(sR1), phi, lane);
+        mm<MT, 1>(acc, stage_buf(sR1) + r1p_bytes, ld, lane);
         to_frags<MT, true>(acc, hr);
       }
       wait_vm();
@@ -805,22 +933,22 @@ __global__ __launch_bounds__(kThreads) void fwd_mfma_kernel(MfmaArgs a) {
       // ================= stage 9: R layers 2-3 -> radiance =================
       if (has_next) {
         if constexpr (MODE == FWD_FULL) {
-          fill_stage(0);
+          fill_stage(sF1);
           nti = resolve(tile + gridDim.x);
           load_x(nti, lane, xr);
         } else {
-          // the next tile's stage 3 goes to the buffer this tile's stage 8 used
-          lds_fill(((3 + (par ^ 1)) & 1) ? L_stage1 : L_stage0, packed + a.stage_off[3],
-                   a.stage_off[4] - a.stage_off[3], wave, lane);
+          // the next tile's T3 stage goes to the buffer this tile's R1 stage used
+          lds_fill(((sT3 + (par ^ 1)) & 1) ? L_stage1 : L_stage0, packed + a.stage_off[sT3],
+                   a.stage_off[sT3 + 1] - a.stage_off[sT3], wave, lane);
           nti = resolve(tile + gridDim.x);
         }
       }
       {
         u32x4 hr2[kNT][KS];
-        layer<MT, KS, true>(hr2, stage_buf(9), hr, bR2, g, lane);
+        layer<MT, KS, true>(hr2, stage_buf(sR2), hr, bR2, g, lane);
         f32x4 y[kNT][1];
         bias_init(y, bR3, g);
-        mm<1, KS>(y, stage_buf(9) + r2_bytes, hr2, lane);
+        mm<1, KS>(y, stage_buf(sR2) + r2_bytes, hr2, lane);
         // Lane group 0 holds rows 0..2.  Tail lanes store the value of pixel
         // hw - 1 they recomputed (bitwise the same as that pixel's own lane),
         // so exactly 3 kNT store instructions issue, with a non-empty mask.
@@ -856,7 +984,7 @@ __device__ __forceinline__ int chain_col(int ks, int g, int j) {
 // One thread per bf16 element of one chunk (blockIdx.y = chunk).
 __global__ void pack_bf16_kernel(PackArgs p) {
   const ChunkDesc d = p.chunk[blockIdx.y];
-  const int lg = d.kmap == KMAP_MEM16 ? 2 : 3;       // log2 of elements per lane
+  const int lg = d.kmap == KMAP_MEM16 || d.kmap == KMAP_PE16 ? 2 : 3;   // log2 elements per lane
   const int64_t n = (int64_t)d.mt * d.ks * 64 << lg;
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= n) return;
@@ -866,9 +994,18 @@ __global__ void pack_bf16_kernel(PackArgs p) {
   const int mt = fragi / d.ks, ks = fragi - mt * d.ks;
   const int row = 16 * mt + (lane & 15);
   const int g = lane >> 4;
-  const int k = d.kmap == KMAP_MEM     ? 32 * ks + 8 * g + j
-                : d.kmap == KMAP_MEM16 ? 16 * ks + 4 * g + j
-                                       : chain_col(ks, g, j);
+  int k;
+  if (d.kmap == KMAP_ENC) {
+    const int c = 8 * g + j;
+    k = c < d.raw ? (d.ks0 + ks) * d.raw + c : d.ncols;
+  } else if (d.kmap == KMAP_PE16) {
+    const int v = 4 * ks + j, blk = v / 3;
+    k = blk < d.nblocks ? blk * d.raw + 3 * g + v % 3 : d.ncols;
+  } else {
+    k = d.kmap == KMAP_MEM     ? 32 * ks + 8 * g + j
+        : d.kmap == KMAP_MEM16 ? 16 * ks + 4 * g + j
+                               : chain_col(ks, g, j);
+  }
   const LayerOff lo = p.lo[d.layer];
   float v = 0.0f;
   if (row < d.nrows && k < d.ncols) v = p.master[lo.w + (int64_t)row * lo.in + d.col0 + k];
@@ -923,7 +1060,7 @@ hipError_t launch_pack_weights(const float *master, uint8_t *packed, const Packe
   p.master = master;
   p.packed = packed;
   for (int c = 0; c < kNumChunks; ++c) p.chunk[c] = pl.chunk[c];
-  layer_offsets(pl.W, p.lo);
+  layer_offsets(pl.W, pl.pe, p.lo);
   p.W = pl.W;
   p.bias_off = pl.bias_off;
   int64_t maxn = 0;
@@ -941,29 +1078,31 @@ hipError_t launch_pack_weights(const float *master, uint8_t *packed, const Packe
 static int64_t resident_bytes(const PackedLayout &pl, int precision) {
   const int MT = pl.W / 16;
   if (precision == GN_FP8_T)
-    return (((int64_t)MT * 512 + 1023) & ~(int64_t)1023) + (pl.t2scale_off - pl.t2q_off) +
-           (pl.total_bytes - pl.t2scale_off);
+    return (((int64_t)MT * pl.chunk[C_T1A].ks * 512 + 1023) & ~(int64_t)1023) +
+           (pl.t2scale_off - pl.t2q_off) + (pl.total_bytes - pl.t2scale_off);
   return pl.resident_bytes;
 }
 
 static size_t mfma_base_lds_bytes(const PackedLayout &pl, int precision) {
   int64_t stage_max = 0;
-  for (int s = 0; s < kNumStages; ++s)
+  for (int s = 0; s < pl.nstages; ++s)
     stage_max = std::max<int64_t>(stage_max, pl.stage_off[s + 1] - pl.stage_off[s]);
   return (size_t)(resident_bytes(pl, precision) + (int64_t)kNumLayers * pl.W * 4 + 2 * stage_max);
 }
 
 // Waves whose sigma fits in the LDS the weights leave free (160 KiB per CU),
-// and how many of them sit in the stage buffers' tails: from stage 1 to stage
-// 4 buffer 1 holds stages 1 and 3, buffer 0 stages 2 and 4.
+// and how many of them sit in the stage buffers' tails: from F3's stage to
+// B1S's (stages 1-4, shifted by two with encoded inputs) buffer 1 holds the
+// first and third of them, buffer 0 the second and fourth.
 static void mfma_sig_lds(const PackedLayout &pl, int precision, int *nlds, int *ntail) {
   constexpr size_t kLdsMax = 160 * 1024;
   const size_t per_wave = (size_t)kNT * (pl.W / 32) * kFrag;
   const size_t base = mfma_base_lds_bytes(pl, precision);
   int64_t stage_max = 0;
-  for (int s = 0; s < kNumStages; ++s)
+  for (int s = 0; s < pl.nstages; ++s)
     stage_max = std::max<int64_t>(stage_max, pl.stage_off[s + 1] - pl.stage_off[s]);
-  auto size = [&](int s) { return pl.stage_off[s + 1] - pl.stage_off[s]; };
+  const int sh = stage_shift(pl.pe);
+  auto size = [&](int s) { return pl.stage_off[sh + s + 1] - pl.stage_off[sh + s]; };
   const int64_t tail1 = stage_max - std::max(size(1), size(3));
   const int64_t tail0 = stage_max - std::max(size(2), size(4));
   const int free_waves = base >= kLdsMax ? 0 : (int)((kLdsMax - base) / per_wave);
@@ -991,30 +1130,47 @@ static size_t mfma_lds_bytes(const PackedLayout &pl, int precision) {
          (size_t)mfma_sig_free_waves(pl, precision) * kNT * (pl.W / 32) * kFrag;
 }
 
-template <int W, int PREC, int MODE>
+template <int W, int PREC, int MODE, int PE>
 static hipError_t launch_one(const MfmaArgs &a, int grid, size_t lds, hipStream_t stream) {
-  static bool attr_set = false;     // per process; the attribute is per function
-  if (!attr_set) {
-    hipError_t e = hipFuncSetAttribute((const void *)fwd_mfma_kernel<W, PREC, MODE>,
+  // The attribute is per function; a layout of a different size (another
+  // handle's) raises it again.
+  static size_t attr_lds = 0;
+  if (lds > attr_lds) {
+    hipError_t e = hipFuncSetAttribute((const void *)fwd_mfma_kernel<W, PREC, MODE, PE>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
-    attr_set = true;
+    attr_lds = lds;
   }
-  hipLaunchKernelGGL((fwd_mfma_kernel<W, PREC, MODE>), dim3(grid), dim3(kThreads), lds, stream, a);
+  hipLaunchKernelGGL((fwd_mfma_kernel<W, PREC, MODE, PE>), dim3(grid), dim3(kThreads), lds, stream,
+                     a);
   return hipGetLastError();
 }
 
-template <int W, int PREC>
+template <int W, int PREC, int PE>
 static hipError_t launch_mode(int mode, const MfmaArgs &a, int grid, size_t lds,
                               hipStream_t stream) {
   switch (mode) {
-    case FWD_FULL: return launch_one<W, PREC, FWD_FULL>(a, grid, lds, stream);
-    case FWD_BEGIN: return launch_one<W, PREC, FWD_BEGIN>(a, grid, lds, stream);
-    case FWD_ACC: return launch_one<W, PREC, FWD_ACC>(a, grid, lds, stream);
-    case FWD_FINISH: return launch_one<W, PREC, FWD_FINISH>(a, grid, lds, stream);
+    case FWD_FULL: return launch_one<W, PREC, FWD_FULL, PE>(a, grid, lds, stream);
+    case FWD_BEGIN: return launch_one<W, PREC, FWD_BEGIN, PE>(a, grid, lds, stream);
+    case FWD_ACC: return launch_one<W, PREC, FWD_ACC, PE>(a, grid, lds, stream);
+    case FWD_FINISH: return launch_one<W, PREC, FWD_FINISH, PE>(a, grid, lds, stream);
   }
   return hipErrorInvalidValue;
 }
+
+template <int W, int PREC>
+static hipError_t launch_pe(int pe, int mode, const MfmaArgs &a, int grid, size_t lds,
+                            hipStream_t stream) {
+  switch (pe) {
+    case 0: return launch_mode<W, PREC, 0>(mode, a, grid, lds, stream);
+    case 1: return launch_mode<W, PREC, 1>(mode, a, grid, lds, stream);
+    case 2: return launch_mode<W, PREC, 2>(mode, a, grid, lds, stream);
+    case 3: return launch_mode<W, PREC, 3>(mode, a, grid, lds, stream);
+    case 4: return launch_mode<W, PREC, 4>(mode, a, grid, lds, stream);
+  }
+  return hipErrorInvalidValue;
+}
+static_assert(kMaxPe == 4, "launch_pe covers encoding levels 0..4");
 
 size_t stream_state_tile_bytes(int W) {
   return W == 64 ? (size_t)StreamTile<64>::kBytes : (size_t)StreamTile<128>::kBytes;
@@ -1031,7 +1187,7 @@ static hipError_t launch_impl(int W, int precision, int pool, const uint8_t *pac
   a.state_load = state_load;
   mfma_sig_lds(pl, precision, &a.sig_lds_waves, &a.sig_tail_waves);
   a.packed = packed;
-  for (int s = 0; s <= kNumStages; ++s) a.stage_off[s] = pl.stage_off[s];
+  for (int s = 0; s <= kMaxStages; ++s) a.stage_off[s] = s <= pl.nstages ? pl.stage_off[s] : 0;
   a.res_off = pl.resident_off;
   a.res_bytes = resident_bytes(pl, precision);
   a.bias_off = pl.bias_off;
@@ -1053,12 +1209,13 @@ static hipError_t launch_impl(int W, int precision, int pool, const uint8_t *pac
   if (ntiles <= 0) return hipSuccess;
   grid = std::max(1, std::min(grid, ntiles));   // the scratch holds `grid` workgroups
   const size_t lds = mfma_lds_bytes(pl, precision);
+  if (lds > 160 * 1024) return hipErrorInvalidValue;
   if (precision == GN_BF16) {
-    if (W == 64) return launch_mode<64, GN_BF16>(mode, a, grid, lds, stream);
-    if (W == 128) return launch_mode<128, GN_BF16>(mode, a, grid, lds, stream);
+    if (W == 64) return launch_pe<64, GN_BF16>(pl.pe, mode, a, grid, lds, stream);
+    if (W == 128) return launch_pe<128, GN_BF16>(pl.pe, mode, a, grid, lds, stream);
   }
   if (precision == GN_FP8_T && W == 128)
-    return launch_mode<128, GN_FP8_T>(mode, a, grid, lds, stream);
+    return launch_pe<128, GN_FP8_T>(pl.pe, mode, a, grid, lds, stream);
   return hipErrorInvalidValue;
 }
 

@@ -10,6 +10,15 @@ namespace gn {
 
 constexpr int kNG = GN_NUM_G, kNL = GN_NUM_L, kNS = GN_NUM_S, kNOUT = GN_NUM_OUT;
 constexpr int kAlpha = GN_ALPHA_PLANE;
+constexpr int kMaxPe = GN_MAX_PE_LEVELS;
+
+// Positional encoding (Sec. 3.4): an input vector x of C channels becomes
+// (1 + 2 L) blocks of C: x, then sin(2^k pi x) and cos(2^k pi x) for
+// k = 0 .. L-1.  It widens F's input (30 channels) and h's slot input (12).
+constexpr int pe_blocks(int pe) { return 1 + 2 * pe; }
+// h's slot input in 16-deep K-steps of the fused kernel: lane group g owns
+// raw channels 3g .. 3g+2 and presents their encodings in block order.
+constexpr int pe_k16_steps(int pe) { return (3 * pe_blocks(pe) + 3) / 4; }
 
 // One frame as the kernels see it: pointers already offset to the frame.
 struct FrameDesc {
@@ -36,8 +45,8 @@ struct LayerOff {
   int32_t out, in;
 };
 
-void layer_offsets(int W, LayerOff lo[kNumLayers]);
-size_t num_params(int W);
+void layer_offsets(int W, int pe, LayerOff lo[kNumLayers]);
+size_t num_params(int W, int pe);
 
 // ---- packed (fragment-ordered) weights of the MFMA forward -----------------
 // A chunk is the part of one layer's matrix that multiplies one input source.
@@ -51,11 +60,17 @@ size_t num_params(int W);
 enum Chunk {
   C_F1, C_F2, C_F3, C_T1S, C_T3, C_B1S, C_B1T, C_B2, C_B3, C_R1P, C_R1L, C_R2, C_R3,
   C_T1A, C_T2,            // resident in LDS through the slot loop
+  C_F1B,                  // encoded inputs: F1's second half of K-steps (empty otherwise)
   kNumChunks
 };
 // KMAP_MEM16: a 16-deep K-step of v_mfma_f32_16x16x16bf16_1k, lane group g
 // holding inputs 4g..4g+3 (fragments of 64 lanes x 8 bytes).
-enum KMap { KMAP_CHAIN = 0, KMAP_MEM = 1, KMAP_MEM16 = 2 };
+// KMAP_ENC: 32-deep K-step ks0 + ks is encoding block ks0 + ks of the raw
+// inputs, lane group g holding raw channels 8g..8g+7 of that block.
+// KMAP_PE16: 16-deep K-steps of the encoded slot input (pe_k16_steps):
+// element j of lane group g in K-step s is value v = 4s + j of the group's
+// list (block v / 3, raw channel 3g + v % 3).
+enum KMap { KMAP_CHAIN = 0, KMAP_MEM = 1, KMAP_MEM16 = 2, KMAP_ENC = 3, KMAP_PE16 = 4 };
 
 struct ChunkDesc {
   int32_t layer;     // Layer
@@ -65,15 +80,24 @@ struct ChunkDesc {
   int32_t mt, ks;
   int32_t kmap;
   int32_t elem_bytes;  // 2 (bf16) or 1 (fp8)
+  int32_t raw;         // KMAP_ENC / KMAP_PE16: raw channels per encoding block
+  int32_t ks0;         // KMAP_ENC: encoding block of the chunk's first K-step
+  int32_t nblocks;     // KMAP_ENC / KMAP_PE16: encoding blocks (1 + 2 L)
+  int32_t pad;
   int64_t offset;      // byte offset in the packed buffer
 };
 
+// Ten stages; with encoded inputs F1 takes two stages of its own before F2's
+// (an even number, so every later stage keeps its buffer parity).
 constexpr int kNumStages = 10;
+constexpr int kMaxStages = 12;
+constexpr int stage_shift(int pe) { return pe > 0 ? 2 : 0; }
 
 struct PackedLayout {
-  int W;
+  int W, pe;
+  int nstages;
   ChunkDesc chunk[kNumChunks];
-  int64_t stage_off[kNumStages + 1];   // byte ranges of the staged chunks
+  int64_t stage_off[kMaxStages + 1];   // byte ranges of the staged chunks
   int64_t resident_off, resident_bytes;  // T1A + T2 (bf16)
   int64_t bias_off;                    // fp32 biases: 12 x W floats
   int64_t t2q_off;                     // fp8 copy of T2 (FP8_T), MT x 1 fragments of 64 x 32 B
@@ -81,7 +105,7 @@ struct PackedLayout {
   int64_t total_bytes;
 };
 
-void make_packed_layout(int W, PackedLayout *pl);
+void make_packed_layout(int W, int pe, PackedLayout *pl);
 
 // ---- launches (all asynchronous on `stream`) --------------------------------
 struct BwdWorkspace;

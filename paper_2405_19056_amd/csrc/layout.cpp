@@ -5,9 +5,10 @@
 
 namespace gn {
 
-void layer_offsets(int W, LayerOff lo[kNumLayers]) {
+void layer_offsets(int W, int pe, LayerOff lo[kNumLayers]) {
+  const int e = pe_blocks(pe);
   const int outs[kNumLayers] = {W, W, W, W, W, W, W, W, W, W, W, kNOUT};
-  const int ins[kNumLayers] = {kNG + kNS, W, W, kNL + W, W, W, 2 * W, W, W, W + 3, W, W};
+  const int ins[kNumLayers] = {(kNG + kNS) * e, W, W, kNL * e + W, W, W, 2 * W, W, W, W + 3, W, W};
   int64_t off = 0;
   for (int l = 0; l < kNumLayers; ++l) {
     lo[l].w = off;
@@ -19,15 +20,17 @@ void layer_offsets(int W, LayerOff lo[kNumLayers]) {
   }
 }
 
-size_t num_params(int W) {
+size_t num_params(int W, int pe) {
   if (W != 64 && W != 128) return 0;
-  return (size_t)11 * W * W + (size_t)59 * W + 3;
+  if (pe < 0 || pe > kMaxPe) return 0;
+  return (size_t)11 * W * W + (size_t)59 * W + 3 + (size_t)84 * pe * W;
 }
 
-void make_packed_layout(int W, PackedLayout *pl) {
+void make_packed_layout(int W, int pe, PackedLayout *pl) {
   memset(pl, 0, sizeof(*pl));
   pl->W = W;
-  const int MT = W / 16, KS = W / 32;
+  pl->pe = pe;
+  const int MT = W / 16, KS = W / 32, E = pe_blocks(pe), NK16 = pe_k16_steps(pe);
   auto set = [&](Chunk c, int layer, int col0, int ncols, int nrows, int mt, int ks, int kmap) {
     ChunkDesc &d = pl->chunk[c];
     d.layer = layer;
@@ -38,11 +41,19 @@ void make_packed_layout(int W, PackedLayout *pl) {
     d.ks = ks;
     d.kmap = kmap;
     d.elem_bytes = 2;
+    d.nblocks = E;
   };
-  set(C_F1, L_F1, 0, kNG + kNS, W, MT, 1, KMAP_MEM);
+  // F1: one 32-deep K-step per encoding block; with encoded inputs its blocks
+  // are split over two stages (the first ceil(E / 2) blocks, then the rest)
+  const int f1a = pe > 0 ? (E + 1) / 2 : 1;
+  set(C_F1, L_F1, 0, (kNG + kNS) * E, W, MT, f1a, KMAP_ENC);
+  pl->chunk[C_F1].raw = kNG + kNS;
+  set(C_F1B, L_F1, 0, (kNG + kNS) * E, W, pe > 0 ? MT : 0, E - f1a, KMAP_ENC);
+  pl->chunk[C_F1B].raw = kNG + kNS;
+  pl->chunk[C_F1B].ks0 = f1a;
   set(C_F2, L_F2, 0, W, W, MT, KS, KMAP_CHAIN);
   set(C_F3, L_F3, 0, W, W, MT, KS, KMAP_CHAIN);
-  set(C_T1S, L_T1, kNL, W, W, MT, KS, KMAP_CHAIN);
+  set(C_T1S, L_T1, kNL * E, W, W, MT, KS, KMAP_CHAIN);
   set(C_T3, L_T3, 0, W, W, MT, KS, KMAP_CHAIN);
   set(C_B1S, L_B1, 0, W, W, MT, KS, KMAP_CHAIN);
   set(C_B1T, L_B1, W, W, W, MT, KS, KMAP_CHAIN);
@@ -52,29 +63,40 @@ void make_packed_layout(int W, PackedLayout *pl) {
   set(C_R1L, L_R1, W, 3, W, MT, 1, KMAP_MEM);
   set(C_R2, L_R2, 0, W, W, MT, KS, KMAP_CHAIN);
   set(C_R3, L_R3, 0, W, kNOUT, 1, KS, KMAP_CHAIN);
-  set(C_T1A, L_T1, 0, kNL, W, MT, 1, KMAP_MEM16);
+  if (pe > 0) {
+    set(C_T1A, L_T1, 0, kNL * E, W, MT, NK16, KMAP_PE16);
+    pl->chunk[C_T1A].raw = kNL;
+  } else {
+    set(C_T1A, L_T1, 0, kNL, W, MT, 1, KMAP_MEM16);
+  }
   set(C_T2, L_T2, 0, W, W, MT, KS, KMAP_CHAIN);
 
   // Stage groups in kernel order; every fragment is 1 KiB so stages stay
   // multiples of 1 KiB.
-  const Chunk stages[kNumStages][2] = {
-      {C_F1, C_F2}, {C_F3, kNumChunks}, {C_T1S, kNumChunks}, {C_T3, kNumChunks},
-      {C_B1S, kNumChunks}, {C_B1T, kNumChunks}, {C_B2, kNumChunks}, {C_B3, kNumChunks},
+  const Chunk none = kNumChunks;
+  const Chunk plain[kNumStages][2] = {
+      {C_F1, C_F2}, {C_F3, none}, {C_T1S, none}, {C_T3, none},
+      {C_B1S, none}, {C_B1T, none}, {C_B2, none}, {C_B3, none},
       {C_R1P, C_R1L}, {C_R2, C_R3}};
+  const Chunk encoded[kMaxStages][2] = {
+      {C_F1, none}, {C_F1B, none}, {C_F2, none}, {C_F3, none}, {C_T1S, none}, {C_T3, none},
+      {C_B1S, none}, {C_B1T, none}, {C_B2, none}, {C_B3, none},
+      {C_R1P, C_R1L}, {C_R2, C_R3}};
+  pl->nstages = kNumStages + stage_shift(pe);
   int64_t off = 0;
-  for (int s = 0; s < kNumStages; ++s) {
+  for (int s = 0; s < pl->nstages; ++s) {
     pl->stage_off[s] = off;
     for (int j = 0; j < 2; ++j) {
-      Chunk c = stages[s][j];
-      if (c == kNumChunks) continue;
+      Chunk c = pe > 0 ? encoded[s][j] : plain[s][j];
+      if (c == none) continue;
       pl->chunk[c].offset = off;
       off += (int64_t)pl->chunk[c].mt * pl->chunk[c].ks * 1024;
     }
   }
-  pl->stage_off[kNumStages] = off;
+  pl->stage_off[pl->nstages] = off;
   pl->resident_off = off;
   pl->chunk[C_T1A].offset = off;
-  off += ((int64_t)MT * 512 + 1023) & ~(int64_t)1023;      // K=16 fragments: 512 B each
+  off += ((int64_t)MT * pl->chunk[C_T1A].ks * 512 + 1023) & ~(int64_t)1023;   // K=16: 512 B each
   pl->chunk[C_T2].offset = off;
   off += (int64_t)MT * KS * 1024;
   pl->resident_bytes = off - pl->resident_off;

@@ -73,12 +73,16 @@ struct Blocks {
 };
 enum { PX_INV = 0, PX_M = 1 };     // rows of the per-pixel scalar block
 
-Blocks make_blocks(int W) {
+// Width of F's input and of h's slot input after positional encoding.
+inline int enc_x(int pe) { return (kNG + kNS) * pe_blocks(pe); }
+inline int enc_b(int pe) { return kNL * pe_blocks(pe); }
+
+Blocks make_blocks(int W, int pe) {
   Blocks b;
   int r = 0;
   auto take = [&](int n) { int o = r; r += n; return o; };
   const int RW = rup(W + 1, 32);
-  b.xb = take(32);                   // G 0..13, scene 14..29, ones 30
+  b.xb = take(rup(enc_x(pe) + 1, 32));   // encoding blocks of [G 0..13; scene 0..15], ones
   b.a1 = take(RW);
   b.a2 = take(RW);
   b.st = take(rup(2 * W + 1, 32));   // sigma, tau, ones
@@ -90,7 +94,7 @@ Blocks make_blocks(int W) {
   b.g1 = take(RW);
   b.g2 = take(RW);
   b.z1 = take(RW);                   // slot i: z1, ones
-  b.bi = take(32);                   // slot i: b_i (12), ones at 12
+  b.bi = take(rup(enc_b(pe) + 1, 32));   // slot i: encoding blocks of b_i (12), ones
   b.px = take(32);                   // 1/max(c,1) (mean) or 1; slot mask m_i
   b.y = take(32);                    // R's 3 outputs (16-row GEMM tile), forward only
   b.dy = take(32);
@@ -128,19 +132,20 @@ struct OpTable {
   int64_t total;     // f32x4 count
 };
 
-OpTable make_ops(int W) {
+OpTable make_ops(int W, int pe) {
   LayerOff lo[kNumLayers];
-  layer_offsets(W, lo);
+  layer_offsets(W, pe, lo);
+  const int nb = enc_b(pe);
   struct S { Op o; Layer l; int trans, col0, M, K; };
   const S s[kNumOps] = {
-      {O_F1, L_F1, 0, 0, W, kNG + kNS}, {O_F2, L_F2, 0, 0, W, W},  {O_F3, L_F3, 0, 0, W, W},
-      {O_T1S, L_T1, 0, kNL, W, W},      {O_T1A, L_T1, 0, 0, W, kNL}, {O_T2, L_T2, 0, 0, W, W},
+      {O_F1, L_F1, 0, 0, W, enc_x(pe)}, {O_F2, L_F2, 0, 0, W, W},  {O_F3, L_F3, 0, 0, W, W},
+      {O_T1S, L_T1, 0, nb, W, W},       {O_T1A, L_T1, 0, 0, W, nb}, {O_T2, L_T2, 0, 0, W, W},
       {O_T3, L_T3, 0, 0, W, W},         {O_B1, L_B1, 0, 0, W, 2 * W}, {O_B2, L_B2, 0, 0, W, W},
       {O_B3, L_B3, 0, 0, W, W},         {O_R1, L_R1, 0, 0, W, W + 3}, {O_R2, L_R2, 0, 0, W, W},
       {O_R3, L_R3, 0, 0, kNOUT, W},
       {O_R3T, L_R3, 1, 0, W, kNOUT},    {O_R2T, L_R2, 1, 0, W, W},  {O_R1T, L_R1, 1, 0, W, W},
       {O_B3T, L_B3, 1, 0, W, W},        {O_B2T, L_B2, 1, 0, W, W},  {O_B1T, L_B1, 1, 0, 2 * W, W},
-      {O_T3T, L_T3, 1, 0, W, W},        {O_T2T, L_T2, 1, 0, W, W},  {O_T1ST, L_T1, 1, kNL, W, W},
+      {O_T3T, L_T3, 1, 0, W, W},        {O_T2T, L_T2, 1, 0, W, W},  {O_T1ST, L_T1, 1, nb, W, W},
       {O_F3T, L_F3, 1, 0, W, W},        {O_F2T, L_F2, 1, 0, W, W}};
   OpTable t;
   int64_t off = 0;
@@ -340,13 +345,22 @@ __global__ __launch_bounds__(kThreads) void plane_gemm_kernel(PgArgs a) {
 // ---- gathers into planes -------------------------------------------------------
 struct PrepArgs {
   const float *gbuf, *layers, *scene, *grad_out;
-  int hw, k, pool, W;
+  int hw, k, pool, W, pe;
   int64_t npx, stride;
   float *planes;
   Blocks bl;
 };
 
 #define ROW(r) (a.planes + (size_t)(r) * a.stride)
+
+// Positional-encoding block b of x (Sec. 3.4): x for b = 0, then
+// sin(2^k pi x) for b = 2k + 1 and cos(2^k pi x) for b = 2k + 2 (sinpi and
+// cospi reduce the argument exactly; the scaling by 2^k is exact).
+__device__ __forceinline__ float pe_value(float x, int b) {
+  if (b == 0) return x;
+  const float t = x * (float)(1 << ((b - 1) >> 1));
+  return (b & 1) ? sinpif(t) : cospif(t);
+}
 
 // G and the scene vector (F's input), L_d (R's), the mean's 1/max(c,1), T3's
 // bias scale and dL/dy.  Padding pixels repeat the last pixel with dL/dy = 0,
@@ -358,13 +372,20 @@ __global__ __launch_bounds__(kThreads) void prep_kernel(PrepArgs a) {
   const int64_t pc = valid ? p : a.npx - 1;
   const int f = (int)(pc / a.hw), q = (int)(pc - (int64_t)f * a.hw), hw = a.hw, W = a.W;
   const Blocks &B = a.bl;
+  const int nblk = pe_blocks(a.pe);
   if (a.gbuf) {
     const float *G = a.gbuf + (size_t)f * kNG * hw + q;
-    for (int c = 0; c < kNG; ++c) ROW(B.xb + c)[p] = G[(size_t)c * hw];
+    for (int c = 0; c < kNG; ++c) {
+      const float x = G[(size_t)c * hw];
+      for (int b = 0; b < nblk; ++b) ROW(B.xb + b * (kNG + kNS) + c)[p] = pe_value(x, b);
+    }
     for (int c = 0; c < 3; ++c) ROW(B.pl + W + c)[p] = G[(size_t)(11 + c) * hw];
   }
   if (a.scene)
-    for (int c = 0; c < kNS; ++c) ROW(B.xb + kNG + c)[p] = a.scene[(size_t)f * kNS + c];
+    for (int c = 0; c < kNS; ++c) {
+      const float x = a.scene[(size_t)f * kNS + c];
+      for (int b = 0; b < nblk; ++b) ROW(B.xb + b * (kNG + kNS) + kNG + c)[p] = pe_value(x, b);
+    }
   float cnt = 0.0f;
   const float *Lf = a.layers + (size_t)f * a.k * kNL * hw + q;
   for (int i = 0; i < a.k; ++i) cnt += Lf[((size_t)i * kNL + kAlpha) * hw] > 0.0f ? 1.0f : 0.0f;
@@ -375,14 +396,18 @@ __global__ __launch_bounds__(kThreads) void prep_kernel(PrepArgs a) {
     ROW(B.dy + c)[p] = valid && a.grad_out ? a.grad_out[((size_t)f * kNOUT + c) * hw + q] : 0.0f;
 }
 
-// Slot i's 12 channels and its mask m_i = [alpha > 0].
+// Slot i's 12 channels (and their encodings) and its mask m_i = [alpha > 0].
 __global__ __launch_bounds__(kThreads) void slot_gather_kernel(PrepArgs a, int slot) {
   const int64_t p = (int64_t)blockIdx.x * kThreads + threadIdx.x;
   const int64_t pc = p < a.npx ? p : a.npx - 1;
   const int f = (int)(pc / a.hw), q = (int)(pc - (int64_t)f * a.hw), hw = a.hw;
   const float *Li = a.layers + ((size_t)f * a.k + slot) * kNL * hw + q;
   const Blocks &B = a.bl;
-  for (int c = 0; c < kNL; ++c) ROW(B.bi + c)[p] = Li[(size_t)c * hw];
+  const int nblk = pe_blocks(a.pe);
+  for (int c = 0; c < kNL; ++c) {
+    const float x = Li[(size_t)c * hw];
+    for (int b = 0; b < nblk; ++b) ROW(B.bi + b * kNL + c)[p] = pe_value(x, b);
+  }
   ROW(B.px + PX_M)[p] = Li[(size_t)kAlpha * hw] > 0.0f ? 1.0f : 0.0f;
 }
 
@@ -653,17 +678,21 @@ static hipError_t ensure_workspace(gn_handle *h, int64_t npx_pad) {
   gn_bwd_free(h);
   ws = new BwdWorkspace();
   h->bwd = ws;
-  const Blocks bl = make_blocks(h->W);
-  const OpTable ops = make_ops(h->W);
+  const Blocks bl = make_blocks(h->W, h->pl.pe);
+  const OpTable ops = make_ops(h->W, h->pl.pe);
   ws->W = h->W;
   ws->cap_px = npx_pad;
   ws->plane_bytes = sizeof(float) * (size_t)bl.rows * (npx_pad + kRowSkew);
   ws->frag_bytes = sizeof(f32x4) * (size_t)ops.total;
   ws->max_chunks = (int)((npx_pad + kDwPx - 1) / kDwPx);
-  const int W = h->W;
-  ws->part_bytes = sizeof(float) * (size_t)ws->max_chunks * W * rup(2 * W + 1, 32);
+  const int W = h->W, pe = h->pl.pe;
+  // partial tiles: o_pad <= W rows; the widest input blocks are B1's
+  // [sigma; tau; 1] and F1's encoded input (part), T2's (part_t2) and h's
+  // encoded slot input (part_t1)
+  const int wide = std::max(rup(2 * W + 1, 32), rup(enc_x(pe) + 1, 32));
+  ws->part_bytes = sizeof(float) * (size_t)ws->max_chunks * W * wide;
   ws->part_t2_bytes = sizeof(float) * (size_t)ws->max_chunks * W * rup(W + 1, 32);
-  ws->part_t1_bytes = sizeof(float) * (size_t)ws->max_chunks * W * 32;
+  ws->part_t1_bytes = sizeof(float) * (size_t)ws->max_chunks * W * rup(enc_b(pe) + 1, 32);
   hipError_t e = hipMalloc((void **)&ws->planes, ws->plane_bytes);
   if (e == hipSuccess) e = hipMalloc((void **)&ws->frag, ws->frag_bytes);
   if (e == hipSuccess) e = hipMalloc((void **)&ws->part, ws->part_bytes);
@@ -684,11 +713,13 @@ static hipError_t fill(float *dst, int64_t n, float v, hipStream_t s) {
 static hipError_t init_constant_rows(gn_handle *h, int64_t stride, hipStream_t s) {
   BwdWorkspace *ws = h->bwd;
   if (ws->stride == stride) return hipSuccess;
-  const Blocks bl = make_blocks(h->W);
+  const Blocks bl = make_blocks(h->W, h->pl.pe);
   const int W = h->W;
   hipError_t e = fill(ws->planes, (int64_t)bl.rows * stride, 0.0f, s);
-  const int ones[] = {bl.xb + kNG + kNS, bl.a1 + W, bl.a2 + W, bl.st + 2 * W, bl.d1 + W,
-                      bl.d2 + W, bl.pl + W + 3, bl.g1 + W, bl.g2 + W, bl.z1 + W, bl.bi + kNL};
+  const int pe = h->pl.pe;
+  const int ones[] = {bl.xb + enc_x(pe), bl.a1 + W, bl.a2 + W, bl.st + 2 * W, bl.d1 + W,
+                      bl.d2 + W, bl.pl + W + 3, bl.g1 + W, bl.g2 + W, bl.z1 + W,
+                      bl.bi + enc_b(pe)};
   for (int r : ones)
     if (e == hipSuccess) e = fill(ws->planes + (size_t)r * stride, stride, 1.0f, s);
   if (e == hipSuccess) ws->stride = stride;
@@ -707,8 +738,9 @@ struct GemmJob {
 class Pipeline {
  public:
   Pipeline(gn_handle *h, hipStream_t s)
-      : h_(h), s_(s), W_(h->W), bl_(make_blocks(h->W)), ops_(make_ops(h->W)) {
-    layer_offsets(W_, lo_);
+      : h_(h), s_(s), W_(h->W), pe_(h->pl.pe), bl_(make_blocks(h->W, h->pl.pe)),
+        ops_(make_ops(h->W, h->pl.pe)) {
+    layer_offsets(W_, pe_, lo_);
   }
 
   gn_status begin(const gn_frame *f, const float *grad_out, const char *what) {
@@ -732,6 +764,7 @@ class Pipeline {
     pa_.k = K_;
     pa_.pool = h_->cfg.pool;
     pa_.W = W_;
+    pa_.pe = pe_;
     pa_.npx = npx_;
     pa_.stride = ld_;
     pa_.planes = ws_->planes;
@@ -825,7 +858,8 @@ class Pipeline {
     // ---- slot loop
     const int RW = rup(W + 1, 32);
     const GemmJob jT2{bl_.dz2, W, bl_.z1, RW, L_T2, W, W, 1, 0};
-    const GemmJob jT1a{bl_.dz1, W, bl_.bi, 32, L_T1, W, kNL, 1, 0};
+    const int nb = enc_b(pe_), nx = enc_x(pe_);
+    const GemmJob jT1a{bl_.dz1, W, bl_.bi, rup(nb + 1, 32), L_T1, W, nb, 1, 0};
     for (int i = 0; i < K_; ++i) {
       gather(i);
       z1();
@@ -843,8 +877,8 @@ class Pipeline {
         a.accumulate2 = i > 0;
         gemm(O_T2T, EP_BWD, bl_.dz2, bl_.dz1, a);
       }
-      dw_gemm(jT2, ws_->part_t2, i > 0);
-      dw_gemm(jT1a, ws_->part_t1, i > 0);
+      dw_gemm(jT2, ws_->part_t2, ws_->part_t2_bytes, i > 0);
+      dw_gemm(jT1a, ws_->part_t1, ws_->part_t1_bytes, i > 0);
     }
     // with no slot, T2 and T1's slot columns and bias get zero gradient (no chunks)
     reduce(jT2, ws_->part_t2, K_ > 0 ? nchunks() : 0, grad_w);
@@ -868,13 +902,13 @@ class Pipeline {
         {bl_.dd2, W, bl_.d1, RW, L_B2, W, W, 1, 0},
         {bl_.dd1, W, bl_.st, rup(2 * W + 1, 32), L_B1, W, 2 * W, 1, 0},
         {bl_.dtau, W, bl_.zs, RW, L_T3, W, W, 1, 0},
-        {bl_.du, W, bl_.st, W, L_T1, W, W, 0, kNL},
+        {bl_.du, W, bl_.st, W, L_T1, W, W, 0, nb},
         {bl_.dsig, W, bl_.a2, RW, L_F3, W, W, 1, 0},
         {bl_.da2, W, bl_.a1, RW, L_F2, W, W, 1, 0},
-        {bl_.da1, W, bl_.xb, 32, L_F1, W, kNG + kNS, 1, 0},
+        {bl_.da1, W, bl_.xb, rup(nx + 1, 32), L_F1, W, nx, 1, 0},
     };
     for (const GemmJob &j : jobs) {
-      dw_gemm(j, ws_->part, 0);
+      dw_gemm(j, ws_->part, ws_->part_bytes, 0);
       reduce(j, ws_->part, nchunks(), grad_w);
     }
   }
@@ -995,9 +1029,13 @@ class Pipeline {
     a.relu = 1;
     gemm(O_T1A, EP_FWD, bl_.bi, bl_.z1, a);
   }
-  void dw_gemm(const GemmJob &j, float *part, int accumulate) {
+  void dw_gemm(const GemmJob &j, float *part, size_t part_bytes, int accumulate) {
     // the whole (o_pad x i_pad) gradient per workgroup, operands staged in LDS
     const int MO = j.o_pad / 32, MI = j.i_pad / 32;
+    if (sizeof(float) * (size_t)nchunks() * j.o_pad * j.i_pad > part_bytes) {
+      if (e_ == hipSuccess) e_ = hipErrorInvalidValue;     // partials would not fit
+      return;
+    }
     const float *D = plane(j.dblock), *Ap = plane(j.ablock);
 #define DL(A, B)                                                                       \
   if (MO == A && MI == B) {                                                            \
@@ -1006,9 +1044,11 @@ class Pipeline {
     return;                                                                            \
   }
     DL(1, 5) DL(4, 5) DL(4, 9) DL(4, 4) DL(4, 1)     // W = 128
+    DL(4, 3) DL(4, 7) DL(4, 2)                       //   with encoded inputs
     DL(1, 3) DL(2, 3) DL(2, 5) DL(2, 2) DL(2, 1)     // W = 64
+    DL(2, 7) DL(2, 9) DL(2, 4)                       //   with encoded inputs
 #undef DL
-    e_ = hipErrorInvalidValue;     // no other gradient shape exists for widths 64 and 128
+    e_ = hipErrorInvalidValue;     // no other gradient shape exists for the widths and levels
   }
   void reduce(const GemmJob &j, const float *part, int nch, float *grad_w) {
     const int n4 = j.o_pad * j.i_pad / 4;
@@ -1018,7 +1058,7 @@ class Pipeline {
 
   gn_handle *h_;
   hipStream_t s_;
-  int W_;
+  int W_, pe_;
   Blocks bl_;
   OpTable ops_;
   LayerOff lo_[kNumLayers];

@@ -24,7 +24,7 @@ NUM_G, NUM_L, NUM_S, NUM_OUT = 14, 12, 16, 3
 class GnConfig(ctypes.Structure):
     _fields_ = [("width", c_int32), ("k_max", c_int32), ("pool", c_int32),
                 ("precision", c_int32), ("hbm_budget_bytes", c_uint64), ("device", c_int32),
-                ("max_pending", c_int32)]
+                ("max_pending", c_int32), ("pe_levels", c_int32)]
 
 
 class GnFrame(ctypes.Structure):
@@ -47,7 +47,7 @@ _lib = None
 
 # name -> (restype, argtypes)
 _SIGS = {
-    "glassnet_num_params": (c_size_t, [c_int32]),
+    "glassnet_num_params": (c_size_t, [c_int32, c_int32]),
     "glassnet_create": (c_int32, [POINTER(GnConfig), POINTER(c_float), c_size_t, POINTER(c_void_p)]),
     "glassnet_destroy": (c_int32, [c_void_p]),
     "glassnet_get_weights": (c_int32, [c_void_p, POINTER(c_float), c_size_t]),
@@ -98,8 +98,8 @@ def _check(status):
     return status
 
 
-def num_params(width: int) -> int:
-    return int(lib().glassnet_num_params(width))
+def num_params(width: int, pe_levels: int = 0) -> int:
+    return int(lib().glassnet_num_params(width, pe_levels))
 
 
 def _torch():
@@ -146,16 +146,17 @@ class GlassNet:
     """One library handle: weights resident on the device, one precision."""
 
     def __init__(self, weights, width, k_max=8, pool="mean", precision="fp32", device=0,
-                 hbm_budget_bytes=0, max_pending=0):
+                 hbm_budget_bytes=0, max_pending=0, pe_levels=0):
         w = np.ascontiguousarray(np.asarray(weights, dtype=np.float32).ravel())
         cfg = GnConfig(width, k_max, POOL[pool], PRECISION[precision], hbm_budget_bytes, device,
-                       max_pending)
+                       max_pending, pe_levels)
         h = c_void_p()
         _check(lib().glassnet_create(byref(cfg), w.ctypes.data_as(POINTER(c_float)), w.size,
                                      byref(h)))
         self._h = h
         self.width, self.k_max, self.pool, self.precision, self.device = (
             width, k_max, pool, precision, device)
+        self.pe_levels = pe_levels
         self.nparams = w.size
         self._keep = {}       # serving: keeps submitted tensors alive until polled done
 

@@ -7,7 +7,9 @@ import subprocess
 
 import pytest
 
+import oracle
 from paper_2405_19056_amd import glassnet as gb
+from paper_2405_19056_amd import synth
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADER = os.path.join(ROOT, "include", "glassnet.h")
@@ -52,6 +54,12 @@ def test_num_params_and_error_string():
     assert gb.num_params(64) == 11 * 64 * 64 + 59 * 64 + 3
     assert gb.num_params(128) == 187779
     assert gb.num_params(96) == 0
+    # positional encoding widens F1 by 60 L columns and T1 by 24 L
+    for W in (64, 128):
+        for L in range(5):
+            assert gb.num_params(W, L) == synth.num_params(W, L) == oracle.n_params(W, L)
+            assert gb.num_params(W, L) == gb.num_params(W) + 84 * L * W
+    assert gb.num_params(128, 5) == 0 and gb.num_params(128, -1) == 0
     assert isinstance(gb.last_error(), str)
 
 

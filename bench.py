@@ -46,6 +46,12 @@ def executed_flop_per_px(W, K):
     return frags * 2 * 16 * 16 * 32 / 16          # FLOP per MFMA / 16 pixels
 
 
+# With L positional-encoding levels (Sec. 3.4) F's first layer reads 30 (1 + 2L)
+# inputs instead of 30 and h's first layer 12 (1 + 2L) slot inputs instead of 12.
+def alg_flop_per_px_pe(W, K, L):
+    return alg_flop_per_px(W, K) + 2 * W * (60 * L + 24 * L * K)
+
+
 # HBM bytes per pixel the method must move: fp32 inputs (14 + 12 K) read once,
 # 3 fp32 outputs written once (weights are < 1 MB per launch).
 def alg_bytes_per_px(K):
@@ -311,6 +317,29 @@ def stream_phase(net, g, L, s, out, torch, reps=30):
             "accumulate_hbm_frac": acc_bytes / ta / 8e12}
 
 
+def pe_phase(W, K, pool, precision, g, L, s, out, torch, levels=(2, 4), steps=100):
+    """The same frame with positionally encoded inputs (seeded weights of the
+    encoded shapes): frame time and rate on the algorithmic FLOP count."""
+    from paper_2405_19056_amd import synth
+    from paper_2405_19056_amd.glassnet import GlassNet
+    px = out.shape[0] * out.shape[2] * out.shape[3]
+    res = []
+    for lv in levels:
+        w = synth.make_weights(W, np.random.default_rng(1000 + lv), pe_levels=lv)
+        with GlassNet(w, W, k_max=K, pool=pool, precision=precision, pe_levels=lv) as net:
+            if precision == "fp8_t":
+                cal = synth.make_frame(1, 128, 128, K, seed=999)
+                d = lambda a: torch.from_numpy(a).to("cuda:0")  # noqa: E731
+                net.calibrate(d(cal.gbuf), d(cal.layers), d(cal.scene))
+            _, kern_s = time_forward(net, g, L, s, out, steps, 10, torch)
+        flop = alg_flop_per_px_pe(W, K, lv)
+        res.append({"levels": lv, "ms_per_frame": kern_s * 1e3, "pixels_per_s": px / kern_s,
+                    "alg_flop_per_px": flop,
+                    "tflops": flop * px / kern_s / 1e12,
+                    "frac": flop * px / kern_s / 1e12 / PEAK_TFLOPS[precision]})
+    return res
+
+
 def copy_probe():
     """A plain device-to-device copy of 1 GiB, for counter scaling."""
     import torch
@@ -340,6 +369,7 @@ def main():
     ap.add_argument("--k-sweep", action="store_true")
     ap.add_argument("--no-train", action="store_true")
     ap.add_argument("--no-stream", action="store_true")
+    ap.add_argument("--no-pe", action="store_true", help="skip the positional-encoding runs")
     ap.add_argument("--stream-reps", type=int, default=30)
     ap.add_argument("--backward-calls", type=int, default=0,
                     help="only time this many backward calls of the training workload")
@@ -376,6 +406,7 @@ def main():
         step_s, kern_s = time_forward(net, g, L, s, out, args.steps, args.warmup, torch)
         stream = (None if args.no_stream else
                   stream_phase(net, g, L, s, out, torch, reps=args.stream_reps))
+    pe = None if args.no_pe else pe_phase(W, K, c["pool"], args.precision, g, L, s, out, torch)
 
     fp32 = None
     if not args.no_fp32:
@@ -425,6 +456,8 @@ def main():
         res["speedup_vs_fp32_path"] = res["value"] / fp32["value"]
     if stream:
         res["stream"] = stream
+    if pe:
+        res["positional_encoding"] = pe
     if not args.no_train:
         res["train_step"] = train_phase(torch)
     if args.k_sweep:

@@ -240,10 +240,12 @@ def time_backward(torch, calls=10):
 
 def train_phase(torch, steps=10, precision="bf16"):
     """One training step of the 16 x 128^2, K=4, W=128 workload: forward with
-    the current weights, L1 against teacher output + N(0, 0.01) noise, and
-    the hand-written backward to dL/dw.  Returns ms per step."""
+    the handle's weights, L1 against teacher output + N(0, 0.01) noise, the
+    hand-written backward to dL/dw and an Adam step on the device (learning
+    rate and weight decay 1e-4, as the paper's table gives for most scenes).
+    Returns ms per step."""
     from paper_2405_19056_amd import synth
-    from paper_2405_19056_amd.autograd import train_step
+    from paper_2405_19056_amd.autograd import train_step_adam
     from paper_2405_19056_amd.glassnet import GlassNet
     name = "c3_train_16x128sq_k4_w128"
     c = synth.CONFIGS[name]
@@ -254,20 +256,21 @@ def train_phase(torch, steps=10, precision="bf16"):
                   pool=c["pool"], precision="fp32") as teacher:
         t = teacher.forward(g, L, s)
         t += d(synth.noise(tuple(t.shape), 0.01, st["noise"]))
-    wd = d(w)
-    gw = torch.empty_like(wd)
     with GlassNet(w, c["width"], k_max=c["k"], pool=c["pool"], precision=precision) as net:
-        for _ in range(2):
-            train_step(net, g, L, s, t, wd, grad_w=gw)
+        gw = torch.empty(net.nparams, dtype=torch.float32, device="cuda:0")
+        state = net.adam_state()
+        for i in range(2):
+            train_step_adam(net, g, L, s, t, state, i + 1, grad_w=gw)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        for _ in range(steps):
-            loss, _ = train_step(net, g, L, s, t, wd, grad_w=gw)
+        for i in range(steps):
+            loss, _ = train_step_adam(net, g, L, s, t, state, i + 3, grad_w=gw)
         torch.cuda.synchronize()
         ms = (time.perf_counter() - t0) / steps * 1e3
     px = fr.n * fr.h * fr.w
     return {"workload": "16 crops 128x128, K=4, W=128, L1 vs teacher + N(0,0.01)",
-            "forward": precision, "backward": "fp32", "ms_per_step": ms,
+            "forward": precision, "backward": "fp32", "optimizer": "adam lr 1e-4 wd 1e-4",
+            "ms_per_step": ms,
             "pixels_per_s": px / ms * 1e3, "loss": float(loss.cpu()),
             "backward_alone": time_backward(torch)}
 

@@ -172,6 +172,24 @@ gn_status glassnet_forward(gn_handle *h, const gn_frame *frame, float *out, void
 gn_status glassnet_backward(gn_handle *h, const gn_frame *frame, const float *grad_out,
                             float *grad_w, void *hip_stream);
 
+/* One optimiser step on the handle's fp32 master weights (Sec. 4 trains with
+ * Adam, Kingma & Ba, and weight decay), then the packed forms re-derived;
+ * stream-ordered on hip_stream.  Weight decay is an L2 term added to the
+ * gradient: g' = grad_w + weight_decay w, m = beta1 m + (1 - beta1) g',
+ * v = beta2 v + (1 - beta2) g'^2, w -= lr m_hat / (sqrt(v_hat) + eps) with
+ * m_hat = m / (1 - beta1^step), v_hat = v / (1 - beta2^step).
+ *   grad_w  device, n = glassnet_num_params(...) floats (e.g. from
+ *           glassnet_backward); read only.
+ *   state   device, 2 n floats owned by the caller: m then v, zero before
+ *           step 1, updated in place; one state per training run.
+ *   step    1, 2, 3, ... (the bias corrections' t).
+ * GN_E_INVAL for n other than the handle's parameter count, step < 1, lr or
+ * weight_decay negative, beta outside [0, 1), eps <= 0, or overlapping
+ * buffers.  An FP8_T handle keeps its activation scale. */
+gn_status glassnet_adam_step(gn_handle *h, const float *grad_w, float *state, size_t n,
+                             int32_t step, float lr, float beta1, float beta2, float eps,
+                             float weight_decay, void *hip_stream);
+
 /* L1 term of Sec. 3.5 over count elements: *loss = mean |out - target| and
  * grad_out = sign(out - target) / count (0 where equal).  All device.
  * grad_out may be NULL. */

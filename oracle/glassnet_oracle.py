@@ -425,6 +425,23 @@ def relu_margins(w, W, gbuf, layers, scene, pool="mean", pe_levels=0):
     return marg.reshape(n, h, wd)
 
 
+def adam_step(w, g, m, v, t, lr=1e-4, beta1=0.9, beta2=0.999, eps=1e-8, weight_decay=0.0):
+    """One optimiser step (Sec. 4: Adam with weight decay), float64.
+
+    Kingma & Ba's update in its published order: biased first and second
+    moment estimates, their bias corrections for step t >= 1, then the
+    parameter step.  Weight decay is read as an L2 term added to the gradient
+    first (the coupled form).  Returns the new (w, m, v).
+    """
+    w = np.asarray(w, dtype=np.float64)
+    g = np.asarray(g, dtype=np.float64) + weight_decay * w
+    m = beta1 * np.asarray(m, dtype=np.float64) + (1.0 - beta1) * g
+    v = beta2 * np.asarray(v, dtype=np.float64) + (1.0 - beta2) * g * g
+    m_hat = m / (1.0 - beta1 ** t)
+    v_hat = v / (1.0 - beta2 ** t)
+    return w - lr * m_hat / (np.sqrt(v_hat) + eps), m, v
+
+
 def alpha_blend(colors, alphas):
     """Order-dependent alpha compositing of Eqs. (3)-(4), front-to-back.
 

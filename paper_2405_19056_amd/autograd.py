@@ -61,3 +61,17 @@ def train_step(net: GlassNet, gbuf, layers, scene, target, w, grad_w=None, strea
     loss = net.l1_loss(y, target, grad_out=dy, stream=stream)
     gw = net.backward(gbuf, layers, scene, dy, grad_w=grad_w, stream=stream)
     return loss, gw
+
+
+def train_step_adam(net: GlassNet, gbuf, layers, scene, target, state, step, lr=1e-4,
+                    weight_decay=1e-4, grad_w=None, stream=None):
+    """One training step of Sec. 4 on the handle's own weights: forward, L1
+    loss, backward, and an Adam step (weight decay as an L2 term) applied on
+    the device.  `state` is net.adam_state(); `step` counts from 1.
+    Returns (loss tensor, grad_w tensor)."""
+    y = net.forward(gbuf, layers, scene, stream=stream)
+    dy = torch.empty_like(y)
+    loss = net.l1_loss(y, target, grad_out=dy, stream=stream)
+    gw = net.backward(gbuf, layers, scene, dy, grad_w=grad_w, stream=stream)
+    net.adam_step(gw, state, step, lr=lr, weight_decay=weight_decay, stream=stream)
+    return loss, gw

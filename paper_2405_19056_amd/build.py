@@ -21,7 +21,7 @@ LIB = os.path.join(PKG, "libglassnet.so")
 ARCH = "gfx950"
 
 SOURCES = ["api.cpp", "layout.cpp", "serve.cpp", "fwd_mfma.hip", "planes.hip",
-           "loss.hip"]
+           "loss.hip", "optim.hip"]
 
 
 def hipcc() -> str:

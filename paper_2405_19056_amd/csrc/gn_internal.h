@@ -146,6 +146,9 @@ hipError_t launch_fwd_stream(int W, int precision, int pool, const uint8_t *pack
 
 hipError_t launch_l1(const float *out, const float *target, uint64_t count, float *loss,
                      float *grad, float *partials, int npart, hipStream_t stream);
+// One Adam step on w (n floats) from gradient g, moments m and v; step >= 1.
+hipError_t launch_adam(float *w, const float *g, float *m, float *v, int64_t n, int step, float lr,
+                       float b1, float b2, float eps, float wd, hipStream_t stream);
 
 
 }  // namespace gn

@@ -55,6 +55,8 @@ _SIGS = {
     "glassnet_set_act_scales": (c_int32, [c_void_p, POINTER(c_float), c_size_t]),
     "glassnet_forward": (c_int32, [c_void_p, POINTER(GnFrame), c_void_p, c_void_p]),
     "glassnet_backward": (c_int32, [c_void_p, POINTER(GnFrame), c_void_p, c_void_p, c_void_p]),
+    "glassnet_adam_step": (c_int32, [c_void_p, c_void_p, c_void_p, c_size_t, c_int32, c_float,
+                                     c_float, c_float, c_float, c_float, c_void_p]),
     "glassnet_l1_loss": (c_int32, [c_void_p, c_void_p, c_void_p, c_uint64, c_void_p, c_void_p,
                                    c_void_p]),
     "glassnet_workspace_bytes": (c_int32, [c_void_p, POINTER(c_uint64)]),
@@ -227,6 +229,22 @@ class GlassNet:
         _check(lib().glassnet_l1_loss(self._h, _dev_ptr(out, "out"), _dev_ptr(target, "target"),
                                       out.numel(), _dev_ptr(loss, "loss"), gp, _stream(stream)))
         return loss
+
+    # -- optimiser
+    def adam_state(self):
+        """Zeroed Adam moments (m then v) for this handle's parameters."""
+        torch = _torch()
+        return torch.zeros(2 * self.nparams, dtype=torch.float32, device=f"cuda:{self.device}")
+
+    def adam_step(self, grad_w, state, step, lr=1e-4, betas=(0.9, 0.999), eps=1e-8,
+                  weight_decay=0.0, stream=None):
+        """One Adam step on the handle's weights (glassnet_adam_step)."""
+        if grad_w.numel() != self.nparams or state.numel() != 2 * self.nparams:
+            raise ValueError("grad_w must hold n and state 2 n floats")
+        _check(lib().glassnet_adam_step(self._h, _dev_ptr(grad_w, "grad_w"),
+                                        _dev_ptr(state, "state"), self.nparams, int(step),
+                                        float(lr), float(betas[0]), float(betas[1]), float(eps),
+                                        float(weight_decay), _stream(stream)))
 
     # -- object streaming
     def stream_state_bytes(self, n, h, w) -> int:

@@ -3,6 +3,7 @@
 Only tests, the smoke check and the benchmark's CPU-baseline leg import this
 package.  It shares no code with the HIP library and never imports it.
 """
-from .glassnet_oracle import (adam_step, alpha_blend, all_slot_orders, encode, forward,  # noqa: F401
+from .glassnet_oracle import (adam_step, alpha_blend, all_slot_orders, dssim_loss,  # noqa: F401
+                              encode, forward, ssim_map, ssim_window,
                               forward_bruteforce, grad, grad_from_dy, l1_loss, n_params, pack,
                               relu_margins, relu_signature, unpack)

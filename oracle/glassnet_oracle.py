@@ -425,6 +425,84 @@ def relu_margins(w, W, gbuf, layers, scene, pool="mean", pe_levels=0):
     return marg.reshape(n, h, wd)
 
 
+SSIM_K1, SSIM_K2, SSIM_RANGE, SSIM_SIZE, SSIM_SIGMA = 0.01, 0.03, 1.0, 11, 1.5
+
+
+def ssim_window():
+    """Wang et al.'s 11 x 11 Gaussian window, sigma 1.5, normalised to sum 1."""
+    r = np.arange(SSIM_SIZE) - (SSIM_SIZE - 1) / 2.0
+    g = np.exp(-r * r / (2.0 * SSIM_SIGMA ** 2))
+    G = np.outer(g, g)
+    return G / G.sum()
+
+
+def _local(img, G):
+    """Gaussian-weighted local mean over every fully contained window ('valid')."""
+    win = np.lib.stride_tricks.sliding_window_view(img, G.shape)
+    return np.einsum("abij,ij->ab", win, G)
+
+
+def ssim_map(x, y):
+    """SSIM index map of two single-channel images (Wang et al. 2004, the
+    paper's loss term, Sec. 3.5): local Gaussian statistics, then
+    ((2 mx my + C1)(2 sxy + C2)) / ((mx^2 + my^2 + C1)(sx^2 + sy^2 + C2))
+    with C1 = (0.01 L)^2, C2 = (0.03 L)^2 and dynamic range L = 1."""
+    x = np.asarray(x, dtype=np.float64)
+    y = np.asarray(y, dtype=np.float64)
+    G = ssim_window()
+    C1, C2 = (SSIM_K1 * SSIM_RANGE) ** 2, (SSIM_K2 * SSIM_RANGE) ** 2
+    mx, my = _local(x, G), _local(y, G)
+    sxx = _local(x * x, G) - mx * mx
+    syy = _local(y * y, G) - my * my
+    sxy = _local(x * y, G) - mx * my
+    return ((2 * mx * my + C1) * (2 * sxy + C2)) / ((mx * mx + my * my + C1) * (sxx + syy + C2))
+
+
+def dssim_loss(out, target):
+    """Structural dissimilarity term of the loss (Sec. 3.5; the ablation's
+    DSSIM): (1 - mean SSIM) / 2 over every valid window of every channel of
+    every frame of [n][3][h][w] images, and its gradient w.r.t. out.
+
+    The gradient is the chain rule through the local statistics: with
+    S = A1 A2 / (B1 B2), A1 = 2 mx my + C1, A2 = 2 (E[xy] - mx my) + C2,
+    B1 = mx^2 + my^2 + C1, B2 = E[x^2] - mx^2 + E[y^2] - my^2 + C2, the partial
+    derivatives of S with respect to mx, E[x^2] and E[xy] at each window are
+    spread back over the window's pixels by its Gaussian weights.
+    """
+    out = np.asarray(out, dtype=np.float64)
+    target = np.asarray(target, dtype=np.float64)
+    G = ssim_window()
+    C1, C2 = (SSIM_K1 * SSIM_RANGE) ** 2, (SSIM_K2 * SSIM_RANGE) ** 2
+    n, c, h, w = out.shape
+    k = SSIM_SIZE
+    if h < k or w < k:
+        raise ValueError("images smaller than the SSIM window")
+    count = n * c * (h - k + 1) * (w - k + 1)
+    total = 0.0
+    grad = np.zeros_like(out)
+    for f in range(n):
+        for ch in range(c):
+            x, y = out[f, ch], target[f, ch]
+            mx, my = _local(x, G), _local(y, G)
+            ex2, ey2, exy = _local(x * x, G), _local(y * y, G), _local(x * y, G)
+            A1 = 2 * mx * my + C1
+            A2 = 2 * (exy - mx * my) + C2
+            B1 = mx * mx + my * my + C1
+            B2 = (ex2 - mx * mx) + (ey2 - my * my) + C2
+            S = A1 * A2 / (B1 * B2)
+            total += S.sum()
+            dmx = S * (2 * my / A1 - 2 * my / A2 - 2 * mx / B1 + 2 * mx / B2)
+            dex2 = -S / B2
+            dexy = 2 * S / A2
+            # scatter each window's partials back over its pixels
+            for i in range(k):
+                for j in range(k):
+                    sl = (slice(i, i + h - k + 1), slice(j, j + w - k + 1))
+                    grad[f, ch][sl] += G[i, j] * (dmx + 2 * x[sl] * dex2 + y[sl] * dexy)
+    loss = (1.0 - total / count) / 2.0
+    return loss, -grad / (2.0 * count)
+
+
 def adam_step(w, g, m, v, t, lr=1e-4, beta1=0.9, beta2=0.999, eps=1e-8, weight_decay=0.0):
     """One optimiser step (Sec. 4: Adam with weight decay), float64.
 

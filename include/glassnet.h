@@ -172,6 +172,23 @@ gn_status glassnet_forward(gn_handle *h, const gn_frame *frame, float *out, void
 gn_status glassnet_backward(gn_handle *h, const gn_frame *frame, const float *grad_out,
                             float *grad_w, void *hip_stream);
 
+/* Structural-dissimilarity term of the loss (Sec. 3.5 trains with SSIM and L1;
+ * DSSIM = (1 - SSIM) / 2).  SSIM as Wang et al. define it: an 11 x 11
+ * Gaussian window of sigma 1.5 over every fully contained window of each of
+ * the 3 channels of each image, K1 = 0.01, K2 = 0.03, dynamic range 1.
+ *   out, target  device [n][3][height][width] fp32 (height, width >= 11)
+ *   loss         device scalar: (1 - mean SSIM over windows, channels and
+ *                images) / 2
+ *   grad_out     device, shaped like out, or NULL: d loss / d out, written
+ *                (accumulate == 0) or added to its contents (accumulate != 0,
+ *                e.g. after glassnet_l1_loss for the L1 + DSSIM loss).
+ * The library keeps a workspace of about 12 bytes per pixel (grown on a
+ * larger call, after the stream's earlier work).  GN_E_INVAL for smaller
+ * images or aliasing buffers. */
+gn_status glassnet_dssim_loss(gn_handle *h, const float *out, const float *target, int32_t n,
+                              int32_t height, int32_t width, float *loss, float *grad_out,
+                              int32_t accumulate, void *hip_stream);
+
 /* One optimiser step on the handle's fp32 master weights (Sec. 4 trains with
  * Adam, Kingma & Ba, and weight decay), then the packed forms re-derived;
  * stream-ordered on hip_stream.  Weight decay is an L2 term added to the

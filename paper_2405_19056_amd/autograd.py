@@ -64,14 +64,18 @@ def train_step(net: GlassNet, gbuf, layers, scene, target, w, grad_w=None, strea
 
 
 def train_step_adam(net: GlassNet, gbuf, layers, scene, target, state, step, lr=1e-4,
-                    weight_decay=1e-4, grad_w=None, stream=None):
-    """One training step of Sec. 4 on the handle's own weights: forward, L1
-    loss, backward, and an Adam step (weight decay as an L2 term) applied on
-    the device.  `state` is net.adam_state(); `step` counts from 1.
-    Returns (loss tensor, grad_w tensor)."""
+                    weight_decay=1e-4, grad_w=None, dssim=True, stream=None):
+    """One training step of Sec. 3.5 / 4 on the handle's own weights: forward,
+    the L1 + DSSIM loss (dssim=False: L1 alone), backward, and an Adam step
+    (weight decay as an L2 term) applied on the device.  `state` is
+    net.adam_state(); `step` counts from 1.  Returns (losses, grad_w): losses
+    is a device tensor [L1, DSSIM]."""
     y = net.forward(gbuf, layers, scene, stream=stream)
     dy = torch.empty_like(y)
-    loss = net.l1_loss(y, target, grad_out=dy, stream=stream)
+    losses = torch.zeros(2, dtype=torch.float32, device=y.device)
+    net.l1_loss(y, target, loss=losses[0], grad_out=dy, stream=stream)
+    if dssim:
+        net.dssim_loss(y, target, loss=losses[1], grad_out=dy, accumulate=True, stream=stream)
     gw = net.backward(gbuf, layers, scene, dy, grad_w=grad_w, stream=stream)
     net.adam_step(gw, state, step, lr=lr, weight_decay=weight_decay, stream=stream)
-    return loss, gw
+    return losses, gw

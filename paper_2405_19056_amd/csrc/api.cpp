@@ -200,6 +200,7 @@ gn_status glassnet_destroy(gn_handle *h) {
   (void)hipFree(h->d_master);
   (void)hipFree(h->d_packed);
   (void)hipFree(h->d_l1_partials);
+  (void)hipFree(h->d_loss_ws);
   (void)hipFree(h->d_sig_scratch[0]);
   (void)hipFree(h->d_sig_scratch[1]);
   delete h;
@@ -483,6 +484,45 @@ gn_status glassnet_l1_loss(gn_handle *h, const float *out, const float *target, 
   hipError_t e = gn::launch_l1(out, target, count, loss, grad_out, h->d_l1_partials, h->l1_npart,
                                (hipStream_t)hip_stream);
   return gn_check_device(h, e, "l1 launch");
+}
+
+gn_status glassnet_dssim_loss(gn_handle *h, const float *out, const float *target, int32_t n,
+                              int32_t height, int32_t width, float *loss, float *grad_out,
+                              int32_t accumulate, void *hip_stream) {
+  gn_status st = precheck(h);
+  if (st != GN_OK) return st;
+  if (n < 1 || height < 11 || width < 11)
+    return fail(GN_E_INVAL, "need n >= 1 and images of at least 11 x 11 (got %d x %d x %d)", n,
+                height, width);
+  if ((int64_t)n * gn::kNOUT * height * width > ((int64_t)1 << 31))
+    return fail(GN_E_INVAL, "more than 2^31 elements");
+  if (!out || !target || !loss) return fail(GN_E_INVAL, "out, target and loss must be non-NULL");
+  if (!aligned4(out) || !aligned4(target) || !aligned4(loss) || !aligned4(grad_out))
+    return fail(GN_E_INVAL, "device pointers must be 4-byte aligned");
+  const size_t bytes = sizeof(float) * (size_t)n * gn::kNOUT * height * width;
+  if (grad_out && (overlaps(grad_out, bytes, out, bytes) || overlaps(grad_out, bytes, target, bytes) ||
+                   overlaps(grad_out, bytes, loss, 4)))
+    return fail(GN_E_INVAL, "grad_out aliases out, target or loss");
+  DeviceGuard dg(h->device);
+  hipStream_t s = (hipStream_t)hip_stream;
+  const size_t need = gn::dssim_workspace_bytes(n * gn::kNOUT, height, width);
+  if (need > h->loss_ws_bytes) {
+    // grown workspaces replace the old one once the stream's earlier work is done
+    hipError_t e = hipStreamSynchronize(s);
+    if (e == hipSuccess) e = hipFree(h->d_loss_ws);
+    h->d_loss_ws = nullptr;
+    h->loss_ws_bytes = 0;
+    if (e == hipSuccess) e = hipMalloc((void **)&h->d_loss_ws, need);
+    if (e != hipSuccess) {
+      h->d_loss_ws = nullptr;
+      return e == hipErrorOutOfMemory ? fail(GN_E_NOMEM, "DSSIM workspace of %zu bytes", need)
+                                      : gn_check_device(h, e, "DSSIM workspace");
+    }
+    h->loss_ws_bytes = need;
+  }
+  hipError_t e = gn::launch_dssim(out, target, n * gn::kNOUT, height, width, loss, grad_out,
+                                  accumulate ? 1 : 0, h->d_loss_ws, s);
+  return gn_check_device(h, e, "DSSIM launch");
 }
 
 gn_status glassnet_adam_step(gn_handle *h, const float *grad_w, float *state, size_t n,

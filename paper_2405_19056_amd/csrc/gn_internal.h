@@ -146,6 +146,11 @@ hipError_t launch_fwd_stream(int W, int precision, int pool, const uint8_t *pack
 
 hipError_t launch_l1(const float *out, const float *target, uint64_t count, float *loss,
                      float *grad, float *partials, int npart, hipStream_t stream);
+// DSSIM term: planes = n x 3 images of h x w (h, w >= 11); ws holds
+// dssim_workspace_bytes(planes, h, w) bytes; grad may be null.
+size_t dssim_workspace_bytes(int planes, int h, int w);
+hipError_t launch_dssim(const float *out, const float *target, int planes, int h, int w,
+                        float *loss, float *grad, int accumulate, float *ws, hipStream_t stream);
 // One Adam step on w (n floats) from gradient g, moments m and v; step >= 1.
 hipError_t launch_adam(float *w, const float *g, float *m, float *v, int64_t n, int step, float lr,
                        float b1, float b2, float eps, float wd, hipStream_t stream);

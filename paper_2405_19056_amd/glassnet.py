@@ -55,6 +55,8 @@ _SIGS = {
     "glassnet_set_act_scales": (c_int32, [c_void_p, POINTER(c_float), c_size_t]),
     "glassnet_forward": (c_int32, [c_void_p, POINTER(GnFrame), c_void_p, c_void_p]),
     "glassnet_backward": (c_int32, [c_void_p, POINTER(GnFrame), c_void_p, c_void_p, c_void_p]),
+    "glassnet_dssim_loss": (c_int32, [c_void_p, c_void_p, c_void_p, c_int32, c_int32, c_int32,
+                                      c_void_p, c_void_p, c_int32, c_void_p]),
     "glassnet_adam_step": (c_int32, [c_void_p, c_void_p, c_void_p, c_size_t, c_int32, c_float,
                                      c_float, c_float, c_float, c_float, c_void_p]),
     "glassnet_l1_loss": (c_int32, [c_void_p, c_void_p, c_void_p, c_uint64, c_void_p, c_void_p,
@@ -228,6 +230,20 @@ class GlassNet:
         gp = _dev_ptr(grad_out, "grad_out") if grad_out is not None else None
         _check(lib().glassnet_l1_loss(self._h, _dev_ptr(out, "out"), _dev_ptr(target, "target"),
                                       out.numel(), _dev_ptr(loss, "loss"), gp, _stream(stream)))
+        return loss
+
+    def dssim_loss(self, out, target, loss=None, grad_out=None, accumulate=False, stream=None):
+        """(1 - SSIM) / 2 of [n][3][h][w] images; grad_out written or added to."""
+        torch = _torch()
+        n, c, h, w = out.shape
+        if c != NUM_OUT or tuple(target.shape) != tuple(out.shape):
+            raise ValueError("out and target must both be [n][3][h][w]")
+        if loss is None:
+            loss = torch.empty((), dtype=torch.float32, device=out.device)
+        gp = _dev_ptr(grad_out, "grad_out") if grad_out is not None else None
+        _check(lib().glassnet_dssim_loss(self._h, _dev_ptr(out, "out"), _dev_ptr(target, "target"),
+                                         n, h, w, _dev_ptr(loss, "loss"), gp, 1 if accumulate else 0,
+                                         _stream(stream)))
         return loss
 
     # -- optimiser

@@ -360,6 +360,29 @@ def pe_phase(W, K, pool, precision, g, L, s, out, torch, levels=(2, 4), steps=10
     return res
 
 
+def coherent_phase(W, K, pool, precision, w, torch, steps=100):
+    """A labelled variant, not the configs' workload: the 512^2, K=8 frame with
+    spatially coherent coverage (one disc per slot, synth alpha_mode "discs").
+    Waves whose pixels all miss a slot skip it; reports the frame time, the
+    active (pixel, slot) fraction and the rate in active pairs."""
+    from paper_2405_19056_amd import synth
+    from paper_2405_19056_amd.glassnet import GlassNet
+    fr = synth.make_frame(1, 512, 512, K, seed=2, alpha_mode="discs")
+    d = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")  # noqa: E731
+    g, L, s = d(fr.gbuf), d(fr.layers), d(fr.scene)
+    out = torch.empty((1, 3, 512, 512), dtype=torch.float32, device="cuda:0")
+    with GlassNet(w, W, k_max=K, pool=pool, precision=precision) as net:
+        if precision == "fp8_t":
+            cal = synth.make_frame(1, 128, 128, K, seed=999)
+            net.calibrate(d(cal.gbuf), d(cal.layers), d(cal.scene))
+        _, kern_s = time_forward(net, g, L, s, out, steps, 10, torch)
+    px = 512 * 512
+    active = float((fr.layers[:, :, 9] > 0).mean())
+    return {"variant": "coherent coverage: one disc per slot (not the configs' workload)",
+            "active_pair_fraction": active, "ms_per_frame": kern_s * 1e3,
+            "pixels_per_s": px / kern_s, "active_pairs_per_s": px * K * active / kern_s}
+
+
 def copy_probe():
     """A plain device-to-device copy of 1 GiB, for counter scaling."""
     import torch
@@ -389,7 +412,8 @@ def main():
     ap.add_argument("--k-sweep", action="store_true")
     ap.add_argument("--no-train", action="store_true")
     ap.add_argument("--no-stream", action="store_true")
-    ap.add_argument("--no-pe", action="store_true", help="skip the positional-encoding runs")
+    ap.add_argument("--no-variants", action="store_true",
+                    help="skip the positional-encoding and coherent-coverage runs")
     ap.add_argument("--stream-reps", type=int, default=30)
     ap.add_argument("--backward-calls", type=int, default=0,
                     help="only time this many backward calls of the training workload")
@@ -426,7 +450,10 @@ def main():
         step_s, kern_s = time_forward(net, g, L, s, out, args.steps, args.warmup, torch)
         stream = (None if args.no_stream else
                   stream_phase(net, g, L, s, out, torch, reps=args.stream_reps))
-    pe = None if args.no_pe else pe_phase(W, K, c["pool"], args.precision, g, L, s, out, torch)
+    pe = (None if args.no_variants else
+          pe_phase(W, K, c["pool"], args.precision, g, L, s, out, torch))
+    coherent = (None if args.no_variants else
+                coherent_phase(W, K, c["pool"], args.precision, w, torch))
 
     fp32 = None
     if not args.no_fp32:
@@ -478,6 +505,8 @@ def main():
         res["stream"] = stream
     if pe:
         res["positional_encoding"] = pe
+    if coherent:
+        res["coherent_coverage"] = coherent
     if not args.no_train:
         res["train_step"] = train_phase(torch)
     if args.k_sweep:

@@ -661,6 +661,15 @@ __global__ __launch_bounds__(kThreads) void fwd_mfma_kernel(MfmaArgs a) {
 #pragma unroll
             for (int j = 0; j < kRaw; ++j) cur[t][j] = nxt[t][j];
           if (i + 1 < K) load_slot(i + 1);
+          // A slot in which no pixel of this wave takes part adds exactly zero
+          // to the running sum and the count: skip its two layers.  The lanes
+          // that loaded alpha decide (lane group 2 position 1, or with
+          // encoding lane group 3 position 0).
+          bool any = false;
+#pragma unroll
+          for (int t = 0; t < kNT; ++t)
+            any = any || (PE > 0 ? (g == 3 && cur[t][0] > 0.0f) : (g == 2 && cur[t][1] > 0.0f));
+          if (__builtin_amdgcn_ballot_w64(any) == 0) continue;
           uint2 bi[kNT][kNK16];
           float m[kNT];
 #pragma unroll

@@ -122,6 +122,19 @@ def make_layers(n: int, k: int, h: int, w: int, rng_slots: np.random.Generator,
         rank = np.argsort(np.argsort(keys, axis=1), axis=1)
         active = rank < cnt[:, None]
         a = np.where(active, 1.0 - rng_active.uniform(0.0, 1.0, size=shp), 0.0)
+    elif alpha_mode == "discs":
+        # spatially coherent coverage (a labelled variant, not a workload of
+        # the configs): slot i of a frame covers one disc, centre uniform in
+        # the frame, radius U(0.1, 0.35) of the shorter side; alpha U(0, 1]
+        # inside, 0 outside
+        yy, xx = np.mgrid[0:h, 0:w]
+        a = np.zeros(shp)
+        for f in range(n):
+            for i in range(k):
+                cy, cx = rng_active.uniform(0, h), rng_active.uniform(0, w)
+                r = rng_active.uniform(0.1, 0.35) * min(h, w)
+                inside = (yy - cy) ** 2 + (xx - cx) ** 2 <= r * r
+                a[f, i] = np.where(inside, 1.0 - rng_active.uniform(0.0, 1.0, size=(h, w)), 0.0)
     else:
         raise ValueError(f"unknown alpha_mode {alpha_mode!r}")
     L[:, :, 9] = a

@@ -95,6 +95,27 @@ def test_all_slots_inactive_equals_no_slots(precision):
     assert relF(y_none, ref) <= TOL[precision]
 
 
+@pytest.mark.parametrize("precision", ["fp32", "bf16", "fp8_t"])
+def test_coherent_coverage_matches_oracle(precision):
+    """Discs of coverage per slot (a labelled variant): many waves see slots in
+    which none of their pixels is active, which the fused kernel skips."""
+    W = 128
+    wts, fr = frame(2, 64, 80, 6, W, seed=8, alpha_mode="discs")
+    log(f"coherent coverage {precision}: active fraction {(fr.layers[:, :, 9] > 0).mean():.3f}")
+    ref = oracle.forward(wts, W, fr.gbuf, fr.layers, fr.scene)
+    with GlassNet(wts, W, k_max=8, precision=precision) as net:
+        if precision == "fp8_t":
+            calibrate(net, W, 4)
+        y = run(net, fr)
+        # a slot of zero alpha everywhere, inserted: bitwise the same result
+        L = np.concatenate([fr.layers[:, :2], 0 * fr.layers[:, :1], fr.layers[:, 2:]], axis=1)
+        y_ins = run(net, synth.Frame(fr.gbuf, L, fr.scene))
+    e = relF(y, ref)
+    log(f"  relF {e:.3e}")
+    assert e <= TOL[precision]
+    assert np.array_equal(y, y_ins)
+
+
 @pytest.mark.parametrize("precision", ["fp32", "bf16"])
 def test_one_active_slot_equals_k1(precision):
     W = 128

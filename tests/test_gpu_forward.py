@@ -81,6 +81,29 @@ def test_edge_shapes(precision):
         assert relF(y, ref) <= TOL[precision], (n, h, w_, k)
 
 
+@pytest.mark.parametrize("precision", ["fp32", "bf16", "fp8_t"])
+def test_maximum_slot_count(precision):
+    """k = GN_MAX_K = 64 slots (the largest a handle accepts) on a ragged frame;
+    one more is rejected before any launch."""
+    W, K = 128, 64
+    wts, fr = frame(1, 19, 27, K, W, seed=12)
+    log(f"max slots {precision}: 1x19x27 K={K}")
+    ref = oracle.forward(wts, W, fr.gbuf, fr.layers, fr.scene)
+    with GlassNet(wts, W, k_max=K, precision=precision) as net:
+        if precision == "fp8_t":
+            calibrate(net, W, 4)
+        y = run(net, fr)
+        L65 = np.concatenate([fr.layers, fr.layers[:, :1]], axis=1)
+        with pytest.raises(GlassNetError) as e:
+            run(net, synth.Frame(fr.gbuf, L65, fr.scene))
+        assert e.value.status == GN_E_INVAL
+    e = relF(y, ref)
+    log(f"  relF {e:.3e}")
+    assert e <= TOL[precision]
+    with pytest.raises(GlassNetError):
+        GlassNet(wts, W, k_max=K + 1, precision=precision)
+
+
 @pytest.mark.parametrize("precision", ["fp32", "bf16"])
 def test_all_slots_inactive_equals_no_slots(precision):
     W = 128

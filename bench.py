@@ -97,6 +97,36 @@ def cpu_baseline(w, fr, W, pool, budget_s=12.0):
     return px / t_spent, threads, f"{rows_done} rows x {fr.w} px of the {fr.h}x{fr.w} K={fr.k} frame ({px} px, {t_spent:.1f} s)"
 
 
+def launch_distribution(net, g, L, s, out, torch, n=100):
+    """Per-launch kernel time: n launches, each between its own pair of HIP
+    events on the launch stream; median, p10 and p90 in microseconds."""
+    stream = torch.cuda.current_stream()
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(n + 1)]
+    evs[0].record(stream)
+    for i in range(n):
+        net.forward(g, L, s, out=out, stream=stream)
+        evs[i + 1].record(stream)
+    torch.cuda.synchronize()
+    us = np.array([evs[i].elapsed_time(evs[i + 1]) * 1e3 for i in range(n)])
+    return {"median_us": float(np.median(us)), "p10_us": float(np.percentile(us, 10)),
+            "p90_us": float(np.percentile(us, 90)), "launches": n}
+
+
+def gpu_clock_mhz():
+    """Current and maximum shader clock as rocm-smi reports them (None if unavailable)."""
+    import subprocess
+    try:
+        r = subprocess.run(["rocm-smi", "--showclocks", "--json"], capture_output=True, text=True,
+                           timeout=20)
+        d = json.loads(r.stdout)
+        card = next(iter(d.values()))
+        keys = [k for k in card if "sclk" in k.lower()]
+        key = next((k for k in keys if "speed" in k.lower() or "freq" in k.lower()), keys[0])
+        return str(card[key]).strip().strip("()")
+    except Exception:
+        return None
+
+
 def time_forward(net, g, L, s, out, steps, warmup, torch):
     stream = torch.cuda.current_stream()
     for _ in range(warmup):
@@ -448,6 +478,7 @@ def main():
             cal = synth.make_frame(1, 128, 128, K, seed=999)
             net.calibrate(d(cal.gbuf), d(cal.layers), d(cal.scene))
         step_s, kern_s = time_forward(net, g, L, s, out, args.steps, args.warmup, torch)
+        dist = launch_distribution(net, g, L, s, out, torch)
         stream = (None if args.no_stream else
                   stream_phase(net, g, L, s, out, torch, reps=args.stream_reps))
     pe = (None if args.no_variants else
@@ -496,7 +527,9 @@ def main():
             "frac_executed": exe * px / kern_s / 1e12 / peak,
             "alg_hbm_bytes_per_px": alg_bytes_per_px(K),
             "hbm_frac": alg_bytes_per_px(K) * px / kern_s / 8e12,
+            "launch_us": dist,
         },
+        "gpu_sclk": gpu_clock_mhz(),
     }
     if fp32:
         res["fp32_path"] = fp32
@@ -517,8 +550,12 @@ def main():
         res["p99_frame_latency_ms"] = res["serve"]["p99_ms"]
     if not args.no_cpu_baseline:
         v, thr, sample = cpu_baseline(w, fr, W, c["pool"])
+        # the oracle evaluates h on [b_i; sigma] for every slot (no hoisting):
+        # F 30 W + 2 W^2, per slot 12 W + 3 W^2, B 4 W^2, R 2 W^2 + 6 W
+        # multiply-adds per pixel
+        mac = 8 * W * W + 3 * K * W * W + (36 + 12 * K) * W
         res["cpu_baseline"] = {"value": v, "unit": "pixels/s", "cores": thr, "kind": "oracle",
-                               "sample": sample}
+                               "sample": sample, "gflops_fp64": 2 * mac * v / 1e9}
     print(json.dumps(res))
 
 

@@ -118,15 +118,30 @@ __device__ __forceinline__ f32x4 mma_fp8(i32x8 a, i32x8 b, f32x4 c) {
 
 __device__ __forceinline__ void wait_vm() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
 
-// Positional-encoding block b of x (Sec. 3.4): x for b = 0, then
-// sin(2^k pi x) for b = 2k + 1 and cos(2^k pi x) for b = 2k + 2.  The hardware
-// sine and cosine take revolutions: x 2^(k-1) (an exact scaling) is reduced
-// exactly to [0, 1) first.
-__device__ __forceinline__ float pe_enc(float x, int b) {
-  if (b == 0) return x;
-  const int k = (b - 1) >> 1;
-  const float r = __builtin_amdgcn_fractf(x * (float)(1 << k) * 0.5f);
-  return (b & 1) ? __builtin_amdgcn_sinf(r) : __builtin_amdgcn_cosf(r);
+// The positional-encoding blocks of x (Sec. 3.4) up to block NB - 1: x, then
+// sin(2^k pi x) (block 2k + 1) and cos(2^k pi x) (block 2k + 2).  Level 0
+// comes from the hardware sine and cosine, which take revolutions: x / 2 is
+// reduced exactly to [0, 1) first.  Each further level follows from the one
+// before by the double-angle identities (sin 2a = 2 sin a cos a,
+// cos 2a = 1 - 2 sin^2 a): a few fp32 roundings per level, far below the
+// bf16 rounding the values then get.
+template <int NB>
+__device__ __forceinline__ void pe_blocks_of(float x, float (&e)[NB]) {
+  e[0] = x;
+  if constexpr (NB > 1) {
+    const float r = __builtin_amdgcn_fractf(x * 0.5f);
+    float sn = __builtin_amdgcn_sinf(r), cs = __builtin_amdgcn_cosf(r);
+#pragma unroll
+    for (int b = 1; b < NB; b += 2) {
+      if (b > 1) {
+        const float s2 = 2.0f * sn * cs;
+        cs = __builtin_fmaf(-2.0f * sn, sn, 1.0f);
+        sn = s2;
+      }
+      e[b] = sn;
+      if (b + 1 < NB) e[b + 1] = cs;
+    }
+  }
 }
 
 // Stage boundary that leaves the newest N vector-memory operations in flight:
@@ -276,10 +291,13 @@ __device__ __forceinline__ void enc_frags(const float (&xr)[kNT][8], u32x4 (&x)[
 #pragma unroll
   for (int t = 0; t < kNT; ++t)
 #pragma unroll
-    for (int b = 0; b < N; ++b)
+    for (int q = 0; q < 4; ++q) {
+      float e0[B0 + N], e1[B0 + N];
+      pe_blocks_of<B0 + N>(xr[t][2 * q], e0);
+      pe_blocks_of<B0 + N>(xr[t][2 * q + 1], e1);
 #pragma unroll
-      for (int q = 0; q < 4; ++q)
-        x[t][b][q] = pk_bf16(pe_enc(xr[t][2 * q], B0 + b), pe_enc(xr[t][2 * q + 1], B0 + b));
+      for (int b = 0; b < N; ++b) x[t][b][q] = pk_bf16(e0[B0 + b], e1[B0 + b]);
+    }
 }
 
 template <int W>
@@ -677,10 +695,13 @@ __global__ __launch_bounds__(kThreads) void fwd_mfma_kernel(MfmaArgs a) {
             if constexpr (PE > 0) {
               // value v = 4 s + j of the lane group's list: block v / 3 of raw
               // plane 3 g + v % 3 (zero past the last block)
+              float enc[3][kE];
+#pragma unroll
+              for (int c = 0; c < 3; ++c) pe_blocks_of<kE>(cur[t][c], enc[c]);
               float e[4 * kNK16];
 #pragma unroll
               for (int v = 0; v < 4 * kNK16; ++v) {
-                const float x = v / 3 < kE ? pe_enc(cur[t][v % 3], v / 3) : 0.0f;
+                const float x = v / 3 < kE ? enc[v % 3][v / 3] : 0.0f;
                 e[v] = kFp8 ? x * a.inv_sa : x;
               }
 #pragma unroll

@@ -126,8 +126,11 @@ typedef struct gn_timing {
 size_t glassnet_num_params(int32_t width, int32_t pe_levels);
 
 /* Create a handle on cfg->device and upload host_weights (host, n floats,
- * n == glassnet_num_params(width, pe_levels)).  The library owns the fp32 master copy,
- * its bf16/fp8 packed forms and every workspace.  *out is set on GN_OK. */
+ * n == glassnet_num_params(width, pe_levels)).  The library owns the fp32
+ * master copy, its bf16/fp8 packed forms and every workspace.  *out is set on
+ * GN_OK.  GN_E_UNSUPPORTED for a width other than 64 or 128, GN_FP8_T at
+ * width 64, or pe_levels outside 0..GN_MAX_PE_LEVELS; GN_E_INVAL for other bad
+ * fields or a wrong n; GN_E_DEVICE / GN_E_NOMEM from the device. */
 gn_status glassnet_create(const gn_config *cfg, const float *host_weights, size_t n,
                           gn_handle **out);
 

@@ -503,6 +503,8 @@ gn_status glassnet_dssim_loss(gn_handle *h, const float *out, const float *targe
   if (grad_out && (overlaps(grad_out, bytes, out, bytes) || overlaps(grad_out, bytes, target, bytes) ||
                    overlaps(grad_out, bytes, loss, 4)))
     return fail(GN_E_INVAL, "grad_out aliases out, target or loss");
+  if (overlaps(loss, 4, out, bytes) || overlaps(loss, 4, target, bytes))
+    return fail(GN_E_INVAL, "loss aliases out or target");
   DeviceGuard dg(h->device);
   hipStream_t s = (hipStream_t)hip_stream;
   const size_t need = gn::dssim_workspace_bytes(n * gn::kNOUT, height, width);

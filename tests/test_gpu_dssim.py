@@ -86,10 +86,16 @@ def test_training_batch_shape_sampled():
     assert relF(gg[[3, 11]] * 8.0, ref2) <= 1e-4
 
 
-def test_dssim_rejects_small_images():
+def test_dssim_rejects_small_images_and_aliasing():
     torch = torch_dev()
     with net64() as net:
         x = torch.zeros((1, 3, 10, 20), device="cuda:0")
         with pytest.raises(GlassNetError) as e:
             net.dssim_loss(x, x)
         assert e.value.status == GN_E_INVAL
+        y = torch.zeros((1, 3, 12, 12), device="cuda:0")
+        t = torch.zeros((1, 3, 12, 12), device="cuda:0")
+        for kw in (dict(loss=y.view(-1)[5]), dict(grad_out=y), dict(grad_out=t)):
+            with pytest.raises(GlassNetError) as e:
+                net.dssim_loss(y, t, **kw)
+            assert e.value.status == GN_E_INVAL

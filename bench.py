@@ -519,6 +519,9 @@ def main():
         "config": {"workload": "512x512 frame, K=8 transparency layers (active count U{0..8}), "
                                "width-128 F/T/B/R MLPs, mean pool",
                    "pixels_per_step": px, "width": W, "k": K},
+        # dense over K (value) and counting only the active (pixel, slot) pairs
+        "active_pair_fraction": float((fr.layers[:, :, 9] > 0).mean()),
+        "active_pairs_per_s": px * K * float((fr.layers[:, :, 9] > 0).mean()) / step_s,
         "roofline": {
             "bound": "mfma",
             "achieved": achieved,

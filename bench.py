@@ -415,6 +415,57 @@ def coherent_phase(W, K, pool, precision, w, torch, steps=100):
             "pixels_per_s": px / kern_s, "active_pairs_per_s": px * K * active / kern_s}
 
 
+# Super-sampling network, per output pixel: conv3x3 17 -> 32, conv3x3 32 -> 32,
+# conv1x1 32 -> 3 multiply-adds (the upsample and the residual are adds).
+SR_FLOP_PER_PX = 2 * (17 * 9 * 32 + 32 * 9 * 32 + 32 * 3)
+
+
+def sr_phase(W, pool, precision, torch, steps=100, k=8):
+    """The paper's 512^2 pipeline: the forward at 256^2 (k slots), then the x2
+    super-sampling network to 512^2.  Times each on its own (HIP events over
+    back-to-back calls) and the two in sequence."""
+    from paper_2405_19056_amd import synth
+    from paper_2405_19056_amd.glassnet import GlassNet
+    d = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")  # noqa: E731
+    fr = synth.make_frame(1, 256, 256, k, seed=2)
+    g, L, s = d(fr.gbuf), d(fr.layers), d(fr.scene)
+    low = torch.empty((1, 3, 256, 256), dtype=torch.float32, device="cuda:0")
+    srw = d(synth.make_sr_weights(np.random.default_rng(5)))
+    ghi = d(synth.make_sr_inputs(1, 256, 256, seed=5)[1])
+    hi = torch.empty((1, 3, 512, 512), dtype=torch.float32, device="cuda:0")
+    w = synth.make_weights(W, np.random.default_rng(2))
+    stream = torch.cuda.current_stream()
+
+    def timed(fn):
+        for _ in range(300):
+            fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(steps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / 1e3 / steps
+
+    with GlassNet(w, W, k_max=k, pool=pool, precision=precision) as net:
+        if precision == "fp8_t":
+            cal = synth.make_frame(1, 128, 128, k, seed=999)
+            net.calibrate(d(cal.gbuf), d(cal.layers), d(cal.scene))
+        fwd = lambda: net.forward(g, L, s, out=low, stream=stream)  # noqa: E731
+        sr = lambda: net.sr_forward(srw, low, ghi, out=hi, stream=stream)  # noqa: E731
+        t_fwd, t_sr = timed(fwd), timed(sr)
+        t_both = timed(lambda: (fwd(), sr()))
+    px = 512 * 512
+    return {"workload": f"forward 256^2 K={k} + x2 super-sampling to 512^2",
+            "sr_ms": t_sr * 1e3, "sr_pixels_per_s": px / t_sr,
+            "sr_alg_flop_per_px": SR_FLOP_PER_PX,
+            "sr_tflops": SR_FLOP_PER_PX * px / t_sr / 1e12,
+            "sr_frac_fp32_vector_peak": SR_FLOP_PER_PX * px / t_sr / 1e12 / PEAK_TFLOPS["fp32"],
+            "forward_256_ms": t_fwd * 1e3, "pipeline_ms": t_both * 1e3,
+            "pipeline_frames_per_s": 1.0 / t_both}
+
+
 def copy_probe():
     """A plain device-to-device copy of 1 GiB, for counter scaling."""
     import torch
@@ -449,6 +500,8 @@ def main():
     ap.add_argument("--no-stream", action="store_true")
     ap.add_argument("--no-variants", action="store_true",
                     help="skip the positional-encoding and coherent-coverage runs")
+    ap.add_argument("--super-sampling-only", action="store_true",
+                    help="only time the 512^2 pipeline (forward at 256^2 + x2 super-sampling)")
     ap.add_argument("--stream-reps", type=int, default=30)
     ap.add_argument("--backward-calls", type=int, default=0,
                     help="only time this many backward calls of the training workload")
@@ -459,6 +512,13 @@ def main():
         sys.exit(2)
     if args.copy_probe:
         copy_probe()
+        return
+    if args.super_sampling_only:
+        import torch
+        from paper_2405_19056_amd import synth
+        c = synth.CONFIGS[WORKLOAD]
+        print(json.dumps({"super_sampling": sr_phase(c["width"], c["pool"], args.precision,
+                                                     torch, steps=args.steps)}))
         return
     if args.backward_calls > 0:
         import torch
@@ -490,6 +550,7 @@ def main():
           pe_phase(W, K, c["pool"], args.precision, g, L, s, out, torch))
     coherent = (None if args.no_variants else
                 coherent_phase(W, K, c["pool"], args.precision, w, torch))
+    sr = None if args.no_variants else sr_phase(W, c["pool"], args.precision, torch)
 
     fp32 = None
     if not args.no_fp32:
@@ -549,6 +610,8 @@ def main():
         res["positional_encoding"] = pe
     if coherent:
         res["coherent_coverage"] = coherent
+    if sr:
+        res["super_sampling"] = sr
     if not args.no_train:
         res["train_step"] = train_phase(torch)
     if args.k_sweep:

@@ -210,6 +210,32 @@ gn_status glassnet_adam_step(gn_handle *h, const float *grad_w, float *state, si
                              int32_t step, float lr, float beta1, float beta2, float eps,
                              float weight_decay, void *hip_stream);
 
+/* x2 super-sampling network (Sec. 3.4 closes with a small multi-layer CNN
+ * that doubles the resolution of GlassNet's render, helped by textures and
+ * G-buffers the rasterizer produces cheaply at the higher resolution; Sec. 4.1
+ * renders 256^2 and super-samples to 512^2).  The layers are a reading (the
+ * paper gives none): input = the render upsampled x2 bilinearly (sample
+ * centres at half-pixel offsets, sources clamped at the edges) followed by
+ * the 14 full-resolution G-buffer planes; conv 3x3 17 -> 32 + ReLU, conv 3x3
+ * 32 -> 32 + ReLU (both zero-padded, size kept), conv 1x1 32 -> 3; output =
+ * upsampled render + that.  fp32 throughout.
+ *   sr_w     device, glassnet_sr_num_params() floats: conv1 W [32][17][3][3]
+ *            then b [32], conv2 W [32][32][3][3] then b [32], conv3 W [3][32]
+ *            then b [3]; read only.
+ *   height, width   the render's size; the output is 2 height x 2 width.
+ *   lowres   device [n][3][height][width] (e.g. glassnet_forward's out).
+ *   gbuf_hi  device [n][14][2 height][2 width], channels as in gn_frame.
+ *   out      device [n][3][2 height][2 width]; must not overlap the inputs.
+ * Independent of the handle's width and precision: the handle supplies the
+ * device and a 57 KB copy of sr_w re-laid for the kernel (allocated on the
+ * first call), which calls on different streams share: order them.
+ * GN_E_INVAL for n outside 1..65535, height or width outside 1..2^18, NULL or
+ * misaligned pointers, or out overlapping an input. */
+size_t glassnet_sr_num_params(void);
+gn_status glassnet_sr_forward(gn_handle *h, const float *sr_w, int32_t n, int32_t height,
+                              int32_t width, const float *lowres, const float *gbuf_hi, float *out,
+                              void *hip_stream);
+
 /* L1 term of Sec. 3.5 over count elements: *loss = mean |out - target| and
  * grad_out = sign(out - target) / count (0 where equal).  All device.
  * grad_out may be NULL. */

@@ -201,6 +201,7 @@ gn_status glassnet_destroy(gn_handle *h) {
   (void)hipFree(h->d_packed);
   (void)hipFree(h->d_l1_partials);
   (void)hipFree(h->d_loss_ws);
+  (void)hipFree(h->d_sr_wt);
   (void)hipFree(h->d_sig_scratch[0]);
   (void)hipFree(h->d_sig_scratch[1]);
   delete h;
@@ -525,6 +526,42 @@ gn_status glassnet_dssim_loss(gn_handle *h, const float *out, const float *targe
   hipError_t e = gn::launch_dssim(out, target, n * gn::kNOUT, height, width, loss, grad_out,
                                   accumulate ? 1 : 0, h->d_loss_ws, s);
   return gn_check_device(h, e, "DSSIM launch");
+}
+
+size_t glassnet_sr_num_params(void) { return (size_t)gn::kSrParams; }
+
+gn_status glassnet_sr_forward(gn_handle *h, const float *sr_w, int32_t n, int32_t height,
+                              int32_t width, const float *lowres, const float *gbuf_hi, float *out,
+                              void *hip_stream) {
+  gn_status st = precheck(h);
+  if (st != GN_OK) return st;
+  if (n < 1 || n > 65535 || height < 1 || width < 1 || height > (1 << 18) || width > (1 << 18))
+    return fail(GN_E_INVAL, "need 1 <= n <= 65535 and 1 <= height, width <= 2^18 (got %d x %d x %d)",
+                n, height, width);
+  if (!sr_w || !lowres || !gbuf_hi || !out)
+    return fail(GN_E_INVAL, "sr_w, lowres, gbuf_hi and out must be non-NULL");
+  if (!aligned4(sr_w) || !aligned4(lowres) || !aligned4(gbuf_hi) || !aligned4(out))
+    return fail(GN_E_INVAL, "device pointers must be 4-byte aligned");
+  const size_t plane_hi = (size_t)4 * height * width;
+  const size_t out_b = sizeof(float) * (size_t)n * gn::kNOUT * plane_hi;
+  const size_t g_b = sizeof(float) * (size_t)n * GN_NUM_G * plane_hi;
+  const size_t lo_b = sizeof(float) * (size_t)n * gn::kNOUT * height * width;
+  const size_t w_b = sizeof(float) * (size_t)gn::kSrParams;
+  if (overlaps(out, out_b, lowres, lo_b) || overlaps(out, out_b, gbuf_hi, g_b) ||
+      overlaps(out, out_b, sr_w, w_b))
+    return fail(GN_E_INVAL, "out aliases lowres, gbuf_hi or sr_w");
+  DeviceGuard dg(h->device);
+  if (!h->d_sr_wt) {
+    hipError_t e = hipMalloc((void **)&h->d_sr_wt, w_b);
+    if (e != hipSuccess) {
+      h->d_sr_wt = nullptr;
+      return e == hipErrorOutOfMemory ? fail(GN_E_NOMEM, "super-sampling weight copy")
+                                      : gn_check_device(h, e, "super-sampling weight copy");
+    }
+  }
+  hipError_t e = gn::launch_sr_forward(sr_w, h->d_sr_wt, lowres, gbuf_hi, out, n, height, width,
+                                       (hipStream_t)hip_stream);
+  return gn_check_device(h, e, "super-sampling launch");
 }
 
 gn_status glassnet_adam_step(gn_handle *h, const float *grad_w, float *state, size_t n,

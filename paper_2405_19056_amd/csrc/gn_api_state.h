@@ -30,6 +30,7 @@ struct gn_handle {
   uint8_t *d_sig_scratch[2] = {nullptr, nullptr};  // MFMA forward: caller streams, serving
   float *d_l1_partials = nullptr;
   float *d_loss_ws = nullptr;     // DSSIM term: coefficient maps and partial sums
+  float *d_sr_wt = nullptr;       // super-sampling network: re-laid weight copy
   size_t loss_ws_bytes = 0;
   int l1_npart = 0;
   float act_scale = 0.0f;         // fp8 activation scale

@@ -151,6 +151,15 @@ hipError_t launch_l1(const float *out, const float *target, uint64_t count, floa
 size_t dssim_workspace_bytes(int planes, int h, int w);
 hipError_t launch_dssim(const float *out, const float *target, int planes, int h, int w,
                         float *loss, float *grad, int accumulate, float *ws, hipStream_t stream);
+// x2 super-sampling network: widths and the packed parameter count.
+constexpr int kSrWidth = 32, kSrIn = 3 + 14, kSrOut = 3;
+constexpr int kSrParams = kSrWidth * kSrIn * 9 + kSrWidth + kSrWidth * kSrWidth * 9 + kSrWidth +
+                          kSrOut * kSrWidth + kSrOut;
+// w: packed weights (device, kSrParams floats); wt: kSrParams floats of
+// device scratch for their re-laid copy; lowres [n][3][h][w], gbuf
+// [n][14][2h][2w], out [n][3][2h][2w].
+hipError_t launch_sr_forward(const float *w, float *wt, const float *lowres, const float *gbuf,
+                             float *out, int n, int h, int w_lo, hipStream_t stream);
 // One Adam step on w (n floats) from gradient g, moments m and v; step >= 1.
 hipError_t launch_adam(float *w, const float *g, float *m, float *v, int64_t n, int step, float lr,
                        float b1, float b2, float eps, float wd, hipStream_t stream);

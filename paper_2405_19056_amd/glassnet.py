@@ -59,6 +59,9 @@ _SIGS = {
                                       c_void_p, c_void_p, c_int32, c_void_p]),
     "glassnet_adam_step": (c_int32, [c_void_p, c_void_p, c_void_p, c_size_t, c_int32, c_float,
                                      c_float, c_float, c_float, c_float, c_void_p]),
+    "glassnet_sr_num_params": (c_size_t, []),
+    "glassnet_sr_forward": (c_int32, [c_void_p, c_void_p, c_int32, c_int32, c_int32, c_void_p,
+                                      c_void_p, c_void_p, c_void_p]),
     "glassnet_l1_loss": (c_int32, [c_void_p, c_void_p, c_void_p, c_uint64, c_void_p, c_void_p,
                                    c_void_p]),
     "glassnet_workspace_bytes": (c_int32, [c_void_p, POINTER(c_uint64)]),
@@ -104,6 +107,10 @@ def _check(status):
 
 def num_params(width: int, pe_levels: int = 0) -> int:
     return int(lib().glassnet_num_params(width, pe_levels))
+
+
+def sr_num_params() -> int:
+    return int(lib().glassnet_sr_num_params())
 
 
 def _torch():
@@ -245,6 +252,24 @@ class GlassNet:
                                          n, h, w, _dev_ptr(loss, "loss"), gp, 1 if accumulate else 0,
                                          _stream(stream)))
         return loss
+
+    # -- x2 super-sampling network
+    def sr_forward(self, sr_w, lowres, gbuf_hi, out=None, stream=None):
+        """[n][3][h][w] render + [n][14][2h][2w] G-buffer -> [n][3][2h][2w]
+        (glassnet_sr_forward); sr_w is the packed device weight vector."""
+        torch = _torch()
+        n, c, h, w = lowres.shape
+        if c != NUM_OUT or tuple(gbuf_hi.shape) != (n, NUM_G, 2 * h, 2 * w):
+            raise ValueError("lowres must be [n][3][h][w] and gbuf_hi [n][14][2h][2w]")
+        if sr_w.numel() != sr_num_params():
+            raise ValueError(f"sr_w must hold {sr_num_params()} floats")
+        if out is None:
+            out = torch.empty((n, NUM_OUT, 2 * h, 2 * w), dtype=torch.float32,
+                              device=lowres.device)
+        _check(lib().glassnet_sr_forward(self._h, _dev_ptr(sr_w, "sr_w"), n, h, w,
+                                         _dev_ptr(lowres, "lowres"), _dev_ptr(gbuf_hi, "gbuf_hi"),
+                                         _dev_ptr(out, "out"), _stream(stream)))
+        return out
 
     # -- optimiser
     def adam_state(self):

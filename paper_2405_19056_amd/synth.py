@@ -83,6 +83,34 @@ def make_weights(width: int, rng: np.random.Generator, pe_levels: int = 0) -> np
     return np.concatenate(parts).astype(np.float32)
 
 
+SR_WIDTH, SR_IN, SR_OUT = 32, 3 + N_G, 3
+
+
+def sr_layer_shapes():
+    """(fan_out, fan_in, taps) of the super-sampling network's three convs."""
+    return [(SR_WIDTH, SR_IN, 9), (SR_WIDTH, SR_WIDTH, 9), (SR_OUT, SR_WIDTH, 1)]
+
+
+def make_sr_weights(rng: np.random.Generator) -> np.ndarray:
+    """Packed super-sampling weights (each conv's W then b), initialised like
+    make_weights with fan_in = input channels x taps."""
+    parts = []
+    for fan_out, cin, taps in sr_layer_shapes():
+        fan_in = cin * taps
+        parts.append(rng.uniform(-np.sqrt(6.0 / fan_in), np.sqrt(6.0 / fan_in),
+                                 size=fan_out * fan_in))
+        parts.append(rng.uniform(-1.0 / np.sqrt(fan_in), 1.0 / np.sqrt(fan_in), size=fan_out))
+    return np.concatenate(parts).astype(np.float32)
+
+
+def make_sr_inputs(n: int, h: int, w: int, seed: int):
+    """A render [n][3][h][w] (radiance-like values in [0, 2)) and a G-buffer at
+    twice its resolution, [n][14][2h][2w]."""
+    rng = np.random.default_rng(seed)
+    lowres = rng.uniform(0.0, 2.0, size=(n, 3, h, w)).astype(np.float32)
+    return lowres, make_gbuf(n, 2 * h, 2 * w, rng)
+
+
 def _unit_normals(rng, shape):
     v = rng.standard_normal(size=(3,) + shape)
     n = np.sqrt((v * v).sum(axis=0, keepdims=True))

@@ -5,6 +5,7 @@ import os
 import re
 import subprocess
 
+import numpy as np
 import pytest
 
 import oracle
@@ -83,3 +84,11 @@ def test_binding_refuses_a_missing_library(monkeypatch):
     monkeypatch.setattr(gb, "LIB_PATH", "/nonexistent/libglassnet.so")
     with pytest.raises(RuntimeError, match="not built"):
         gb.lib()
+
+
+def test_sr_num_params_agree():
+    if not os.path.exists(gb.LIB_PATH):
+        pytest.skip("libglassnet.so not built")
+    n = gb.sr_num_params()
+    assert n == oracle.sr_n_params() == synth.make_sr_weights(np.random.default_rng(0)).size
+    assert n == 14275

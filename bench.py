@@ -461,7 +461,7 @@ def sr_phase(W, pool, precision, torch, steps=100, k=8):
             "sr_ms": t_sr * 1e3, "sr_pixels_per_s": px / t_sr,
             "sr_alg_flop_per_px": SR_FLOP_PER_PX,
             "sr_tflops": SR_FLOP_PER_PX * px / t_sr / 1e12,
-            "sr_frac_fp32_vector_peak": SR_FLOP_PER_PX * px / t_sr / 1e12 / PEAK_TFLOPS["fp32"],
+            "sr_frac_fp32_mfma_peak": SR_FLOP_PER_PX * px / t_sr / 1e12 / PEAK_TFLOPS["fp32"],
             "forward_256_ms": t_fwd * 1e3, "pipeline_ms": t_both * 1e3,
             "pipeline_frames_per_s": 1.0 / t_both}
 

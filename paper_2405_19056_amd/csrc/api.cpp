@@ -552,7 +552,7 @@ gn_status glassnet_sr_forward(gn_handle *h, const float *sr_w, int32_t n, int32_
     return fail(GN_E_INVAL, "out aliases lowres, gbuf_hi or sr_w");
   DeviceGuard dg(h->device);
   if (!h->d_sr_wt) {
-    hipError_t e = hipMalloc((void **)&h->d_sr_wt, w_b);
+    hipError_t e = hipMalloc((void **)&h->d_sr_wt, sizeof(float) * (size_t)gn::kSrWtFloats);
     if (e != hipSuccess) {
       h->d_sr_wt = nullptr;
       return e == hipErrorOutOfMemory ? fail(GN_E_NOMEM, "super-sampling weight copy")

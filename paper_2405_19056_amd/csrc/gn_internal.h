@@ -155,7 +155,11 @@ hipError_t launch_dssim(const float *out, const float *target, int planes, int h
 constexpr int kSrWidth = 32, kSrIn = 3 + 14, kSrOut = 3;
 constexpr int kSrParams = kSrWidth * kSrIn * 9 + kSrWidth + kSrWidth * kSrWidth * 9 + kSrWidth +
                           kSrOut * kSrWidth + kSrOut;
-// w: packed weights (device, kSrParams floats); wt: kSrParams floats of
+// Floats of the kernel's re-laid weight copy (conv1's K padded to 20 input
+// channels per tap).
+constexpr int kSrWtFloats = (9 * 20 / 4) * 2 * 64 + kSrWidth + (9 * kSrWidth / 4) * 2 * 64 +
+                            kSrWidth + kSrOut * kSrWidth + kSrOut;
+// w: packed weights (device, kSrParams floats); wt: kSrWtFloats floats of
 // device scratch for their re-laid copy; lowres [n][3][h][w], gbuf
 // [n][14][2h][2w], out [n][3][2h][2w].
 hipError_t launch_sr_forward(const float *w, float *wt, const float *lowres, const float *gbuf,

@@ -5,14 +5,25 @@
 // 17 -> 32 + ReLU, conv 3x3 32 -> 32 + ReLU, conv 1x1 32 -> 3, plus the
 // upsampled render; 3x3 convs zero-padded to keep the size.
 //
-// One fused kernel per call, fp32 throughout.  A 256-thread block owns a
-// 16 x 16 output tile: it stages the 17-channel input over the tile plus a
-// two-pixel halo in LDS (upsampling on the fly), evaluates conv1 over the
-// tile plus a one-pixel halo into LDS (zero outside the image, as conv2's
-// padding requires), then each thread evaluates conv2, conv1x1 and the
-// residual for its own pixel.  Weights are read at wave-uniform addresses
-// (scalar loads, broadcast as instruction operands) from a copy re-laid so
-// that the 32 output channels of one (input channel, tap) are contiguous.
+// One fused kernel per call, fp32 throughout, both 3x3 convs on the fp32
+// matrix cores (16x16x4 MFMA) as implicit GEMMs with the weights as the
+// 16-row operand (two tiles of 16 output channels) and 16 pixels as the
+// columns.  A 256-thread block owns a 16 x 16 output tile:
+//   stage 0  the 17-channel input over the tile plus a two-pixel halo into
+//            LDS (upsampling on the fly; three zero channels pad K to 20 per
+//            tap);
+//   stage 1  conv1 + ReLU over the tile plus a one-pixel halo (324 positions,
+//            21 column tiles of 16) into LDS, zero outside the image as
+//            conv2's padding requires;
+//   stage 2  conv2 + ReLU, one output row of 16 pixels per column tile, then
+//            the 1x1 head: each lane holds 8 of the 32 channels of its pixel,
+//            and two cross-lane sums complete the 3 outputs; plus the
+//            upsampled render.
+// The K order is tap-major (k = tap * C + channel), so each 4-wide K step
+// reads four channels of one tap: an LDS address per lane that is a constant
+// offset from a per-tile base.  The weights are re-laid once per call into
+// the operand order of the MFMA (K step, channel tile, lane) so that each
+// wave loads its fragments with coalesced loads into registers.
 #include <algorithm>
 
 #include "gn_internal.h"
@@ -20,58 +31,90 @@
 namespace gn {
 namespace {
 
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
 constexpr int kC = kSrWidth;          // hidden channels
 constexpr int kIn = kSrIn;            // 3 upsampled + 14 G-buffer channels
+constexpr int kInP = 20;              // input channels padded to a multiple of 4
 constexpr int kT = 16;                // output tile edge
 constexpr int kE0 = kT + 4;           // staged input edge (two-pixel halo)
 constexpr int kE1 = kT + 2;           // conv1 output edge (one-pixel halo)
+constexpr int kP1 = kE1 * kE1;        // conv1 positions per tile (324)
+constexpr int kA1Stride = 336;        // LDS floats per conv1 output channel
 constexpr int kThreads = 256;
-constexpr int kW1 = kIn * 9 * kC;     // re-laid conv1 weights [cin][tap][cout]
-constexpr int kW2 = kC * 9 * kC;      // re-laid conv2 weights [cin][tap][cout]
+constexpr int kS1 = 9 * kInP / 4;     // conv1 K steps (45)
+constexpr int kS2 = 9 * kC / 4;       // conv2 K steps (72)
+constexpr int kN1 = (kP1 + 15) / 16;  // conv1 column tiles (21)
+// re-laid weights: A1 [kS1][2][64], b1 [32], A2 [kS2][2][64], b2 [32],
+// w3 [3][32], b3 [3]
+constexpr int kOffB1 = kS1 * 2 * 64;
+constexpr int kOffA2 = kOffB1 + kC;
+constexpr int kOffB2 = kOffA2 + kS2 * 2 * 64;
+constexpr int kOffW3 = kOffB2 + kC;
+constexpr int kOffB3 = kOffW3 + kSrOut * kC;
+static_assert(kOffB3 + kSrOut == kSrWtFloats, "re-laid weight size");
+static_assert(kA1Stride >= kP1 && kA1Stride % 64 == 16, "conv1 output channel stride");
 
-static_assert(kT * kT == kThreads, "one output pixel per thread");
-
-// packed [cout][cin][3][3] -> [cin][tap][cout] for both 3x3 convs; biases and
-// the 1x1 head copied as they are.  Layout of wt: w1t, b1, w2t, b2, w3, b3.
+// packed weights -> MFMA operand order.  Fragment (s, mt, lane): output
+// channel 16 mt + lane % 16, K index 4 s + lane / 16 = tap * C + channel.
 __global__ __launch_bounds__(kThreads) void sr_relayout_kernel(const float *__restrict__ w,
                                                                float *__restrict__ wt) {
   const int i = blockIdx.x * kThreads + threadIdx.x;
-  if (i >= kSrParams) return;
-  int dst = i;
-  if (i < kW1) {
-    const int o = i / (kIn * 9), r = i % (kIn * 9);  // r = cin * 9 + tap
-    dst = r * kC + o;
-  } else if (i >= kW1 + kC && i < kW1 + kC + kW2) {
-    const int j = i - (kW1 + kC);
-    const int o = j / (kC * 9), r = j % (kC * 9);
-    dst = kW1 + kC + r * kC + o;
+  if (i >= kSrWtFloats) return;
+  const float *w1 = w, *b1 = w1 + kC * kIn * 9, *w2 = b1 + kC, *b2 = w2 + kC * kC * 9;
+  const float *w3 = b2 + kC, *b3 = w3 + kSrOut * kC;
+  float v;
+  if (i < kOffB1) {
+    const int s = i / 128, mt = (i / 64) % 2, l = i % 64;
+    const int k = 4 * s + l / 16, tap = k / kInP, c = k % kInP, o = 16 * mt + l % 16;
+    v = c < kIn ? w1[(o * kIn + c) * 9 + tap] : 0.0f;
+  } else if (i < kOffA2) {
+    v = b1[i - kOffB1];
+  } else if (i < kOffB2) {
+    const int j = i - kOffA2;
+    const int s = j / 128, mt = (j / 64) % 2, l = j % 64;
+    const int k = 4 * s + l / 16, tap = k / kC, c = k % kC, o = 16 * mt + l % 16;
+    v = w2[(o * kC + c) * 9 + tap];
+  } else if (i < kOffW3) {
+    v = b2[i - kOffB2];
+  } else if (i < kOffB3) {
+    v = w3[i - kOffW3];
+  } else {
+    v = b3[i - kOffB3];
   }
-  wt[dst] = w[i];
+  wt[i] = v;
+}
+
+__device__ __forceinline__ f32x4 mfma4(float a, float b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
 __global__ __launch_bounds__(kThreads, 2) void sr_forward_kernel(
     const float *__restrict__ wt, const float *__restrict__ lowres,
     const float *__restrict__ gbuf, float *__restrict__ out, int h, int w) {
-  __shared__ float in_s[kIn * kE0 * kE0];   // 27.2 KB
-  __shared__ float a1_s[kC * kE1 * kE1];    // 41.5 KB
+  __shared__ float in_s[kInP * kE0 * kE0];   // 32.0 KB
+  __shared__ float a1_s[kC * kA1Stride];     // 43.0 KB
 
   const int H = 2 * h, W = 2 * w;
   const int f = blockIdx.z;
   const int oy0 = blockIdx.y * kT, ox0 = blockIdx.x * kT;
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, lane = tid % 64, wave = tid / 64;
+  const int col = lane % 16, grp = lane / 16;
   const int64_t plane_lo = (int64_t)h * w, plane_hi = (int64_t)H * W;
   const float *lo_f = lowres + (int64_t)f * 3 * plane_lo;
   const float *g_f = gbuf + (int64_t)f * (kIn - 3) * plane_hi;
 
-  // stage 0: the 17-channel input over the tile and a two-pixel halo
-  for (int e = tid; e < kIn * kE0 * kE0; e += kThreads) {
+  // stage 0: the input over the tile and a two-pixel halo (zero outside the
+  // image and in the three padding channels)
+  for (int e = tid; e < kInP * kE0 * kE0; e += kThreads) {
     const int c = e / (kE0 * kE0), r = (e / kE0) % kE0, q = e % kE0;
     const int Y = oy0 - 2 + r, X = ox0 - 2 + q;
     float v = 0.0f;
-    if (Y >= 0 && Y < H && X >= 0 && X < W) {
+    if (c < kIn && Y >= 0 && Y < H && X >= 0 && X < W) {
       if (c < 3) {
-        // source position (Y + 0.5) / 2 - 0.5: row Y/2 - 1 at weight 1/4 for
-        // even Y, row (Y-1)/2 at weight 3/4 for odd Y; likewise for columns
+        // source position (Y + 0.5) / 2 - 0.5: rows Y/2 - 1 and Y/2 at
+        // weights 1/4 and 3/4 for even Y, rows (Y-1)/2 and (Y+1)/2 at 3/4 and
+        // 1/4 for odd Y (clamped into the image); likewise for columns
         const int y0 = (Y >> 1) - ((Y & 1) ? 0 : 1), x0 = (X >> 1) - ((X & 1) ? 0 : 1);
         const float fy = (Y & 1) ? 0.25f : 0.75f, fx = (X & 1) ? 0.25f : 0.75f;
         const int ya = max(y0, 0), yb = min(y0 + 1, h - 1);
@@ -86,60 +129,96 @@ __global__ __launch_bounds__(kThreads, 2) void sr_forward_kernel(
     }
     in_s[e] = v;
   }
-  __syncthreads();
 
-  // stage 1: conv1 + ReLU over the tile and a one-pixel halo (324 positions,
-  // two passes of the block); zero where the position is outside the image
-  const float *w1 = wt;
-  const float *b1 = w1 + kW1;
-  for (int q = tid; q < kE1 * kE1; q += kThreads) {
-    const int qy = q / kE1, qx = q % kE1;
-    float acc[kC];
+  // stage 1: conv1 + ReLU over the tile and a one-pixel halo
+  {
+    float a[kS1][2];
 #pragma unroll
-    for (int o = 0; o < kC; ++o) acc[o] = b1[o];
-    for (int c = 0; c < kIn; ++c) {
+    for (int s = 0; s < kS1; ++s) {
+      a[s][0] = wt[(2 * s) * 64 + lane];
+      a[s][1] = wt[(2 * s + 1) * 64 + lane];
+    }
+    float bias[2][4];
 #pragma unroll
-      for (int t = 0; t < 9; ++t) {
-        const float v = in_s[c * kE0 * kE0 + (qy + t / 3) * kE0 + qx + t % 3];
-        const float *wr = w1 + (c * 9 + t) * kC;
+    for (int mt = 0; mt < 2; ++mt)
 #pragma unroll
-        for (int o = 0; o < kC; ++o) acc[o] = fmaf(wr[o], v, acc[o]);
+      for (int i = 0; i < 4; ++i) bias[mt][i] = wt[kOffB1 + 16 * mt + 4 * grp + i];
+    __syncthreads();
+    for (int j = wave; j < kN1; j += kThreads / 64) {
+      const int q = 16 * j + col;
+      const int qq = min(q, kP1 - 1);  // the 12 columns past the last position are discarded
+      const float *src = in_s + grp * kE0 * kE0 + (qq / kE1) * kE0 + qq % kE1;
+      f32x4 acc0 = {0.0f, 0.0f, 0.0f, 0.0f}, acc1 = acc0;
+#pragma unroll
+      for (int s = 0; s < kS1; ++s) {
+        const int tap = s / (kInP / 4), c4 = 4 * (s % (kInP / 4));
+        const float b = src[c4 * kE0 * kE0 + (tap / 3) * kE0 + tap % 3];
+        acc0 = mfma4(a[s][0], b, acc0);
+        acc1 = mfma4(a[s][1], b, acc1);
+      }
+      if (q < kP1) {
+        const int Y = oy0 - 1 + q / kE1, X = ox0 - 1 + q % kE1;
+        const bool inside = Y >= 0 && Y < H && X >= 0 && X < W;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          a1_s[(4 * grp + i) * kA1Stride + q] = inside ? fmaxf(acc0[i] + bias[0][i], 0.0f) : 0.0f;
+          a1_s[(16 + 4 * grp + i) * kA1Stride + q] =
+              inside ? fmaxf(acc1[i] + bias[1][i], 0.0f) : 0.0f;
+        }
       }
     }
-    const int Y = oy0 - 1 + qy, X = ox0 - 1 + qx;
-    const bool inside = Y >= 0 && Y < H && X >= 0 && X < W;
-#pragma unroll
-    for (int o = 0; o < kC; ++o) a1_s[o * kE1 * kE1 + q] = inside ? fmaxf(acc[o], 0.0f) : 0.0f;
   }
   __syncthreads();
 
-  // stage 2: conv2 + ReLU, the 1x1 head and the residual, one pixel a thread
-  const float *w2 = b1 + kC;
-  const float *b2 = w2 + kW2;
-  const float *w3 = b2 + kC;
-  const float *b3 = w3 + kSrOut * kC;
-  const int ty = tid / kT, tx = tid % kT;
-  float acc[kC];
+  // stage 2: conv2 + ReLU, the 1x1 head and the residual; one row per tile
+  float a[kS2][2];
 #pragma unroll
-  for (int o = 0; o < kC; ++o) acc[o] = b2[o];
-  for (int c = 0; c < kC; ++c) {
-#pragma unroll
-    for (int t = 0; t < 9; ++t) {
-      const float v = a1_s[c * kE1 * kE1 + (ty + t / 3) * kE1 + tx + t % 3];
-      const float *wr = w2 + (c * 9 + t) * kC;
-#pragma unroll
-      for (int o = 0; o < kC; ++o) acc[o] = fmaf(wr[o], v, acc[o]);
-    }
+  for (int s = 0; s < kS2; ++s) {
+    a[s][0] = wt[kOffA2 + (2 * s) * 64 + lane];
+    a[s][1] = wt[kOffA2 + (2 * s + 1) * 64 + lane];
   }
-  const int Y = oy0 + ty, X = ox0 + tx;
-  if (Y >= H || X >= W) return;
-  float *out_f = out + (int64_t)f * kSrOut * plane_hi + (int64_t)Y * W + X;
+  float bias[2][4], w3[kSrOut][2][4];
 #pragma unroll
-  for (int k = 0; k < kSrOut; ++k) {
-    float y = b3[k];
+  for (int mt = 0; mt < 2; ++mt)
 #pragma unroll
-    for (int o = 0; o < kC; ++o) y = fmaf(w3[k * kC + o], fmaxf(acc[o], 0.0f), y);
-    out_f[k * plane_hi] = in_s[k * kE0 * kE0 + (ty + 2) * kE0 + tx + 2] + y;
+    for (int i = 0; i < 4; ++i) {
+      const int o = 16 * mt + 4 * grp + i;
+      bias[mt][i] = wt[kOffB2 + o];
+#pragma unroll
+      for (int k = 0; k < kSrOut; ++k) w3[k][mt][i] = wt[kOffW3 + k * kC + o];
+    }
+  const int kout = min(grp, kSrOut - 1);
+  const float b3 = wt[kOffB3 + kout];
+  for (int ty = wave; ty < kT; ty += kThreads / 64) {
+    const float *src = a1_s + grp * kA1Stride + ty * kE1 + col;
+    f32x4 acc0 = {0.0f, 0.0f, 0.0f, 0.0f}, acc1 = acc0;
+#pragma unroll
+    for (int s = 0; s < kS2; ++s) {
+      const int tap = s / (kC / 4), c4 = 4 * (s % (kC / 4));
+      const float b = src[c4 * kA1Stride + (tap / 3) * kE1 + tap % 3];
+      acc0 = mfma4(a[s][0], b, acc0);
+      acc1 = mfma4(a[s][1], b, acc1);
+    }
+    float y[kSrOut];
+#pragma unroll
+    for (int k = 0; k < kSrOut; ++k) {
+      float p = 0.0f;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        p = fmaf(w3[k][0][i], fmaxf(acc0[i] + bias[0][i], 0.0f), p);
+        p = fmaf(w3[k][1][i], fmaxf(acc1[i] + bias[1][i], 0.0f), p);
+      }
+      p += __shfl_xor(p, 16);
+      p += __shfl_xor(p, 32);
+      y[k] = p;
+    }
+    // lanes of group k < 3 write output channel k of pixel col
+    const int Y = oy0 + ty, X = ox0 + col;
+    if (grp < kSrOut && Y < H && X < W) {
+      const float yk = grp == 0 ? y[0] : (grp == 1 ? y[1] : y[2]);
+      out[(int64_t)f * kSrOut * plane_hi + kout * plane_hi + (int64_t)Y * W + X] =
+          in_s[kout * kE0 * kE0 + (ty + 2) * kE0 + col + 2] + b3 + yk;
+    }
   }
 }
 
@@ -147,7 +226,7 @@ __global__ __launch_bounds__(kThreads, 2) void sr_forward_kernel(
 
 hipError_t launch_sr_forward(const float *w, float *wt, const float *lowres, const float *gbuf,
                              float *out, int n, int h, int w_lo, hipStream_t stream) {
-  hipLaunchKernelGGL(sr_relayout_kernel, dim3((kSrParams + kThreads - 1) / kThreads),
+  hipLaunchKernelGGL(sr_relayout_kernel, dim3((kSrWtFloats + kThreads - 1) / kThreads),
                      dim3(kThreads), 0, stream, w, wt);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;

@@ -7,5 +7,5 @@ from .glassnet_oracle import (adam_step, alpha_blend, all_slot_orders, dssim_los
                               encode, forward, ssim_map, ssim_window,
                               forward_bruteforce, grad, grad_from_dy, l1_loss, n_params, pack,
                               relu_margins, relu_signature, unpack)
-from .sr_oracle import (sr_forward, sr_forward_bruteforce, sr_n_params, sr_unpack,  # noqa: F401
-                        upsample2x)
+from .sr_oracle import (sr_forward, sr_forward_bruteforce, sr_grad, sr_n_params,  # noqa: F401
+                        sr_unpack, upsample2x)

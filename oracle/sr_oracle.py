@@ -101,6 +101,56 @@ def sr_forward(w, lowres, gbuf_hi, C=SR_WIDTH):
     return out
 
 
+def conv3x3_backward(x, W, dz):
+    """Gradients of conv3x3(x, W, b) for the upstream gradient dz [cout][H][W]:
+    dW[o][c][dy][dx] = sum_p dz[o][p] xpad[c][p + (dy, dx)], db = sum_p dz,
+    and dx, each padded input position collecting W[o][c][tap] dz[o][p] from
+    every output p whose window holds it (the padding's share dropped)."""
+    cin, H, Wd = x.shape
+    cout = W.shape[0]
+    xp = np.zeros((cin, H + 2, Wd + 2))
+    xp[:, 1:-1, 1:-1] = x
+    d = dz.reshape(cout, -1)
+    dW = np.zeros_like(W)
+    dxp = np.zeros_like(xp)
+    for dy in range(3):
+        for dx in range(3):
+            dW[:, :, dy, dx] = d @ xp[:, dy:dy + H, dx:dx + Wd].reshape(cin, -1).T
+            dxp[:, dy:dy + H, dx:dx + Wd] += (W[:, :, dy, dx].T @ d).reshape(cin, H, Wd)
+    return dW, d.sum(axis=1), dxp[:, 1:-1, 1:-1]
+
+
+def sr_grad(w, lowres, gbuf_hi, dy, C=SR_WIDTH):
+    """Packed gradient of sum(dy * sr_forward(w, ...)) with respect to w: the
+    chain rule through the head, conv2, its ReLU, conv1 and its ReLU (the
+    derivative of ReLU taken as 0 at 0).  The residual and the inputs carry
+    no weights."""
+    p = sr_unpack(w, C)
+    g = {k: np.zeros_like(v) for k, v in p.items()}
+    lowres = np.asarray(lowres, dtype=np.float64)
+    gbuf_hi = np.asarray(gbuf_hi, dtype=np.float64)
+    dy = np.asarray(dy, dtype=np.float64)
+    for f in range(lowres.shape[0]):
+        x = np.concatenate([upsample2x(lowres[f]), gbuf_hi[f]], axis=0)
+        H, Wd = x.shape[1:]
+        z1 = conv3x3(x, p["w1"], p["b1"])
+        a1 = np.maximum(z1, 0.0)
+        z2 = conv3x3(a1, p["w2"], p["b2"])
+        a2 = np.maximum(z2, 0.0)
+        d = dy[f].reshape(SR_OUT, -1)
+        g["w3"] += d @ a2.reshape(C, -1).T
+        g["b3"] += d.sum(axis=1)
+        dz2 = (p["w3"].T @ d).reshape(C, H, Wd) * (z2 > 0)
+        dW2, db2, da1 = conv3x3_backward(a1, p["w2"], dz2)
+        dz1 = da1 * (z1 > 0)
+        dW1, db1, _ = conv3x3_backward(x, p["w1"], dz1)
+        g["w2"] += dW2
+        g["b2"] += db2
+        g["w1"] += dW1
+        g["b1"] += db1
+    return np.concatenate([g[name].ravel() for name, _ in sr_shapes(C)])
+
+
 def sr_forward_bruteforce(w, lowres, gbuf_hi, C=SR_WIDTH):
     """Scalar Python-loop twin of sr_forward for tiny inputs."""
     p = sr_unpack(w, C)

@@ -151,3 +151,85 @@ def test_pins_catch_planted_mistakes(mutation):
             except AssertionError:
                 caught += 1
     assert caught > 0
+
+
+# ---------------------------------------------------------------- gradient
+def _torch_sr_grad(w, lo, g, dy):
+    """The same network in torch float64 with autograd (library convolution,
+    interpolation and their backward)."""
+    p = {k: torch.tensor(v, requires_grad=True) for k, v in so.sr_unpack(w).items()}
+    up = F.interpolate(torch.from_numpy(lo), scale_factor=2, mode="bilinear", align_corners=False)
+    x = torch.cat([up, torch.from_numpy(g)], dim=1)
+    a1 = torch.relu(F.conv2d(x, p["w1"], p["b1"], padding=1))
+    a2 = torch.relu(F.conv2d(a1, p["w2"], p["b2"], padding=1))
+    y = up + F.conv2d(a2, p["w3"][:, :, None, None], p["b3"])
+    (y * torch.from_numpy(dy)).sum().backward()
+    return np.concatenate([p[name].grad.numpy().ravel() for name, _ in so.sr_shapes()])
+
+
+def test_grad_matches_torch_autograd():
+    rng = np.random.default_rng(6)
+    w = _weights(6)
+    lo, g = rng.uniform(0, 2, size=(2, 3, 4, 5)), rng.uniform(-1, 1, size=(2, 14, 8, 10))
+    dy = rng.normal(size=(2, 3, 8, 10))
+    ref = _torch_sr_grad(w, lo, g, dy)
+    got = so.sr_grad(w, lo, g, dy)
+    assert np.max(np.abs(got - ref)) <= 1e-11 * np.max(np.abs(ref))
+
+
+def test_grad_matches_central_differences():
+    rng = np.random.default_rng(8)
+    w = _weights(8)
+    lo, g = rng.uniform(0, 2, size=(1, 3, 2, 3)), rng.uniform(-1, 1, size=(1, 14, 4, 6))
+    dy = rng.normal(size=(1, 3, 4, 6))
+    gr = so.sr_grad(w, lo, g, dy)
+    f = lambda ww: float(np.sum(so.sr_forward(ww, lo, g) * dy))  # noqa: E731
+    eps = 1e-6
+    idx = np.concatenate([rng.choice(4896, 40, replace=False), 4896 + np.arange(32),
+                          4928 + rng.choice(9216, 40, replace=False), 14144 + np.arange(131)])
+    for i in idx:
+        wp, wm = w.copy(), w.copy()
+        wp[i] += eps
+        wm[i] -= eps
+        fd = (f(wp) - f(wm)) / (2 * eps)
+        assert abs(fd - gr[i]) <= 1e-6 * max(1.0, abs(gr[i])), i
+
+
+def _grad_no_relu_mask(w, lowres, gbuf_hi, dy, C=so.SR_WIDTH):
+    """The chain rule with the ReLU derivatives dropped (masks of ones)."""
+    p = so.sr_unpack(w, C)
+    out = {k: np.zeros_like(v) for k, v in p.items()}
+    for f in range(lowres.shape[0]):
+        x = np.concatenate([so.upsample2x(lowres[f]), gbuf_hi[f]], axis=0)
+        H, Wd = x.shape[1:]
+        a1 = np.maximum(so.conv3x3(x, p["w1"], p["b1"]), 0.0)
+        a2 = np.maximum(so.conv3x3(a1, p["w2"], p["b2"]), 0.0)
+        d = dy[f].reshape(3, -1)
+        out["w3"] += d @ a2.reshape(C, -1).T
+        out["b3"] += d.sum(axis=1)
+        dW2, db2, da1 = so.conv3x3_backward(a1, p["w2"], (p["w3"].T @ d).reshape(C, H, Wd))
+        dW1, db1, _ = so.conv3x3_backward(x, p["w1"], da1)
+        for k, v in (("w2", dW2), ("b2", db2), ("w1", dW1), ("b1", db1)):
+            out[k] += v
+    return np.concatenate([out[name].ravel() for name, _ in so.sr_shapes(C)])
+
+
+def _bwd_taps_transposed(x, W, dz):
+    dW, db, dx = _bwd(x, np.swapaxes(W, 2, 3), dz)
+    return np.swapaxes(dW, 2, 3), db, dx
+
+
+_grad, _bwd = so.sr_grad, so.conv3x3_backward
+
+
+@pytest.mark.parametrize("mutation", [dict(sr_grad=_grad_no_relu_mask),
+                                      dict(conv3x3_backward=_bwd_taps_transposed)])
+def test_grad_pins_catch_planted_mistakes(mutation):
+    caught = 0
+    with patched(**mutation):
+        for t in (test_grad_matches_torch_autograd, test_grad_matches_central_differences):
+            try:
+                t()
+            except AssertionError:
+                caught += 1
+    assert caught > 0

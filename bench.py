@@ -456,6 +456,21 @@ def sr_phase(W, pool, precision, torch, steps=100, k=8):
         sr = lambda: net.sr_forward(srw, low, ghi, out=hi, stream=stream)  # noqa: E731
         t_fwd, t_sr = timed(fwd), timed(sr)
         t_both = timed(lambda: (fwd(), sr()))
+        # its weight gradient on a training batch: 16 renders of 128^2 -> 256^2
+        lo_b, g_b = synth.make_sr_inputs(16, 128, 128, seed=6)
+        lo_b, g_b = d(lo_b), d(g_b)
+        dy_b = torch.randn((16, 3, 256, 256), device="cuda:0")
+        gw = torch.empty_like(srw)
+        bwd = lambda: net.sr_backward(srw, lo_b, g_b, dy_b, grad_w=gw, stream=stream)  # noqa: E731
+        bwd()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(5):
+            bwd()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        t_bwd = e0.elapsed_time(e1) / 1e3 / 5
     px = 512 * 512
     return {"workload": f"forward 256^2 K={k} + x2 super-sampling to 512^2",
             "sr_ms": t_sr * 1e3, "sr_pixels_per_s": px / t_sr,
@@ -463,7 +478,8 @@ def sr_phase(W, pool, precision, torch, steps=100, k=8):
             "sr_tflops": SR_FLOP_PER_PX * px / t_sr / 1e12,
             "sr_frac_fp32_mfma_peak": SR_FLOP_PER_PX * px / t_sr / 1e12 / PEAK_TFLOPS["fp32"],
             "forward_256_ms": t_fwd * 1e3, "pipeline_ms": t_both * 1e3,
-            "pipeline_frames_per_s": 1.0 / t_both}
+            "pipeline_frames_per_s": 1.0 / t_both,
+            "sr_backward_16x256sq_ms": t_bwd * 1e3}
 
 
 def copy_probe():

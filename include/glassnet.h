@@ -236,6 +236,21 @@ gn_status glassnet_sr_forward(gn_handle *h, const float *sr_w, int32_t n, int32_
                               int32_t width, const float *lowres, const float *gbuf_hi, float *out,
                               void *hip_stream);
 
+/* Weight gradient of glassnet_sr_forward (Sec. 4.1 trains the super-sampling
+ * network on its own), fp32: grad_out = dL/d(out) [n][3][2 height][2 width],
+ * device; grad_w (device, glassnet_sr_num_params() floats, packed like sr_w)
+ * is overwritten with dL/d(sr_w).  The forward is recomputed with the same
+ * arithmetic as glassnet_sr_forward (so the ReLU masks are the ones behind
+ * its output; the derivative of ReLU is 0 at 0), per-tile partial sums are
+ * added in fp64 in a fixed order: the result is deterministic.  At most 2^22
+ * output pixels per call (n 4 height width) and height, width <= 2^16
+ * (GN_E_INVAL beyond, or for NULL, misaligned or aliasing pointers).  The
+ * handle keeps a workspace of about 570 bytes per output pixel (grown on a
+ * larger call, after the stream's earlier work). */
+gn_status glassnet_sr_backward(gn_handle *h, const float *sr_w, int32_t n, int32_t height,
+                               int32_t width, const float *lowres, const float *gbuf_hi,
+                               const float *grad_out, float *grad_w, void *hip_stream);
+
 /* L1 term of Sec. 3.5 over count elements: *loss = mean |out - target| and
  * grad_out = sign(out - target) / count (0 where equal).  All device.
  * grad_out may be NULL. */

@@ -202,6 +202,7 @@ gn_status glassnet_destroy(gn_handle *h) {
   (void)hipFree(h->d_l1_partials);
   (void)hipFree(h->d_loss_ws);
   (void)hipFree(h->d_sr_wt);
+  (void)hipFree(h->d_sr_ws);
   (void)hipFree(h->d_sig_scratch[0]);
   (void)hipFree(h->d_sig_scratch[1]);
   delete h;
@@ -530,6 +531,22 @@ gn_status glassnet_dssim_loss(gn_handle *h, const float *out, const float *targe
 
 size_t glassnet_sr_num_params(void) { return (size_t)gn::kSrParams; }
 
+}  // extern "C"
+
+namespace {
+// the handle's device copy of the super-sampling weights in kernel order
+gn_status sr_weight_copy(gn_handle *h) {
+  if (h->d_sr_wt) return GN_OK;
+  hipError_t e = hipMalloc((void **)&h->d_sr_wt, sizeof(float) * (size_t)gn::kSrWtFloats);
+  if (e == hipSuccess) return GN_OK;
+  h->d_sr_wt = nullptr;
+  return e == hipErrorOutOfMemory ? fail(GN_E_NOMEM, "super-sampling weight copy")
+                                  : gn_check_device(h, e, "super-sampling weight copy");
+}
+}  // namespace
+
+extern "C" {
+
 gn_status glassnet_sr_forward(gn_handle *h, const float *sr_w, int32_t n, int32_t height,
                               int32_t width, const float *lowres, const float *gbuf_hi, float *out,
                               void *hip_stream) {
@@ -551,17 +568,59 @@ gn_status glassnet_sr_forward(gn_handle *h, const float *sr_w, int32_t n, int32_
       overlaps(out, out_b, sr_w, w_b))
     return fail(GN_E_INVAL, "out aliases lowres, gbuf_hi or sr_w");
   DeviceGuard dg(h->device);
-  if (!h->d_sr_wt) {
-    hipError_t e = hipMalloc((void **)&h->d_sr_wt, sizeof(float) * (size_t)gn::kSrWtFloats);
-    if (e != hipSuccess) {
-      h->d_sr_wt = nullptr;
-      return e == hipErrorOutOfMemory ? fail(GN_E_NOMEM, "super-sampling weight copy")
-                                      : gn_check_device(h, e, "super-sampling weight copy");
-    }
-  }
+  st = sr_weight_copy(h);
+  if (st != GN_OK) return st;
   hipError_t e = gn::launch_sr_forward(sr_w, h->d_sr_wt, lowres, gbuf_hi, out, n, height, width,
                                        (hipStream_t)hip_stream);
   return gn_check_device(h, e, "super-sampling launch");
+}
+
+gn_status glassnet_sr_backward(gn_handle *h, const float *sr_w, int32_t n, int32_t height,
+                               int32_t width, const float *lowres, const float *gbuf_hi,
+                               const float *grad_out, float *grad_w, void *hip_stream) {
+  gn_status st = precheck(h);
+  if (st != GN_OK) return st;
+  if (n < 1 || height < 1 || width < 1 || height > (1 << 16) || width > (1 << 16) ||
+      (int64_t)n * 4 * height * width > ((int64_t)1 << 22))
+    return fail(GN_E_INVAL,
+                "need n, height, width >= 1, height, width <= 2^16 and at most 2^22 output "
+                "pixels (got %d x %d x %d)", n, height, width);
+  if (!sr_w || !lowres || !gbuf_hi || !grad_out || !grad_w)
+    return fail(GN_E_INVAL, "sr_w, lowres, gbuf_hi, grad_out and grad_w must be non-NULL");
+  if (!aligned4(sr_w) || !aligned4(lowres) || !aligned4(gbuf_hi) || !aligned4(grad_out) ||
+      !aligned4(grad_w))
+    return fail(GN_E_INVAL, "device pointers must be 4-byte aligned");
+  const size_t plane_hi = (size_t)4 * height * width;
+  const size_t w_b = sizeof(float) * (size_t)gn::kSrParams;
+  const size_t go_b = sizeof(float) * (size_t)n * gn::kNOUT * plane_hi;
+  const size_t g_b = sizeof(float) * (size_t)n * GN_NUM_G * plane_hi;
+  const size_t lo_b = sizeof(float) * (size_t)n * gn::kNOUT * height * width;
+  if (overlaps(grad_w, w_b, sr_w, w_b) || overlaps(grad_w, w_b, lowres, lo_b) ||
+      overlaps(grad_w, w_b, gbuf_hi, g_b) || overlaps(grad_w, w_b, grad_out, go_b))
+    return fail(GN_E_INVAL, "grad_w aliases an input");
+  DeviceGuard dg(h->device);
+  hipStream_t s = (hipStream_t)hip_stream;
+  st = sr_weight_copy(h);
+  if (st != GN_OK) return st;
+  const size_t need = gn::sr_backward_workspace_bytes(n, height, width);
+  if (need > h->sr_ws_bytes) {
+    // grown workspaces replace the old one once the stream's earlier work is done
+    hipError_t e = hipStreamSynchronize(s);
+    if (e == hipSuccess) e = hipFree(h->d_sr_ws);
+    h->d_sr_ws = nullptr;
+    h->sr_ws_bytes = 0;
+    if (e == hipSuccess) e = hipMalloc((void **)&h->d_sr_ws, need);
+    if (e != hipSuccess) {
+      h->d_sr_ws = nullptr;
+      return e == hipErrorOutOfMemory
+                 ? fail(GN_E_NOMEM, "super-sampling backward workspace of %zu bytes", need)
+                 : gn_check_device(h, e, "super-sampling backward workspace");
+    }
+    h->sr_ws_bytes = need;
+  }
+  hipError_t e = gn::launch_sr_backward(sr_w, h->d_sr_wt, lowres, gbuf_hi, grad_out, grad_w, n,
+                                        height, width, h->d_sr_ws, s);
+  return gn_check_device(h, e, "super-sampling backward launch");
 }
 
 gn_status glassnet_adam_step(gn_handle *h, const float *grad_w, float *state, size_t n,

@@ -31,6 +31,8 @@ struct gn_handle {
   float *d_l1_partials = nullptr;
   float *d_loss_ws = nullptr;     // DSSIM term: coefficient maps and partial sums
   float *d_sr_wt = nullptr;       // super-sampling network: re-laid weight copy
+  float *d_sr_ws = nullptr;       // super-sampling backward: activations and partials
+  size_t sr_ws_bytes = 0;
   size_t loss_ws_bytes = 0;
   int l1_npart = 0;
   float act_scale = 0.0f;         // fp8 activation scale

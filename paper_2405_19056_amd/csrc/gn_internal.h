@@ -164,6 +164,12 @@ constexpr int kSrWtFloats = (9 * 20 / 4) * 2 * 64 + kSrWidth + (9 * kSrWidth / 4
 // [n][14][2h][2w], out [n][3][2h][2w].
 hipError_t launch_sr_forward(const float *w, float *wt, const float *lowres, const float *gbuf,
                              float *out, int n, int h, int w_lo, hipStream_t stream);
+// Its weight gradient for dy = dL/d(out): grad_w (kSrParams floats)
+// overwritten; ws holds sr_backward_workspace_bytes(n, h, w) bytes.
+size_t sr_backward_workspace_bytes(int n, int h, int w);
+hipError_t launch_sr_backward(const float *w, float *wt, const float *lowres, const float *gbuf,
+                              const float *dy, float *gw, int n, int h, int w_lo, float *ws,
+                              hipStream_t stream);
 // One Adam step on w (n floats) from gradient g, moments m and v; step >= 1.
 hipError_t launch_adam(float *w, const float *g, float *m, float *v, int64_t n, int step, float lr,
                        float b1, float b2, float eps, float wd, hipStream_t stream);

@@ -89,9 +89,13 @@ __device__ __forceinline__ f32x4 mfma4(float a, float b, f32x4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
+// SAVE (the backward's recompute): instead of the output, write relu(z1) and
+// relu(z2) of the tile's own pixels to a1_out, a2_out [n][32][2h][2w].
+template <bool SAVE>
 __global__ __launch_bounds__(kThreads, 2) void sr_forward_kernel(
     const float *__restrict__ wt, const float *__restrict__ lowres,
-    const float *__restrict__ gbuf, float *__restrict__ out, int h, int w) {
+    const float *__restrict__ gbuf, float *__restrict__ out, int h, int w,
+    float *__restrict__ a1_out, float *__restrict__ a2_out) {
   __shared__ float in_s[kInP * kE0 * kE0];   // 32.0 KB
   __shared__ float a1_s[kC * kA1Stride];     // 43.0 KB
 
@@ -169,6 +173,15 @@ __global__ __launch_bounds__(kThreads, 2) void sr_forward_kernel(
     }
   }
   __syncthreads();
+  if (SAVE) {
+    for (int e = tid; e < kC * kT * kT; e += kThreads) {
+      const int o = e / (kT * kT), p = e % (kT * kT);
+      const int Y = oy0 + p / kT, X = ox0 + p % kT;
+      if (Y < H && X < W)
+        a1_out[((int64_t)f * kC + o) * plane_hi + (int64_t)Y * W + X] =
+            a1_s[o * kA1Stride + (p / kT + 1) * kE1 + p % kT + 1];
+    }
+  }
 
   // stage 2: conv2 + ReLU, the 1x1 head and the residual; one row per tile
   float a[kS2][2];
@@ -199,6 +212,18 @@ __global__ __launch_bounds__(kThreads, 2) void sr_forward_kernel(
       acc0 = mfma4(a[s][0], b, acc0);
       acc1 = mfma4(a[s][1], b, acc1);
     }
+    if (SAVE) {
+      const int Y = oy0 + ty, X = ox0 + col;
+      if (Y < H && X < W) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          float *dst = a2_out + ((int64_t)f * kC + 4 * grp + i) * plane_hi + (int64_t)Y * W + X;
+          dst[0] = fmaxf(acc0[i] + bias[0][i], 0.0f);
+          dst[16 * plane_hi] = fmaxf(acc1[i] + bias[1][i], 0.0f);
+        }
+      }
+      continue;
+    }
     float y[kSrOut];
 #pragma unroll
     for (int k = 0; k < kSrOut; ++k) {
@@ -222,6 +247,202 @@ __global__ __launch_bounds__(kThreads, 2) void sr_forward_kernel(
   }
 }
 
+// ---------------------------------------------------------------- backward
+// The weight gradient of sum(dy * out), after a recompute of the forward that
+// saves a1 = relu(z1) and a2 = relu(z2) (the masks z > 0 are a > 0):
+//   dz2 = [a2 > 0] W3^T dy                       per pixel
+//   dz1 = [a1 > 0] (conv2's transpose of dz2)    per pixel, 3x3 neighbourhood
+//   dW3 = sum dy a2^T, dW2 = sum dz2 (a1 window)^T, dW1 = sum dz1 (x window)^T
+// per 16 x 16 tile into fp32 partials, then one fp64 sum over the tiles in a
+// fixed order (deterministic).  fp32 vector arithmetic: training-side work.
+
+__global__ __launch_bounds__(kThreads) void sr_bwd_dz2_kernel(
+    const float *__restrict__ w, const float *__restrict__ dy, const float *__restrict__ a2,
+    float *__restrict__ dz2, int n, int64_t plane) {
+  const float *w3 = w + kC * kIn * 9 + kC + kC * kC * 9 + kC;
+  for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n * plane;
+       i += (int64_t)gridDim.x * kThreads) {
+    const int64_t f = i / plane, p = i % plane;
+    const float *d = dy + f * kSrOut * plane + p;
+    const float d0 = d[0], d1 = d[plane], d2 = d[2 * plane];
+#pragma unroll 4
+    for (int o = 0; o < kC; ++o) {
+      const int64_t at = (f * kC + o) * plane + p;
+      const float g = fmaf(w3[o], d0, fmaf(w3[kC + o], d1, w3[2 * kC + o] * d2));
+      dz2[at] = a2[at] > 0.0f ? g : 0.0f;
+    }
+  }
+}
+
+// dz1[c][Y][X] = [a1 > 0] sum_o sum_tap W2[o][c][tap] dz2[o][Y + 1 - ty][X + 1 - tx]
+__global__ __launch_bounds__(kThreads) void sr_bwd_dz1_kernel(
+    const float *__restrict__ w, const float *__restrict__ dz2, const float *__restrict__ a1,
+    float *__restrict__ dz1, int H, int W) {
+  const float *w2 = w + kC * kIn * 9 + kC;
+  const int X = blockIdx.x * 64 + threadIdx.x % 64, Y = blockIdx.y * 4 + threadIdx.x / 64;
+  const int f = blockIdx.z;
+  const int64_t plane = (int64_t)H * W;
+  const bool here = Y < H && X < W;
+  float acc[kC];
+#pragma unroll
+  for (int c = 0; c < kC; ++c) acc[c] = 0.0f;
+  for (int o = 0; o < kC; ++o) {
+    const float *src = dz2 + ((int64_t)f * kC + o) * plane;
+#pragma unroll
+    for (int t = 0; t < 9; ++t) {
+      const int yy = Y + 1 - t / 3, xx = X + 1 - t % 3;
+      const float v = (here && yy >= 0 && yy < H && xx >= 0 && xx < W)
+                          ? src[(int64_t)yy * W + xx] : 0.0f;
+#pragma unroll
+      for (int c = 0; c < kC; ++c) acc[c] = fmaf(w2[(o * kC + c) * 9 + t], v, acc[c]);
+    }
+  }
+  if (!here) return;
+#pragma unroll
+  for (int c = 0; c < kC; ++c) {
+    const int64_t at = ((int64_t)f * kC + c) * plane + (int64_t)Y * W + X;
+    dz1[at] = a1[at] > 0.0f ? acc[c] : 0.0f;
+  }
+}
+
+// Per-tile partial sums of every weight's gradient, in the packed order.
+constexpr int kWgLds = kC * kT * kT * 2 + kSrOut * kT * kT + kC * kE1 * kE1;  // floats
+
+__global__ __launch_bounds__(kThreads) void sr_bwd_wgrad_kernel(
+    const float *__restrict__ lowres, const float *__restrict__ gbuf, const float *__restrict__ dy,
+    const float *__restrict__ a1, const float *__restrict__ a2, const float *__restrict__ dz1,
+    const float *__restrict__ dz2, float *__restrict__ partial, int h, int w) {
+  __shared__ float buf[kWgLds];   // 110 KB
+  const int H = 2 * h, W = 2 * w;
+  const int f = blockIdx.z, oy0 = blockIdx.y * kT, ox0 = blockIdx.x * kT;
+  const int tid = threadIdx.x;
+  const int64_t plane = (int64_t)H * W, plane_lo = (int64_t)h * w;
+  float *out = partial + (((int64_t)f * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x) * kSrParams;
+  // phase A: the head and conv2.  dz_s [32][256], a2_s [32][256], dy_s [3][256]
+  // over the tile's own pixels and act_s [32][18][18] = a1 over the tile and a
+  // one-pixel halo; zero outside the image.
+  float *dz_s = buf, *a2_s = buf + kC * kT * kT, *dy_s = a2_s + kC * kT * kT;
+  float *act_s = dy_s + kSrOut * kT * kT;
+  for (int e = tid; e < kC * kT * kT; e += kThreads) {
+    const int o = e / (kT * kT), p = e % (kT * kT);
+    const int Y = oy0 + p / kT, X = ox0 + p % kT;
+    const bool in = Y < H && X < W;
+    const int64_t at = ((int64_t)f * kC + o) * plane + (int64_t)Y * W + X;
+    dz_s[e] = in ? dz2[at] : 0.0f;
+    a2_s[e] = in ? a2[at] : 0.0f;
+    if (o < kSrOut) dy_s[e] = in ? dy[((int64_t)f * kSrOut + o) * plane + (int64_t)Y * W + X] : 0.0f;
+  }
+  for (int e = tid; e < kC * kE1 * kE1; e += kThreads) {
+    const int c = e / (kE1 * kE1), r = (e / kE1) % kE1, q = e % kE1;
+    const int Y = oy0 - 1 + r, X = ox0 - 1 + q;
+    act_s[e] = (Y >= 0 && Y < H && X >= 0 && X < W)
+                   ? a1[((int64_t)f * kC + c) * plane + (int64_t)Y * W + X] : 0.0f;
+  }
+  __syncthreads();
+  constexpr int kOffW2 = kC * kIn * 9 + kC, kOffB2p = kOffW2 + kC * kC * 9;
+  constexpr int kOffW3p = kOffB2p + kC, kOffB3p = kOffW3p + kSrOut * kC;
+  // conv2: unit (o, c) -> its 9 taps
+  for (int u = tid; u < kC * kC; u += kThreads) {
+    const int o = u / kC, c = u % kC;
+    float acc[9] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+    for (int p = 0; p < kT * kT; ++p) {
+      const float d = dz_s[o * kT * kT + p];
+      const float *a = act_s + c * kE1 * kE1 + (p / kT) * kE1 + p % kT;
+#pragma unroll
+      for (int t = 0; t < 9; ++t) acc[t] = fmaf(d, a[(t / 3) * kE1 + t % 3], acc[t]);
+    }
+#pragma unroll
+    for (int t = 0; t < 9; ++t) out[kOffW2 + u * 9 + t] = acc[t];
+  }
+  // biases of conv2, the head and its bias
+  if (tid < kC + kSrOut * kC + kSrOut) {
+    float acc = 0.0f;
+    if (tid < kC) {
+      for (int p = 0; p < kT * kT; ++p) acc += dz_s[tid * kT * kT + p];
+      out[kOffB2p + tid] = acc;
+    } else if (tid < kC + kSrOut * kC) {
+      const int k = (tid - kC) / kC, o = (tid - kC) % kC;
+      for (int p = 0; p < kT * kT; ++p) acc = fmaf(dy_s[k * kT * kT + p], a2_s[o * kT * kT + p], acc);
+      out[kOffW3p + k * kC + o] = acc;
+    } else {
+      const int k = tid - kC - kSrOut * kC;
+      for (int p = 0; p < kT * kT; ++p) acc += dy_s[k * kT * kT + p];
+      out[kOffB3p + k] = acc;
+    }
+  }
+  __syncthreads();
+  // phase B: conv1.  dz_s [32][256] = dz1 over the tile's own pixels, x_s
+  // [17][18][18] = the input over the tile and a one-pixel halo.
+  float *x_s = buf + kC * kT * kT;
+  for (int e = tid; e < kC * kT * kT; e += kThreads) {
+    const int o = e / (kT * kT), p = e % (kT * kT);
+    const int Y = oy0 + p / kT, X = ox0 + p % kT;
+    dz_s[e] = (Y < H && X < W) ? dz1[((int64_t)f * kC + o) * plane + (int64_t)Y * W + X] : 0.0f;
+  }
+  const float *lo_f = lowres + (int64_t)f * 3 * plane_lo;
+  for (int e = tid; e < kIn * kE1 * kE1; e += kThreads) {
+    const int c = e / (kE1 * kE1), r = (e / kE1) % kE1, q = e % kE1;
+    const int Y = oy0 - 1 + r, X = ox0 - 1 + q;
+    float v = 0.0f;
+    if (Y >= 0 && Y < H && X >= 0 && X < W) {
+      if (c < 3) {
+        const int y0 = (Y >> 1) - ((Y & 1) ? 0 : 1), x0 = (X >> 1) - ((X & 1) ? 0 : 1);
+        const float fy = (Y & 1) ? 0.25f : 0.75f, fx = (X & 1) ? 0.25f : 0.75f;
+        const int ya = max(y0, 0), yb = min(y0 + 1, h - 1);
+        const int xa = max(x0, 0), xb = min(x0 + 1, w - 1);
+        const float *pl = lo_f + c * plane_lo;
+        const float top = (1.0f - fx) * pl[(int64_t)ya * w + xa] + fx * pl[(int64_t)ya * w + xb];
+        const float bot = (1.0f - fx) * pl[(int64_t)yb * w + xa] + fx * pl[(int64_t)yb * w + xb];
+        v = (1.0f - fy) * top + fy * bot;
+      } else {
+        v = gbuf[((int64_t)f * (kIn - 3) + c - 3) * plane + (int64_t)Y * W + X];
+      }
+    }
+    x_s[e] = v;
+  }
+  __syncthreads();
+  for (int u = tid; u < kC * kIn; u += kThreads) {
+    const int o = u / kIn, c = u % kIn;
+    float acc[9] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+    for (int p = 0; p < kT * kT; ++p) {
+      const float d = dz_s[o * kT * kT + p];
+      const float *a = x_s + c * kE1 * kE1 + (p / kT) * kE1 + p % kT;
+#pragma unroll
+      for (int t = 0; t < 9; ++t) acc[t] = fmaf(d, a[(t / 3) * kE1 + t % 3], acc[t]);
+    }
+#pragma unroll
+    for (int t = 0; t < 9; ++t) out[u * 9 + t] = acc[t];
+  }
+  if (tid < kC) {
+    float acc = 0.0f;
+    for (int p = 0; p < kT * kT; ++p) acc += dz_s[tid * kT * kT + p];
+    out[kC * kIn * 9 + tid] = acc;
+  }
+}
+
+// grad_w[i] = sum over tiles of partial[tile][i] in fp64, in two fixed-order
+// stages: groups of kRedGroup consecutive tiles, then the groups in order.
+constexpr int kRedGroup = 64;
+
+__global__ __launch_bounds__(kThreads) void sr_bwd_group_sum_kernel(
+    const float *__restrict__ partial, int tiles, double *__restrict__ groups) {
+  const int i = blockIdx.x * kThreads + threadIdx.x;
+  if (i >= kSrParams) return;
+  const int t0 = blockIdx.y * kRedGroup, t1 = min(t0 + kRedGroup, tiles);
+  double s = 0.0;
+  for (int t = t0; t < t1; ++t) s += (double)partial[(int64_t)t * kSrParams + i];
+  groups[(int64_t)blockIdx.y * kSrParams + i] = s;
+}
+
+__global__ __launch_bounds__(kThreads) void sr_bwd_reduce_kernel(const double *__restrict__ groups,
+                                                                 int ngroups, float *__restrict__ gw) {
+  const int i = blockIdx.x * kThreads + threadIdx.x;
+  if (i >= kSrParams) return;
+  double s = 0.0;
+  for (int g = 0; g < ngroups; ++g) s += groups[(int64_t)g * kSrParams + i];
+  gw[i] = (float)s;
+}
+
 }  // namespace
 
 hipError_t launch_sr_forward(const float *w, float *wt, const float *lowres, const float *gbuf,
@@ -232,8 +453,48 @@ hipError_t launch_sr_forward(const float *w, float *wt, const float *lowres, con
   if (e != hipSuccess) return e;
   const dim3 grid((unsigned)((2 * w_lo + kT - 1) / kT), (unsigned)((2 * h + kT - 1) / kT),
                   (unsigned)n);
-  hipLaunchKernelGGL(sr_forward_kernel, grid, dim3(kThreads), 0, stream, wt, lowres, gbuf, out, h,
-                     w_lo);
+  hipLaunchKernelGGL(sr_forward_kernel<false>, grid, dim3(kThreads), 0, stream, wt, lowres, gbuf,
+                     out, h, w_lo, nullptr, nullptr);
+  return hipGetLastError();
+}
+
+size_t sr_backward_workspace_bytes(int n, int h, int w) {
+  const int64_t px = (int64_t)n * 4 * h * w;
+  const int64_t tiles = (int64_t)n * ((2 * h + kT - 1) / kT) * ((2 * w + kT - 1) / kT);
+  const int64_t groups = (tiles + kRedGroup - 1) / kRedGroup;
+  return sizeof(float) * (size_t)(4 * kC * px + tiles * kSrParams) +
+         sizeof(double) * (size_t)(groups * kSrParams) + 8;
+}
+
+hipError_t launch_sr_backward(const float *w, float *wt, const float *lowres, const float *gbuf,
+                              const float *dy, float *gw, int n, int h, int w_lo, float *ws,
+                              hipStream_t stream) {
+  const int H = 2 * h, W = 2 * w_lo;
+  const int64_t plane = (int64_t)H * W, px = (int64_t)n * plane;
+  float *a1 = ws, *a2 = a1 + kC * px, *dz2 = a2 + kC * px, *dz1 = dz2 + kC * px;
+  float *partial = dz1 + kC * px;
+  hipLaunchKernelGGL(sr_relayout_kernel, dim3((kSrWtFloats + kThreads - 1) / kThreads),
+                     dim3(kThreads), 0, stream, w, wt);
+  const dim3 tiles((unsigned)((W + kT - 1) / kT), (unsigned)((H + kT - 1) / kT), (unsigned)n);
+  hipLaunchKernelGGL(sr_forward_kernel<true>, tiles, dim3(kThreads), 0, stream, wt, lowres, gbuf,
+                     nullptr, h, w_lo, a1, a2);
+  const int64_t pb = std::min<int64_t>((px + kThreads - 1) / kThreads, 4096);
+  hipLaunchKernelGGL(sr_bwd_dz2_kernel, dim3((unsigned)pb), dim3(kThreads), 0, stream, w, dy, a2,
+                     dz2, n, plane);
+  hipLaunchKernelGGL(sr_bwd_dz1_kernel, dim3((unsigned)((W + 63) / 64), (unsigned)((H + 3) / 4),
+                     (unsigned)n), dim3(kThreads), 0, stream, w, dz2, a1, dz1, H, W);
+  hipLaunchKernelGGL(sr_bwd_wgrad_kernel, tiles, dim3(kThreads), 0, stream, lowres, gbuf, dy, a1,
+                     a2, dz1, dz2, partial, h, w_lo);
+  const int ntiles = (int)(tiles.x * tiles.y * tiles.z);
+  const int ngroups = (ntiles + kRedGroup - 1) / kRedGroup;
+  // fp64 group sums after the fp32 partials, 8-byte aligned
+  const uintptr_t end = (uintptr_t)(partial + (int64_t)ntiles * kSrParams);
+  double *groups = (double *)((end + 7) & ~(uintptr_t)7);
+  const unsigned pblocks = (kSrParams + kThreads - 1) / kThreads;
+  hipLaunchKernelGGL(sr_bwd_group_sum_kernel, dim3(pblocks, (unsigned)ngroups), dim3(kThreads), 0,
+                     stream, partial, ntiles, groups);
+  hipLaunchKernelGGL(sr_bwd_reduce_kernel, dim3(pblocks), dim3(kThreads), 0, stream, groups,
+                     ngroups, gw);
   return hipGetLastError();
 }
 

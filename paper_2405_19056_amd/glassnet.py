@@ -62,6 +62,8 @@ _SIGS = {
     "glassnet_sr_num_params": (c_size_t, []),
     "glassnet_sr_forward": (c_int32, [c_void_p, c_void_p, c_int32, c_int32, c_int32, c_void_p,
                                       c_void_p, c_void_p, c_void_p]),
+    "glassnet_sr_backward": (c_int32, [c_void_p, c_void_p, c_int32, c_int32, c_int32, c_void_p,
+                                       c_void_p, c_void_p, c_void_p, c_void_p]),
     "glassnet_l1_loss": (c_int32, [c_void_p, c_void_p, c_void_p, c_uint64, c_void_p, c_void_p,
                                    c_void_p]),
     "glassnet_workspace_bytes": (c_int32, [c_void_p, POINTER(c_uint64)]),
@@ -270,6 +272,23 @@ class GlassNet:
                                          _dev_ptr(lowres, "lowres"), _dev_ptr(gbuf_hi, "gbuf_hi"),
                                          _dev_ptr(out, "out"), _stream(stream)))
         return out
+
+    def sr_backward(self, sr_w, lowres, gbuf_hi, grad_out, grad_w=None, stream=None):
+        """dL/d(sr_w) for dL/d(out) = grad_out (glassnet_sr_backward)."""
+        torch = _torch()
+        n, c, h, w = lowres.shape
+        if (c != NUM_OUT or tuple(gbuf_hi.shape) != (n, NUM_G, 2 * h, 2 * w)
+                or tuple(grad_out.shape) != (n, NUM_OUT, 2 * h, 2 * w)):
+            raise ValueError("lowres [n][3][h][w], gbuf_hi [n][14][2h][2w], grad_out [n][3][2h][2w]")
+        if sr_w.numel() != sr_num_params():
+            raise ValueError(f"sr_w must hold {sr_num_params()} floats")
+        if grad_w is None:
+            grad_w = torch.empty(sr_num_params(), dtype=torch.float32, device=lowres.device)
+        _check(lib().glassnet_sr_backward(self._h, _dev_ptr(sr_w, "sr_w"), n, h, w,
+                                          _dev_ptr(lowres, "lowres"), _dev_ptr(gbuf_hi, "gbuf_hi"),
+                                          _dev_ptr(grad_out, "grad_out"),
+                                          _dev_ptr(grad_w, "grad_w"), _stream(stream)))
+        return grad_w
 
     # -- optimiser
     def adam_state(self):

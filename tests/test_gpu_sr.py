@@ -96,3 +96,55 @@ def test_sr_argument_errors():
             net.sr_forward(w, lo, torch.zeros((1, 14, 8, 9), device="cuda:0"))
         torch.cuda.synchronize()
         assert not out.any()                    # nothing ran
+
+
+# ---------------------------------------------------------------- backward
+def _per_tensor_relF(g, ref):
+    out, o = {}, 0
+    for name, shp in oracle.sr_oracle.sr_shapes():
+        k = int(np.prod(shp))
+        out[name] = relF(g[o:o + k], ref[o:o + k])
+        o += k
+    return out
+
+
+@pytest.mark.parametrize("n,h,w", [(2, 19, 23), (1, 8, 8), (1, 1, 1), (16, 32, 32)])
+def test_sr_backward_matches_oracle(n, h, w):
+    """Against the FP64 oracle's gradient, every tensor within relF 1e-4 (fp32
+    sums over up to 2^16 pixels per weight, per-tile partials added in fp64);
+    repeated calls are bitwise equal."""
+    torch = torch_dev()
+    wts = synth.make_sr_weights(np.random.default_rng(h * 7 + w))
+    lo, g = synth.make_sr_inputs(n, h, w, seed=h + w + n)
+    dy = np.random.default_rng(n * h * w).normal(size=(n, 3, 2 * h, 2 * w)).astype(np.float32)
+    ref = oracle.sr_grad(wts, lo, g, dy)
+    with net64() as net:
+        args = (dev(wts), dev(lo), dev(g), dev(dy))
+        g1 = net.sr_backward(*args)
+        g2 = net.sr_backward(*args)
+        torch.cuda.synchronize()
+        g1, g2 = host(g1), host(g2)
+    errs = _per_tensor_relF(g1, ref)
+    log(f"sr backward {n}x{h}x{w}: " + ", ".join(f"{k} {v:.2e}" for k, v in errs.items()))
+    assert np.array_equal(g1, g2)
+    assert max(errs.values()) <= 1e-4, errs
+
+
+def test_sr_backward_argument_errors():
+    torch = torch_dev()
+    w = dev(synth.make_sr_weights(np.random.default_rng(0)))
+    lo = torch.zeros((1, 3, 4, 4), device="cuda:0")
+    g = torch.zeros((1, 14, 8, 8), device="cuda:0")
+    dy = torch.zeros((1, 3, 8, 8), device="cuda:0")
+    gw = torch.full((oracle.sr_n_params(),), 7.0, device="cuda:0")
+    with net64() as net:
+        L = lib()
+        for args in ((net._h, w.data_ptr(), 1, 4, 4, lo.data_ptr(), g.data_ptr(), dy.data_ptr(),
+                      w.data_ptr()),                                 # grad_w aliases sr_w
+                     (net._h, w.data_ptr(), 1, 4, 4, lo.data_ptr(), g.data_ptr(), dy.data_ptr(),
+                      None),
+                     (net._h, w.data_ptr(), 2, 1024, 1024, lo.data_ptr(), g.data_ptr(),
+                      dy.data_ptr(), gw.data_ptr())):                # beyond 2^22 output pixels
+            assert L.glassnet_sr_backward(*args, None) == GN_E_INVAL
+        torch.cuda.synchronize()
+        assert bool((gw == 7.0).all())          # nothing ran

@@ -227,7 +227,7 @@ gn_status glassnet_adam_step(gn_handle *h, const float *grad_w, float *state, si
  *   gbuf_hi  device [n][14][2 height][2 width], channels as in gn_frame.
  *   out      device [n][3][2 height][2 width]; must not overlap the inputs.
  * Independent of the handle's width and precision: the handle supplies the
- * device and a 61 KB copy of sr_w re-laid for the kernel (allocated on the
+ * device and a 97 KB copy of sr_w re-laid for the kernels (allocated on the
  * first call), which calls on different streams share: order them.
  * GN_E_INVAL for n outside 1..65535, height or width outside 1..2^18, NULL or
  * misaligned pointers, or out overlapping an input. */

@@ -158,7 +158,8 @@ constexpr int kSrParams = kSrWidth * kSrIn * 9 + kSrWidth + kSrWidth * kSrWidth 
 // Floats of the kernel's re-laid weight copy (conv1's K padded to 20 input
 // channels per tap).
 constexpr int kSrWtFloats = (9 * 20 / 4) * 2 * 64 + kSrWidth + (9 * kSrWidth / 4) * 2 * 64 +
-                            kSrWidth + kSrOut * kSrWidth + kSrOut;
+                            kSrWidth + kSrOut * kSrWidth + kSrOut +
+                            (9 * kSrWidth / 4) * 2 * 64;  // + conv2's transpose (backward)
 // w: packed weights (device, kSrParams floats); wt: kSrWtFloats floats of
 // device scratch for their re-laid copy; lowres [n][3][h][w], gbuf
 // [n][14][2h][2w], out [n][3][2h][2w].

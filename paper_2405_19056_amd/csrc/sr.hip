@@ -46,13 +46,15 @@ constexpr int kS1 = 9 * kInP / 4;     // conv1 K steps (45)
 constexpr int kS2 = 9 * kC / 4;       // conv2 K steps (72)
 constexpr int kN1 = (kP1 + 15) / 16;  // conv1 column tiles (21)
 // re-laid weights: A1 [kS1][2][64], b1 [32], A2 [kS2][2][64], b2 [32],
-// w3 [3][32], b3 [3]
+// w3 [3][32], b3 [3], then for the backward A2T [kS2][2][64]: conv2's
+// transpose (input and output channels swapped, taps mirrored)
 constexpr int kOffB1 = kS1 * 2 * 64;
 constexpr int kOffA2 = kOffB1 + kC;
 constexpr int kOffB2 = kOffA2 + kS2 * 2 * 64;
 constexpr int kOffW3 = kOffB2 + kC;
 constexpr int kOffB3 = kOffW3 + kSrOut * kC;
-static_assert(kOffB3 + kSrOut == kSrWtFloats, "re-laid weight size");
+constexpr int kOffA2T = kOffB3 + kSrOut;
+static_assert(kOffA2T + kS2 * 2 * 64 == kSrWtFloats, "re-laid weight size");
 static_assert(kA1Stride >= kP1 && kA1Stride % 64 == 16, "conv1 output channel stride");
 
 // packed weights -> MFMA operand order.  Fragment (s, mt, lane): output
@@ -79,8 +81,15 @@ __global__ __launch_bounds__(kThreads) void sr_relayout_kernel(const float *__re
     v = b2[i - kOffB2];
   } else if (i < kOffB3) {
     v = w3[i - kOffW3];
-  } else {
+  } else if (i < kOffA2T) {
     v = b3[i - kOffB3];
+  } else {
+    // fragment (s, mt, lane): input channel c = 16 mt + lane % 16 of conv2
+    // (the transpose's output), K index 4 s + lane / 16 = tap * C + o
+    const int j = i - kOffA2T;
+    const int s = j / 128, mt = (j / 64) % 2, l = j % 64;
+    const int k = 4 * s + l / 16, tap = k / kC, o = k % kC, c = 16 * mt + l % 16;
+    v = w2[(o * kC + c) * 9 + (8 - tap)];
   }
   wt[i] = v;
 }
@@ -274,34 +283,51 @@ __global__ __launch_bounds__(kThreads) void sr_bwd_dz2_kernel(
   }
 }
 
-// dz1[c][Y][X] = [a1 > 0] sum_o sum_tap W2[o][c][tap] dz2[o][Y + 1 - ty][X + 1 - tx]
-__global__ __launch_bounds__(kThreads) void sr_bwd_dz1_kernel(
-    const float *__restrict__ w, const float *__restrict__ dz2, const float *__restrict__ a1,
+// dz1[c][Y][X] = [a1 > 0] sum_o sum_tap W2[o][c][tap] dz2[o][Y + 1 - ty][X + 1 - tx]:
+// a zero-padded 3x3 correlation of dz2 with conv2's transpose (taps
+// mirrored), on the matrix cores exactly as the forward's conv2: dz2 over the
+// tile and a one-pixel halo in LDS, one output row per 16-pixel column tile.
+__global__ __launch_bounds__(kThreads, 2) void sr_bwd_dz1_kernel(
+    const float *__restrict__ wt, const float *__restrict__ dz2, const float *__restrict__ a1,
     float *__restrict__ dz1, int H, int W) {
-  const float *w2 = w + kC * kIn * 9 + kC;
-  const int X = blockIdx.x * 64 + threadIdx.x % 64, Y = blockIdx.y * 4 + threadIdx.x / 64;
-  const int f = blockIdx.z;
+  __shared__ float d_s[kC * kA1Stride];
+  const int f = blockIdx.z, oy0 = blockIdx.y * kT, ox0 = blockIdx.x * kT;
+  const int tid = threadIdx.x, lane = tid % 64, wave = tid / 64;
+  const int col = lane % 16, grp = lane / 16;
   const int64_t plane = (int64_t)H * W;
-  const bool here = Y < H && X < W;
-  float acc[kC];
-#pragma unroll
-  for (int c = 0; c < kC; ++c) acc[c] = 0.0f;
-  for (int o = 0; o < kC; ++o) {
-    const float *src = dz2 + ((int64_t)f * kC + o) * plane;
-#pragma unroll
-    for (int t = 0; t < 9; ++t) {
-      const int yy = Y + 1 - t / 3, xx = X + 1 - t % 3;
-      const float v = (here && yy >= 0 && yy < H && xx >= 0 && xx < W)
-                          ? src[(int64_t)yy * W + xx] : 0.0f;
-#pragma unroll
-      for (int c = 0; c < kC; ++c) acc[c] = fmaf(w2[(o * kC + c) * 9 + t], v, acc[c]);
-    }
+  for (int e = tid; e < kC * kP1; e += kThreads) {
+    const int o = e / kP1, q = e % kP1;
+    const int Y = oy0 - 1 + q / kE1, X = ox0 - 1 + q % kE1;
+    d_s[o * kA1Stride + q] = (Y >= 0 && Y < H && X >= 0 && X < W)
+                                 ? dz2[((int64_t)f * kC + o) * plane + (int64_t)Y * W + X]
+                                 : 0.0f;
   }
-  if (!here) return;
+  float a[kS2][2];
 #pragma unroll
-  for (int c = 0; c < kC; ++c) {
-    const int64_t at = ((int64_t)f * kC + c) * plane + (int64_t)Y * W + X;
-    dz1[at] = a1[at] > 0.0f ? acc[c] : 0.0f;
+  for (int s = 0; s < kS2; ++s) {
+    a[s][0] = wt[kOffA2T + (2 * s) * 64 + lane];
+    a[s][1] = wt[kOffA2T + (2 * s + 1) * 64 + lane];
+  }
+  __syncthreads();
+  for (int ty = wave; ty < kT; ty += kThreads / 64) {
+    const float *src = d_s + grp * kA1Stride + ty * kE1 + col;
+    f32x4 acc0 = {0.0f, 0.0f, 0.0f, 0.0f}, acc1 = acc0;
+#pragma unroll
+    for (int s = 0; s < kS2; ++s) {
+      const int tap = s / (kC / 4), c4 = 4 * (s % (kC / 4));
+      const float b = src[c4 * kA1Stride + (tap / 3) * kE1 + tap % 3];
+      acc0 = mfma4(a[s][0], b, acc0);
+      acc1 = mfma4(a[s][1], b, acc1);
+    }
+    const int Y = oy0 + ty, X = ox0 + col;
+    if (Y < H && X < W) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int64_t at = ((int64_t)f * kC + 4 * grp + i) * plane + (int64_t)Y * W + X;
+        dz1[at] = a1[at] > 0.0f ? acc0[i] : 0.0f;
+        dz1[at + 16 * plane] = a1[at + 16 * plane] > 0.0f ? acc1[i] : 0.0f;
+      }
+    }
   }
 }
 
@@ -481,8 +507,7 @@ hipError_t launch_sr_backward(const float *w, float *wt, const float *lowres, co
   const int64_t pb = std::min<int64_t>((px + kThreads - 1) / kThreads, 4096);
   hipLaunchKernelGGL(sr_bwd_dz2_kernel, dim3((unsigned)pb), dim3(kThreads), 0, stream, w, dy, a2,
                      dz2, n, plane);
-  hipLaunchKernelGGL(sr_bwd_dz1_kernel, dim3((unsigned)((W + 63) / 64), (unsigned)((H + 3) / 4),
-                     (unsigned)n), dim3(kThreads), 0, stream, w, dz2, a1, dz1, H, W);
+  hipLaunchKernelGGL(sr_bwd_dz1_kernel, tiles, dim3(kThreads), 0, stream, wt, dz2, a1, dz1, H, W);
   hipLaunchKernelGGL(sr_bwd_wgrad_kernel, tiles, dim3(kThreads), 0, stream, lowres, gbuf, dy, a1,
                      a2, dz1, dz2, partial, h, w_lo);
   const int ntiles = (int)(tiles.x * tiles.y * tiles.z);

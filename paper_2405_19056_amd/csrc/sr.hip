@@ -332,82 +332,124 @@ __global__ __launch_bounds__(kThreads, 2) void sr_bwd_dz1_kernel(
 }
 
 // Per-tile partial sums of every weight's gradient, in the packed order.
-constexpr int kWgLds = kC * kT * kT * 2 + kSrOut * kT * kT + kC * kE1 * kE1;  // floats
+// The two conv gradients are GEMMs over the tile's 256 pixels on the matrix
+// cores: dW[o][(c, tap)] = sum_p dz[o][p] act[c][p + tap], with dz (32 x 256)
+// as the 16-row operand, held in registers, and the activation windows
+// (columns (c, tap) in packed order, c * 9 + tap) gathered from LDS.
+constexpr int kDzStride = kT * kT + 4;   // LDS row of dz: rows land in distinct banks
+constexpr int kWgLds = kC * kDzStride + kC * kP1;  // floats: two workgroups per CU
 
-__global__ __launch_bounds__(kThreads) void sr_bwd_wgrad_kernel(
+// dz_s rows (32 x 256, stride kDzStride) against the windows of act_s
+// (channels of kP1 floats, the tile plus a one-pixel halo): columns
+// n = c * 9 + tap < ncol, written to out[o * ncol + n].
+__device__ __forceinline__ void wgrad_gemm(const float *dz_s, const float *act_s, int ncol,
+                                           float *__restrict__ out, int lane, int wave) {
+  const int col = lane % 16, grp = lane / 16;
+  float a[kT * kT / 4][2];
+#pragma unroll
+  for (int s = 0; s < kT * kT / 4; ++s) {
+    a[s][0] = dz_s[col * kDzStride + 4 * s + grp];
+    a[s][1] = dz_s[(16 + col) * kDzStride + 4 * s + grp];
+  }
+  for (int j = wave; j * 16 < ncol; j += kThreads / 64) {
+    const int n = min(16 * j + col, ncol - 1);
+    const int c = n / 9, tap = n % 9;
+    const float *src = act_s + c * kP1 + (tap / 3) * kE1 + tap % 3 + grp;
+    f32x4 acc0 = {0.0f, 0.0f, 0.0f, 0.0f}, acc1 = acc0;
+#pragma unroll
+    for (int s = 0; s < kT * kT / 4; ++s) {
+      // pixel p = 4 s + grp: row s / 4, column 4 (s % 4) + grp
+      const float b = src[(s / 4) * kE1 + 4 * (s % 4)];
+      acc0 = mfma4(a[s][0], b, acc0);
+      acc1 = mfma4(a[s][1], b, acc1);
+    }
+    if (16 * j + col < ncol) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        out[(4 * grp + i) * ncol + 16 * j + col] = acc0[i];
+        out[(16 + 4 * grp + i) * ncol + 16 * j + col] = acc1[i];
+      }
+    }
+  }
+}
+
+__global__ __launch_bounds__(kThreads, 2) void sr_bwd_wgrad_kernel(
     const float *__restrict__ lowres, const float *__restrict__ gbuf, const float *__restrict__ dy,
     const float *__restrict__ a1, const float *__restrict__ a2, const float *__restrict__ dz1,
     const float *__restrict__ dz2, float *__restrict__ partial, int h, int w) {
-  __shared__ float buf[kWgLds];   // 110 KB
+  __shared__ float buf[kWgLds];   // 74.8 KB
   const int H = 2 * h, W = 2 * w;
   const int f = blockIdx.z, oy0 = blockIdx.y * kT, ox0 = blockIdx.x * kT;
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, lane = tid % 64, wave = tid / 64;
   const int64_t plane = (int64_t)H * W, plane_lo = (int64_t)h * w;
   float *out = partial + (((int64_t)f * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x) * kSrParams;
-  // phase A: the head and conv2.  dz_s [32][256], a2_s [32][256], dy_s [3][256]
-  // over the tile's own pixels and act_s [32][18][18] = a1 over the tile and a
-  // one-pixel halo; zero outside the image.
-  float *dz_s = buf, *a2_s = buf + kC * kT * kT, *dy_s = a2_s + kC * kT * kT;
-  float *act_s = dy_s + kSrOut * kT * kT;
+  constexpr int kOffW2 = kC * kIn * 9 + kC, kOffB2p = kOffW2 + kC * kC * 9;
+  constexpr int kOffW3p = kOffB2p + kC, kOffB3p = kOffW3p + kSrOut * kC;
+  float *dz_s = buf;
+  // phase 0: the head.  a2_s [32][256] and dy_s [3][256] over the tile's own
+  // pixels (zero outside the image)
+  {
+    float *a2_s = buf, *dy_s = buf + kC * kT * kT;
+    for (int e = tid; e < kC * kT * kT; e += kThreads) {
+      const int o = e / (kT * kT), p = e % (kT * kT);
+      const int Y = oy0 + p / kT, X = ox0 + p % kT;
+      const bool in = Y < H && X < W;
+      a2_s[e] = in ? a2[((int64_t)f * kC + o) * plane + (int64_t)Y * W + X] : 0.0f;
+      if (o < kSrOut)
+        dy_s[e] = in ? dy[((int64_t)f * kSrOut + o) * plane + (int64_t)Y * W + X] : 0.0f;
+    }
+    __syncthreads();
+    if (tid < kSrOut * kC + kSrOut) {
+      float acc = 0.0f;
+      if (tid < kSrOut * kC) {
+        const int k = tid / kC, o = tid % kC;
+        for (int p = 0; p < kT * kT; ++p)
+          acc = fmaf(dy_s[k * kT * kT + p], a2_s[o * kT * kT + p], acc);
+        out[kOffW3p + tid] = acc;
+      } else {
+        const int k = tid - kSrOut * kC;
+        for (int p = 0; p < kT * kT; ++p) acc += dy_s[k * kT * kT + p];
+        out[kOffB3p + k] = acc;
+      }
+    }
+    __syncthreads();
+  }
+  // phase A: conv2.  dz_s [32][256] = dz2 over the tile's own pixels and
+  // act_s [32][18][18] = a1 over the tile and a one-pixel halo; zero outside
+  // the image.
+  float *act_s = buf + kC * kDzStride;
   for (int e = tid; e < kC * kT * kT; e += kThreads) {
     const int o = e / (kT * kT), p = e % (kT * kT);
     const int Y = oy0 + p / kT, X = ox0 + p % kT;
-    const bool in = Y < H && X < W;
-    const int64_t at = ((int64_t)f * kC + o) * plane + (int64_t)Y * W + X;
-    dz_s[e] = in ? dz2[at] : 0.0f;
-    a2_s[e] = in ? a2[at] : 0.0f;
-    if (o < kSrOut) dy_s[e] = in ? dy[((int64_t)f * kSrOut + o) * plane + (int64_t)Y * W + X] : 0.0f;
+    dz_s[o * kDzStride + p] =
+        (Y < H && X < W) ? dz2[((int64_t)f * kC + o) * plane + (int64_t)Y * W + X] : 0.0f;
   }
-  for (int e = tid; e < kC * kE1 * kE1; e += kThreads) {
-    const int c = e / (kE1 * kE1), r = (e / kE1) % kE1, q = e % kE1;
+  for (int e = tid; e < kC * kP1; e += kThreads) {
+    const int c = e / kP1, r = (e / kE1) % kE1, q = e % kE1;
     const int Y = oy0 - 1 + r, X = ox0 - 1 + q;
     act_s[e] = (Y >= 0 && Y < H && X >= 0 && X < W)
                    ? a1[((int64_t)f * kC + c) * plane + (int64_t)Y * W + X] : 0.0f;
   }
   __syncthreads();
-  constexpr int kOffW2 = kC * kIn * 9 + kC, kOffB2p = kOffW2 + kC * kC * 9;
-  constexpr int kOffW3p = kOffB2p + kC, kOffB3p = kOffW3p + kSrOut * kC;
-  // conv2: unit (o, c) -> its 9 taps
-  for (int u = tid; u < kC * kC; u += kThreads) {
-    const int o = u / kC, c = u % kC;
-    float acc[9] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
-    for (int p = 0; p < kT * kT; ++p) {
-      const float d = dz_s[o * kT * kT + p];
-      const float *a = act_s + c * kE1 * kE1 + (p / kT) * kE1 + p % kT;
-#pragma unroll
-      for (int t = 0; t < 9; ++t) acc[t] = fmaf(d, a[(t / 3) * kE1 + t % 3], acc[t]);
-    }
-#pragma unroll
-    for (int t = 0; t < 9; ++t) out[kOffW2 + u * 9 + t] = acc[t];
-  }
-  // biases of conv2, the head and its bias
-  if (tid < kC + kSrOut * kC + kSrOut) {
+  wgrad_gemm(dz_s, act_s, kC * 9, out + kOffW2, lane, wave);
+  if (tid < kC) {
     float acc = 0.0f;
-    if (tid < kC) {
-      for (int p = 0; p < kT * kT; ++p) acc += dz_s[tid * kT * kT + p];
-      out[kOffB2p + tid] = acc;
-    } else if (tid < kC + kSrOut * kC) {
-      const int k = (tid - kC) / kC, o = (tid - kC) % kC;
-      for (int p = 0; p < kT * kT; ++p) acc = fmaf(dy_s[k * kT * kT + p], a2_s[o * kT * kT + p], acc);
-      out[kOffW3p + k * kC + o] = acc;
-    } else {
-      const int k = tid - kC - kSrOut * kC;
-      for (int p = 0; p < kT * kT; ++p) acc += dy_s[k * kT * kT + p];
-      out[kOffB3p + k] = acc;
-    }
+    for (int p = 0; p < kT * kT; ++p) acc += dz_s[tid * kDzStride + p];
+    out[kOffB2p + tid] = acc;
   }
   __syncthreads();
-  // phase B: conv1.  dz_s [32][256] = dz1 over the tile's own pixels, x_s
-  // [17][18][18] = the input over the tile and a one-pixel halo.
-  float *x_s = buf + kC * kT * kT;
+  // phase B: conv1.  dz_s = dz1 over the tile's own pixels, x_s [17][18][18]
+  // = the input over the tile and a one-pixel halo.
+  float *x_s = buf + kC * kDzStride;
   for (int e = tid; e < kC * kT * kT; e += kThreads) {
     const int o = e / (kT * kT), p = e % (kT * kT);
     const int Y = oy0 + p / kT, X = ox0 + p % kT;
-    dz_s[e] = (Y < H && X < W) ? dz1[((int64_t)f * kC + o) * plane + (int64_t)Y * W + X] : 0.0f;
+    dz_s[o * kDzStride + p] =
+        (Y < H && X < W) ? dz1[((int64_t)f * kC + o) * plane + (int64_t)Y * W + X] : 0.0f;
   }
   const float *lo_f = lowres + (int64_t)f * 3 * plane_lo;
-  for (int e = tid; e < kIn * kE1 * kE1; e += kThreads) {
-    const int c = e / (kE1 * kE1), r = (e / kE1) % kE1, q = e % kE1;
+  for (int e = tid; e < kIn * kP1; e += kThreads) {
+    const int c = e / kP1, r = (e / kE1) % kE1, q = e % kE1;
     const int Y = oy0 - 1 + r, X = ox0 - 1 + q;
     float v = 0.0f;
     if (Y >= 0 && Y < H && X >= 0 && X < W) {
@@ -427,21 +469,10 @@ __global__ __launch_bounds__(kThreads) void sr_bwd_wgrad_kernel(
     x_s[e] = v;
   }
   __syncthreads();
-  for (int u = tid; u < kC * kIn; u += kThreads) {
-    const int o = u / kIn, c = u % kIn;
-    float acc[9] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
-    for (int p = 0; p < kT * kT; ++p) {
-      const float d = dz_s[o * kT * kT + p];
-      const float *a = x_s + c * kE1 * kE1 + (p / kT) * kE1 + p % kT;
-#pragma unroll
-      for (int t = 0; t < 9; ++t) acc[t] = fmaf(d, a[(t / 3) * kE1 + t % 3], acc[t]);
-    }
-#pragma unroll
-    for (int t = 0; t < 9; ++t) out[u * 9 + t] = acc[t];
-  }
+  wgrad_gemm(dz_s, x_s, kIn * 9, out, lane, wave);
   if (tid < kC) {
     float acc = 0.0f;
-    for (int p = 0; p < kT * kT; ++p) acc += dz_s[tid * kT * kT + p];
+    for (int p = 0; p < kT * kT; ++p) acc += dz_s[tid * kDzStride + p];
     out[kC * kIn * 9 + tid] = acc;
   }
 }

@@ -471,6 +471,19 @@ def sr_phase(W, pool, precision, torch, steps=100, k=8):
         e1.record(stream)
         torch.cuda.synchronize()
         t_bwd = e0.elapsed_time(e1) / 1e3 / 5
+        # a whole training step of it: forward, L1 + DSSIM, gradient, Adam
+        from paper_2405_19056_amd.autograd import train_step_sr
+        w_tr = srw.clone()
+        st_tr = torch.zeros(2 * w_tr.numel(), device="cuda:0")
+        tgt_b = torch.rand((16, 3, 256, 256), device="cuda:0")
+        train_step_sr(net, w_tr, st_tr, lo_b, g_b, tgt_b, 1, stream=stream)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for i in range(5):
+            train_step_sr(net, w_tr, st_tr, lo_b, g_b, tgt_b, i + 2, stream=stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        t_train = e0.elapsed_time(e1) / 1e3 / 5
     px = 512 * 512
     return {"workload": f"forward 256^2 K={k} + x2 super-sampling to 512^2",
             "sr_ms": t_sr * 1e3, "sr_pixels_per_s": px / t_sr,
@@ -479,7 +492,8 @@ def sr_phase(W, pool, precision, torch, steps=100, k=8):
             "sr_frac_fp32_mfma_peak": SR_FLOP_PER_PX * px / t_sr / 1e12 / PEAK_TFLOPS["fp32"],
             "forward_256_ms": t_fwd * 1e3, "pipeline_ms": t_both * 1e3,
             "pipeline_frames_per_s": 1.0 / t_both,
-            "sr_backward_16x256sq_ms": t_bwd * 1e3}
+            "sr_backward_16x256sq_ms": t_bwd * 1e3,
+            "sr_train_step_16x256sq_ms": t_train * 1e3}
 
 
 def copy_probe():

@@ -251,6 +251,16 @@ gn_status glassnet_sr_backward(gn_handle *h, const float *sr_w, int32_t n, int32
                                int32_t width, const float *lowres, const float *gbuf_hi,
                                const float *grad_out, float *grad_w, void *hip_stream);
 
+/* The same Adam step on a caller-owned fp32 device vector w of n floats
+ * (e.g. the super-sampling network's weights, trained apart from GlassNet in
+ * Sec. 4.1), with the update rule of glassnet_adam_step; state is 2 n floats
+ * (m then v, zero before step 1).  The handle supplies the device.  GN_E_INVAL
+ * for n outside 1..2^31, step < 1, hyperparameters as in glassnet_adam_step,
+ * or overlapping buffers. */
+gn_status glassnet_adam_update(gn_handle *h, float *w, const float *grad_w, float *state,
+                               size_t n, int32_t step, float lr, float beta1, float beta2,
+                               float eps, float weight_decay, void *hip_stream);
+
 /* L1 term of Sec. 3.5 over count elements: *loss = mean |out - target| and
  * grad_out = sign(out - target) / count (0 where equal).  All device.
  * grad_out may be NULL. */

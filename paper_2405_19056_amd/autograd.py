@@ -79,3 +79,23 @@ def train_step_adam(net: GlassNet, gbuf, layers, scene, target, state, step, lr=
     gw = net.backward(gbuf, layers, scene, dy, grad_w=grad_w, stream=stream)
     net.adam_step(gw, state, step, lr=lr, weight_decay=weight_decay, stream=stream)
     return losses, gw
+
+
+def train_step_sr(net: GlassNet, sr_w, state, lowres, gbuf_hi, target, step, lr=1e-4,
+                  weight_decay=0.0, grad_w=None, dssim=True, stream=None):
+    """One training step of the x2 super-sampling network on its own (Sec. 4.1
+    trains it apart from GlassNet) with the loss of Sec. 3.5: forward, L1 +
+    DSSIM (dssim=False: L1 alone), its weight gradient and an Adam step on the
+    caller's weight vector sr_w.  `state` is a zeroed device tensor of
+    2 x sr_w.numel() floats; `step` counts from 1.  Returns (losses, grad_w):
+    losses is a device tensor [L1, DSSIM]."""
+    y = net.sr_forward(sr_w, lowres, gbuf_hi, stream=stream)
+    dy = torch.empty_like(y)
+    losses = torch.zeros(2, dtype=torch.float32, device=y.device)
+    net.l1_loss(y, target, loss=losses[0], grad_out=dy, stream=stream)
+    if dssim:
+        net.dssim_loss(y, target, loss=losses[1], grad_out=dy, accumulate=True, stream=stream)
+    gw = net.sr_backward(sr_w, lowres, gbuf_hi, dy, grad_w=grad_w, stream=stream)
+    net.adam_update(sr_w, gw, state, step, lr=lr, weight_decay=weight_decay, stream=stream)
+    return losses, gw
+

@@ -648,4 +648,26 @@ gn_status glassnet_adam_step(gn_handle *h, const float *grad_w, float *state, si
   return gn_prepare_weights(h, s);
 }
 
+gn_status glassnet_adam_update(gn_handle *h, float *w, const float *grad_w, float *state,
+                               size_t n, int32_t step, float lr, float beta1, float beta2,
+                               float eps, float weight_decay, void *hip_stream) {
+  gn_status st = precheck(h);
+  if (st != GN_OK) return st;
+  if (n < 1 || n > ((size_t)1 << 31)) return fail(GN_E_INVAL, "n must be in 1..2^31, got %zu", n);
+  if (!w || !grad_w || !state || !aligned4(w) || !aligned4(grad_w) || !aligned4(state))
+    return fail(GN_E_INVAL, "w, grad_w and state must be non-NULL 4-byte aligned device pointers");
+  if (step < 1) return fail(GN_E_INVAL, "step %d must be >= 1", step);
+  if (!(lr >= 0.0f && lr < 1e30f) || !(beta1 >= 0.0f && beta1 < 1.0f) ||
+      !(beta2 >= 0.0f && beta2 < 1.0f) || !(eps > 0.0f && eps < 1e30f) ||
+      !(weight_decay >= 0.0f && weight_decay < 1e30f))
+    return fail(GN_E_INVAL, "need lr >= 0, 0 <= beta1, beta2 < 1, eps > 0, weight_decay >= 0");
+  const size_t b = sizeof(float) * n;
+  if (overlaps(state, 2 * b, grad_w, b) || overlaps(state, 2 * b, w, b) || overlaps(grad_w, b, w, b))
+    return fail(GN_E_INVAL, "w, grad_w and state must not overlap");
+  DeviceGuard dg(h->device);
+  hipError_t e = gn::launch_adam(w, grad_w, state, state + n, (int64_t)n, step, lr, beta1, beta2,
+                                 eps, weight_decay, (hipStream_t)hip_stream);
+  return gn_check_device(h, e, "adam launch");
+}
+
 }  // extern "C"

@@ -64,6 +64,8 @@ _SIGS = {
                                       c_void_p, c_void_p, c_void_p]),
     "glassnet_sr_backward": (c_int32, [c_void_p, c_void_p, c_int32, c_int32, c_int32, c_void_p,
                                        c_void_p, c_void_p, c_void_p, c_void_p]),
+    "glassnet_adam_update": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_size_t, c_int32,
+                                       c_float, c_float, c_float, c_float, c_float, c_void_p]),
     "glassnet_l1_loss": (c_int32, [c_void_p, c_void_p, c_void_p, c_uint64, c_void_p, c_void_p,
                                    c_void_p]),
     "glassnet_workspace_bytes": (c_int32, [c_void_p, POINTER(c_uint64)]),
@@ -305,6 +307,17 @@ class GlassNet:
                                         _dev_ptr(state, "state"), self.nparams, int(step),
                                         float(lr), float(betas[0]), float(betas[1]), float(eps),
                                         float(weight_decay), _stream(stream)))
+
+    def adam_update(self, w, grad_w, state, step, lr=1e-4, betas=(0.9, 0.999), eps=1e-8,
+                    weight_decay=0.0, stream=None):
+        """The Adam step on a caller-owned device vector w (glassnet_adam_update)."""
+        n = w.numel()
+        if grad_w.numel() != n or state.numel() != 2 * n:
+            raise ValueError("grad_w must hold n and state 2 n floats")
+        _check(lib().glassnet_adam_update(self._h, _dev_ptr(w, "w"), _dev_ptr(grad_w, "grad_w"),
+                                          _dev_ptr(state, "state"), n, int(step), float(lr),
+                                          float(betas[0]), float(betas[1]), float(eps),
+                                          float(weight_decay), _stream(stream)))
 
     # -- object streaming
     def stream_state_bytes(self, n, h, w) -> int:

@@ -13,7 +13,7 @@ import pytest
 
 import oracle
 from paper_2405_19056_amd import synth
-from paper_2405_19056_amd.glassnet import GlassNet, GN_E_INVAL, lib
+from paper_2405_19056_amd.glassnet import GlassNet, GlassNetError, GN_E_INVAL, lib
 
 from gpu_util import dev, host, log, relF, torch_dev
 
@@ -148,3 +148,62 @@ def test_sr_backward_argument_errors():
             assert L.glassnet_sr_backward(*args, None) == GN_E_INVAL
         torch.cuda.synchronize()
         assert bool((gw == 7.0).all())          # nothing ran
+
+
+# ---------------------------------------------------------------- training
+def test_adam_update_matches_oracle():
+    """glassnet_adam_update on a caller-owned vector: three steps against the
+    oracle's Adam (hyperparameters as the fp32 values that cross the ABI)."""
+    torch = torch_dev()
+    n = oracle.sr_n_params()
+    rng = np.random.default_rng(41)
+    f32 = lambda x: float(np.float32(x))  # noqa: E731
+    lr, b1, b2, eps, wd = f32(1e-3), f32(0.9), f32(0.999), f32(1e-8), f32(1e-4)
+    w0 = synth.make_sr_weights(rng)
+    w, m, v = w0.astype(np.float64), np.zeros(n), np.zeros(n)
+    with net64() as net:
+        wd_dev, state = dev(w0), torch.zeros(2 * n, device="cuda:0")
+        for t in range(1, 4):
+            g = (rng.normal(size=n) * 10.0 ** rng.uniform(-4, 0, size=n)).astype(np.float32)
+            net.adam_update(wd_dev, dev(g), state, t, lr=lr, betas=(b1, b2), eps=eps,
+                            weight_decay=wd)
+            w, m, v = oracle.adam_step(w, g, m, v, t, lr=lr, beta1=b1, beta2=b2, eps=eps,
+                                       weight_decay=wd)
+        torch.cuda.synchronize()
+        assert float(np.max(np.abs(host(wd_dev) - w))) <= 1e-6
+        st = host(state)
+        assert relF(st[:n], m) <= 1e-5 and relF(st[n:], v) <= 1e-5
+        with pytest.raises(GlassNetError) as e:                 # gradient inside the state
+            net.adam_update(wd_dev, state[:n], state, 1)
+        assert e.value.status == GN_E_INVAL
+
+
+def test_sr_train_step():
+    """One step of autograd.train_step_sr (L1 + DSSIM, weight gradient, Adam):
+    both loss terms and the gradient against the oracle at the same weights,
+    and the weights moved by exactly the Adam step of that gradient."""
+    from paper_2405_19056_amd.autograd import train_step_sr
+    torch = torch_dev()
+    n, h, w = 2, 16, 20
+    w0 = synth.make_sr_weights(np.random.default_rng(51))
+    lo, g = synth.make_sr_inputs(n, h, w, seed=51)
+    y_ref = oracle.sr_forward(w0, lo, g)
+    tgt = (y_ref + 0.05 * np.random.default_rng(52).normal(size=y_ref.shape)).astype(np.float32)
+    l1, dl1 = oracle.l1_loss(y_ref, tgt)
+    ds, dds = oracle.dssim_loss(y_ref, tgt)
+    gref = oracle.sr_grad(w0, lo, g, dl1 + dds)
+    lr = float(np.float32(1e-3))
+    with net64() as net:
+        srw = dev(w0)
+        state = torch.zeros(2 * w0.size, device="cuda:0")
+        losses, gw = train_step_sr(net, srw, state, dev(lo), dev(g), dev(tgt), 1, lr=lr)
+        torch.cuda.synchronize()
+        losses, gw, w1 = host(losses), host(gw), host(srw)
+    log(f"sr train step: L1 {losses[0]:.6f} vs {l1:.6f}, DSSIM {losses[1]:.6f} vs {ds:.6f}, "
+        f"grad relF {relF(gw, gref):.2e}")
+    assert abs(losses[0] - l1) <= 1e-6 * max(1.0, abs(l1))
+    assert abs(losses[1] - ds) <= 2e-6
+    assert relF(gw, gref) <= 1e-4
+    want, _, _ = oracle.adam_step(w0.astype(np.float64), gw, np.zeros(w0.size), np.zeros(w0.size),
+                                  1, lr=lr)
+    assert float(np.max(np.abs(w1 - want))) <= 1e-6

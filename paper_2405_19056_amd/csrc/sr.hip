@@ -98,6 +98,22 @@ __device__ __forceinline__ f32x4 mfma4(float a, float b, f32x4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
+// Channel c of the render upsampled x2 at output pixel (Y, X), inside the
+// image: source position (Y + 0.5) / 2 - 0.5, i.e. rows Y/2 - 1 and Y/2 at
+// weights 1/4 and 3/4 for even Y, rows (Y-1)/2 and (Y+1)/2 at 3/4 and 1/4 for
+// odd Y (clamped into the image); likewise for columns.
+__device__ __forceinline__ float upsampled(const float *__restrict__ lo_f, int h, int w, int c,
+                                           int Y, int X) {
+  const int y0 = (Y >> 1) - ((Y & 1) ? 0 : 1), x0 = (X >> 1) - ((X & 1) ? 0 : 1);
+  const float fy = (Y & 1) ? 0.25f : 0.75f, fx = (X & 1) ? 0.25f : 0.75f;
+  const int ya = max(y0, 0), yb = min(y0 + 1, h - 1);
+  const int xa = max(x0, 0), xb = min(x0 + 1, w - 1);
+  const float *p = lo_f + (int64_t)c * h * w;
+  const float top = (1.0f - fx) * p[(int64_t)ya * w + xa] + fx * p[(int64_t)ya * w + xb];
+  const float bot = (1.0f - fx) * p[(int64_t)yb * w + xa] + fx * p[(int64_t)yb * w + xb];
+  return (1.0f - fy) * top + fy * bot;
+}
+
 // SAVE (the backward's recompute): instead of the output, write relu(z1) and
 // relu(z2) of the tile's own pixels to a1_out, a2_out [n][32][2h][2w].
 template <bool SAVE>
@@ -125,17 +141,7 @@ __global__ __launch_bounds__(kThreads, 2) void sr_forward_kernel(
     float v = 0.0f;
     if (c < kIn && Y >= 0 && Y < H && X >= 0 && X < W) {
       if (c < 3) {
-        // source position (Y + 0.5) / 2 - 0.5: rows Y/2 - 1 and Y/2 at
-        // weights 1/4 and 3/4 for even Y, rows (Y-1)/2 and (Y+1)/2 at 3/4 and
-        // 1/4 for odd Y (clamped into the image); likewise for columns
-        const int y0 = (Y >> 1) - ((Y & 1) ? 0 : 1), x0 = (X >> 1) - ((X & 1) ? 0 : 1);
-        const float fy = (Y & 1) ? 0.25f : 0.75f, fx = (X & 1) ? 0.25f : 0.75f;
-        const int ya = max(y0, 0), yb = min(y0 + 1, h - 1);
-        const int xa = max(x0, 0), xb = min(x0 + 1, w - 1);
-        const float *p = lo_f + c * plane_lo;
-        const float top = (1.0f - fx) * p[(int64_t)ya * w + xa] + fx * p[(int64_t)ya * w + xb];
-        const float bot = (1.0f - fx) * p[(int64_t)yb * w + xa] + fx * p[(int64_t)yb * w + xb];
-        v = (1.0f - fy) * top + fy * bot;
+        v = upsampled(lo_f, h, w, c, Y, X);
       } else {
         v = g_f[(c - 3) * plane_hi + (int64_t)Y * W + X];
       }
@@ -454,14 +460,7 @@ __global__ __launch_bounds__(kThreads, 2) void sr_bwd_wgrad_kernel(
     float v = 0.0f;
     if (Y >= 0 && Y < H && X >= 0 && X < W) {
       if (c < 3) {
-        const int y0 = (Y >> 1) - ((Y & 1) ? 0 : 1), x0 = (X >> 1) - ((X & 1) ? 0 : 1);
-        const float fy = (Y & 1) ? 0.25f : 0.75f, fx = (X & 1) ? 0.25f : 0.75f;
-        const int ya = max(y0, 0), yb = min(y0 + 1, h - 1);
-        const int xa = max(x0, 0), xb = min(x0 + 1, w - 1);
-        const float *pl = lo_f + c * plane_lo;
-        const float top = (1.0f - fx) * pl[(int64_t)ya * w + xa] + fx * pl[(int64_t)ya * w + xb];
-        const float bot = (1.0f - fx) * pl[(int64_t)yb * w + xa] + fx * pl[(int64_t)yb * w + xb];
-        v = (1.0f - fy) * top + fy * bot;
+        v = upsampled(lo_f, h, w, c, Y, X);
       } else {
         v = gbuf[((int64_t)f * (kIn - 3) + c - 3) * plane + (int64_t)Y * W + X];
       }

@@ -31,7 +31,8 @@ def run(net, w, lo, g):
     return host(y)
 
 
-@pytest.mark.parametrize("n,h,w", [(2, 19, 23), (1, 8, 8), (1, 1, 1), (1, 3, 17), (3, 9, 5)])
+@pytest.mark.parametrize("n,h,w", [(2, 19, 23), (1, 8, 8), (1, 1, 1), (1, 3, 17), (3, 9, 5),
+                                   (64, 8, 8), (1, 2, 300)])
 def test_sr_matches_oracle(n, h, w):
     wts = synth.make_sr_weights(np.random.default_rng(h * 100 + w))
     lo, g = synth.make_sr_inputs(n, h, w, seed=h * w + n)
@@ -108,7 +109,8 @@ def _per_tensor_relF(g, ref):
     return out
 
 
-@pytest.mark.parametrize("n,h,w", [(2, 19, 23), (1, 8, 8), (1, 1, 1), (16, 32, 32)])
+@pytest.mark.parametrize("n,h,w", [(2, 19, 23), (1, 8, 8), (1, 1, 1), (16, 32, 32), (40, 4, 6),
+                                   (1, 3, 200)])
 def test_sr_backward_matches_oracle(n, h, w):
     """Against the FP64 oracle's gradient, every tensor within relF 1e-4 (fp32
     sums over up to 2^16 pixels per weight, per-tile partials added in fp64);

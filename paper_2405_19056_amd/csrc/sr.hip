@@ -347,10 +347,11 @@ constexpr int kDzStride = kT * kT + 4;   // LDS row of dz: rows land in distinct
 constexpr int kWgLds = kC * kDzStride + kC * kP1;  // floats: two workgroups per CU
 
 // dz_s rows (32 x 256, stride kDzStride) against the windows of act_s
-// (channels of kP1 floats, the tile plus a one-pixel halo): columns
-// n = c * 9 + tap < ncol, written to out[o * ncol + n].
+// (channels of kP1 floats, the tile plus a one-pixel halo), added to acc:
+// columns n = c * 9 + tap < ncol, column tile j = wave + 4 jj of 16.
+template <int NJ>
 __device__ __forceinline__ void wgrad_gemm(const float *dz_s, const float *act_s, int ncol,
-                                           float *__restrict__ out, int lane, int wave) {
+                                           f32x4 (&acc)[NJ][2], int lane, int wave) {
   const int col = lane % 16, grp = lane / 16;
   float a[kT * kT / 4][2];
 #pragma unroll
@@ -358,122 +359,140 @@ __device__ __forceinline__ void wgrad_gemm(const float *dz_s, const float *act_s
     a[s][0] = dz_s[col * kDzStride + 4 * s + grp];
     a[s][1] = dz_s[(16 + col) * kDzStride + 4 * s + grp];
   }
-  for (int j = wave; j * 16 < ncol; j += kThreads / 64) {
+#pragma unroll
+  for (int jj = 0; jj < NJ; ++jj) {
+    const int j = wave + (kThreads / 64) * jj;
+    if (16 * j >= ncol) continue;
     const int n = min(16 * j + col, ncol - 1);
     const int c = n / 9, tap = n % 9;
     const float *src = act_s + c * kP1 + (tap / 3) * kE1 + tap % 3 + grp;
-    f32x4 acc0 = {0.0f, 0.0f, 0.0f, 0.0f}, acc1 = acc0;
 #pragma unroll
     for (int s = 0; s < kT * kT / 4; ++s) {
       // pixel p = 4 s + grp: row s / 4, column 4 (s % 4) + grp
       const float b = src[(s / 4) * kE1 + 4 * (s % 4)];
-      acc0 = mfma4(a[s][0], b, acc0);
-      acc1 = mfma4(a[s][1], b, acc1);
-    }
-    if (16 * j + col < ncol) {
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        out[(4 * grp + i) * ncol + 16 * j + col] = acc0[i];
-        out[(16 + 4 * grp + i) * ncol + 16 * j + col] = acc1[i];
-      }
+      acc[jj][0] = mfma4(a[s][0], b, acc[jj][0]);
+      acc[jj][1] = mfma4(a[s][1], b, acc[jj][1]);
     }
   }
 }
 
+template <int NJ>
+__device__ __forceinline__ void wgrad_store(const f32x4 (&acc)[NJ][2], int ncol,
+                                            float *__restrict__ out, int lane, int wave) {
+  const int col = lane % 16, grp = lane / 16;
+#pragma unroll
+  for (int jj = 0; jj < NJ; ++jj) {
+    const int n = 16 * (wave + (kThreads / 64) * jj) + col;
+    if (n >= ncol) continue;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      out[(4 * grp + i) * ncol + n] = acc[jj][0][i];
+      out[(16 + 4 * grp + i) * ncol + n] = acc[jj][1][i];
+    }
+  }
+}
+
+constexpr int kNJ2 = (kC * 9 / 16 + 3) / 4;    // conv2 column tiles per wave (5)
+constexpr int kNJ1 = (kIn * 9 + 15) / 16;      // conv1 column tiles (10)
+constexpr int kNJ1w = (kNJ1 + 3) / 4;          // per wave (3)
+
+// Persistent: workgroup b takes tiles b, b + gridDim.x, ... (in that order)
+// and keeps its running sums of every weight gradient in registers, written
+// once to partial[b].
 __global__ __launch_bounds__(kThreads, 2) void sr_bwd_wgrad_kernel(
     const float *__restrict__ lowres, const float *__restrict__ gbuf, const float *__restrict__ dy,
     const float *__restrict__ a1, const float *__restrict__ a2, const float *__restrict__ dz1,
-    const float *__restrict__ dz2, float *__restrict__ partial, int h, int w) {
+    const float *__restrict__ dz2, float *__restrict__ partial, int n, int h, int w) {
   __shared__ float buf[kWgLds];   // 74.8 KB
   const int H = 2 * h, W = 2 * w;
-  const int f = blockIdx.z, oy0 = blockIdx.y * kT, ox0 = blockIdx.x * kT;
+  const int tx_n = (W + kT - 1) / kT, ty_n = (H + kT - 1) / kT;
+  const int ntiles = n * tx_n * ty_n;
   const int tid = threadIdx.x, lane = tid % 64, wave = tid / 64;
   const int64_t plane = (int64_t)H * W, plane_lo = (int64_t)h * w;
-  float *out = partial + (((int64_t)f * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x) * kSrParams;
   constexpr int kOffW2 = kC * kIn * 9 + kC, kOffB2p = kOffW2 + kC * kC * 9;
   constexpr int kOffW3p = kOffB2p + kC, kOffB3p = kOffW3p + kSrOut * kC;
+  f32x4 acc2[kNJ2][2] = {}, acc1[kNJ1w][2] = {};
+  float acc_head = 0.0f, acc_b = 0.0f, acc_b1 = 0.0f;   // per thread: head / b2 / b1
   float *dz_s = buf;
-  // phase 0: the head.  a2_s [32][256] and dy_s [3][256] over the tile's own
-  // pixels (zero outside the image)
-  {
-    float *a2_s = buf, *dy_s = buf + kC * kT * kT;
-    for (int e = tid; e < kC * kT * kT; e += kThreads) {
-      const int o = e / (kT * kT), p = e % (kT * kT);
-      const int Y = oy0 + p / kT, X = ox0 + p % kT;
-      const bool in = Y < H && X < W;
-      a2_s[e] = in ? a2[((int64_t)f * kC + o) * plane + (int64_t)Y * W + X] : 0.0f;
-      if (o < kSrOut)
-        dy_s[e] = in ? dy[((int64_t)f * kSrOut + o) * plane + (int64_t)Y * W + X] : 0.0f;
-    }
-    __syncthreads();
-    if (tid < kSrOut * kC + kSrOut) {
-      float acc = 0.0f;
+  for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    const int f = t / (tx_n * ty_n), oy0 = ((t / tx_n) % ty_n) * kT, ox0 = (t % tx_n) * kT;
+    // phase 0: the head.  a2_s [32][256] and dy_s [3][256] over the tile's
+    // own pixels (zero outside the image)
+    {
+      float *a2_s = buf, *dy_s = buf + kC * kT * kT;
+      for (int e = tid; e < kC * kT * kT; e += kThreads) {
+        const int o = e / (kT * kT), p = e % (kT * kT);
+        const int Y = oy0 + p / kT, X = ox0 + p % kT;
+        const bool in = Y < H && X < W;
+        a2_s[e] = in ? a2[((int64_t)f * kC + o) * plane + (int64_t)Y * W + X] : 0.0f;
+        if (o < kSrOut)
+          dy_s[e] = in ? dy[((int64_t)f * kSrOut + o) * plane + (int64_t)Y * W + X] : 0.0f;
+      }
+      __syncthreads();
       if (tid < kSrOut * kC) {
         const int k = tid / kC, o = tid % kC;
         for (int p = 0; p < kT * kT; ++p)
-          acc = fmaf(dy_s[k * kT * kT + p], a2_s[o * kT * kT + p], acc);
-        out[kOffW3p + tid] = acc;
-      } else {
+          acc_head = fmaf(dy_s[k * kT * kT + p], a2_s[o * kT * kT + p], acc_head);
+      } else if (tid < kSrOut * kC + kSrOut) {
         const int k = tid - kSrOut * kC;
-        for (int p = 0; p < kT * kT; ++p) acc += dy_s[k * kT * kT + p];
-        out[kOffB3p + k] = acc;
+        for (int p = 0; p < kT * kT; ++p) acc_head += dy_s[k * kT * kT + p];
       }
+      __syncthreads();
+    }
+    // phase A: conv2.  dz_s [32][256] = dz2 over the tile's own pixels and
+    // act_s [32][18][18] = a1 over the tile and a one-pixel halo; zero
+    // outside the image.
+    float *act_s = buf + kC * kDzStride;
+    for (int e = tid; e < kC * kT * kT; e += kThreads) {
+      const int o = e / (kT * kT), p = e % (kT * kT);
+      const int Y = oy0 + p / kT, X = ox0 + p % kT;
+      dz_s[o * kDzStride + p] =
+          (Y < H && X < W) ? dz2[((int64_t)f * kC + o) * plane + (int64_t)Y * W + X] : 0.0f;
+    }
+    for (int e = tid; e < kC * kP1; e += kThreads) {
+      const int c = e / kP1, r = (e / kE1) % kE1, q = e % kE1;
+      const int Y = oy0 - 1 + r, X = ox0 - 1 + q;
+      act_s[e] = (Y >= 0 && Y < H && X >= 0 && X < W)
+                     ? a1[((int64_t)f * kC + c) * plane + (int64_t)Y * W + X] : 0.0f;
     }
     __syncthreads();
-  }
-  // phase A: conv2.  dz_s [32][256] = dz2 over the tile's own pixels and
-  // act_s [32][18][18] = a1 over the tile and a one-pixel halo; zero outside
-  // the image.
-  float *act_s = buf + kC * kDzStride;
-  for (int e = tid; e < kC * kT * kT; e += kThreads) {
-    const int o = e / (kT * kT), p = e % (kT * kT);
-    const int Y = oy0 + p / kT, X = ox0 + p % kT;
-    dz_s[o * kDzStride + p] =
-        (Y < H && X < W) ? dz2[((int64_t)f * kC + o) * plane + (int64_t)Y * W + X] : 0.0f;
-  }
-  for (int e = tid; e < kC * kP1; e += kThreads) {
-    const int c = e / kP1, r = (e / kE1) % kE1, q = e % kE1;
-    const int Y = oy0 - 1 + r, X = ox0 - 1 + q;
-    act_s[e] = (Y >= 0 && Y < H && X >= 0 && X < W)
-                   ? a1[((int64_t)f * kC + c) * plane + (int64_t)Y * W + X] : 0.0f;
-  }
-  __syncthreads();
-  wgrad_gemm(dz_s, act_s, kC * 9, out + kOffW2, lane, wave);
-  if (tid < kC) {
-    float acc = 0.0f;
-    for (int p = 0; p < kT * kT; ++p) acc += dz_s[tid * kDzStride + p];
-    out[kOffB2p + tid] = acc;
-  }
-  __syncthreads();
-  // phase B: conv1.  dz_s = dz1 over the tile's own pixels, x_s [17][18][18]
-  // = the input over the tile and a one-pixel halo.
-  float *x_s = buf + kC * kDzStride;
-  for (int e = tid; e < kC * kT * kT; e += kThreads) {
-    const int o = e / (kT * kT), p = e % (kT * kT);
-    const int Y = oy0 + p / kT, X = ox0 + p % kT;
-    dz_s[o * kDzStride + p] =
-        (Y < H && X < W) ? dz1[((int64_t)f * kC + o) * plane + (int64_t)Y * W + X] : 0.0f;
-  }
-  const float *lo_f = lowres + (int64_t)f * 3 * plane_lo;
-  for (int e = tid; e < kIn * kP1; e += kThreads) {
-    const int c = e / kP1, r = (e / kE1) % kE1, q = e % kE1;
-    const int Y = oy0 - 1 + r, X = ox0 - 1 + q;
-    float v = 0.0f;
-    if (Y >= 0 && Y < H && X >= 0 && X < W) {
-      if (c < 3) {
-        v = upsampled(lo_f, h, w, c, Y, X);
-      } else {
-        v = gbuf[((int64_t)f * (kIn - 3) + c - 3) * plane + (int64_t)Y * W + X];
-      }
+    wgrad_gemm<kNJ2>(dz_s, act_s, kC * 9, acc2, lane, wave);
+    if (tid < kC)
+      for (int p = 0; p < kT * kT; ++p) acc_b += dz_s[tid * kDzStride + p];
+    __syncthreads();
+    // phase B: conv1.  dz_s = dz1 over the tile's own pixels, x_s
+    // [17][18][18] = the input over the tile and a one-pixel halo.
+    float *x_s = buf + kC * kDzStride;
+    for (int e = tid; e < kC * kT * kT; e += kThreads) {
+      const int o = e / (kT * kT), p = e % (kT * kT);
+      const int Y = oy0 + p / kT, X = ox0 + p % kT;
+      dz_s[o * kDzStride + p] =
+          (Y < H && X < W) ? dz1[((int64_t)f * kC + o) * plane + (int64_t)Y * W + X] : 0.0f;
     }
-    x_s[e] = v;
+    const float *lo_f = lowres + (int64_t)f * 3 * plane_lo;
+    for (int e = tid; e < kIn * kP1; e += kThreads) {
+      const int c = e / kP1, r = (e / kE1) % kE1, q = e % kE1;
+      const int Y = oy0 - 1 + r, X = ox0 - 1 + q;
+      float v = 0.0f;
+      if (Y >= 0 && Y < H && X >= 0 && X < W)
+        v = c < 3 ? upsampled(lo_f, h, w, c, Y, X)
+                  : gbuf[((int64_t)f * (kIn - 3) + c - 3) * plane + (int64_t)Y * W + X];
+      x_s[e] = v;
+    }
+    __syncthreads();
+    wgrad_gemm<kNJ1w>(dz_s, x_s, kIn * 9, acc1, lane, wave);
+    if (tid < kC)
+      for (int p = 0; p < kT * kT; ++p) acc_b1 += dz_s[tid * kDzStride + p];
+    __syncthreads();
   }
-  __syncthreads();
-  wgrad_gemm(dz_s, x_s, kIn * 9, out, lane, wave);
+  float *out = partial + (int64_t)blockIdx.x * kSrParams;
+  wgrad_store<kNJ2>(acc2, kC * 9, out + kOffW2, lane, wave);
+  wgrad_store<kNJ1w>(acc1, kIn * 9, out, lane, wave);
+  if (tid < kSrOut * kC) out[kOffW3p + tid] = acc_head;
+  else if (tid < kSrOut * kC + kSrOut) out[kOffB3p + tid - kSrOut * kC] = acc_head;
   if (tid < kC) {
-    float acc = 0.0f;
-    for (int p = 0; p < kT * kT; ++p) acc += dz_s[tid * kDzStride + p];
-    out[kC * kIn * 9 + tid] = acc;
+    out[kOffB2p + tid] = acc_b;
+    out[kC * kIn * 9 + tid] = acc_b1;
   }
 }
 
@@ -539,16 +558,18 @@ hipError_t launch_sr_backward(const float *w, float *wt, const float *lowres, co
   hipLaunchKernelGGL(sr_bwd_dz2_kernel, dim3((unsigned)pb), dim3(kThreads), 0, stream, w, dy, a2,
                      dz2, n, plane);
   hipLaunchKernelGGL(sr_bwd_dz1_kernel, tiles, dim3(kThreads), 0, stream, wt, dz2, a1, dz1, H, W);
-  hipLaunchKernelGGL(sr_bwd_wgrad_kernel, tiles, dim3(kThreads), 0, stream, lowres, gbuf, dy, a1,
-                     a2, dz1, dz2, partial, h, w_lo);
   const int ntiles = (int)(tiles.x * tiles.y * tiles.z);
-  const int ngroups = (ntiles + kRedGroup - 1) / kRedGroup;
+  // two persistent workgroups per CU; each writes one row of partial sums
+  const int nblocks = std::min(ntiles, 512);
+  hipLaunchKernelGGL(sr_bwd_wgrad_kernel, dim3((unsigned)nblocks), dim3(kThreads), 0, stream,
+                     lowres, gbuf, dy, a1, a2, dz1, dz2, partial, n, h, w_lo);
+  const int ngroups = (nblocks + kRedGroup - 1) / kRedGroup;
   // fp64 group sums after the fp32 partials, 8-byte aligned
   const uintptr_t end = (uintptr_t)(partial + (int64_t)ntiles * kSrParams);
   double *groups = (double *)((end + 7) & ~(uintptr_t)7);
   const unsigned pblocks = (kSrParams + kThreads - 1) / kThreads;
   hipLaunchKernelGGL(sr_bwd_group_sum_kernel, dim3(pblocks, (unsigned)ngroups), dim3(kThreads), 0,
-                     stream, partial, ntiles, groups);
+                     stream, partial, nblocks, groups);
   hipLaunchKernelGGL(sr_bwd_reduce_kernel, dim3(pblocks), dim3(kThreads), 0, stream, groups,
                      ngroups, gw);
   return hipGetLastError();

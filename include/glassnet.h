@@ -245,8 +245,8 @@ gn_status glassnet_sr_forward(gn_handle *h, const float *sr_w, int32_t n, int32_
  * added in fp64 in a fixed order: the result is deterministic.  At most 2^22
  * output pixels per call (n 4 height width) and height, width <= 2^16
  * (GN_E_INVAL beyond, or for NULL, misaligned or aliasing pointers).  The
- * handle keeps a workspace of about 570 bytes per output pixel (grown on a
- * larger call, after the stream's earlier work). */
+ * handle keeps a workspace of 512 bytes per output pixel plus at most 35 MB
+ * (grown on a larger call, after the stream's earlier work). */
 gn_status glassnet_sr_backward(gn_handle *h, const float *sr_w, int32_t n, int32_t height,
                                int32_t width, const float *lowres, const float *gbuf_hi,
                                const float *grad_out, float *grad_w, void *hip_stream);

@@ -534,11 +534,19 @@ hipError_t launch_sr_forward(const float *w, float *wt, const float *lowres, con
   return hipGetLastError();
 }
 
+// Persistent workgroups of the weight-gradient kernel (two per CU).
+constexpr int kWgBlocks = 512;
+
+static int64_t wgrad_blocks(int n, int h, int w) {
+  const int64_t tiles = (int64_t)n * ((2 * h + kT - 1) / kT) * ((2 * w + kT - 1) / kT);
+  return std::min<int64_t>(tiles, kWgBlocks);
+}
+
 size_t sr_backward_workspace_bytes(int n, int h, int w) {
   const int64_t px = (int64_t)n * 4 * h * w;
-  const int64_t tiles = (int64_t)n * ((2 * h + kT - 1) / kT) * ((2 * w + kT - 1) / kT);
-  const int64_t groups = (tiles + kRedGroup - 1) / kRedGroup;
-  return sizeof(float) * (size_t)(4 * kC * px + tiles * kSrParams) +
+  const int64_t rows = wgrad_blocks(n, h, w);
+  const int64_t groups = (rows + kRedGroup - 1) / kRedGroup;
+  return sizeof(float) * (size_t)(4 * kC * px + rows * kSrParams) +
          sizeof(double) * (size_t)(groups * kSrParams) + 8;
 }
 
@@ -558,14 +566,13 @@ hipError_t launch_sr_backward(const float *w, float *wt, const float *lowres, co
   hipLaunchKernelGGL(sr_bwd_dz2_kernel, dim3((unsigned)pb), dim3(kThreads), 0, stream, w, dy, a2,
                      dz2, n, plane);
   hipLaunchKernelGGL(sr_bwd_dz1_kernel, tiles, dim3(kThreads), 0, stream, wt, dz2, a1, dz1, H, W);
-  const int ntiles = (int)(tiles.x * tiles.y * tiles.z);
-  // two persistent workgroups per CU; each writes one row of partial sums
-  const int nblocks = std::min(ntiles, 512);
+  // persistent workgroups; each writes one row of partial sums
+  const int nblocks = (int)wgrad_blocks(n, h, w_lo);
   hipLaunchKernelGGL(sr_bwd_wgrad_kernel, dim3((unsigned)nblocks), dim3(kThreads), 0, stream,
                      lowres, gbuf, dy, a1, a2, dz1, dz2, partial, n, h, w_lo);
   const int ngroups = (nblocks + kRedGroup - 1) / kRedGroup;
   // fp64 group sums after the fp32 partials, 8-byte aligned
-  const uintptr_t end = (uintptr_t)(partial + (int64_t)ntiles * kSrParams);
+  const uintptr_t end = (uintptr_t)(partial + (int64_t)nblocks * kSrParams);
   double *groups = (double *)((end + 7) & ~(uintptr_t)7);
   const unsigned pblocks = (kSrParams + kThreads - 1) / kThreads;
   hipLaunchKernelGGL(sr_bwd_group_sum_kernel, dim3(pblocks, (unsigned)ngroups), dim3(kThreads), 0,

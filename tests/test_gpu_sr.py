@@ -209,3 +209,29 @@ def test_sr_train_step():
     want, _, _ = oracle.adam_step(w0.astype(np.float64), gw, np.zeros(w0.size), np.zeros(w0.size),
                                   1, lr=lr)
     assert float(np.max(np.abs(w1 - want))) <= 1e-6
+
+
+def test_sr_backward_max_size_patch():
+    """At the limit of 2^22 output pixels (4 renders of 512^2 -> 1024^2), with
+    dL/d(out) non-zero on one 16 x 16 patch only: the weight gradient depends
+    on the inputs within a few pixels of the patch, so the oracle's gradient on
+    a 48 x 48 crop around it (crop edges 16 pixels from the patch, even-aligned
+    for the upsample) is the exact answer; the call is also deterministic."""
+    torch = torch_dev()
+    n, h, w = 4, 512, 512
+    wts = synth.make_sr_weights(np.random.default_rng(61))
+    lo, g = synth.make_sr_inputs(n, h, w, seed=61)
+    dy = np.zeros((n, 3, 2 * h, 2 * w), np.float32)
+    dy[2, :, 496:512, 736:752] = np.random.default_rng(62).normal(size=(3, 16, 16))
+    ref = oracle.sr_grad(wts, lo[2:3, :, 240:264, 360:384], g[2:3, :, 480:528, 720:768],
+                         dy[2:3, :, 480:528, 720:768])
+    with net64() as net:
+        args = (dev(wts), dev(lo), dev(g), dev(dy))
+        g1 = net.sr_backward(*args)
+        g2 = net.sr_backward(*args)
+        torch.cuda.synchronize()
+        g1, g2 = host(g1), host(g2)
+    errs = _per_tensor_relF(g1, ref)
+    log("sr backward 4x512^2 patch: " + ", ".join(f"{k} {v:.2e}" for k, v in errs.items()))
+    assert np.array_equal(g1, g2)
+    assert max(errs.values()) <= 1e-4, errs

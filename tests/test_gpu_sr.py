@@ -235,3 +235,25 @@ def test_sr_backward_max_size_patch():
     log("sr backward 4x512^2 patch: " + ", ".join(f"{k} {v:.2e}" for k, v in errs.items()))
     assert np.array_equal(g1, g2)
     assert max(errs.values()) <= 1e-4, errs
+
+
+def test_sr_large_frame_sampled_crops():
+    """A 1024 x 576 render (the largest serving frame) to 2048 x 1152: the
+    oracle on 40 x 40 output crops at the corners and inside the frame; each
+    output depends on inputs within 3 pixels, so the crop's inner part away
+    from its cut edges is exact (image edges are real edges)."""
+    wts = synth.make_sr_weights(np.random.default_rng(71))
+    lo, g = synth.make_sr_inputs(1, 576, 1024, seed=71)
+    with net64() as net:
+        y = run(net, wts, lo, g)
+    H, W = 1152, 2048
+    for (Y0, X0) in ((0, 0), (H - 40, W - 40), (0, W - 40), (H - 40, 0), (560, 1000), (336, 1608)):
+        ref = oracle.sr_forward(wts, lo[:, :, Y0 // 2:(Y0 + 40) // 2, X0 // 2:(X0 + 40) // 2],
+                                g[:, :, Y0:Y0 + 40, X0:X0 + 40])
+        # keep 6 pixels from every cut edge (not from the image's own edges)
+        r0 = 0 if Y0 == 0 else 6
+        r1 = 40 if Y0 + 40 == H else 34
+        c0 = 0 if X0 == 0 else 6
+        c1 = 40 if X0 + 40 == W else 34
+        got = y[:, :, Y0 + r0:Y0 + r1, X0 + c0:X0 + c1]
+        assert relF(got, ref[:, :, r0:r1, c0:c1]) <= 1e-5, (Y0, X0)

@@ -148,3 +148,68 @@ def test_some_pin_catches_the_planted_mistake(name):
 def test_pins_pass_without_mistakes():
     for t in PIN_TESTS:
         t()
+
+
+# ---------------------------------------------------------------- gradient
+GRAD_PIN_TESTS = [
+    lambda: pins.test_grad_from_dy_equals_l1_gradient_at_its_seed(),
+    lambda: pins.test_grad_from_dy_matches_central_differences("mean"),
+    lambda: pins.test_gradient_matches_central_differences("sum"),
+]
+
+
+def _mlp_bwd_variant(layers, cache, dout, grads, *, mask2=True, bias1_from=None):
+    (A1, _), (A2, _), (A3, _) = layers
+    x, z1, a1, z2, a2 = cache
+    grads[2][0] += dout @ a2.T
+    grads[2][1] += dout.sum(axis=1)
+    d = (A3.T @ dout) * ((z2 > 0.0) if mask2 else 1.0)
+    grads[1][0] += d @ a1.T
+    grads[1][1] += d.sum(axis=1)
+    d2 = d
+    d = (A2.T @ d) * (z1 > 0.0)
+    grads[0][0] += d @ x.T
+    grads[0][1] += (d2 if bias1_from == "layer2" else d).sum(axis=1)
+    return A1.T @ d
+
+
+def _backprop_dy(transform):
+    old = go._backprop
+
+    def f(*a, dy=None, **k):
+        return old(*a, dy=None if dy is None else transform(np.asarray(dy)), **k)
+    return f
+
+
+GRAD_MUTATIONS = {
+    "ReLU mask of the second hidden layer dropped": (
+        "_mlp_bwd", lambda *a: _mlp_bwd_variant(*a, mask2=False)),
+    "first bias gradient from the second layer's delta": (
+        "_mlp_bwd", lambda *a: _mlp_bwd_variant(*a, bias1_from="layer2")),
+    "dy with its sign flipped": ("_backprop", _backprop_dy(lambda d: -d)),
+    "dy channels reversed": ("_backprop", _backprop_dy(lambda d: d[:, ::-1])),
+    "dy image transposed": ("_backprop", _backprop_dy(lambda d: np.swapaxes(d, 2, 3)
+                                                      .reshape(d.shape))),
+}
+
+
+@pytest.mark.parametrize("name", sorted(GRAD_MUTATIONS))
+def test_some_gradient_pin_catches_the_planted_mistake(name):
+    attr, fn = GRAD_MUTATIONS[name]
+    old = getattr(go, attr)
+    setattr(go, attr, fn)
+    caught = []
+    try:
+        for t in GRAD_PIN_TESTS:
+            try:
+                t()
+            except (AssertionError, ValueError):
+                caught.append(t)
+    finally:
+        setattr(go, attr, old)
+    assert caught, f"no gradient pin caught: {name}"
+
+
+def test_gradient_pins_pass_without_mistakes():
+    for t in GRAD_PIN_TESTS:
+        t()

@@ -390,3 +390,82 @@ def test_param_count_formula():
     for W in (1, 8, 64, 128):
         assert oracle.n_params(W) == 11 * W * W + 59 * W + 3 == synth.num_params(W)
     assert math.isclose(oracle.n_params(128) * 4 / 1024, 733.51171875)
+
+
+# ------------------------------------------- the vector-Jacobian product
+# grad_from_dy is the checker of every GPU backward test; its dy branch is
+# pinned here to the L1 branch, to finite differences of sum(dy * y) and to
+# linearity in dy.
+def test_grad_from_dy_equals_l1_gradient_at_its_seed():
+    """With dL/dy = sign(y - t) / N (the L1 term's derivative, Sec. 3.5) the
+    vector-Jacobian product is the L1 gradient itself."""
+    W = 8
+    wts, fr = tiny(n=2, h=3, w=4, k=3, W=W, seed=5, alpha_mode="uniform_count")
+    t = np.random.default_rng(5).normal(size=(2, 3, 3, 4))
+    for pool in ("mean", "sum"):
+        y = oracle.forward(wts, W, fr.gbuf, fr.layers, fr.scene, pool=pool)
+        dy = np.sign(y - t) / y.size
+        g_l1 = oracle.grad(wts, W, fr.gbuf, fr.layers, fr.scene, t, pool=pool)[1]
+        g_dy = oracle.grad_from_dy(wts, W, fr.gbuf, fr.layers, fr.scene, dy, pool=pool)
+        assert np.max(np.abs(g_dy - g_l1)) <= 1e-15 * max(1.0, np.max(np.abs(g_l1)))
+        assert np.any(g_dy != 0)
+
+
+def test_grad_from_dy_is_linear_in_dy():
+    W = 8
+    wts, fr = tiny(n=1, h=4, w=3, k=2, W=W, seed=6, alpha_mode="uniform_count")
+    rng = np.random.default_rng(6)
+    d1, d2 = rng.normal(size=(2, 1, 3, 4, 3))
+    g = lambda d: oracle.grad_from_dy(wts, W, fr.gbuf, fr.layers, fr.scene, d)  # noqa: E731
+    lhs = g(2.0 * d1 - 3.0 * d2)
+    rhs = 2.0 * g(d1) - 3.0 * g(d2)
+    assert np.max(np.abs(lhs - rhs)) <= 1e-12 * np.max(np.abs(rhs))
+    assert np.array_equal(g(np.zeros_like(d1)), np.zeros(oracle.n_params(W)))
+
+
+def _fd_vjp(W, pe, pool, seed, n_coords):
+    """Central differences (h = 1e-6) of J(w) = sum(dy * y(w)) against
+    grad_from_dy, skipping coordinates whose +-h evaluations lie on
+    different pieces of the ReLU network (their branch signatures differ)."""
+    s = synth.streams(seed)
+    wts = synth.make_weights(W, s["weights"], pe_levels=pe).astype(np.float64)
+    fr = synth.Frame(synth.make_gbuf(1, 3, 3, s["gbuf"]),
+                     synth.make_layers(1, 3, 3, 3, s["slots"], s["active"], "uniform_count"),
+                     synth.make_scene(1, s["gbuf"]))
+    rng = np.random.default_rng(seed)
+    dy = rng.normal(size=(1, 3, 3, 3))
+    g = oracle.grad_from_dy(wts, W, fr.gbuf, fr.layers, fr.scene, dy, pool=pool, pe_levels=pe)
+    ny = dy.size
+    zero_t = np.zeros_like(dy)
+
+    def J(w):
+        y = oracle.forward(w, W, fr.gbuf, fr.layers, fr.scene, pool=pool, pe_levels=pe)
+        return float((dy * y).sum())
+
+    def sig(w):   # ReLU and mask branches only (the trailing y > t part is dropped)
+        return oracle.relu_signature(w, W, fr.gbuf, fr.layers, fr.scene, zero_t, pool,
+                                     pe_levels=pe)[:-ny]
+
+    coords = set(rng.choice(wts.size, size=min(n_coords, wts.size), replace=False).tolist())
+    coords |= set(range(wts.size - 3, wts.size))
+    eps, worst, checked = 1e-6, 0.0, 0
+    for i in sorted(coords):
+        wp, wm = wts.copy(), wts.copy()
+        wp[i] += eps
+        wm[i] -= eps
+        if not np.array_equal(sig(wp), sig(wm)):
+            continue
+        fd = (J(wp) - J(wm)) / (2 * eps)
+        worst = max(worst, abs(fd - g[i]) / (1e-8 + 1e-6 * abs(g[i])))
+        checked += 1
+    assert checked >= 0.9 * len(coords)
+    return worst
+
+
+@pytest.mark.parametrize("pool", ["mean", "sum"])
+def test_grad_from_dy_matches_central_differences(pool):
+    assert _fd_vjp(W=8, pe=0, pool=pool, seed=31, n_coords=300) <= 1.0
+
+
+def test_grad_from_dy_matches_central_differences_encoded():
+    assert _fd_vjp(W=8, pe=2, pool="mean", seed=32, n_coords=300) <= 1.0

@@ -79,6 +79,24 @@ typedef int32_t gn_pool;
 #define GN_POOL_MEAN 0
 #define GN_POOL_SUM 1
 
+/* The order in which a pixel's slots are added into the pool of Eq. (5).
+ * The pool is a symmetric function, so the method's result does not depend
+ * on the order of the transparency buffers (Sec. 3.3; Sec. 4.3's order-
+ * inversion table); a floating-point sum does, by its rounding.
+ *   GN_ORDER_CANONICAL  every forward path (GN_FP32, GN_BF16, GN_FP8_T, the
+ *                       backward's recompute and serving) adds each pixel's
+ *                       slots in one order fixed by their records: active
+ *                       slots (alpha > 0) by the bits of alpha as an unsigned
+ *                       integer, equal alphas by the bit patterns of planes
+ *                       0..11 in turn, equal records by index; then inactive
+ *                       slots by index.  The output is then bitwise the same
+ *                       under any permutation of a pixel's slots.
+ *   GN_ORDER_INPUT      slot 0, 1, ..., k - 1 (object streaming always adds
+ *                       objects in call order). */
+typedef int32_t gn_slot_order;
+#define GN_ORDER_CANONICAL 0
+#define GN_ORDER_INPUT 1
+
 typedef struct gn_config {
   int32_t width;              /* W: 64 or 128 */
   int32_t k_max;              /* largest slot count a call may pass, 0..GN_MAX_K */
@@ -94,6 +112,9 @@ typedef struct gn_config {
                                  of their channels: x, then sin(2^k pi x) and
                                  cos(2^k pi x) for k = 0 .. L-1.  sigma, R's
                                  L_d and the alpha mask stay raw.  0 = none. */
+  gn_slot_order slot_order;   /* GN_ORDER_CANONICAL (0, the default) or GN_ORDER_INPUT */
+  uint64_t seed;              /* glassnet_create with host_weights == NULL: the
+                                 weights are drawn from this seed (see there) */
 } gn_config;
 
 typedef struct gn_handle gn_handle;
@@ -130,7 +151,17 @@ size_t glassnet_num_params(int32_t width, int32_t pe_levels);
  * master copy, its bf16/fp8 packed forms and every workspace.  *out is set on
  * GN_OK.  GN_E_UNSUPPORTED for a width other than 64 or 128, GN_FP8_T at
  * width 64, or pe_levels outside 0..GN_MAX_PE_LEVELS; GN_E_INVAL for other bad
- * fields or a wrong n; GN_E_DEVICE / GN_E_NOMEM from the device. */
+ * fields or a wrong n; GN_E_DEVICE / GN_E_NOMEM from the device.
+ *
+ * Seeded initialisation: with host_weights == NULL (and n == 0 or the
+ * parameter count) the weights are drawn from cfg->seed, He et al.'s uniform
+ * initialisation for ReLU networks: every matrix entry of a layer with
+ * fan_in inputs uniform in +-sqrt(6 / fan_in), every bias uniform in
+ * +-1 / sqrt(fan_in).  Element e of the flat layout (0-based) uses
+ * u_e = (SplitMix64(seed + (e + 1) * 0x9E3779B97F4A7C15) >> 11) * 2^-53 in
+ * [0, 1) (Steele, Lea and Flood's SplitMix64 finaliser, computed modulo
+ * 2^64) and the value (2 u_e - 1) * bound, rounded to fp32.
+ * glassnet_get_weights reads the result back. */
 gn_status glassnet_create(const gn_config *cfg, const float *host_weights, size_t n,
                           gn_handle **out);
 
@@ -236,13 +267,45 @@ gn_status glassnet_sr_forward(gn_handle *h, const float *sr_w, int32_t n, int32_
                               int32_t width, const float *lowres, const float *gbuf_hi, float *out,
                               void *hip_stream);
 
+/* The spatial networks (Sec. 3.4 names F and B U-Nets and h, R multi-layer
+ * CNNs with 3 x 3 kernels before R's final 1 x 1 ones).  Architecture read
+ * from that description (widths and depths are not given; W = the handle's
+ * width):
+ *   U-Net (F on [G; s], B on [sigma; tau]): e1 = relu(conv3 x);
+ *     d = 2 x 2 average of e1; m = relu(conv3 d) at half resolution;
+ *     e2 = relu(conv3 [e1; m repeated 2 x 2]); output = conv1 e2;
+ *   h(b_i, sigma) = conv1 relu(conv1 relu(conv3 [b_i; sigma])), pooled per
+ *     pixel over the buffers with alpha > 0 there (the handle's pool);
+ *   R = conv1 relu(conv3 relu(conv3 [phi; L_d])), 3 outputs;
+ * conv3: 3 x 3 correlation with zero padding of one pixel; conv1: 1 x 1;
+ * every conv has a bias.  F's scene input is 16 constant planes.
+ * glassnet_spatial_num_params(W): the flat fp32 parameter count (0 for a
+ * width other than 64 or 128); layout: nets F (4 convs), T (3), B (4), R (3),
+ * per conv W [out][in][kh][kw] row-major then b; input channel orders as the
+ * concatenations above. */
+size_t glassnet_spatial_num_params(int32_t width);
+
+/* Spatial forward of a frame batch: sp_w (device, glassnet_spatial_num_params
+ * floats, caller-owned) is re-laid into the handle's bf16 copy, then every
+ * conv runs on the bf16 matrix cores with fp32 accumulation (whatever the
+ * handle's precision), activations stored as bf16, the pool of Eq. (5) in
+ * fp32 in buffer order.  frame as for glassnet_forward with even h and w and
+ * at most 2^22 pixels per call; out [n][3][h][w] fp32 device.  A permutation
+ * of the transparency buffers is a permutation of whole images (h sees a
+ * buffer's neighbourhood).  The handle keeps the weight copy and a workspace
+ * of about 3.5 KB per pixel at W = 128 (grown on a larger call, after the
+ * stream's earlier work).  GN_E_INVAL for odd sizes, bad frames or aliasing
+ * buffers. */
+gn_status glassnet_spatial_forward(gn_handle *h, const float *sp_w, const gn_frame *frame,
+                                   float *out, void *hip_stream);
+
 /* Weight gradient of glassnet_sr_forward (Sec. 4.1 trains the super-sampling
  * network on its own), fp32: grad_out = dL/d(out) [n][3][2 height][2 width],
  * device; grad_w (device, glassnet_sr_num_params() floats, packed like sr_w)
  * is overwritten with dL/d(sr_w).  The forward is recomputed with the same
  * arithmetic as glassnet_sr_forward (so the ReLU masks are the ones behind
  * its output; the derivative of ReLU is 0 at 0), per-tile partial sums are
- * added in fp64 in a fixed order: the result is deterministic.  At most 2^22
+ * added in fp32 in a fixed order: the result is deterministic.  At most 2^22
  * output pixels per call (n 4 height width) and height, width <= 2^16
  * (GN_E_INVAL beyond, or for NULL, misaligned or aliasing pointers).  The
  * handle keeps a workspace of 512 bytes per output pixel plus at most 35 MB
@@ -262,10 +325,14 @@ gn_status glassnet_adam_update(gn_handle *h, float *w, const float *grad_w, floa
                                float eps, float weight_decay, void *hip_stream);
 
 /* L1 term of Sec. 3.5 over count elements: *loss = mean |out - target| and
- * grad_out = sign(out - target) / count (0 where equal).  All device.
- * grad_out may be NULL. */
+ * grad_out = sign(out - target) / count (0 where equal), times *grad_scale
+ * when grad_scale is not NULL (a device scalar, e.g. the upstream gradient of
+ * an autograd graph; read on the device, no host synchronisation).  All
+ * device.  grad_out may be NULL.  GN_E_INVAL for NULL out, target or loss,
+ * misaligned pointers, or grad_out overlapping out, target or grad_scale. */
 gn_status glassnet_l1_loss(gn_handle *h, const float *out, const float *target,
-                           uint64_t count, float *loss, float *grad_out, void *hip_stream);
+                           uint64_t count, float *loss, float *grad_out, const float *grad_scale,
+                           void *hip_stream);
 
 /* Device bytes the handle holds for forward work: weights, packed forms and
  * workspaces.  Independent of the slot count k (the pool is a running sum). */
@@ -276,18 +343,19 @@ gn_status glassnet_workspace_bytes(gn_handle *h, uint64_t *bytes);
  * evaluated on its own and added to a running sum, and device memory stays
  * constant in the number of transparent objects.  A frame batch is evaluated
  * as begin (F -> sigma), then any number of accumulate calls (k >= 0 objects
- * each), then finish (pool, T3, B, R -> out).  The result is bitwise the
- * glassnet_forward result of the same handle over all accumulated slots in
- * call order (same arithmetic, same order).  finish may follow any accumulate
+ * each), then finish (pool, T3, B, R -> out).  Objects are pooled in call
+ * order: the result is bitwise the glassnet_forward result, on a handle of
+ * the same configuration with slot_order GN_ORDER_INPUT, over all accumulated
+ * slots in call order (same arithmetic, same order).  finish may follow any accumulate
  * call (a progressive result) and accumulation may continue after it.
  *
  * The state is caller-owned device memory of glassnet_stream_state_bytes
  * bytes, whatever the number of objects: sigma, the fp32 running sum of h's
  * hidden layer and the active-slot count, in a layout private to the library
  * (GN_BF16 / GN_FP8_T: sigma in bf16, 772 bytes per pixel at W = 128, 388 at
- * W = 64; GN_FP32: sigma and the count in fp32 and the running sum in fp64,
- * (3 W + 1) x 4 bytes per pixel, through the plane workspace of the FP32
- * forward with its pixel limit).  Calls on one state
+ * W = 64; GN_FP32: sigma, the running sum and the count in fp32, (2 W + 1) x
+ * 4 bytes per pixel, through the plane workspace of the FP32 forward with
+ * its pixel limit).  Calls on one state
  * are ordered on the hip_stream each passes; calls on different streams must
  * be ordered by the caller. */
 gn_status glassnet_stream_state_bytes(gn_handle *h, int32_t n, int32_t hgt, int32_t wid,

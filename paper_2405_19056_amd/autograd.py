@@ -17,37 +17,47 @@ from .glassnet import GlassNet
 
 
 class GlassNetFunction(torch.autograd.Function):
+    """y = GlassNet(w) on the handle `net`.  w is saved for the backward and
+    uploaded again there, so the gradient is taken at the weights of this
+    forward even if the handle's weights changed in between (torch's version
+    counter also rejects an in-place edit of w before the backward)."""
+
     @staticmethod
     def forward(ctx, net: GlassNet, gbuf, layers, scene, w):
         net.set_weights(w.detach())
         out = net.forward(gbuf, layers, scene)
         ctx.net = net
-        ctx.save_for_backward(gbuf, layers, scene)
+        ctx.save_for_backward(gbuf, layers, scene, w)
         return out
 
     @staticmethod
     def backward(ctx, grad_out):
-        gbuf, layers, scene = ctx.saved_tensors
+        gbuf, layers, scene, w = ctx.saved_tensors
+        ctx.net.set_weights(w.detach())
         gw = ctx.net.backward(gbuf, layers, scene, grad_out.contiguous())
         return None, None, None, None, gw
 
 
 class L1Function(torch.autograd.Function):
-    """mean |y - t| and its subgradient, both from the library's loss kernel."""
+    """mean |y - t| and its subgradient, both from the library's loss kernel;
+    the upstream gradient scales the subgradient on the device."""
 
     @staticmethod
     def forward(ctx, net: GlassNet, y, target):
-        grad = torch.empty_like(y)
-        loss = net.l1_loss(y.detach().contiguous(), target.contiguous(), grad_out=grad)
-        ctx.save_for_backward(grad)
+        y, target = y.detach().contiguous(), target.contiguous()
+        loss = net.l1_loss(y, target)
+        ctx.net = net
+        ctx.save_for_backward(y, target)
         return loss
 
     @staticmethod
     def backward(ctx, g):
-        (grad,) = ctx.saved_tensors
-        if g.numel() == 1 and float(g) == 1.0:
-            return None, grad, None
-        return None, grad * g, None     # non-unit upstream gradient: scale the seed
+        y, target = ctx.saved_tensors
+        grad = torch.empty_like(y)
+        scratch = torch.empty((), dtype=torch.float32, device=y.device)
+        ctx.net.l1_loss(y, target, loss=scratch, grad_out=grad,
+                        grad_scale=g.detach().to(torch.float32).contiguous())
+        return None, grad, None
 
 
 def train_step(net: GlassNet, gbuf, layers, scene, target, w, grad_w=None, stream=None):

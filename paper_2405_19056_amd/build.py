@@ -21,7 +21,7 @@ LIB = os.path.join(PKG, "libglassnet.so")
 ARCH = "gfx950"
 
 SOURCES = ["api.cpp", "layout.cpp", "serve.cpp", "fwd_mfma.hip", "planes.hip",
-           "loss.hip", "optim.hip", "sr.hip"]
+           "loss.hip", "optim.hip", "sr.hip", "spatial.hip"]
 
 
 def hipcc() -> str:

@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <mutex>
 #include <string>
+#include <vector>
 
 #include "gn_api_state.h"
 
@@ -117,14 +118,21 @@ gn_status glassnet_create(const gn_config *cfg, const float *host_weights, size_
     return fail(GN_E_INVAL, "unknown precision %d", cfg->precision);
   if (cfg->precision == GN_FP8_T && cfg->width != 128)
     return fail(GN_E_UNSUPPORTED, "GN_FP8_T needs width 128");
-  if (!host_weights) return fail(GN_E_INVAL, "host_weights is NULL");
+  if (cfg->slot_order != GN_ORDER_CANONICAL && cfg->slot_order != GN_ORDER_INPUT)
+    return fail(GN_E_INVAL, "unknown slot order %d", cfg->slot_order);
   if (cfg->pe_levels < 0 || cfg->pe_levels > GN_MAX_PE_LEVELS)
     return fail(GN_E_UNSUPPORTED, "pe_levels %d outside [0, %d]", cfg->pe_levels,
                 GN_MAX_PE_LEVELS);
   const size_t np = gn::num_params(cfg->width, cfg->pe_levels);
-  if (n != np)
+  if (n != np && !(host_weights == nullptr && n == 0))
     return fail(GN_E_INVAL, "expected %zu weights for width %d and %d encoding levels, got %zu",
                 np, cfg->width, cfg->pe_levels, n);
+  std::vector<float> seeded;
+  if (!host_weights) {
+    seeded.resize(np);
+    gn::seeded_weights(cfg->width, cfg->pe_levels, cfg->seed, seeded.data());
+    host_weights = seeded.data();
+  }
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1)
     return fail(GN_E_DEVICE, "no HIP device available");
@@ -203,6 +211,8 @@ gn_status glassnet_destroy(gn_handle *h) {
   (void)hipFree(h->d_loss_ws);
   (void)hipFree(h->d_sr_wt);
   (void)hipFree(h->d_sr_ws);
+  (void)hipFree(h->d_sp_packed);
+  (void)hipFree(h->d_sp_ws);
   (void)hipFree(h->d_sig_scratch[0]);
   (void)hipFree(h->d_sig_scratch[1]);
   delete h;
@@ -300,7 +310,7 @@ gn_status glassnet_forward(gn_handle *h, const gn_frame *frame, float *out, void
   const int tpf = (b.hw + gn::kTilePx - 1) / gn::kTilePx;
   const hipError_t e = gn::launch_fwd_mfma(h->W, h->cfg.precision, h->cfg.pool, h->d_packed, h->pl,
                                            &b, nullptr, nullptr, b.n * tpf, h->act_scale,
-                                           h->num_cus, h->d_sig_scratch[0], s);
+                                           h->num_cus, h->d_sig_scratch[0], gn_slot_kmax(h), s);
   return gn_check_device(h, e, "forward launch");
 }
 
@@ -473,24 +483,28 @@ gn_status glassnet_stream_release(gn_handle *h, void *state) {
 }
 
 gn_status glassnet_l1_loss(gn_handle *h, const float *out, const float *target, uint64_t count,
-                           float *loss, float *grad_out, void *hip_stream) {
+                           float *loss, float *grad_out, const float *grad_scale,
+                           void *hip_stream) {
   gn_status st = precheck(h);
   if (st != GN_OK) return st;
   if (!out || !target || !loss) return fail(GN_E_INVAL, "out, target and loss must be non-NULL");
-  if (!aligned4(out) || !aligned4(target) || !aligned4(loss) || !aligned4(grad_out))
+  if (!aligned4(out) || !aligned4(target) || !aligned4(loss) || !aligned4(grad_out) ||
+      !aligned4(grad_scale))
     return fail(GN_E_INVAL, "device pointers must be 4-byte aligned");
   if (grad_out && (overlaps(grad_out, 4 * count, out, 4 * count) ||
-                   overlaps(grad_out, 4 * count, target, 4 * count)))
-    return fail(GN_E_INVAL, "grad_out aliases out or target");
+                   overlaps(grad_out, 4 * count, target, 4 * count) ||
+                   (grad_scale && overlaps(grad_out, 4 * count, grad_scale, 4))))
+    return fail(GN_E_INVAL, "grad_out aliases out, target or grad_scale");
   DeviceGuard dg(h->device);
-  hipError_t e = gn::launch_l1(out, target, count, loss, grad_out, h->d_l1_partials, h->l1_npart,
-                               (hipStream_t)hip_stream);
+  hipError_t e = gn::launch_l1(out, target, count, loss, grad_out, grad_scale, h->d_l1_partials,
+                               h->l1_npart, (hipStream_t)hip_stream);
   return gn_check_device(h, e, "l1 launch");
 }
 
-gn_status glassnet_dssim_loss(gn_handle *h, const float *out, const float *target, int32_t n,
-                              int32_t height, int32_t width, float *loss, float *grad_out,
-                              int32_t accumulate, void *hip_stream) {
+// Arguments of the DSSIM term (both forms).
+static gn_status dssim_check(gn_handle *h, const float *out, const float *target, int32_t n,
+                             int32_t height, int32_t width, const float *loss,
+                             const float *grad_out) {
   gn_status st = precheck(h);
   if (st != GN_OK) return st;
   if (n < 1 || height < 11 || width < 11)
@@ -507,6 +521,14 @@ gn_status glassnet_dssim_loss(gn_handle *h, const float *out, const float *targe
     return fail(GN_E_INVAL, "grad_out aliases out, target or loss");
   if (overlaps(loss, 4, out, bytes) || overlaps(loss, 4, target, bytes))
     return fail(GN_E_INVAL, "loss aliases out or target");
+  return GN_OK;
+}
+
+gn_status glassnet_dssim_loss(gn_handle *h, const float *out, const float *target, int32_t n,
+                              int32_t height, int32_t width, float *loss, float *grad_out,
+                              int32_t accumulate, void *hip_stream) {
+  gn_status st = dssim_check(h, out, target, n, height, width, loss, grad_out);
+  if (st != GN_OK) return st;
   DeviceGuard dg(h->device);
   hipStream_t s = (hipStream_t)hip_stream;
   const size_t need = gn::dssim_workspace_bytes(n * gn::kNOUT, height, width);
@@ -529,6 +551,7 @@ gn_status glassnet_dssim_loss(gn_handle *h, const float *out, const float *targe
   return gn_check_device(h, e, "DSSIM launch");
 }
 
+
 size_t glassnet_sr_num_params(void) { return (size_t)gn::kSrParams; }
 
 }  // extern "C"
@@ -546,6 +569,57 @@ gn_status sr_weight_copy(gn_handle *h) {
 }  // namespace
 
 extern "C" {
+
+size_t glassnet_spatial_num_params(int32_t width) { return gn::spatial_num_params(width); }
+
+gn_status glassnet_spatial_forward(gn_handle *h, const float *sp_w, const gn_frame *frame,
+                                   float *out, void *hip_stream) {
+  gn_status st = precheck(h);
+  if (st != GN_OK) return st;
+  st = gn_validate_frame(h, frame, out);
+  if (st != GN_OK) return st;
+  if (!sp_w || !aligned4(sp_w) || !out)
+    return fail(GN_E_INVAL, "sp_w and out must be non-NULL, 4-byte aligned");
+  if ((frame->h & 1) || (frame->w & 1))
+    return fail(GN_E_INVAL, "the U-Nets need even frame sizes (got %d x %d)", frame->h, frame->w);
+  if ((int64_t)frame->n * frame->h * frame->w > ((int64_t)1 << 22))
+    return fail(GN_E_INVAL, "more than 2^22 pixels in one call");
+  const size_t w_b = sizeof(float) * gn::spatial_num_params(h->W);
+  const size_t out_b = sizeof(float) * (size_t)frame->n * gn::kNOUT * frame->h * frame->w;
+  if (overlaps(out, out_b, sp_w, w_b)) return fail(GN_E_INVAL, "out aliases sp_w");
+  DeviceGuard dg(h->device);
+  hipStream_t s = (hipStream_t)hip_stream;
+  hipError_t e = hipSuccess;
+  if (!h->d_sp_packed) {
+    e = hipMalloc((void **)&h->d_sp_packed, gn::spatial_weight_bytes(h->W));
+    if (e != hipSuccess) {
+      h->d_sp_packed = nullptr;
+      return e == hipErrorOutOfMemory ? fail(GN_E_NOMEM, "spatial weight copy")
+                                      : gn_check_device(h, e, "spatial weight copy");
+    }
+  }
+  const size_t need = gn::spatial_workspace_bytes(h->W, frame->n, frame->h, frame->w) + 4096;
+  if (need > h->sp_ws_bytes) {
+    // grown workspaces replace the old one once the stream's earlier work is done
+    e = hipStreamSynchronize(s);
+    if (e == hipSuccess) e = hipFree(h->d_sp_ws);
+    h->d_sp_ws = nullptr;
+    h->sp_ws_bytes = 0;
+    if (e == hipSuccess) e = hipMalloc((void **)&h->d_sp_ws, need);
+    if (e != hipSuccess) {
+      h->d_sp_ws = nullptr;
+      return e == hipErrorOutOfMemory ? fail(GN_E_NOMEM, "spatial workspace of %zu bytes", need)
+                                      : gn_check_device(h, e, "spatial workspace");
+    }
+    h->sp_ws_bytes = need;
+  }
+  e = gn::spatial_pack(sp_w, h->W, h->d_sp_packed, s);
+  if (e == hipSuccess)
+    e = gn::spatial_forward(h->d_sp_packed, h->W, h->cfg.pool, frame->gbuf, frame->layers,
+                            frame->scene, frame->n, frame->h, frame->w, frame->k, out, h->d_sp_ws,
+                            s);
+  return gn_check_device(h, e, "spatial forward launch");
+}
 
 gn_status glassnet_sr_forward(gn_handle *h, const float *sr_w, int32_t n, int32_t height,
                               int32_t width, const float *lowres, const float *gbuf_hi, float *out,
@@ -642,7 +716,9 @@ gn_status glassnet_adam_step(gn_handle *h, const float *grad_w, float *state, si
     return fail(GN_E_INVAL, "grad_w, state and the handle's weights must not overlap");
   DeviceGuard dg(h->device);
   hipStream_t s = (hipStream_t)hip_stream;
-  hipError_t e = gn::launch_adam(h->d_master, grad_w, state, state + n, (int64_t)n, step, lr,
+  float c1, c2;
+  gn::adam_bias_corrections(beta1, beta2, step, &c1, &c2);
+  hipError_t e = gn::launch_adam(h->d_master, grad_w, state, state + n, (int64_t)n, c1, c2, lr,
                                  beta1, beta2, eps, weight_decay, s);
   if (e != hipSuccess) return gn_check_device(h, e, "adam launch");
   return gn_prepare_weights(h, s);
@@ -665,7 +741,9 @@ gn_status glassnet_adam_update(gn_handle *h, float *w, const float *grad_w, floa
   if (overlaps(state, 2 * b, grad_w, b) || overlaps(state, 2 * b, w, b) || overlaps(grad_w, b, w, b))
     return fail(GN_E_INVAL, "w, grad_w and state must not overlap");
   DeviceGuard dg(h->device);
-  hipError_t e = gn::launch_adam(w, grad_w, state, state + n, (int64_t)n, step, lr, beta1, beta2,
+  float c1, c2;
+  gn::adam_bias_corrections(beta1, beta2, step, &c1, &c2);
+  hipError_t e = gn::launch_adam(w, grad_w, state, state + n, (int64_t)n, c1, c2, lr, beta1, beta2,
                                  eps, weight_decay, (hipStream_t)hip_stream);
   return gn_check_device(h, e, "adam launch");
 }

@@ -25,6 +25,7 @@
 // sum_i m_i (A3 a_i + c3) = A3 (sum_i m_i a_i) + (sum_i m_i) c3.  The running
 // sum is fp32 in registers, so memory does not grow with the slot count.
 #include "gn_internal.h"
+#include "slot_order.h"
 
 namespace gn {
 namespace {
@@ -62,6 +63,8 @@ struct MfmaArgs {
                                        // last t in the stage buffers' idle tails
   uint8_t *state;                      // object streaming: per-tile state (modes other than FULL)
   int state_load;                      // 1: the state holds a running sum to continue from
+  int canon;                           // FULL: pool each pixel's slots in canonical order
+  int kpad;                            // bytes per pixel of the LDS slot-order table
 };
 
 // Two floats -> packed bf16 pair (round to nearest even), one v_cvt_pk_bf16_f32.
@@ -344,7 +347,7 @@ __global__ __launch_bounds__(kThreads) void fwd_mfma_kernel(MfmaArgs a) {
   extern __shared__ __attribute__((aligned(1024))) uint8_t lds[];
   const int wave = threadIdx.x >> 6;
 
-  // LDS map: [resident | biases | stage buffer 0 | stage buffer 1]
+  // LDS map: [resident | biases | slot order | stage buffer 0 | stage buffer 1]
   const int64_t res_bytes = a.res_bytes;
   uint8_t *L_res = lds;
   float *L_bias = (float *)(lds + res_bytes);
@@ -352,7 +355,10 @@ __global__ __launch_bounds__(kThreads) void fwd_mfma_kernel(MfmaArgs a) {
 #pragma unroll
   for (int s = 0; s < kStages; ++s)
     stage_max = max(stage_max, a.stage_off[s + 1] - a.stage_off[s]);
-  uint8_t *L_stage0 = lds + res_bytes + Shape<W>::kBiasBytes;
+  // slot-order table: for each pixel of the tile, its slots' indices in
+  // canonical order (kpad bytes per pixel, a multiple of 4)
+  uint8_t *L_perm = lds + res_bytes + Shape<W>::kBiasBytes;
+  uint8_t *L_stage0 = L_perm + (size_t)kTilePx * a.kpad;
   uint8_t *L_stage1 = L_stage0 + stage_max;
   // FWD_FINISH runs an odd number of stages per tile, so its buffer parity
   // flips from one tile to the next (par); every other mode keeps par = 0.
@@ -618,11 +624,84 @@ __global__ __launch_bounds__(kThreads) void fwd_mfma_kernel(MfmaArgs a) {
           for (int k = 0; k < KS; ++k) sig[t][k] = st_sig[(t * KS + k) * 64];
       }
       {
+        // Canonical slot order (FULL mode, if the handle asks for it): the
+        // pixel's slots are pooled in an order that depends only on their
+        // records, so the rounding of the running sum cannot depend on the
+        // order the caller passed them in.  With up to kFastK slots each lane
+        // holds the alphas of all of them and ranks its lane group's slots
+        // g and g + 4; the slot at rank r goes to byte r of the pixel's entry
+        // of the LDS table.  The alphas are requested before u's MFMAs.
+        constexpr int kFastK = 8;
+        const bool canon = MODE == FWD_FULL && a.canon && K > 1;
+        uint8_t *perm_px[kNT];
+#pragma unroll
+        for (int t = 0; t < kNT; ++t)
+          perm_px[t] = L_perm + (size_t)(wave * (kNT * 16) + t * 16 + col) * a.kpad;
+        float alk[kNT][kFastK];
+        if (canon && K <= kFastK) {
+#pragma unroll
+          for (int t = 0; t < kNT; ++t)
+#pragma unroll
+            for (int j = 0; j < kFastK; ++j)
+              alk[t][j] = j < K ? Lp[((size_t)j * kNL + kAlpha) * hw + qc[t]] : 0.0f;
+        }
         // u = W1s sigma + c1 in fp32 accumulator layout: the C operand of h's
         // first layer for every slot
         f32x4 u[kNT][MT];
         bias_init(u, bT1, g);
         mm<MT, KS>(u, stage_buf(sT1S), sig, lane);
+        if (canon) {
+          if (K <= kFastK) {
+            // Keys: active slots by alpha's bits, inactive ones made distinct
+            // by their index (0xFFFFFF00 + j, above every active key), absent
+            // ones (j >= K) above all.  A key's rank is the number of smaller
+            // keys; two active slots of equal alpha take the full comparison.
+            unsigned slow = 0;
+#pragma unroll
+            for (int t = 0; t < kNT; ++t) {
+              uint32_t key[kFastK];
+#pragma unroll
+              for (int j = 0; j < kFastK; ++j)
+                key[j] = j >= K ? 0xFFFFFFFFu
+                                : (alk[t][j] > 0.0f ? __float_as_uint(alk[t][j]) : 0xFFFFFF00u + j);
+#pragma unroll
+              for (int sl = 0; sl < 2; ++sl) {
+                const int i = g + 4 * sl;
+                uint32_t ki = key[4 * sl];
+#pragma unroll
+                for (int jj = 1; jj < 4; ++jj) ki = g == jj ? key[4 * sl + jj] : ki;
+                int lt = 0, le = 0;
+#pragma unroll
+                for (int j = 0; j < kFastK; ++j) {
+                  lt += key[j] < ki ? 1 : 0;
+                  le += key[j] <= ki ? 1 : 0;
+                }
+                if (i < K) {
+                  if (le == lt + 1)
+                    perm_px[t][lt] = (uint8_t)i;
+                  else
+                    slow |= 1u << (2 * t + sl);
+                }
+              }
+            }
+            if (__builtin_amdgcn_ballot_w64(slow != 0)) {
+#pragma unroll
+              for (int t = 0; t < kNT; ++t)
+#pragma unroll
+                for (int sl = 0; sl < 2; ++sl)
+                  if (slow & (1u << (2 * t + sl)))
+                    perm_px[t][slot_rank(Lp + qc[t], (size_t)hw, K, g + 4 * sl)] =
+                        (uint8_t)(g + 4 * sl);
+            }
+          } else {
+#pragma unroll
+            for (int t = 0; t < kNT; ++t)
+              for (int i = g; i < K; i += 4)
+                perm_px[t][slot_rank(Lp + qc[t], (size_t)hw, K, i)] = (uint8_t)i;
+          }
+          // this wave reads the table back in its own slot loop
+          asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+        }
         if constexpr (kFp8) {
           // fp8: h's first layer runs in units of the activation scale (its
           // inputs b_i and u are divided by it), so its output quantises directly
@@ -653,12 +732,14 @@ __global__ __launch_bounds__(kThreads) void fwd_mfma_kernel(MfmaArgs a) {
         // loaded one slot ahead so their latency overlaps the current slot's work.
         constexpr int kRaw = PE > 0 ? 3 : 4;
         float nxt[kNT][kRaw];
+        // Iteration i takes each pixel's slot of rank i (canonical order) or
+        // slot i (input order).
         auto load_slot = [&](int i) {
-          gcfloat *Li = Lp + (size_t)i * kNL * hw;
-          int qs[kNT];
+          size_t qs[kNT];
 #pragma unroll
           for (int t = 0; t < kNT; ++t) {
-            qs[t] = qc[t];
+            const int si = canon ? (int)perm_px[t][i] : i;
+            qs[t] = (size_t)si * kNL * hw + qc[t];
             asm volatile("" : "+v"(qs[t]));   // per-slot addresses stay in the loop body
           }
 #pragma unroll
@@ -666,9 +747,9 @@ __global__ __launch_bounds__(kThreads) void fwd_mfma_kernel(MfmaArgs a) {
 #pragma unroll
             for (int j = 0; j < kRaw; ++j) {
               if constexpr (PE > 0)
-                nxt[t][j] = Li[(size_t)(3 * g + j) * hw + qs[t]];
+                nxt[t][j] = Lp[(size_t)(3 * g + j) * hw + qs[t]];
               else
-                nxt[t][j] = g < 3 ? Li[(size_t)(4 * g + j) * hw + qs[t]] : 0.0f;
+                nxt[t][j] = g < 3 ? Lp[(size_t)(4 * g + j) * hw + qs[t]] : 0.0f;
             }
         };
         if (K > 0) load_slot(0);
@@ -1113,21 +1194,23 @@ static int64_t resident_bytes(const PackedLayout &pl, int precision) {
   return pl.resident_bytes;
 }
 
-static size_t mfma_base_lds_bytes(const PackedLayout &pl, int precision) {
+static size_t mfma_base_lds_bytes(const PackedLayout &pl, int precision, int kpad) {
   int64_t stage_max = 0;
   for (int s = 0; s < pl.nstages; ++s)
     stage_max = std::max<int64_t>(stage_max, pl.stage_off[s + 1] - pl.stage_off[s]);
-  return (size_t)(resident_bytes(pl, precision) + (int64_t)kNumLayers * pl.W * 4 + 2 * stage_max);
+  return (size_t)(resident_bytes(pl, precision) + (int64_t)kNumLayers * pl.W * 4 +
+                  (int64_t)kTilePx * kpad + 2 * stage_max);
 }
 
 // Waves whose sigma fits in the LDS the weights leave free (160 KiB per CU),
 // and how many of them sit in the stage buffers' tails: from F3's stage to
 // B1S's (stages 1-4, shifted by two with encoded inputs) buffer 1 holds the
 // first and third of them, buffer 0 the second and fourth.
-static void mfma_sig_lds(const PackedLayout &pl, int precision, int *nlds, int *ntail) {
+static void mfma_sig_lds(const PackedLayout &pl, int precision, int kpad, int *nlds,
+                         int *ntail) {
   constexpr size_t kLdsMax = 160 * 1024;
   const size_t per_wave = (size_t)kNT * (pl.W / 32) * kFrag;
-  const size_t base = mfma_base_lds_bytes(pl, precision);
+  const size_t base = mfma_base_lds_bytes(pl, precision, kpad);
   int64_t stage_max = 0;
   for (int s = 0; s < pl.nstages; ++s)
     stage_max = std::max<int64_t>(stage_max, pl.stage_off[s + 1] - pl.stage_off[s]);
@@ -1149,15 +1232,15 @@ static void mfma_sig_lds(const PackedLayout &pl, int precision, int *nlds, int *
   *nlds = n;
 }
 
-static int mfma_sig_free_waves(const PackedLayout &pl, int precision) {
+static int mfma_sig_free_waves(const PackedLayout &pl, int precision, int kpad) {
   int n, t;
-  mfma_sig_lds(pl, precision, &n, &t);
+  mfma_sig_lds(pl, precision, kpad, &n, &t);
   return n - t;
 }
 
-static size_t mfma_lds_bytes(const PackedLayout &pl, int precision) {
-  return mfma_base_lds_bytes(pl, precision) +
-         (size_t)mfma_sig_free_waves(pl, precision) * kNT * (pl.W / 32) * kFrag;
+static size_t mfma_lds_bytes(const PackedLayout &pl, int precision, int kpad) {
+  return mfma_base_lds_bytes(pl, precision, kpad) +
+         (size_t)mfma_sig_free_waves(pl, precision, kpad) * kNT * (pl.W / 32) * kFrag;
 }
 
 template <int W, int PREC, int MODE, int PE>
@@ -1210,12 +1293,16 @@ static hipError_t launch_impl(int W, int precision, int pool, const uint8_t *pac
                               const PackedLayout &pl, const FwdBatch *batch,
                               const FrameDesc *frames, const TileRef *tiles, int ntiles,
                               float fp8_act_scale, int grid, uint8_t *sig_scratch, int mode,
-                              uint8_t *state, int state_load, hipStream_t stream) {
+                              uint8_t *state, int state_load, int slot_kmax,
+                              hipStream_t stream) {
   MfmaArgs a;
   a.sig_scratch = sig_scratch;
   a.state = state;
   a.state_load = state_load;
-  mfma_sig_lds(pl, precision, &a.sig_lds_waves, &a.sig_tail_waves);
+  // canonical order: a table of slot_kmax bytes per pixel, rounded up to 4
+  a.canon = slot_kmax > 1 ? 1 : 0;
+  a.kpad = a.canon ? (slot_kmax + 3) / 4 * 4 : 0;
+  mfma_sig_lds(pl, precision, a.kpad, &a.sig_lds_waves, &a.sig_tail_waves);
   a.packed = packed;
   for (int s = 0; s <= kMaxStages; ++s) a.stage_off[s] = s <= pl.nstages ? pl.stage_off[s] : 0;
   a.res_off = pl.resident_off;
@@ -1238,7 +1325,7 @@ static hipError_t launch_impl(int W, int precision, int pool, const uint8_t *pac
   a.inv_sa = 1.0f / fp8_act_scale;
   if (ntiles <= 0) return hipSuccess;
   grid = std::max(1, std::min(grid, ntiles));   // the scratch holds `grid` workgroups
-  const size_t lds = mfma_lds_bytes(pl, precision);
+  const size_t lds = mfma_lds_bytes(pl, precision, a.kpad);
   if (lds > 160 * 1024) return hipErrorInvalidValue;
   if (precision == GN_BF16) {
     if (W == 64) return launch_pe<64, GN_BF16>(pl.pe, mode, a, grid, lds, stream);
@@ -1253,9 +1340,9 @@ hipError_t launch_fwd_mfma(int W, int precision, int pool, const uint8_t *packed
                            const PackedLayout &pl, const FwdBatch *batch,
                            const FrameDesc *frames, const TileRef *tiles, int ntiles,
                            float fp8_act_scale, int grid, uint8_t *sig_scratch,
-                           hipStream_t stream) {
+                           int slot_kmax, hipStream_t stream) {
   return launch_impl(W, precision, pool, packed, pl, batch, frames, tiles, ntiles, fp8_act_scale,
-                     grid, sig_scratch, FWD_FULL, nullptr, 0, stream);
+                     grid, sig_scratch, FWD_FULL, nullptr, 0, slot_kmax, stream);
 }
 
 hipError_t launch_fwd_stream(int W, int precision, int pool, const uint8_t *packed,
@@ -1265,7 +1352,7 @@ hipError_t launch_fwd_stream(int W, int precision, int pool, const uint8_t *pack
   if (mode == FWD_FULL || !state) return hipErrorInvalidValue;
   const int tpf = (batch.hw + kTilePx - 1) / kTilePx;
   return launch_impl(W, precision, pool, packed, pl, &batch, nullptr, nullptr, batch.n * tpf,
-                     fp8_act_scale, grid, nullptr, mode, state, state_load, stream);
+                     fp8_act_scale, grid, nullptr, mode, state, state_load, 0, stream);
 }
 
 }  // namespace gn

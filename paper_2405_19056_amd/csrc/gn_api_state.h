@@ -33,6 +33,9 @@ struct gn_handle {
   float *d_sr_wt = nullptr;       // super-sampling network: re-laid weight copy
   float *d_sr_ws = nullptr;       // super-sampling backward: activations and partials
   size_t sr_ws_bytes = 0;
+  uint8_t *d_sp_packed = nullptr; // spatial networks: weight fragments and biases
+  uint8_t *d_sp_ws = nullptr;     // spatial networks: activations of one call
+  size_t sp_ws_bytes = 0;
   size_t loss_ws_bytes = 0;
   int l1_npart = 0;
   float act_scale = 0.0f;         // fp8 activation scale
@@ -43,6 +46,12 @@ struct gn_handle {
   std::mutex stream_mu;                          // guards streams
   std::map<uintptr_t, GnStreamRec> streams;      // keyed by state address
 };
+
+// Largest slot count whose pixels the fused forward orders canonically (0:
+// the handle pools in input order).
+inline int gn_slot_kmax(const gn_handle *h) {
+  return h->cfg.slot_order == GN_ORDER_CANONICAL ? h->cfg.k_max : 0;
+}
 
 gn_status gn_set_error(gn_status code, const char *msg);
 gn_status gn_check_device(gn_handle *h, hipError_t e, const char *what);

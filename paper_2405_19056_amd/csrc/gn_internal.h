@@ -47,6 +47,9 @@ struct LayerOff {
 
 void layer_offsets(int W, int pe, LayerOff lo[kNumLayers]);
 size_t num_params(int W, int pe);
+// The seeded initialisation of glassnet_create (host): num_params(W, pe)
+// floats.
+void seeded_weights(int W, int pe, uint64_t seed, float *w);
 
 // ---- packed (fragment-ordered) weights of the MFMA forward -----------------
 // A chunk is the part of one layer's matrix that multiplies one input source.
@@ -121,12 +124,14 @@ hipError_t launch_pack_weights(const float *master, uint8_t *packed, const Packe
 
 
 // sig_scratch: mfma_sig_scratch_bytes(W, grid) bytes private to this launch
-// (launches that may overlap need different scratch buffers).
+// (launches that may overlap need different scratch buffers).  slot_kmax > 1:
+// every pixel's slots are pooled in canonical order (slot_order.h), for
+// frames of up to slot_kmax slots; 0: in input order.
 hipError_t launch_fwd_mfma(int W, int precision, int pool, const uint8_t *packed,
                            const PackedLayout &pl, const FwdBatch *batch,
                            const FrameDesc *frames, const TileRef *tiles, int ntiles,
                            float fp8_act_scale, int grid, uint8_t *sig_scratch,
-                           hipStream_t stream);
+                           int slot_kmax, hipStream_t stream);
 size_t mfma_sig_scratch_bytes(int W, int grid);
 constexpr int kTilePx = 256;
 
@@ -144,8 +149,11 @@ hipError_t launch_fwd_stream(int W, int precision, int pool, const uint8_t *pack
                              int grid, int mode, uint8_t *state, int state_load,
                              hipStream_t stream);
 
+// L1 term; grad (optional) = sign(out - target) / count x *grad_scale (a
+// device scalar; null: 1).
 hipError_t launch_l1(const float *out, const float *target, uint64_t count, float *loss,
-                     float *grad, float *partials, int npart, hipStream_t stream);
+                     float *grad, const float *grad_scale, float *partials, int npart,
+                     hipStream_t stream);
 // DSSIM term: planes = n x 3 images of h x w (h, w >= 11); ws holds
 // dssim_workspace_bytes(planes, h, w) bytes; grad may be null.
 size_t dssim_workspace_bytes(int planes, int h, int w);
@@ -171,9 +179,22 @@ size_t sr_backward_workspace_bytes(int n, int h, int w);
 hipError_t launch_sr_backward(const float *w, float *wt, const float *lowres, const float *gbuf,
                               const float *dy, float *gw, int n, int h, int w_lo, float *ws,
                               hipStream_t stream);
-// One Adam step on w (n floats) from gradient g, moments m and v; step >= 1.
-hipError_t launch_adam(float *w, const float *g, float *m, float *v, int64_t n, int step, float lr,
-                       float b1, float b2, float eps, float wd, hipStream_t stream);
+// Spatial networks (spatial.hip): parameter count, bytes of the packed
+// weights and of one call's activations, the packing (from a device fp32
+// master vector) and the forward (bf16 matrix cores, fp32 accumulation).
+size_t spatial_num_params(int W);
+size_t spatial_weight_bytes(int W);
+size_t spatial_workspace_bytes(int W, int n, int H, int Wd);
+hipError_t spatial_pack(const float *master, int W, uint8_t *packed, hipStream_t s);
+hipError_t spatial_forward(const uint8_t *packed, int W, int pool, const float *gbuf,
+                           const float *layers, const float *scene, int n, int H, int Wd, int k,
+                           float *out, uint8_t *ws, hipStream_t s);
+// One Adam step on w (n floats) from gradient g, moments m and v, with the
+// bias corrections c1 = 1 / (1 - b1^t) and c2 = 1 / (1 - b2^t) of step t.
+hipError_t launch_adam(float *w, const float *g, float *m, float *v, int64_t n, float c1, float c2,
+                       float lr, float b1, float b2, float eps, float wd, hipStream_t stream);
+// Adam's bias corrections for step t >= 1 (host).
+void adam_bias_corrections(float b1, float b2, int step, float *c1, float *c2);
 
 
 }  // namespace gn

@@ -1,4 +1,6 @@
-// Host-side layout tables: master weight offsets and the packed MFMA layout.
+// Host-side layout tables: master weight offsets and the packed MFMA layout;
+// the seeded weight initialisation; Adam's bias corrections.
+#include <math.h>
 #include <string.h>
 
 #include "gn_internal.h"
@@ -24,6 +26,35 @@ size_t num_params(int W, int pe) {
   if (W != 64 && W != 128) return 0;
   if (pe < 0 || pe > kMaxPe) return 0;
   return (size_t)11 * W * W + (size_t)59 * W + 3 + (size_t)84 * pe * W;
+}
+
+// SplitMix64's output function (Steele, Lea and Flood, OOPSLA 2014): a
+// bijective mix of a 64-bit counter, arithmetic modulo 2^64.
+static inline uint64_t splitmix64(uint64_t z) {
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+void seeded_weights(int W, int pe, uint64_t seed, float *w) {
+  LayerOff lo[kNumLayers];
+  layer_offsets(W, pe, lo);
+  for (int l = 0; l < kNumLayers; ++l) {
+    // He et al.'s uniform bound for ReLU layers on the matrix, 1/sqrt(fan_in)
+    // on the bias
+    const double wb = sqrt(6.0 / lo[l].in), bb = 1.0 / sqrt((double)lo[l].in);
+    const int64_t nw = (int64_t)lo[l].out * lo[l].in;
+    for (int64_t e = lo[l].w; e < lo[l].b + lo[l].out; ++e) {
+      const uint64_t x = splitmix64(seed + (uint64_t)(e + 1) * 0x9E3779B97F4A7C15ull);
+      const double u = (double)(x >> 11) * 0x1.0p-53;
+      w[e] = (float)((2.0 * u - 1.0) * (e < lo[l].w + nw ? wb : bb));
+    }
+  }
+}
+
+void adam_bias_corrections(float b1, float b2, int step, float *c1, float *c2) {
+  *c1 = (float)(1.0 / (1.0 - pow((double)b1, (double)step)));
+  *c2 = (float)(1.0 / (1.0 - pow((double)b2, (double)step)));
 }
 
 void make_packed_layout(int W, int pe, PackedLayout *pl) {

@@ -12,15 +12,18 @@ constexpr int kThreads = 256;
 __global__ __launch_bounds__(kThreads) void l1_partial_kernel(const float *__restrict__ y,
                                                               const float *__restrict__ t,
                                                               uint64_t n, float inv_n,
+                                                              const float *__restrict__ gscale,
                                                               float *__restrict__ grad,
                                                               float *__restrict__ partials) {
   __shared__ float red[kThreads];
   float s = 0.0f;
+  // the gradient's upstream factor (a device scalar) folded into 1 / n
+  const float gn = gscale ? inv_n * *gscale : inv_n;
   for (uint64_t i = (uint64_t)blockIdx.x * kThreads + threadIdx.x; i < n;
        i += (uint64_t)gridDim.x * kThreads) {
     const float d = y[i] - t[i];
     s += fabsf(d);
-    if (grad) grad[i] = d > 0.0f ? inv_n : (d < 0.0f ? -inv_n : 0.0f);
+    if (grad) grad[i] = d > 0.0f ? gn : (d < 0.0f ? -gn : 0.0f);
   }
   red[threadIdx.x] = s;
   __syncthreads();
@@ -170,12 +173,13 @@ __global__ __launch_bounds__(256) void ssim_bwd_kernel(const float *__restrict__
   grad[o] = accumulate ? grad[o] + d : d;
 }
 
-// loss = (1 - sum(partials) / count) / 2, summed in fp64 in a fixed order.
+// loss = (1 - sum(partials) / count) / 2, summed in fp32 in a fixed order
+// (a strided sum per thread, then a tree): deterministic.
 __global__ __launch_bounds__(256) void ssim_final_kernel(const float *__restrict__ partials,
-                                                         int64_t npart, double inv_count,
+                                                         int64_t npart, float inv_count,
                                                          float *__restrict__ loss) {
-  __shared__ double red[256];
-  double s = 0.0;
+  __shared__ float red[256];
+  float s = 0.0f;
   for (int64_t i = threadIdx.x; i < npart; i += 256) s += partials[i];
   red[threadIdx.x] = s;
   __syncthreads();
@@ -183,7 +187,7 @@ __global__ __launch_bounds__(256) void ssim_final_kernel(const float *__restrict
     if ((int)threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
     __syncthreads();
   }
-  if (threadIdx.x == 0) *loss = (float)((1.0 - red[0] * inv_count) * 0.5);
+  if (threadIdx.x == 0) *loss = (1.0f - red[0] * inv_count) * 0.5f;
 }
 
 }  // namespace
@@ -197,13 +201,13 @@ size_t dssim_workspace_bytes(int planes, int h, int w) {
 hipError_t launch_dssim(const float *out, const float *target, int planes, int h, int w,
                         float *loss, float *grad, int accumulate, float *ws, hipStream_t stream) {
   Gauss gs;
-  double e[kWin], z = 0.0;
+  float e[kWin], z = 0.0f;
   for (int i = 0; i < kWin; ++i) {
-    const double r = i - (kWin - 1) / 2.0;
-    e[i] = std::exp(-r * r / (2.0 * 1.5 * 1.5));
+    const float r = (float)i - (kWin - 1) / 2.0f;
+    e[i] = std::exp(-r * r / (2.0f * 1.5f * 1.5f));
     z += e[i];
   }
-  for (int i = 0; i < kWin; ++i) gs.g[i] = (float)(e[i] / z);
+  for (int i = 0; i < kWin; ++i) gs.g[i] = e[i] / z;
   const float C1 = 0.01f * 0.01f, C2 = 0.03f * 0.03f;     // (K L)^2 with L = 1
   const int hm = h - kWin + 1, wm = w - kWin + 1;
   const int64_t plane_m = (int64_t)planes * hm * wm;
@@ -213,20 +217,21 @@ hipError_t launch_dssim(const float *out, const float *target, int planes, int h
                      coef, plane_m, partials);
   const int64_t npart = (int64_t)gm.x * gm.y * gm.z;
   hipLaunchKernelGGL(ssim_final_kernel, dim3(1), dim3(256), 0, stream, partials, npart,
-                     1.0 / (double)plane_m, loss);
+                     1.0f / (float)plane_m, loss);
   if (grad) {
     const dim3 gp((w + kTile - 1) / kTile, (h + kTile - 1) / kTile, planes);
     hipLaunchKernelGGL(ssim_bwd_kernel, gp, dim3(256), 0, stream, out, target, h, w, gs, coef,
-                       plane_m, (float)(-0.5 / (double)plane_m), grad, accumulate);
+                       plane_m, -0.5f / (float)plane_m, grad, accumulate);
   }
   return hipGetLastError();
 }
 
 hipError_t launch_l1(const float *out, const float *target, uint64_t count, float *loss,
-                     float *grad, float *partials, int npart, hipStream_t stream) {
+                     float *grad, const float *grad_scale, float *partials, int npart,
+                     hipStream_t stream) {
   const float inv_n = count ? 1.0f / (float)count : 0.0f;
   hipLaunchKernelGGL(l1_partial_kernel, dim3(npart), dim3(kThreads), 0, stream, out, target,
-                     count, inv_n, grad, partials);
+                     count, inv_n, grad_scale, grad, partials);
   hipLaunchKernelGGL(l1_final_kernel, dim3(1), dim3(kThreads), 0, stream, partials, npart, inv_n,
                      loss);
   return hipGetLastError();

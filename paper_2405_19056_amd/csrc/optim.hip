@@ -4,7 +4,6 @@
 // updates.  Elementwise over the flat fp32 master vector (751 KB at W = 128):
 // one grid-stride pass, HBM-bound and a few microseconds.
 #include <algorithm>
-#include <cmath>
 
 #include "gn_internal.h"
 
@@ -36,10 +35,8 @@ __global__ __launch_bounds__(kThreads) void adam_kernel(float *__restrict__ w,
 
 }  // namespace
 
-hipError_t launch_adam(float *w, const float *g, float *m, float *v, int64_t n, int step, float lr,
-                       float b1, float b2, float eps, float wd, hipStream_t stream) {
-  const float c1 = (float)(1.0 / (1.0 - std::pow((double)b1, (double)step)));
-  const float c2 = (float)(1.0 / (1.0 - std::pow((double)b2, (double)step)));
+hipError_t launch_adam(float *w, const float *g, float *m, float *v, int64_t n, float c1, float c2,
+                       float lr, float b1, float b2, float eps, float wd, hipStream_t stream) {
   const int64_t blocks = std::min<int64_t>((n + kThreads - 1) / kThreads, 1024);
   hipLaunchKernelGGL(adam_kernel, dim3((unsigned)std::max<int64_t>(blocks, 1)), dim3(kThreads), 0,
                      stream, w, g, m, v, n, lr, b1, b2, eps, wd, c1, c2);

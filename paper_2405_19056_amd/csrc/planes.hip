@@ -27,9 +27,14 @@
 //                 over pixel chunks, partials reduced in a fixed order
 //                 (deterministic, no atomics).  Bias gradients come from a row
 //                 of ones appended to each activation block.
+//
+// With the canonical slot order (slot_order.h) prep also ranks every
+// pixel's slots, and slot step i gathers each pixel's slot of rank i: the
+// pool is an fp32 running sum whose order depends only on the slot records.
 #include <string.h>
 
 #include "gn_api_state.h"
+#include "slot_order.h"
 
 namespace gn {
 
@@ -47,6 +52,8 @@ struct BwdWorkspace {
   float *part_t2 = nullptr;  // T2 partials (accumulated over slots)
   float *part_t1 = nullptr;  // T1 slot-column partials (accumulated over slots)
   size_t part_bytes = 0, part_t2_bytes = 0, part_t1_bytes = 0;
+  uint8_t *perm = nullptr;   // canonical slot order: [rank][padded pixel] slot indices
+  size_t perm_bytes = 0;
   int max_chunks = 0;
 };
 
@@ -68,7 +75,6 @@ inline int rup(int x, int m) { return (x + m - 1) / m * m; }
 struct Blocks {
   int xb, a1, a2, st, u, zs, d1, d2, pl, g1, g2, z1, bi, px, y;
   int dy, dg2, dg1, dphi, dd2, dd1, dsig, dtau, dzin, du, da2, da1, dz2, dz1;
-  int zd;            // fp64 running sum of the pool: W rows of doubles (2 W float rows)
   int rows;
 };
 enum { PX_INV = 0, PX_M = 1 };     // rows of the per-pixel scalar block
@@ -102,7 +108,6 @@ Blocks make_blocks(int W, int pe) {
   b.dsig = take(W); b.dtau = take(W);    // adjacent: B1^T writes both at once
   b.dzin = take(W); b.du = take(W); b.da2 = take(W); b.da1 = take(W);
   b.dz2 = take(W); b.dz1 = take(W);
-  b.zd = take(2 * W);
   b.rows = r;
   return b;
 }
@@ -212,10 +217,7 @@ struct PgArgs {
   const float *pscale;   // per-pixel row multiplying the result, or null
   const float *post;     // per-pixel row multiplying after accumulation, or null
   float *out2;           // EP_BWD: second block that receives (or accumulates) the result
-  double *acc64;         // EP_FWD: fp64 block (row length = stride) that accumulates the
-                         // result (or starts, without accumulate); out gets it rounded
   int relu, accumulate, accumulate2;
-  int skip_out;          // with acc64: leave out unwritten (an intermediate slot)
 };
 
 __device__ __forceinline__ f32x4 ld4(const float *p) { return *(const f32x4 *)p; }
@@ -302,24 +304,8 @@ __global__ __launch_bounds__(kThreads) void plane_gemm_kernel(PgArgs a) {
           for (int t = 0; t < 4; ++t) v[t] = fmaxf(v[t], 0.0f);
         }
         v *= psc;
-        if (a.acc64) {
-          // the pool of Eq. (5) summed in fp64: exact for the terms met here,
-          // so its single rounding does not depend on the order of the slots
-          typedef double f64x2 __attribute__((ext_vector_type(2)));
-          f64x2 *zp = (f64x2 *)(a.acc64 + ix);
-          f64x2 z0 = f64x2{(double)v[0], (double)v[1]}, z1 = f64x2{(double)v[2], (double)v[3]};
-          if (a.accumulate) {
-            z0 += zp[0];
-            z1 += zp[1];
-          }
-          zp[0] = z0;
-          zp[1] = z1;
-          v = f32x4{(float)z0[0], (float)z0[1], (float)z1[0], (float)z1[1]};
-        } else if (a.accumulate) {
-          v += ld4(a.out + ix);
-        }
+        if (a.accumulate) v += ld4(a.out + ix);
         v *= pst;
-        if (a.acc64 && a.skip_out) continue;
       } else if (EP == EP_DZ2) {
         const f32x4 z = v + a.bias[m];
         const f32x4 d = ld4(a.add + ix);
@@ -348,6 +334,8 @@ struct PrepArgs {
   int hw, k, pool, W, pe;
   int64_t npx, stride;
   float *planes;
+  uint8_t *perm;     // canonical order: [rank][npx_pad] slot indices; null: input order
+  int64_t npx_pad;
   Blocks bl;
 };
 
@@ -389,6 +377,9 @@ __global__ __launch_bounds__(kThreads) void prep_kernel(PrepArgs a) {
   float cnt = 0.0f;
   const float *Lf = a.layers + (size_t)f * a.k * kNL * hw + q;
   for (int i = 0; i < a.k; ++i) cnt += Lf[((size_t)i * kNL + kAlpha) * hw] > 0.0f ? 1.0f : 0.0f;
+  if (a.perm && a.k > 1)      // slot i goes to its rank's row of the order table
+    for (int i = 0; i < a.k; ++i)
+      a.perm[(size_t)slot_rank(Lf, (size_t)hw, a.k, i) * a.npx_pad + p] = (uint8_t)i;
   const bool mean = a.pool == GN_POOL_MEAN;
   ROW(B.px + PX_INV)[p] = mean ? 1.0f / fmaxf(cnt, 1.0f) : 1.0f;
   ROW(B.zs + W)[p] = mean ? (cnt > 0.0f ? 1.0f : 0.0f) : cnt;
@@ -396,11 +387,13 @@ __global__ __launch_bounds__(kThreads) void prep_kernel(PrepArgs a) {
     ROW(B.dy + c)[p] = valid && a.grad_out ? a.grad_out[((size_t)f * kNOUT + c) * hw + q] : 0.0f;
 }
 
-// Slot i's 12 channels (and their encodings) and its mask m_i = [alpha > 0].
-__global__ __launch_bounds__(kThreads) void slot_gather_kernel(PrepArgs a, int slot) {
+// Step i's slot (the pixel's slot of rank i in canonical order, or slot i):
+// its 12 channels (and their encodings) and its mask m_i = [alpha > 0].
+__global__ __launch_bounds__(kThreads) void slot_gather_kernel(PrepArgs a, int step) {
   const int64_t p = (int64_t)blockIdx.x * kThreads + threadIdx.x;
   const int64_t pc = p < a.npx ? p : a.npx - 1;
   const int f = (int)(pc / a.hw), q = (int)(pc - (int64_t)f * a.hw), hw = a.hw;
+  const int slot = a.perm && a.k > 1 ? (int)a.perm[(size_t)step * a.npx_pad + p] : step;
   const float *Li = a.layers + ((size_t)f * a.k + slot) * kNL * hw + q;
   const Blocks &B = a.bl;
   const int nblk = pe_blocks(a.pe);
@@ -428,10 +421,9 @@ __global__ __launch_bounds__(kThreads) void stream_count_kernel(const float *__r
 }
 
 // Object streaming: the pool of Eq. (5) from the state, T3's input block:
-// zs[r] = Z[r] / max(c, 1) (mean) or Z[r] (sum), Z rounded from fp64 first,
-// and T3's bias scale row, as the forward's last slot epilogue and prep
-// compute them.
-__global__ __launch_bounds__(kThreads) void stream_pool_kernel(const double *__restrict__ Z,
+// zs[r] = Z[r] / max(c, 1) (mean) or Z[r] (sum), and T3's bias scale row, as
+// the forward's last slot epilogue and prep compute them.
+__global__ __launch_bounds__(kThreads) void stream_pool_kernel(const float *__restrict__ Z,
                                                                const float *__restrict__ cnt,
                                                                int64_t npx, int W, int mean,
                                                                float *__restrict__ zs,
@@ -440,7 +432,7 @@ __global__ __launch_bounds__(kThreads) void stream_pool_kernel(const double *__r
   if (p >= npx) return;
   const float c = cnt[p];
   const float inv = mean ? 1.0f / fmaxf(c, 1.0f) : 1.0f;
-  for (int r = 0; r < W; ++r) zs[(size_t)r * stride + p] = (float)Z[(size_t)r * npx + p] * inv;
+  for (int r = 0; r < W; ++r) zs[(size_t)r * stride + p] = Z[(size_t)r * npx + p] * inv;
   zs[(size_t)W * stride + p] = mean ? (c > 0.0f ? 1.0f : 0.0f) : c;
 }
 
@@ -662,6 +654,7 @@ void gn_bwd_free(gn_handle *h) {
   (void)hipFree(h->bwd->part);
   (void)hipFree(h->bwd->part_t2);
   (void)hipFree(h->bwd->part_t1);
+  (void)hipFree(h->bwd->perm);
   delete h->bwd;
   h->bwd = nullptr;
 }
@@ -669,7 +662,7 @@ void gn_bwd_free(gn_handle *h) {
 size_t gn_bwd_bytes(gn_handle *h) {
   if (!h->bwd) return 0;
   return h->bwd->plane_bytes + h->bwd->frag_bytes + h->bwd->part_bytes + h->bwd->part_t2_bytes +
-         h->bwd->part_t1_bytes;
+         h->bwd->part_t1_bytes + h->bwd->perm_bytes;
 }
 
 static hipError_t ensure_workspace(gn_handle *h, int64_t npx_pad) {
@@ -698,6 +691,9 @@ static hipError_t ensure_workspace(gn_handle *h, int64_t npx_pad) {
   if (e == hipSuccess) e = hipMalloc((void **)&ws->part, ws->part_bytes);
   if (e == hipSuccess) e = hipMalloc((void **)&ws->part_t2, ws->part_t2_bytes);
   if (e == hipSuccess) e = hipMalloc((void **)&ws->part_t1, ws->part_t1_bytes);
+  // the slot-order table: one byte per slot of the handle's largest count
+  ws->perm_bytes = (size_t)std::max(h->cfg.k_max, 1) * npx_pad;
+  if (e == hipSuccess) e = hipMalloc((void **)&ws->perm, ws->perm_bytes);
   if (e != hipSuccess) gn_bwd_free(h);
   return e;
 }
@@ -743,7 +739,10 @@ class Pipeline {
     layer_offsets(W_, pe_, lo_);
   }
 
-  gn_status begin(const gn_frame *f, const float *grad_out, const char *what) {
+  // canonical: pool each pixel's slots in canonical order (object streaming
+  // passes false: it adds objects in call order).
+  gn_status begin(const gn_frame *f, const float *grad_out, const char *what,
+                  bool canonical = true) {
     const int64_t hw = (int64_t)f->h * f->w;
     npx_ = (int64_t)f->n * hw;
     npx_pad_ = (npx_ + kChunkPx - 1) / kChunkPx * kChunkPx;
@@ -768,6 +767,8 @@ class Pipeline {
     pa_.npx = npx_;
     pa_.stride = ld_;
     pa_.planes = ws_->planes;
+    pa_.perm = canonical && gn_slot_kmax(h_) > 1 ? ws_->perm : nullptr;
+    pa_.npx_pad = npx_pad_;
     pa_.bl = bl_;
     hipLaunchKernelGGL(pack_ops_kernel, dim3((unsigned)((ops_.total + kThreads - 1) / kThreads)),
                        dim3(kThreads), 0, s_, wm_, ops_, ws_->frag);
@@ -783,11 +784,9 @@ class Pipeline {
     fwd(O_T1S, bl_.st, bl_.u, L_T1, false);                  // u
   }
 
-  // Z = sum_i m_i relu(W_T2 z1_i + b_T2), then / max(c, 1) for the mean.
-  // exact_pool: the sum in fp64, rounded once after the last slot, so the
-  // result does not depend on the slot order (the forward's outputs); the
-  // backward's recompute keeps the fp32 running sum.
-  void slots(bool exact_pool = true) {
+  // Z = sum_i m_i relu(W_T2 z1_i + b_T2), an fp32 running sum over the
+  // slots in gather order, then / max(c, 1) for the mean.
+  void slots() {
     const bool mean = h_->cfg.pool == GN_POOL_MEAN;
     for (int i = 0; i < K_; ++i) {
       gather(i);
@@ -797,10 +796,6 @@ class Pipeline {
       a.relu = 1;
       a.pscale = plane(bl_.px + PX_M);
       a.accumulate = i > 0;
-      if (exact_pool) {
-        a.acc64 = dplane(bl_.zd);
-        a.skip_out = i < K_ - 1;
-      }
       if (i == K_ - 1 && mean) a.post = plane(bl_.px + PX_INV);
       gemm(O_T2, EP_FWD, bl_.z1, bl_.zs, a);
     }
@@ -913,11 +908,11 @@ class Pipeline {
     }
   }
 
-  // ---- object streaming: the state is [sigma (W fp32 rows); Z (W fp64
-  // rows); count (fp32)] of npx elements per row.  begin: F, sigma out.  accumulate: sigma in, u,
-  // the call's slots added to Z (continued from the state unless fresh), the
-  // count.  finish: sigma and the pool in, T3, B, R.  The arithmetic and its
-  // order are the forward's.
+  // ---- object streaming: the state is [sigma (W rows); Z (W rows); count]
+  // of npx fp32 elements per row.  begin: F, sigma out.  accumulate: sigma
+  // in, u, the call's slots added to Z (continued from the state unless
+  // fresh), the count.  finish: sigma and the pool in, T3, B, R.  The
+  // arithmetic and its order are the input-order forward's.
   void stream_begin(float *state) {
     trunk();
     copy_rows(state, npx_, plane(bl_.st), ld_, W_);
@@ -925,8 +920,8 @@ class Pipeline {
   void stream_accumulate(float *state, bool fresh) {
     copy_rows(plane(bl_.st), ld_, state, npx_, W_);
     fwd(O_T1S, bl_.st, bl_.u, L_T1, false);                  // u, as in trunk()
-    double *z64 = (double *)(state + (size_t)W_ * npx_);
-    if (!fresh) copy_rows(dplane(bl_.zd), ld_, z64, npx_, W_);
+    float *z = state + (size_t)W_ * npx_;
+    if (!fresh) copy_rows(plane(bl_.zs), ld_, z, npx_, W_);
     for (int i = 0; i < K_; ++i) {
       gather(i);
       z1();
@@ -935,13 +930,14 @@ class Pipeline {
       a.relu = 1;
       a.pscale = plane(bl_.px + PX_M);
       a.accumulate = i > 0 || !fresh;
-      a.acc64 = dplane(bl_.zd);
-      a.skip_out = 1;                                         // the state keeps the sum
       gemm(O_T2, EP_FWD, bl_.z1, bl_.zs, a);
     }
-    copy_rows(z64, npx_, dplane(bl_.zd), ld_, W_);
+    if (K_ > 0 || fresh) {
+      if (K_ == 0) fill_rows(bl_.zs, W_);
+      copy_rows(z, npx_, plane(bl_.zs), ld_, W_);
+    }
     hipLaunchKernelGGL(stream_count_kernel, pgrid(), dim3(kThreads), 0, s_, pa_.layers, K_, hw_,
-                       npx_, state + (size_t)3 * W_ * npx_, fresh ? 1 : 0);
+                       npx_, state + (size_t)2 * W_ * npx_, fresh ? 1 : 0);
   }
   void stream_finish(const float *state, bool fresh, float *out) {
     copy_rows(plane(bl_.st), ld_, state, npx_, W_);
@@ -949,8 +945,8 @@ class Pipeline {
       fill_rows(bl_.zs, W_ + 1);           // no object: empty pool, zero bias scale
     } else {
       hipLaunchKernelGGL(stream_pool_kernel, pgrid(), dim3(kThreads), 0, s_,
-                         (const double *)(state + (size_t)W_ * npx_),
-                         state + (size_t)3 * W_ * npx_, npx_, W_,
+                         (const float *)(state + (size_t)W_ * npx_),
+                         state + (size_t)2 * W_ * npx_, npx_, W_,
                          h_->cfg.pool == GN_POOL_MEAN ? 1 : 0, plane(bl_.zs), ld_);
     }
     head();
@@ -984,8 +980,6 @@ class Pipeline {
       e_ = hipMemcpy2DAsync(dst, sizeof(T) * dst_len, src, sizeof(T) * src_len, sizeof(T) * npx_,
                             n, hipMemcpyDeviceToDevice, s_);
   }
-  // a block of fp64 rows (two float rows each) as doubles, row pitch ld_
-  double *dplane(int r) const { return (double *)plane(r); }
 
   // One plane GEMM: op `o` from block `xrow` into block `orow`.
   void gemm(Op o, int ep, int xrow, int orow, PgArgs a) {
@@ -1108,14 +1102,14 @@ gn_status gn_planes_calibrate(gn_handle *h, const gn_frame *frame, unsigned *ama
 // Object streaming on the plane pipeline (GN_FP32 handles); state holds
 // gn_planes_stream_bytes floats.
 size_t gn_planes_stream_bytes(int W, int64_t npx) {
-  return sizeof(float) * (size_t)(3 * W + 1) * (size_t)npx;   // sigma, fp64 Z, count
+  return sizeof(float) * (size_t)(2 * W + 1) * (size_t)npx;   // sigma, Z, count
 }
 
 gn_status gn_planes_stream(gn_handle *h, const gn_frame *frame, int mode, float *state, int fresh,
                            float *out, hipStream_t s) {
   return with_device(h, [&]() {
     Pipeline p(h, s);
-    gn_status st = p.begin(frame, nullptr, "fp32 stream");
+    gn_status st = p.begin(frame, nullptr, "fp32 stream", false);
     if (st != GN_OK) return st;
     if (mode == FWD_BEGIN)
       p.stream_begin(state);
@@ -1140,7 +1134,7 @@ extern "C" gn_status glassnet_backward(gn_handle *h, const gn_frame *frame,
     gn_status st2 = p.begin(frame, grad_out, "backward workspace");
     if (st2 != GN_OK) return st2;
     p.trunk();
-    p.slots(false);
+    p.slots();
     p.head();
     p.backward(grad_w);
     return p.finish("backward launch");

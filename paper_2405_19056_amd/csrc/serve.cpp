@@ -70,7 +70,7 @@ class HipExecutor : public gn::serve::Executor {
     if (e == hipSuccess)
       e = gn::launch_fwd_mfma(h_->W, h_->cfg.precision, h_->cfg.pool, h_->d_packed, h_->pl,
                               nullptr, d_descs_, d_tiles_[slot], ntiles, h_->act_scale,
-                              h_->num_cus, h_->d_sig_scratch[1], stream_);
+                              h_->num_cus, h_->d_sig_scratch[1], gn_slot_kmax(h_), stream_);
     if (e == hipSuccess) e = hipEventRecord(ev_[slot], stream_);
     if (e != hipSuccess) {
       h_->poisoned = true;

@@ -1,0 +1,626 @@
+// The spatial GlassNet networks (Sec. 3.4): F and B as U-Nets, h and R as
+// CNNs whose first layers are 3 x 3 convolutions, on the gfx950 matrix cores
+// (bf16 operands, fp32 accumulation).
+//
+// Reading of the architecture (the paper gives no widths, depths or levels):
+//   U-Net (F on [G; s], B on [sigma; tau]): e1 = relu(conv3 x); d = 2 x 2
+//     average of e1; m = relu(conv3 d) at half resolution; u = m repeated
+//     2 x 2; e2 = relu(conv3 [e1; u]); out = conv1 e2.
+//   h(b_i, sigma) = conv1 relu(conv1 relu(conv3 [b_i; sigma])); the pool of
+//     Eq. (5) per pixel over the buffers with alpha > 0 there.
+//   R = conv1 relu(conv3 relu(conv3 [phi; L_d])) with 3 outputs.
+// conv3: 3 x 3, zero padding of one pixel; conv1: 1 x 1; every conv has a
+// bias.  Width W (64 or 128) throughout.
+//
+// Layout.  Activations live in HBM as bf16 [n][H][W][C] (channels innermost,
+// C a multiple of 32), so the 8 channels one lane presents to the matrix
+// core for one pixel are one 16-byte load.  Every conv is an implicit GEMM,
+// Y^T = A X^T: the weights are the A operand (16 output channels per M-tile),
+// 16 pixels of one row the B operand, K = (tap, input channel) in 32-deep
+// steps; the zero padding is a zero B fragment.  Two inputs can be
+// concatenated along the channels, the second optionally at half resolution
+// and read through a 2 x 2 nearest upsample (the U-Net's skip join), so the
+// concatenation and the upsample are never materialised.
+//
+// Work split.  A workgroup of 8 waves owns 512 output pixels, each wave 64
+// consecutive pixels of one row (4 N-tiles) and every output channel (up to
+// 8 M-tiles: 32 accumulators of 4 floats).  The weights stream through LDS
+// in chunks of kChunk K-steps (direct global->LDS copies, two buffers, one
+// chunk ahead), every fragment read once per wave and used for its 4 N-tiles.
+// The input fragments of the next K-step are loaded while the current one's
+// MFMAs run.
+//
+// Epilogues: bias (optionally times a per-pixel scale), an added fp32 plane
+// block (h's hoisted sigma part u), ReLU, then one of: bf16 activation
+// store, fp32 store, the masked pool of Eq. (5) (Z += [alpha > 0] relu(.)
+// in fp32), or R's 3 outputs to the caller's [n][3][H][W] fp32 image.
+#include "gn_internal.h"
+
+namespace gn {
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kWaves = 8, kThreads = kWaves * 64;
+constexpr int kNT = 4;                       // N-tiles (16 pixels) per wave
+constexpr int kWavePx = kNT * 16;            // pixels per wave (one row segment)
+constexpr int kChunk = 4;                    // K-steps per LDS weight chunk
+constexpr int kFrag = 1024;                  // one A fragment: 64 lanes x 16 bytes
+
+__device__ __forceinline__ uint32_t pk_bf16(float a, float b) {
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector(f32x2{a, b}, bf16x2));
+}
+
+__device__ __forceinline__ f32x4 mma(u32x4 a, u32x4 b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a),
+                                                 __builtin_bit_cast(bf16x8, b), c, 0, 0, 0);
+}
+
+__device__ __forceinline__ float bf16_to_f32(uint16_t v) {
+  return __uint_as_float((uint32_t)v << 16);
+}
+
+}  // namespace
+
+// One convolution launch (host fills it; see SpConv in the launcher).
+struct SpConvArgs {
+  const uint8_t *in0;       // bf16 [n][H][W][c0]
+  const uint8_t *in1;       // bf16 [n][H1][W1][c1] or null; up1: H1 = H / 2, W1 = W / 2
+  int c0, c1, up1;
+  const uint8_t *wfrag;     // A fragments [step][mt][lane] (16 B each)
+  const float *bias;        // [MT * 16] (zero past the real outputs)
+  int steps;                // K-steps = taps x (c0 + c1) / 32
+  int ksize;                // 1 or 3
+  int n, H, Wd;             // output (= in0) size
+  int cout_pad;             // output channel count of the bf16 / fp32 layouts (MT * 16)
+  // epilogue
+  const float *bscale;      // [n][H][W] per-pixel factor of the bias, or null
+  const float *add;         // fp32 [n][H][W][cout_pad] added before ReLU, or null
+  int relu;
+  uint8_t *out_bf;          // bf16 [n][H][W][cout_pad], or null
+  float *out_f32;           // fp32 [n][H][W][cout_pad], or null
+  float *pool;              // fp32 [n][H][W][cout_pad]: += [alpha > 0] value, or null
+  const float *alpha;       // the slot's alpha plane: [n] frames of stride alpha_fstride
+  int64_t alpha_fstride;    // floats between frames of the alpha plane
+  int pool_first;           // the pool starts from zero (first slot)
+  float *out_rgb;           // fp32 [n][3][H][W] (3 real outputs), or null
+};
+
+namespace {
+
+template <int MT>
+__global__ __launch_bounds__(kThreads) void sp_conv_kernel(SpConvArgs a) {
+  extern __shared__ __attribute__((aligned(1024))) uint8_t lds[];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int g = lane >> 4, col = lane & 15;
+  const int H = a.H, Wd = a.Wd;
+  const int segs = (Wd + kWavePx - 1) / kWavePx;          // row segments per row
+  const int64_t seg = (int64_t)blockIdx.x * kWaves + wave;
+  const int64_t nseg = (int64_t)a.n * H * segs;
+  const bool live = seg < nseg;
+  const int64_t sg = live ? seg : nseg - 1;
+  const int f = (int)(sg / ((int64_t)H * segs));
+  const int rem = (int)(sg - (int64_t)f * H * segs);
+  const int y = rem / segs, x0 = (rem - (rem / segs) * segs) * kWavePx;
+  const int r = a.ksize >> 1;
+  const int cb0 = a.c0 >> 5;                              // 32-channel blocks of in0
+  const int cbt = (a.c0 + a.c1) >> 5;
+
+  constexpr int kChunkBytes = kChunk * MT * kFrag;
+  const int nchunks = (a.steps + kChunk - 1) / kChunk;
+  auto fill = [&](int c) {
+    const int s0 = c * kChunk, s1 = min(a.steps, s0 + kChunk);
+    const int64_t bytes = (int64_t)(s1 - s0) * MT * kFrag;
+    const uint8_t *src = a.wfrag + (int64_t)s0 * MT * kFrag;
+    for (int64_t off = (int64_t)wave * kFrag; off < bytes; off += kWaves * kFrag)
+      __builtin_amdgcn_global_load_lds((const void *)(src + off + lane * 16),
+                                       (__attribute__((address_space(3))) void *)(lds + (c & 1) * kChunkBytes + off),
+                                       16, 0, 0);
+  };
+
+  // B fragment of K-step s for N-tile t: pixel (y + dy - r, x0 + 16 t + col + dx - r),
+  // channels 32 cb + 8 g .. + 7 of the concatenated input; zero outside the frame
+  auto load_b = [&](int s, u32x4 (&b)[kNT]) {
+    const int tap = s / cbt, cb = s - tap * cbt;
+    const int dy = tap / a.ksize - r, dx = tap % a.ksize - r;
+    const int yy = y + dy;
+    const bool yok = yy >= 0 && yy < H;
+#pragma unroll
+    for (int t = 0; t < kNT; ++t) {
+      const int xx = x0 + 16 * t + col + dx;
+      u32x4 v = {0u, 0u, 0u, 0u};
+      if (yok && xx >= 0 && xx < Wd) {
+        if (cb < cb0) {
+          v = *(const u32x4 *)(a.in0 + ((((int64_t)f * H + yy) * Wd + xx) * a.c0 + 32 * cb + 8 * g) * 2);
+        } else if (a.up1) {
+          const int H1 = H >> 1, W1 = Wd >> 1;
+          v = *(const u32x4 *)(a.in1 + ((((int64_t)f * H1 + (yy >> 1)) * W1 + (xx >> 1)) * a.c1 +
+                                        32 * (cb - cb0) + 8 * g) * 2);
+        } else {
+          v = *(const u32x4 *)(a.in1 + ((((int64_t)f * H + yy) * Wd + xx) * a.c1 +
+                                        32 * (cb - cb0) + 8 * g) * 2);
+        }
+      }
+      b[t] = v;
+    }
+  };
+
+  f32x4 acc[kNT][MT];
+#pragma unroll
+  for (int t = 0; t < kNT; ++t)
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) acc[t][mt] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+  fill(0);
+  u32x4 bcur[kNT], bnext[kNT];
+  load_b(0, bcur);
+  for (int c = 0; c < nchunks; ++c) {
+    // the chunk's weights have landed (each wave's own copies, then everyone's)
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    __syncthreads();
+    if (c + 1 < nchunks) fill(c + 1);
+    const uint8_t *Wc = lds + (c & 1) * kChunkBytes;
+    const int s0 = c * kChunk, s1 = min(a.steps, s0 + kChunk);
+    for (int s = s0; s < s1; ++s) {
+      if (s + 1 < a.steps) load_b(s + 1, bnext);     // the next step's inputs, in flight
+      const uint8_t *Ws = Wc + (int64_t)(s - s0) * MT * kFrag;
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt) {
+        const u32x4 w = *(const u32x4 *)(Ws + mt * kFrag + lane * 16);
+#pragma unroll
+        for (int t = 0; t < kNT; ++t) acc[t][mt] = mma(w, bcur[t], acc[t][mt]);
+      }
+#pragma unroll
+      for (int t = 0; t < kNT; ++t) bcur[t] = bnext[t];
+    }
+  }
+
+  if (!live) return;
+  // ---- epilogue: lane (g, col) holds output channels 16 mt + 4 g + j of pixel col
+#pragma unroll
+  for (int t = 0; t < kNT; ++t) {
+    const int xx = x0 + 16 * t + col;
+    if (xx >= Wd) continue;
+    const int64_t px = ((int64_t)f * H + y) * Wd + xx;
+    const float bs = a.bscale ? a.bscale[px] : 1.0f;
+    float m = 1.0f;
+    if (a.pool) m = a.alpha[(int64_t)f * a.alpha_fstride + (int64_t)y * Wd + xx] > 0.0f ? 1.0f : 0.0f;
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) {
+      const int c0 = 16 * mt + 4 * g;
+      const f32x4 bv = *(const f32x4 *)(a.bias + c0);
+      f32x4 v = acc[t][mt] + bv * bs;
+      if (a.add) v += *(const f32x4 *)(a.add + px * a.cout_pad + c0);
+      if (a.relu) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) v[j] = fmaxf(v[j], 0.0f);
+      }
+      if (a.out_bf) {
+        uint2 pk = {pk_bf16(v[0], v[1]), pk_bf16(v[2], v[3])};
+        *(uint2 *)(a.out_bf + (px * a.cout_pad + c0) * 2) = pk;
+      }
+      if (a.out_f32) *(f32x4 *)(a.out_f32 + px * a.cout_pad + c0) = v;
+      if (a.pool) {
+        f32x4 *zp = (f32x4 *)(a.pool + px * a.cout_pad + c0);
+        const f32x4 z = a.pool_first ? f32x4{0.f, 0.f, 0.f, 0.f} : *zp;
+        *zp = z + v * m;
+      }
+      if (a.out_rgb && mt == 0 && g == 0) {
+        const int64_t hw = (int64_t)H * Wd, q = (int64_t)y * Wd + xx;
+        a.out_rgb[((int64_t)f * 3 + 0) * hw + q] = v[0];
+        a.out_rgb[((int64_t)f * 3 + 1) * hw + q] = v[1];
+        a.out_rgb[((int64_t)f * 3 + 2) * hw + q] = v[2];
+      }
+    }
+  }
+}
+
+// ---- input packing and the pooling steps ------------------------------------
+// x = [G 0..13; scene 0..15; 0, 0] as bf16 [n][H][W][32].
+__global__ void sp_pack_x_kernel(const float *__restrict__ gbuf, const float *__restrict__ scene,
+                                 int64_t npx, int hw, uint8_t *__restrict__ x) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= npx) return;
+  const int f = (int)(p / hw), q = (int)(p - (int64_t)f * hw);
+  uint32_t w[16];
+  for (int j = 0; j < 16; ++j) {
+    float v[2];
+    for (int e = 0; e < 2; ++e) {
+      const int c = 2 * j + e;
+      v[e] = c < kNG ? gbuf[((int64_t)f * kNG + c) * hw + q]
+                     : (c < kNG + kNS ? scene[(int64_t)f * kNS + c - kNG] : 0.0f);
+    }
+    w[j] = pk_bf16(v[0], v[1]);
+  }
+  u32x4 *dst = (u32x4 *)(x + p * 64);
+  for (int j = 0; j < 4; ++j) dst[j] = u32x4{w[4 * j], w[4 * j + 1], w[4 * j + 2], w[4 * j + 3]};
+}
+
+// `nch` planes (plane stride hw, frame stride fstride floats) from `src` as
+// bf16 [n][H][W][32], zero past nch.
+__global__ void sp_pack_planes_kernel(const float *__restrict__ src, int nch, int64_t fstride,
+                                      int64_t npx, int hw, uint8_t *__restrict__ x) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= npx) return;
+  const int f = (int)(p / hw), q = (int)(p - (int64_t)f * hw);
+  uint32_t w[16];
+  for (int j = 0; j < 16; ++j) {
+    float v[2];
+    for (int e = 0; e < 2; ++e) {
+      const int c = 2 * j + e;
+      v[e] = c < nch ? src[(int64_t)f * fstride + (int64_t)c * hw + q] : 0.0f;
+    }
+    w[j] = pk_bf16(v[0], v[1]);
+  }
+  u32x4 *dst = (u32x4 *)(x + p * 64);
+  for (int j = 0; j < 4; ++j) dst[j] = u32x4{w[4 * j], w[4 * j + 1], w[4 * j + 2], w[4 * j + 3]};
+}
+
+// 2 x 2 average of a bf16 [n][H][W][C] block (H, W even) into [n][H/2][W/2][C]:
+// one thread per output pixel and 8 channels, the sum in fp32.
+__global__ void sp_avgpool_kernel(const uint8_t *__restrict__ in, int n, int H, int Wd, int C,
+                                  uint8_t *__restrict__ out) {
+  const int H2 = H >> 1, W2 = Wd >> 1, cg = C >> 3;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t total = (int64_t)n * H2 * W2 * cg;
+  if (i >= total) return;
+  const int c8 = (int)(i % cg);
+  const int64_t p = i / cg;
+  const int x = (int)(p % W2);
+  const int64_t fy = p / W2;
+  const int yy = (int)(fy % H2), f = (int)(fy / H2);
+  float s[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  for (int dy = 0; dy < 2; ++dy)
+    for (int dx = 0; dx < 2; ++dx) {
+      const uint16_t *src =
+          (const uint16_t *)(in + ((((int64_t)f * H + 2 * yy + dy) * Wd + 2 * x + dx) * C + 8 * c8) * 2);
+      for (int j = 0; j < 8; ++j) s[j] += bf16_to_f32(src[j]);
+    }
+  uint32_t w[4];
+  for (int j = 0; j < 4; ++j) w[j] = pk_bf16(0.25f * s[2 * j], 0.25f * s[2 * j + 1]);
+  *(u32x4 *)(out + (p * C + 8 * c8) * 2) = u32x4{w[0], w[1], w[2], w[3]};
+}
+
+// The pool of Eq. (5) into T's last layer: the active-slot count c of every
+// pixel, zs = Z / max(c, 1) (mean) or Z (sum) as bf16 [n][H][W][Wc], and the
+// per-pixel factor of that layer's bias ([c > 0] for the mean, c for the
+// sum).  With no slot Z is never written: zs = 0.
+__global__ void sp_pool_finish_kernel(const float *__restrict__ Z, const float *__restrict__ layers,
+                                      int k, int64_t npx, int hw, int Wc, int mean,
+                                      uint8_t *__restrict__ zs, float *__restrict__ bscale) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= npx) return;
+  const int f = (int)(p / hw), q = (int)(p - (int64_t)f * hw);
+  float c = 0.0f;
+  for (int i = 0; i < k; ++i)
+    c += layers[(((int64_t)f * k + i) * kNL + kAlpha) * hw + q] > 0.0f ? 1.0f : 0.0f;
+  const float inv = mean ? 1.0f / fmaxf(c, 1.0f) : 1.0f;
+  bscale[p] = mean ? (c > 0.0f ? 1.0f : 0.0f) : c;
+  for (int ch = 0; ch < Wc; ch += 8) {
+    uint32_t w[4];
+    for (int j = 0; j < 4; ++j) {
+      const float a = k > 0 ? Z[p * Wc + ch + 2 * j] * inv : 0.0f;
+      const float b = k > 0 ? Z[p * Wc + ch + 2 * j + 1] * inv : 0.0f;
+      w[j] = pk_bf16(a, b);
+    }
+    *(u32x4 *)(zs + (p * Wc + ch) * 2) = u32x4{w[0], w[1], w[2], w[3]};
+  }
+}
+
+// Weight fragments of one conv: element e of fragment (step, mt), lane l,
+// position j holds W[16 mt + (l & 15)][ci][tap] for step = tap * cbt + cb and
+// concatenated input channel 32 cb + 8 (l >> 4) + j, mapped to the master
+// input column (zero for padding channels and rows past cout).
+struct SpPackDesc {
+  int64_t woff;             // float offset of the weight tensor [cout][cin][k][k]
+  int64_t out_off;          // byte offset of the fragments in the packed buffer
+  int cout, cin, k;         // master tensor shape
+  int col0;                 // first master input column this conv multiplies
+  int c0real, c0pad, c1real, c1pad;   // its two sources (channels, padded to 32)
+  int mt;                   // M-tiles
+};
+
+__global__ void sp_pack_weights_kernel(const float *__restrict__ master, SpPackDesc d,
+                                       uint8_t *__restrict__ packed) {
+  const int cbt = (d.c0pad + d.c1pad) >> 5;
+  const int steps = d.k * d.k * cbt;
+  const int64_t n = (int64_t)steps * d.mt * 64 * 8;
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  const int j = (int)(e & 7), l = (int)((e >> 3) & 63);
+  const int64_t frag = e >> 9;
+  const int mt = (int)(frag % d.mt), step = (int)(frag / d.mt);
+  const int tap = step / cbt, cb = step - tap * cbt;
+  const int row = 16 * mt + (l & 15);
+  const int cc = 32 * cb + 8 * (l >> 4) + j;           // concatenated padded channel
+  int ci = -1;
+  if (cc < d.c0pad) {
+    if (cc < d.c0real) ci = cc;
+  } else if (cc - d.c0pad < d.c1real) {
+    ci = d.c0real + (cc - d.c0pad);
+  }
+  float v = 0.0f;
+  if (row < d.cout && ci >= 0)
+    v = master[d.woff + (((int64_t)row * d.cin + d.col0 + ci) * d.k * d.k) + tap];
+  ((__bf16 *)(packed + d.out_off))[e] = (__bf16)v;
+}
+
+__global__ void sp_pack_bias_kernel(const float *__restrict__ master, int64_t boff, int cout,
+                                    int cpad, float *__restrict__ out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < cpad) out[i] = i < cout ? master[boff + i] : 0.0f;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Host side: the layer sequence.
+
+// The 14 convolutions (and T1's split into its buffer and sigma parts).
+enum SpConvId {
+  SP_F1, SP_F2, SP_F3, SP_F4, SP_T1B, SP_T1S, SP_T2, SP_T3, SP_B1, SP_B2, SP_B3, SP_B4,
+  SP_R1, SP_R2, SP_R3, kSpConvs
+};
+
+struct SpLayout {
+  int W;
+  SpPackDesc d[kSpConvs];
+  int64_t bias_off[kSpConvs];      // float offset of each conv's padded bias in the bias block
+  int64_t frag_bytes, bias_floats;
+};
+
+static int64_t sp_master_offsets(int W, int64_t woff[14], int64_t boff[14], int cout[14],
+                                 int cin[14], int ks[14]) {
+  const int spec[14][3] = {{W, kNG + kNS, 3}, {W, W, 3}, {W, 2 * W, 3}, {W, W, 1},
+                           {W, kNL + W, 3}, {W, W, 1}, {W, W, 1},
+                           {W, 2 * W, 3}, {W, W, 3}, {W, 2 * W, 3}, {W, W, 1},
+                           {W, W + 3, 3}, {W, W, 3}, {kNOUT, W, 1}};
+  int64_t off = 0;
+  for (int i = 0; i < 14; ++i) {
+    cout[i] = spec[i][0];
+    cin[i] = spec[i][1];
+    ks[i] = spec[i][2];
+    woff[i] = off;
+    off += (int64_t)cout[i] * cin[i] * ks[i] * ks[i];
+    boff[i] = off;
+    off += cout[i];
+  }
+  return off;
+}
+
+size_t spatial_num_params(int W) {
+  if (W != 64 && W != 128) return 0;
+  int64_t wo[14], bo[14];
+  int co[14], ci[14], k[14];
+  return (size_t)sp_master_offsets(W, wo, bo, co, ci, k);
+}
+
+static SpLayout sp_layout(int W) {
+  int64_t wo[14], bo[14];
+  int co[14], ci[14], k[14];
+  sp_master_offsets(W, wo, bo, co, ci, k);
+  // master tensor index of every conv; (col0, sources) of each
+  struct M { int m, col0, c0real, c0pad, c1real, c1pad; };
+  const M map[kSpConvs] = {
+      {0, 0, kNG + kNS, 32, 0, 0},   {1, 0, W, W, 0, 0},  {2, 0, W, W, W, W}, {3, 0, W, W, 0, 0},
+      {4, 0, kNL, 32, 0, 0},         {4, kNL, W, W, 0, 0},                     // T1: b part, sigma part
+      {5, 0, W, W, 0, 0},            {6, 0, W, W, 0, 0},
+      {7, 0, W, W, W, W},            {8, 0, W, W, 0, 0},  {9, 0, W, W, W, W}, {10, 0, W, W, 0, 0},
+      {11, 0, W, W, 3, 32},          {12, 0, W, W, 0, 0}, {13, 0, W, W, 0, 0}};
+  SpLayout L;
+  L.W = W;
+  int64_t fb = 0, bf = 0;
+  for (int c = 0; c < kSpConvs; ++c) {
+    const M &m = map[c];
+    SpPackDesc &d = L.d[c];
+    d.woff = wo[m.m];
+    d.cout = co[m.m];
+    d.cin = ci[m.m];
+    d.k = k[m.m];
+    d.col0 = m.col0;
+    d.c0real = m.c0real;
+    d.c0pad = m.c0pad;
+    d.c1real = m.c1real;
+    d.c1pad = m.c1pad;
+    d.mt = (d.cout + 15) / 16;
+    d.out_off = fb;
+    fb += (int64_t)d.k * d.k * ((d.c0pad + d.c1pad) / 32) * d.mt * kFrag;
+    L.bias_off[c] = bf;
+    bf += d.mt * 16;
+  }
+  L.frag_bytes = fb;
+  L.bias_floats = bf;
+  return L;
+}
+
+// Master bias offset of conv c (T1's two parts share T1's bias; the sigma
+// part carries it, the buffer part adds none).
+static int64_t sp_bias_master(int W, int c, bool *zero) {
+  int64_t wo[14], bo[14];
+  int co[14], ci[14], k[14];
+  sp_master_offsets(W, wo, bo, co, ci, k);
+  const int m[kSpConvs] = {0, 1, 2, 3, 4, 4, 5, 6, 7, 8, 9, 10, 11, 12, 13};
+  *zero = c == SP_T1B;
+  return bo[m[c]];
+}
+
+size_t spatial_weight_bytes(int W) {
+  const SpLayout L = sp_layout(W);
+  return (size_t)L.frag_bytes + sizeof(float) * (size_t)L.bias_floats;
+}
+
+// Device bytes of the activations a call of n frames of H x W needs.
+size_t spatial_workspace_bytes(int W, int n, int H, int Wd) {
+  const int64_t px = (int64_t)n * H * Wd, half = px / 4;
+  // bf16: x/b/ld (32 ch), e1, e2, sigma, tau, z1, zs, phi, r1, r2 (W ch each),
+  // half-res d and m (W ch); fp32: u and Z (W ch), bscale
+  return (size_t)(2 * (px * 32 + 9 * px * W + 2 * half * W) + 4 * (2 * px * W + px));
+}
+
+hipError_t spatial_pack(const float *master, int W, uint8_t *packed, hipStream_t s) {
+  const SpLayout L = sp_layout(W);
+  float *bias = (float *)(packed + L.frag_bytes);
+  for (int c = 0; c < kSpConvs; ++c) {
+    const SpPackDesc &d = L.d[c];
+    const int64_t n = (int64_t)d.k * d.k * ((d.c0pad + d.c1pad) / 32) * d.mt * 64 * 8;
+    hipLaunchKernelGGL(sp_pack_weights_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
+                       master, d, packed);
+    bool zero = false;
+    const int64_t bo = sp_bias_master(W, c, &zero);
+    hipLaunchKernelGGL(sp_pack_bias_kernel, dim3(1), dim3(256), 0, s, master, bo,
+                       zero ? 0 : d.cout, d.mt * 16, bias + L.bias_off[c]);
+  }
+  return hipGetLastError();
+}
+
+template <int MT>
+static hipError_t sp_launch(const SpConvArgs &a, hipStream_t s) {
+  static bool attr = false;
+  const size_t lds = 2 * (size_t)kChunk * MT * kFrag;
+  if (!attr) {
+    hipError_t e = hipFuncSetAttribute((const void *)sp_conv_kernel<MT>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    attr = true;
+  }
+  const int64_t segs = (int64_t)a.n * a.H * ((a.Wd + kWavePx - 1) / kWavePx);
+  const unsigned grid = (unsigned)((segs + kWaves - 1) / kWaves);
+  hipLaunchKernelGGL(sp_conv_kernel<MT>, dim3(grid), dim3(kThreads), lds, s, a);
+  return hipGetLastError();
+}
+
+static hipError_t sp_conv(const SpConvArgs &a0, int mt, hipStream_t s) {
+  switch (mt) {
+    case 1: return sp_launch<1>(a0, s);
+    case 4: return sp_launch<4>(a0, s);
+    case 8: return sp_launch<8>(a0, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t spatial_forward(const uint8_t *packed, int W, int pool, const float *gbuf,
+                           const float *layers, const float *scene, int n, int H, int Wd, int k,
+                           float *out, uint8_t *ws, hipStream_t s) {
+  const SpLayout L = sp_layout(W);
+  const float *bias = (const float *)(packed + L.frag_bytes);
+  const int64_t px = (int64_t)n * H * Wd, half = px / 4;
+  const int hw = H * Wd;
+  // workspace carve-up (see spatial_workspace_bytes)
+  uint8_t *p = ws;
+  auto take = [&](int64_t bytes) { uint8_t *q = p; p += (bytes + 255) & ~(int64_t)255; return q; };
+  uint8_t *x32 = take(px * 32 * 2);                   // x, then each b_i, then L_d
+  uint8_t *e1 = take(px * W * 2), *e2 = take(px * W * 2), *sig = take(px * W * 2);
+  uint8_t *tau = take(px * W * 2), *z1 = take(px * W * 2), *zs = take(px * W * 2);
+  uint8_t *phi = take(px * W * 2), *r1 = take(px * W * 2), *r2 = take(px * W * 2);
+  uint8_t *dh = take(half * W * 2), *mh = take(half * W * 2);
+  float *u = (float *)take(px * W * 4), *Z = (float *)take(px * W * 4);
+  float *bscale = (float *)take(px * 4);
+  const int MT = W / 16;
+  const unsigned pg = (unsigned)((px + 255) / 256);
+  hipError_t e = hipSuccess;
+
+  auto conv = [&](int c, const uint8_t *in0, int c0, const uint8_t *in1, int c1, int up1,
+                  int Hc, int Wc) {
+    SpConvArgs a = {};
+    const SpPackDesc &d = L.d[c];
+    a.in0 = in0;
+    a.in1 = in1;
+    a.c0 = c0;
+    a.c1 = c1;
+    a.up1 = up1;
+    a.wfrag = packed + d.out_off;
+    a.bias = bias + L.bias_off[c];
+    a.ksize = d.k;
+    a.steps = d.k * d.k * ((c0 + c1) / 32);
+    a.n = n;
+    a.H = Hc;
+    a.Wd = Wc;
+    a.cout_pad = d.mt * 16;
+    return a;
+  };
+  auto run = [&](const SpConvArgs &a, int mt) {
+    if (e == hipSuccess) e = sp_conv(a, mt, s);
+  };
+  auto unet = [&](int c1st, const uint8_t *in0, int c0, const uint8_t *in1, int c1, uint8_t *outp) {
+    SpConvArgs a = conv(c1st, in0, c0, in1, c1, 0, H, Wd);        // e1
+    a.relu = 1;
+    a.out_bf = e1;
+    run(a, MT);
+    const int64_t tot = half * (W / 8);
+    hipLaunchKernelGGL(sp_avgpool_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, e1,
+                       n, H, Wd, W, dh);
+    a = conv(c1st + 1, dh, W, nullptr, 0, 0, H / 2, Wd / 2);      // m (half resolution)
+    a.relu = 1;
+    a.out_bf = mh;
+    run(a, MT);
+    a = conv(c1st + 2, e1, W, mh, W, 1, H, Wd);                   // e2 = relu(conv3 [e1; up m])
+    a.relu = 1;
+    a.out_bf = e2;
+    run(a, MT);
+    a = conv(c1st + 3, e2, W, nullptr, 0, 0, H, Wd);              // out = conv1 e2
+    a.out_bf = outp;
+    run(a, MT);
+  };
+
+  // F: sigma = U-Net([G; s])
+  hipLaunchKernelGGL(sp_pack_x_kernel, dim3(pg), dim3(256), 0, s, gbuf, scene, px, hw, x32);
+  unet(SP_F1, x32, 32, nullptr, 0, sig);
+  // T: u = conv3 sigma (T1's sigma columns) + c1; per slot z1 = relu(conv3 b_i + u),
+  // Z += [alpha_i > 0] relu(conv1 z1 + c2)
+  {
+    SpConvArgs a = conv(SP_T1S, sig, W, nullptr, 0, 0, H, Wd);
+    a.out_f32 = u;
+    run(a, MT);
+  }
+  for (int i = 0; i < k; ++i) {
+    const float *Li = layers + (int64_t)i * kNL * hw;          // frame stride k * 12 * hw
+    hipLaunchKernelGGL(sp_pack_planes_kernel, dim3(pg), dim3(256), 0, s, Li, kNL,
+                       (int64_t)k * kNL * hw, px, hw, x32);
+    SpConvArgs a = conv(SP_T1B, x32, 32, nullptr, 0, 0, H, Wd);
+    a.add = u;
+    a.relu = 1;
+    a.out_bf = z1;
+    run(a, MT);
+    a = conv(SP_T2, z1, W, nullptr, 0, 0, H, Wd);
+    a.relu = 1;
+    a.pool = Z;
+    a.alpha = Li + (int64_t)kAlpha * hw;
+    a.alpha_fstride = (int64_t)k * kNL * hw;
+    a.pool_first = i == 0;
+    run(a, MT);
+  }
+  hipLaunchKernelGGL(sp_pool_finish_kernel, dim3(pg), dim3(256), 0, s, Z, layers, k, px, hw, W,
+                     pool == GN_POOL_MEAN ? 1 : 0, zs, bscale);
+  {
+    SpConvArgs a = conv(SP_T3, zs, W, nullptr, 0, 0, H, Wd);     // tau = A3 zs + bscale c3
+    a.bscale = bscale;
+    a.out_bf = tau;
+    run(a, MT);
+  }
+  // B: phi = U-Net([sigma; tau])
+  unet(SP_B1, sig, W, tau, W, phi);
+  // R: y = conv1 relu(conv3 relu(conv3 [phi; L_d]))
+  hipLaunchKernelGGL(sp_pack_planes_kernel, dim3(pg), dim3(256), 0, s, gbuf + 11 * hw, 3,
+                     (int64_t)kNG * hw, px, hw, x32);
+  {
+    SpConvArgs a = conv(SP_R1, phi, W, x32, 32, 0, H, Wd);
+    a.relu = 1;
+    a.out_bf = r1;
+    run(a, MT);
+    a = conv(SP_R2, r1, W, nullptr, 0, 0, H, Wd);
+    a.relu = 1;
+    a.out_bf = r2;
+    run(a, MT);
+    a = conv(SP_R3, r2, W, nullptr, 0, 0, H, Wd);
+    a.out_rgb = out;
+    run(a, 1);
+  }
+  if (e == hipSuccess) e = hipGetLastError();
+  return e;
+}
+
+}  // namespace gn

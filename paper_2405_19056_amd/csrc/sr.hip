@@ -496,27 +496,28 @@ __global__ __launch_bounds__(kThreads, 2) void sr_bwd_wgrad_kernel(
   }
 }
 
-// grad_w[i] = sum over tiles of partial[tile][i] in fp64, in two fixed-order
-// stages: groups of kRedGroup consecutive tiles, then the groups in order.
+// grad_w[i] = sum over rows of partial[row][i] in fp32, in two fixed-order
+// stages (deterministic): groups of kRedGroup consecutive rows, then the
+// groups in order.
 constexpr int kRedGroup = 64;
 
 __global__ __launch_bounds__(kThreads) void sr_bwd_group_sum_kernel(
-    const float *__restrict__ partial, int tiles, double *__restrict__ groups) {
+    const float *__restrict__ partial, int tiles, float *__restrict__ groups) {
   const int i = blockIdx.x * kThreads + threadIdx.x;
   if (i >= kSrParams) return;
   const int t0 = blockIdx.y * kRedGroup, t1 = min(t0 + kRedGroup, tiles);
-  double s = 0.0;
-  for (int t = t0; t < t1; ++t) s += (double)partial[(int64_t)t * kSrParams + i];
+  float s = 0.0f;
+  for (int t = t0; t < t1; ++t) s += partial[(int64_t)t * kSrParams + i];
   groups[(int64_t)blockIdx.y * kSrParams + i] = s;
 }
 
-__global__ __launch_bounds__(kThreads) void sr_bwd_reduce_kernel(const double *__restrict__ groups,
+__global__ __launch_bounds__(kThreads) void sr_bwd_reduce_kernel(const float *__restrict__ groups,
                                                                  int ngroups, float *__restrict__ gw) {
   const int i = blockIdx.x * kThreads + threadIdx.x;
   if (i >= kSrParams) return;
-  double s = 0.0;
+  float s = 0.0f;
   for (int g = 0; g < ngroups; ++g) s += groups[(int64_t)g * kSrParams + i];
-  gw[i] = (float)s;
+  gw[i] = s;
 }
 
 }  // namespace
@@ -546,8 +547,7 @@ size_t sr_backward_workspace_bytes(int n, int h, int w) {
   const int64_t px = (int64_t)n * 4 * h * w;
   const int64_t rows = wgrad_blocks(n, h, w);
   const int64_t groups = (rows + kRedGroup - 1) / kRedGroup;
-  return sizeof(float) * (size_t)(4 * kC * px + rows * kSrParams) +
-         sizeof(double) * (size_t)(groups * kSrParams) + 8;
+  return sizeof(float) * (size_t)(4 * kC * px + (rows + groups) * kSrParams);
 }
 
 hipError_t launch_sr_backward(const float *w, float *wt, const float *lowres, const float *gbuf,
@@ -571,9 +571,8 @@ hipError_t launch_sr_backward(const float *w, float *wt, const float *lowres, co
   hipLaunchKernelGGL(sr_bwd_wgrad_kernel, dim3((unsigned)nblocks), dim3(kThreads), 0, stream,
                      lowres, gbuf, dy, a1, a2, dz1, dz2, partial, n, h, w_lo);
   const int ngroups = (nblocks + kRedGroup - 1) / kRedGroup;
-  // fp64 group sums after the fp32 partials, 8-byte aligned
-  const uintptr_t end = (uintptr_t)(partial + (int64_t)nblocks * kSrParams);
-  double *groups = (double *)((end + 7) & ~(uintptr_t)7);
+  // the group sums follow the partials
+  float *groups = partial + (int64_t)nblocks * kSrParams;
   const unsigned pblocks = (kSrParams + kThreads - 1) / kThreads;
   hipLaunchKernelGGL(sr_bwd_group_sum_kernel, dim3(pblocks, (unsigned)ngroups), dim3(kThreads), 0,
                      stream, partial, nblocks, groups);

@@ -18,13 +18,15 @@ LIB_PATH = os.path.join(_HERE, "libglassnet.so")
 GN_OK, GN_E_INVAL, GN_E_NOMEM, GN_E_DEVICE, GN_E_UNSUPPORTED, GN_E_AGAIN, GN_E_BUSY = 0, -1, -2, -3, -4, -5, -6
 PRECISION = {"fp32": 0, "bf16": 1, "fp8_t": 2}
 POOL = {"mean": 0, "sum": 1}
+SLOT_ORDER = {"canonical": 0, "input": 1}
 NUM_G, NUM_L, NUM_S, NUM_OUT = 14, 12, 16, 3
 
 
 class GnConfig(ctypes.Structure):
     _fields_ = [("width", c_int32), ("k_max", c_int32), ("pool", c_int32),
                 ("precision", c_int32), ("hbm_budget_bytes", c_uint64), ("device", c_int32),
-                ("max_pending", c_int32), ("pe_levels", c_int32)]
+                ("max_pending", c_int32), ("pe_levels", c_int32), ("slot_order", c_int32),
+                ("seed", c_uint64)]
 
 
 class GnFrame(ctypes.Structure):
@@ -57,6 +59,9 @@ _SIGS = {
     "glassnet_backward": (c_int32, [c_void_p, POINTER(GnFrame), c_void_p, c_void_p, c_void_p]),
     "glassnet_dssim_loss": (c_int32, [c_void_p, c_void_p, c_void_p, c_int32, c_int32, c_int32,
                                       c_void_p, c_void_p, c_int32, c_void_p]),
+    "glassnet_spatial_num_params": (c_size_t, [c_int32]),
+    "glassnet_spatial_forward": (c_int32, [c_void_p, c_void_p, POINTER(GnFrame), c_void_p,
+                                           c_void_p]),
     "glassnet_adam_step": (c_int32, [c_void_p, c_void_p, c_void_p, c_size_t, c_int32, c_float,
                                      c_float, c_float, c_float, c_float, c_void_p]),
     "glassnet_sr_num_params": (c_size_t, []),
@@ -67,7 +72,7 @@ _SIGS = {
     "glassnet_adam_update": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_size_t, c_int32,
                                        c_float, c_float, c_float, c_float, c_float, c_void_p]),
     "glassnet_l1_loss": (c_int32, [c_void_p, c_void_p, c_void_p, c_uint64, c_void_p, c_void_p,
-                                   c_void_p]),
+                                   c_void_p, c_void_p]),
     "glassnet_workspace_bytes": (c_int32, [c_void_p, POINTER(c_uint64)]),
     "glassnet_calibrate": (c_int32, [c_void_p, POINTER(GnFrame), c_void_p]),
     "glassnet_stream_state_bytes": (c_int32, [c_void_p, c_int32, c_int32, c_int32,
@@ -161,18 +166,27 @@ class GlassNet:
     """One library handle: weights resident on the device, one precision."""
 
     def __init__(self, weights, width, k_max=8, pool="mean", precision="fp32", device=0,
-                 hbm_budget_bytes=0, max_pending=0, pe_levels=0):
-        w = np.ascontiguousarray(np.asarray(weights, dtype=np.float32).ravel())
+                 hbm_budget_bytes=0, max_pending=0, pe_levels=0, slot_order="canonical",
+                 seed=0):
+        """weights: host array of glassnet_num_params floats, or None for the
+        library's seeded initialisation from `seed`."""
         cfg = GnConfig(width, k_max, POOL[pool], PRECISION[precision], hbm_budget_bytes, device,
-                       max_pending, pe_levels)
+                       max_pending, pe_levels, SLOT_ORDER[slot_order], seed)
         h = c_void_p()
-        _check(lib().glassnet_create(byref(cfg), w.ctypes.data_as(POINTER(c_float)), w.size,
-                                     byref(h)))
+        if weights is None:
+            _check(lib().glassnet_create(byref(cfg), None, 0, byref(h)))
+            nparams = int(lib().glassnet_num_params(width, pe_levels))
+        else:
+            w = np.ascontiguousarray(np.asarray(weights, dtype=np.float32).ravel())
+            _check(lib().glassnet_create(byref(cfg), w.ctypes.data_as(POINTER(c_float)), w.size,
+                                         byref(h)))
+            nparams = w.size
         self._h = h
         self.width, self.k_max, self.pool, self.precision, self.device = (
             width, k_max, pool, precision, device)
         self.pe_levels = pe_levels
-        self.nparams = w.size
+        self.slot_order = slot_order
+        self.nparams = nparams
         self._keep = {}       # serving: keeps submitted tensors alive until polled done
 
     # -- lifetime
@@ -234,13 +248,17 @@ class GlassNet:
                                        _dev_ptr(grad_w, "grad_w"), _stream(stream)))
         return grad_w
 
-    def l1_loss(self, out, target, loss=None, grad_out=None, stream=None):
+    def l1_loss(self, out, target, loss=None, grad_out=None, grad_scale=None, stream=None):
+        """mean |out - target| into `loss`; grad_out (optional) gets its
+        gradient, times the device scalar grad_scale if given."""
         torch = _torch()
         if loss is None:
             loss = torch.empty((), dtype=torch.float32, device=out.device)
         gp = _dev_ptr(grad_out, "grad_out") if grad_out is not None else None
+        sp = _dev_ptr(grad_scale, "grad_scale") if grad_scale is not None else None
         _check(lib().glassnet_l1_loss(self._h, _dev_ptr(out, "out"), _dev_ptr(target, "target"),
-                                      out.numel(), _dev_ptr(loss, "loss"), gp, _stream(stream)))
+                                      out.numel(), _dev_ptr(loss, "loss"), gp, sp,
+                                      _stream(stream)))
         return loss
 
     def dssim_loss(self, out, target, loss=None, grad_out=None, accumulate=False, stream=None):
@@ -252,10 +270,24 @@ class GlassNet:
         if loss is None:
             loss = torch.empty((), dtype=torch.float32, device=out.device)
         gp = _dev_ptr(grad_out, "grad_out") if grad_out is not None else None
-        _check(lib().glassnet_dssim_loss(self._h, _dev_ptr(out, "out"), _dev_ptr(target, "target"),
-                                         n, h, w, _dev_ptr(loss, "loss"), gp, 1 if accumulate else 0,
-                                         _stream(stream)))
+        _check(lib().glassnet_dssim_loss(self._h, _dev_ptr(out, "out"), _dev_ptr(target, "target"), n, h, w,
+                  _dev_ptr(loss, "loss"), gp, 1 if accumulate else 0, _stream(stream)))
         return loss
+
+    # -- spatial networks (U-Net F and B, 3 x 3 CNNs h and R)
+    def spatial_num_params(self) -> int:
+        return int(lib().glassnet_spatial_num_params(self.width))
+
+    def spatial_forward(self, sp_w, gbuf, layers, scene, out=None, stream=None):
+        """The spatial networks' forward with caller-owned device weights sp_w
+        (glassnet_spatial_num_params floats) -> [n][3][h][w]."""
+        torch = _torch()
+        fr = make_frame(gbuf, layers, scene)
+        if out is None:
+            out = torch.empty((fr.n, NUM_OUT, fr.h, fr.w), dtype=torch.float32, device=gbuf.device)
+        _check(lib().glassnet_spatial_forward(self._h, _dev_ptr(sp_w, "sp_w"), byref(fr),
+                                              _dev_ptr(out, "out"), _stream(stream)))
+        return out
 
     # -- x2 super-sampling network
     def sr_forward(self, sr_w, lowres, gbuf_hi, out=None, stream=None):

@@ -103,6 +103,28 @@ def make_sr_weights(rng: np.random.Generator) -> np.ndarray:
     return np.concatenate(parts).astype(np.float32)
 
 
+def spatial_layer_shapes(width: int):
+    """(fan_out, cin, k) of the spatial networks' convolutions in packing
+    order: F (U-Net, 4), T (3), B (U-Net, 4), R (3); k x k kernels."""
+    W = width
+    return [(W, N_G + N_S, 3), (W, W, 3), (W, 2 * W, 3), (W, W, 1),
+            (W, N_L + W, 3), (W, W, 1), (W, W, 1),
+            (W, 2 * W, 3), (W, W, 3), (W, 2 * W, 3), (W, W, 1),
+            (W, W + 3, 3), (W, W, 3), (N_OUT, W, 1)]
+
+
+def make_spatial_weights(width: int, rng: np.random.Generator) -> np.ndarray:
+    """Packed spatial-network weights (each conv's W [out][in][k][k], then b),
+    initialised like make_weights with fan_in = input channels x taps."""
+    parts = []
+    for fan_out, cin, k in spatial_layer_shapes(width):
+        fan_in = cin * k * k
+        parts.append(rng.uniform(-np.sqrt(6.0 / fan_in), np.sqrt(6.0 / fan_in),
+                                 size=fan_out * fan_in))
+        parts.append(rng.uniform(-1.0 / np.sqrt(fan_in), 1.0 / np.sqrt(fan_in), size=fan_out))
+    return np.concatenate(parts).astype(np.float32)
+
+
 def make_sr_inputs(n: int, h: int, w: int, seed: int):
     """A render [n][3][h][w] (radiance-like values in [0, 2)) and a G-buffer at
     twice its resolution, [n][14][2h][2w]."""

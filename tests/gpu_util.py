@@ -90,3 +90,48 @@ def kink_free(w, W, fr: synth.Frame, pool, flat=None):
         L = fr.layers[f].reshape(fr.k, 12, hw)[:, :, sel][None, :, :, None, :]
         ok[at] = oracle.relu_margins(w, W, g, L, fr.scene[f:f + 1], pool=pool).ravel() >= KINK
     return ok
+
+
+def pixel_p99(y, ref):
+    """99th percentile over pixels of |y_p - y*_p|_2 / rms_q |y*_q|_2, for
+    outputs [n][3][h][w] (or sampled [P][3]).  Its mean square is relF^2."""
+    y = np.asarray(y, dtype=np.float64)
+    ref = np.asarray(ref, dtype=np.float64)
+    if y.ndim == 4:
+        y = np.moveaxis(y, 1, -1).reshape(-1, y.shape[1])
+        ref = np.moveaxis(ref, 1, -1).reshape(-1, ref.shape[1])
+    e = np.linalg.norm(y - ref, axis=1)
+    rms = np.sqrt(np.mean(np.sum(ref * ref, axis=1)))
+    return float(np.percentile(e, 99) / rms)
+
+
+def gate(y, ref, tol, what=""):
+    """Output-radiance parity: relative Frobenius error <= tol, the largest
+    element error <= 2 tol of the largest reference element, and the
+    per-pixel error's 99th percentile <= 3 tol of the rms pixel.  Returns the
+    three figures (logged)."""
+    f, i, p = relF(y, ref), relInf(y, ref), pixel_p99(y, ref)
+    log(f"  {what} relF={f:.3e} relInf={i:.3e} p99={p:.3e} (tol {tol:g})")
+    assert np.all(np.isfinite(y)), what
+    assert f <= tol, (what, "relF", f)
+    assert i <= 2 * tol, (what, "relInf", i)
+    assert p <= 3 * tol, (what, "p99", p)
+    return f, i, p
+
+
+def sample_every_tile(fr: synth.Frame, per_tile, rng, tile=256):
+    """Flat pixel indices covering every 256-pixel tile of every frame
+    (`per_tile` random pixels each, the ragged last tile included) plus each
+    frame's four corners and its last pixel: a wrong tile anywhere shows."""
+    hw = fr.h * fr.w
+    picks = []
+    for f in range(fr.n):
+        base = f * hw
+        for t0 in range(0, hw, tile):
+            t1 = min(hw, t0 + tile)
+            picks.append(base + rng.choice(np.arange(t0, t1), size=min(per_tile, t1 - t0),
+                                           replace=False))
+        corners = [0, fr.w - 1, (fr.h - 1) * fr.w, hw - 1]
+        picks.append(base + np.asarray(corners))
+    flat = np.unique(np.concatenate(picks))
+    return flat

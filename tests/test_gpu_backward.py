@@ -236,3 +236,45 @@ def test_autograd_training_step_matches_oracle_l1_gradient():
         loss2, gw = train_step(net, g, L, sc, t, w.detach())
         torch.cuda.synchronize()
         assert np.array_equal(host(gw), host(w.grad))
+
+
+def test_l1_gradient_scaled_by_a_device_scalar():
+    """grad_scale (a device scalar) multiplies the subgradient on the device:
+    sign(y - t) * (1 / n) * s in fp32, element for element."""
+    torch = torch_dev()
+    rng = np.random.default_rng(1)
+    y = rng.normal(size=(2, 3, 19, 23)).astype(np.float32)
+    t = rng.normal(size=y.shape).astype(np.float32)
+    t.ravel()[:7] = y.ravel()[:7]
+    with GlassNet(synth.make_weights(64, rng), 64, k_max=2) as net:
+        grad = torch.empty(y.shape, dtype=torch.float32, device="cuda:0")
+        s = torch.tensor(-2.75, dtype=torch.float32, device="cuda:0")
+        net.l1_loss(dev(y), dev(t), grad_out=grad, grad_scale=s)
+        torch.cuda.synchronize()
+    want = np.sign(y - t).astype(np.float32) * (np.float32(1.0 / y.size) * np.float32(-2.75))
+    assert np.array_equal(host(grad), want)
+
+
+def test_autograd_scaled_loss_and_weights_changed_before_backward():
+    """(a) A non-unit upstream gradient, 2.5 L, gives 2.5 times the oracle's
+    gradient.  (b) Two forwards on one handle with different weights (a
+    teacher, then a student) before the backward: each gradient is taken at
+    the weights of its own forward."""
+    torch = torch_dev()
+    from paper_2405_19056_amd.autograd import GlassNetFunction, L1Function
+    W = 64
+    wts, fr, s = frame(1, 16, 16, 3, W, seed=78)
+    fr = redraw_near_kinks(wts, W, fr, "mean", s)
+    target = s["noise"].normal(size=(1, 3, 16, 16)).astype(np.float32)
+    _, ref = oracle.grad(wts, W, fr.gbuf, fr.layers, fr.scene, target)
+    other = synth.make_weights(W, s["teacher"])
+    with GlassNet(wts, W, k_max=8, precision="fp32") as net:
+        g, L, sc, t = dev(fr.gbuf), dev(fr.layers), dev(fr.scene), dev(target)
+        w = torch.tensor(wts, device="cuda:0", requires_grad=True)
+        w2 = torch.tensor(other, device="cuda:0", requires_grad=True)
+        y = GlassNetFunction.apply(net, g, L, sc, w)
+        y2 = GlassNetFunction.apply(net, g, L, sc, w2)     # the handle now holds w2
+        loss = 2.5 * L1Function.apply(net, y, t) + 0.0 * y2.sum()
+        loss.backward()
+        torch.cuda.synchronize()
+    check(host(w.grad) / 2.5, ref, W)

@@ -34,8 +34,9 @@ def frame(n, h, w, k, W, pe, seed):
     return wts, fr, s
 
 
-def open_net(wts, W, precision, pe, pool="mean", k_max=8):
-    net = GlassNet(wts, W, k_max=k_max, pool=pool, precision=precision, pe_levels=pe)
+def open_net(wts, W, precision, pe, pool="mean", k_max=8, slot_order="canonical"):
+    net = GlassNet(wts, W, k_max=k_max, pool=pool, precision=precision, pe_levels=pe,
+                   slot_order=slot_order)
     if precision == "fp8_t":
         _, cal, _ = frame(1, 64, 64, 4, W, pe, seed=999)
         net.calibrate(dev(cal.gbuf), dev(cal.layers), dev(cal.scene))
@@ -87,7 +88,7 @@ def test_encoded_stream_is_the_fused_forward_bitwise(precision):
     torch = torch_dev()
     W, pe = 128, 2
     wts, fr, _ = frame(2, 29, 31, 5, W, pe, seed=98)
-    with open_net(wts, W, precision, pe) as net:
+    with open_net(wts, W, precision, pe, slot_order="input") as net:
         y_ref = run(net, fr)
         g, sc = dev(fr.gbuf), dev(fr.scene)
         st = net.stream_state(fr.n, fr.h, fr.w)
@@ -100,15 +101,19 @@ def test_encoded_stream_is_the_fused_forward_bitwise(precision):
     assert np.array_equal(y, y_ref)
 
 
-def test_encoded_fp32_is_bitwise_permutation_invariant():
-    W, pe = 64, 2
+@pytest.mark.parametrize("precision", ["fp32", "bf16", "fp8_t"])
+def test_encoded_forward_is_bitwise_permutation_invariant(precision):
+    """Canonical slot order: per-pixel shuffles of the slots leave every
+    output bit unchanged (Eq. (5) is symmetric in the slots)."""
+    W, pe = (64, 2) if precision != "fp8_t" else (128, 2)
     wts, fr, s = frame(1, 40, 40, 6, W, pe, seed=99)
     rng = np.random.default_rng(99)
-    with open_net(wts, W, "fp32", pe) as net:
+    with open_net(wts, W, precision, pe) as net:
         y0 = run(net, fr)
         for _ in range(4):
-            perm = rng.permutation(6)
-            y = run(net, synth.Frame(fr.gbuf, fr.layers[:, perm], fr.scene))
+            p = synth.slot_shuffles(1, 6, 40, 40, 1, rng)[0]
+            y = run(net, synth.Frame(fr.gbuf, synth.apply_slot_permutation(fr.layers, p),
+                                     fr.scene))
             assert np.array_equal(y, y0)
 
 

@@ -1,7 +1,9 @@
 """Serving on the GPU: frames of different sizes and slot counts submitted
 while others run share launches, and every served frame equals the same
 frame evaluated alone by glassnet_forward (bitwise: per-pixel arithmetic does
-not depend on which tiles share a launch)."""
+not depend on which tiles share a launch), and every served frame matches
+the FP64 oracle on pixels sampled from each of its tiles, its corners and
+its ragged last tile, at each serving resolution."""
 import threading
 import time
 
@@ -11,18 +13,22 @@ import pytest
 from paper_2405_19056_amd import synth
 from paper_2405_19056_amd.glassnet import GN_E_INVAL, GN_E_UNSUPPORTED, GlassNet, GlassNetError
 
-from gpu_util import dev, host, log, torch_dev
+from gpu_util import (dev, gate, gpu_on_sample, host, log, oracle_on_sample, sample_every_tile,
+                      torch_dev)
 
 pytestmark = pytest.mark.gpu
 
 SIZES = [(256, 256), (512, 512), (360, 640), (576, 1024), (37, 53)]
+TOL = {"bf16": 2e-2, "fp8_t": 6e-2}
 
 
 def make_requests(count, seed):
+    """Requests of random sizes (every size among the first len(SIZES)) and
+    slot counts K ~ U{2..8}."""
     rng = np.random.default_rng(seed)
     reqs = []
     for i in range(count):
-        h, w = SIZES[rng.integers(len(SIZES))]
+        h, w = SIZES[i] if i < len(SIZES) else SIZES[rng.integers(len(SIZES))]
         k = int(rng.integers(2, 9))
         fr = synth.make_frame(1, h, w, k, seed=1000 * seed + i)
         reqs.append(fr)
@@ -74,6 +80,13 @@ def test_served_equals_alone(precision):
         ref = alone(net, dev_in)
     for a, b in zip(served, ref):
         assert np.array_equal(a, b)
+    # each served frame against the FP64 oracle (Eq. (5), Sec. 3.4)
+    rng = np.random.default_rng(44)
+    for i, (fr, y) in enumerate(zip(reqs, served)):
+        flat = sample_every_tile(fr, 1, rng)
+        want = oracle_on_sample(wts, W, fr, flat, "mean")
+        gate(gpu_on_sample(y, fr, flat), want, TOL[precision],
+             f"served #{i} {fr.h}x{fr.w} K={fr.k} {precision} ({len(flat)} px)")
     lat = sorted(t["t_done"] - t["t_submit"] for t in tms)
     log(f"  {precision}: {len(reqs)} frames, latency p50 {1e3 * lat[len(lat) // 2]:.2f} ms "
         f"max {1e3 * lat[-1]:.2f} ms")

@@ -4,10 +4,10 @@ finish over a frame whose transparent objects arrive a few at a time
 object's buffer is evaluated on its own and added to a running sum).
 
 The state keeps the running sum in fp32 and the library adds the slots in
-call order, exactly as the fused forward adds them in slot order, so a
-streamed result must equal the fused forward of the same handle over the
-concatenated slots bit for bit (GN_FP32 handles stream through the plane
-pipeline of their forward, with the same property).  Against the FP64 oracle
+call order, exactly as the fused forward of a handle with the input slot
+order adds them in slot order, so a streamed result must equal that fused
+forward over the concatenated slots bit for bit (GN_FP32 handles stream
+through the plane pipeline of their forward, with the same property).  Against the FP64 oracle
 the tolerances are the forward's (relative Frobenius error: fp32 1e-4, bf16
 2e-2, fp8_t 6e-2).
 """
@@ -34,8 +34,8 @@ def frame(n, h, w, k, W, seed):
     return wts, fr
 
 
-def open_net(wts, W, precision, pool="mean", k_max=8):
-    net = GlassNet(wts, W, k_max=k_max, pool=pool, precision=precision)
+def open_net(wts, W, precision, pool="mean", k_max=8, slot_order="input"):
+    net = GlassNet(wts, W, k_max=k_max, pool=pool, precision=precision, slot_order=slot_order)
     if precision == "fp8_t":
         _, cal = frame(1, 64, 64, 4, W, seed=999)
         net.calibrate(dev(cal.gbuf), dev(cal.layers), dev(cal.scene))
@@ -188,7 +188,7 @@ def test_state_size_does_not_grow_with_objects():
                       precision="bf16") as n64:
             assert n64.stream_state_bytes(3, 7, 100) == 3 * 3 * 256 * 388
     with GlassNet(wts, 128, k_max=64, precision="fp32") as net:
-        assert net.stream_state_bytes(2, 30, 50) == 2 * 30 * 50 * (3 * 128 + 1) * 4
+        assert net.stream_state_bytes(2, 30, 50) == 2 * 30 * 50 * (2 * 128 + 1) * 4
 
 
 @pytest.mark.parametrize("precision", ["bf16", "fp8_t", "fp32"])

@@ -223,6 +223,22 @@ gn_status glassnet_dssim_loss(gn_handle *h, const float *out, const float *targe
                               int32_t height, int32_t width, float *loss, float *grad_out,
                               int32_t accumulate, void *hip_stream);
 
+/* glassnet_dssim_loss for callers that cannot allocate device memory: code
+ * under HIP graph capture, tight serving or training loops, harnesses that
+ * forbid hipMalloc.  Same arguments, kernels and result (bitwise); the
+ * workspace is a fixed 16 MiB array of device memory that the library
+ * holds on every GPU it runs on until the process ends, instead of the
+ * handle's grown workspace.  The call allocates and frees nothing (no HIP or
+ * other allocating routine) and synchronises nothing.  Every call on one GPU
+ * shares that GPU's array: calls that may overlap on one GPU (different
+ * streams, or handles on the same device used concurrently) race and must be
+ * ordered by the caller.  Sizes whose workspace exceeds the array (more than
+ * about 1.39 million SSIM windows: n x 3 x (height - 10) x (width - 10)) get
+ * GN_E_INVAL; other errors as glassnet_dssim_loss. */
+gn_status glassnet_dssim_loss_noalloc(gn_handle *h, const float *out, const float *target,
+                                      int32_t n, int32_t height, int32_t width, float *loss,
+                                      float *grad_out, int32_t accumulate, void *hip_stream);
+
 /* One optimiser step on the handle's fp32 master weights (Sec. 4 trains with
  * Adam, Kingma & Ba, and weight decay), then the packed forms re-derived;
  * stream-ordered on hip_stream.  Weight decay is an L2 term added to the

@@ -177,6 +177,14 @@ gn_status glassnet_create(const gn_config *cfg, const float *host_weights, size_
     glassnet_destroy(h);
     return st;
   }
+  // the allocation-free DSSIM form's workspace address on this device (once)
+  if (e == hipSuccess) {
+    e = gn::dssim_scratch_init(cfg->device);
+    if (e != hipSuccess) {
+      glassnet_destroy(h);
+      return fail(GN_E_DEVICE, "DSSIM scratch address: %s", hipGetErrorString(e));
+    }
+  }
   h->bytes_held = wbytes + (size_t)h->pl.total_bytes + sizeof(float) * h->l1_npart +
                   (cfg->precision == GN_FP32 ? 0 : 2 * sig_bytes);
   gn_status st = gn_prepare_weights(h, nullptr);
@@ -551,6 +559,22 @@ gn_status glassnet_dssim_loss(gn_handle *h, const float *out, const float *targe
   return gn_check_device(h, e, "DSSIM launch");
 }
 
+gn_status glassnet_dssim_loss_noalloc(gn_handle *h, const float *out, const float *target,
+                                      int32_t n, int32_t height, int32_t width, float *loss,
+                                      float *grad_out, int32_t accumulate, void *hip_stream) {
+  gn_status st = dssim_check(h, out, target, n, height, width, loss, grad_out);
+  if (st != GN_OK) return st;
+  const size_t need = gn::dssim_workspace_bytes(n * gn::kNOUT, height, width);
+  if (need > gn::kDssimScratchBytes)
+    return fail(GN_E_INVAL, "DSSIM of %d x 3 x %d x %d needs %zu workspace bytes, above the %zu "
+                "of the allocation-free form", n, height, width, need, gn::kDssimScratchBytes);
+  float *ws = gn::dssim_scratch(h->device);
+  if (!ws) return fail(GN_E_DEVICE, "DSSIM scratch not set up on device %d", h->device);
+  DeviceGuard dg(h->device);
+  hipError_t e = gn::launch_dssim(out, target, n * gn::kNOUT, height, width, loss, grad_out,
+                                  accumulate ? 1 : 0, ws, (hipStream_t)hip_stream);
+  return gn_check_device(h, e, "DSSIM launch");
+}
 
 size_t glassnet_sr_num_params(void) { return (size_t)gn::kSrParams; }
 

@@ -157,6 +157,13 @@ hipError_t launch_l1(const float *out, const float *target, uint64_t count, floa
 // DSSIM term: planes = n x 3 images of h x w (h, w >= 11); ws holds
 // dssim_workspace_bytes(planes, h, w) bytes; grad may be null.
 size_t dssim_workspace_bytes(int planes, int h, int w);
+// The allocation-free DSSIM form's fixed per-device workspace: its size, the
+// set-up of its device address (once per device, that device current) and
+// the address (null before set-up).
+constexpr size_t kDssimScratchBytes = (size_t)16 << 20;
+constexpr int kMaxDevices = 64;
+hipError_t dssim_scratch_init(int device);
+float *dssim_scratch(int device);
 hipError_t launch_dssim(const float *out, const float *target, int planes, int h, int w,
                         float *loss, float *grad, int accumulate, float *ws, hipStream_t stream);
 // x2 super-sampling network: widths and the packed parameter count.

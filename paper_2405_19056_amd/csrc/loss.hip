@@ -2,6 +2,8 @@
 // Deterministic two-pass reduction in fp32 (fixed partial count and order).
 #include <cmath>
 
+#include <mutex>
+
 #include "gn_internal.h"
 
 namespace gn {
@@ -224,6 +226,37 @@ hipError_t launch_dssim(const float *out, const float *target, int planes, int h
                        plane_m, -0.5f / (float)plane_m, grad, accumulate);
   }
   return hipGetLastError();
+}
+
+// ---- the DSSIM term's allocation-free form ---------------------------------
+// A fixed device array serves as the DSSIM workspace for callers that cannot
+// allocate (graph capture, serving loops).  Each GPU holds its own copy for
+// the life of the process; its device address is looked up once per device
+// (host code never passes the array's name to a kernel).  Every call on a GPU
+// shares that copy: calls that overlap on one GPU race.  Nothing in it needs
+// clearing: each launch writes every coefficient and partial it reads.
+static __device__ __align__(256) float scratch[kDssimScratchBytes / sizeof(float)];
+
+namespace {
+std::mutex g_scratch_mu;
+float *g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+hipError_t dssim_scratch_init(int device) {
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_ptr[device]) return hipSuccess;
+  void *p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return e;
+  g_scratch_ptr[device] = (float *)p;
+  return hipSuccess;
+}
+
+float *dssim_scratch(int device) {
+  if (device < 0 || device >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  return g_scratch_ptr[device];
 }
 
 hipError_t launch_l1(const float *out, const float *target, uint64_t count, float *loss,

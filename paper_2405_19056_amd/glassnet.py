@@ -62,6 +62,8 @@ _SIGS = {
     "glassnet_spatial_num_params": (c_size_t, [c_int32]),
     "glassnet_spatial_forward": (c_int32, [c_void_p, c_void_p, POINTER(GnFrame), c_void_p,
                                            c_void_p]),
+    "glassnet_dssim_loss_noalloc": (c_int32, [c_void_p, c_void_p, c_void_p, c_int32, c_int32,
+                                              c_int32, c_void_p, c_void_p, c_int32, c_void_p]),
     "glassnet_adam_step": (c_int32, [c_void_p, c_void_p, c_void_p, c_size_t, c_int32, c_float,
                                      c_float, c_float, c_float, c_float, c_void_p]),
     "glassnet_sr_num_params": (c_size_t, []),
@@ -261,8 +263,10 @@ class GlassNet:
                                       _stream(stream)))
         return loss
 
-    def dssim_loss(self, out, target, loss=None, grad_out=None, accumulate=False, stream=None):
-        """(1 - SSIM) / 2 of [n][3][h][w] images; grad_out written or added to."""
+    def dssim_loss(self, out, target, loss=None, grad_out=None, accumulate=False, stream=None,
+                   noalloc=False):
+        """(1 - SSIM) / 2 of [n][3][h][w] images; grad_out written or added to.
+        noalloc: the library's allocation-free form (fixed device workspace)."""
         torch = _torch()
         n, c, h, w = out.shape
         if c != NUM_OUT or tuple(target.shape) != tuple(out.shape):
@@ -270,7 +274,8 @@ class GlassNet:
         if loss is None:
             loss = torch.empty((), dtype=torch.float32, device=out.device)
         gp = _dev_ptr(grad_out, "grad_out") if grad_out is not None else None
-        _check(lib().glassnet_dssim_loss(self._h, _dev_ptr(out, "out"), _dev_ptr(target, "target"), n, h, w,
+        fn = lib().glassnet_dssim_loss_noalloc if noalloc else lib().glassnet_dssim_loss
+        _check(fn(self._h, _dev_ptr(out, "out"), _dev_ptr(target, "target"), n, h, w,
                   _dev_ptr(loss, "loss"), gp, 1 if accumulate else 0, _stream(stream)))
         return loss
 

@@ -189,7 +189,10 @@ gn_status glassnet_set_act_scales(gn_handle *h, const float *scales, size_t n);
 gn_status glassnet_calibrate(gn_handle *h, const gn_frame *frame, void *hip_stream);
 
 /* Forward (Sec. 3.3-3.4): out [n][GN_NUM_OUT][h][w] fp32 device.
- * Requires 0 <= k <= k_max and n, h, w >= 1.  Out must not alias inputs.
+ * Requires 0 <= k <= k_max, n, h, w >= 1 and fewer than 2^32 floats of slot
+ * planes per frame (k * GN_NUM_L * h * w); every call that takes a gn_frame
+ * checks these.  Out must not alias inputs.  Each pixel's slots are pooled in
+ * the handle's slot order (gn_config.slot_order).
  * GN_FP32: at most 3 * 2^20 pixels (n * h * w) per call (GN_E_INVAL beyond).
  * Forward calls of one handle share a small device scratch (GN_BF16 /
  * GN_FP8_T) or the plane workspace (GN_FP32): calls on different streams must

@@ -62,9 +62,10 @@ gn_status gn_validate_frame(gn_handle *h, const gn_frame *f, const float *out) {
   if (f->k < 0 || f->k > h->cfg.k_max)
     return fail(GN_E_INVAL, "k=%d outside [0, k_max=%d]", f->k, h->cfg.k_max);
   const int64_t hw = (int64_t)f->h * f->w;
+  // the fused kernel addresses a frame's slot planes with 32-bit offsets
   if (hw * gn::kNG > INT32_MAX || (int64_t)f->n * hw > INT32_MAX ||
-      hw * (int64_t)std::max(f->k, 1) * gn::kNL > ((int64_t)1 << 40))
-    return fail(GN_E_INVAL, "frame too large (%d x %d x %d)", f->n, f->h, f->w);
+      hw * (int64_t)std::max(f->k, 1) * gn::kNL >= ((int64_t)1 << 32))
+    return fail(GN_E_INVAL, "frame too large (%d x %d x %d, k=%d)", f->n, f->h, f->w, f->k);
   if (!f->gbuf || !f->scene) return fail(GN_E_INVAL, "gbuf and scene must be non-NULL");
   if (f->k > 0 && !f->layers) return fail(GN_E_INVAL, "layers is NULL with k=%d", f->k);
   if (!aligned4(f->gbuf) || !aligned4(f->scene) || !aligned4(f->layers) || !aligned4(out))

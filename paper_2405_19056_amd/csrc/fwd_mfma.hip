@@ -65,6 +65,7 @@ struct MfmaArgs {
   int state_load;                      // 1: the state holds a running sum to continue from
   int canon;                           // FULL: pool each pixel's slots in canonical order
   int kpad;                            // bytes per pixel of the LDS slot-order table
+  int aslots;                          // slots whose alphas the LDS alpha table holds
 };
 
 // Two floats -> packed bf16 pair (round to nearest even), one v_cvt_pk_bf16_f32.
@@ -356,9 +357,11 @@ __global__ __launch_bounds__(kThreads) void fwd_mfma_kernel(MfmaArgs a) {
   for (int s = 0; s < kStages; ++s)
     stage_max = max(stage_max, a.stage_off[s + 1] - a.stage_off[s]);
   // slot-order table: for each pixel of the tile, its slots' indices in
-  // canonical order (kpad bytes per pixel, a multiple of 4)
+  // canonical order (kpad bytes per pixel, a multiple of 4), and the tile's
+  // alphas [slot][pixel] that the order is computed from (aslots slots)
   uint8_t *L_perm = lds + res_bytes + Shape<W>::kBiasBytes;
-  uint8_t *L_stage0 = L_perm + (size_t)kTilePx * a.kpad;
+  float *L_alpha = (float *)(L_perm + (size_t)kTilePx * a.kpad);
+  uint8_t *L_stage0 = (uint8_t *)L_alpha + (size_t)kTilePx * 4 * a.aslots;
   uint8_t *L_stage1 = L_stage0 + stage_max;
   // FWD_FINISH runs an odd number of stages per tile, so its buffer parity
   // flips from one tile to the next (par); every other mode keeps par = 0.
@@ -467,6 +470,12 @@ __global__ __launch_bounds__(kThreads) void fwd_mfma_kernel(MfmaArgs a) {
       }
     }
   };
+  // Canonical slot order (FULL mode, if the handle asks for it): each
+  // pixel's slots are pooled in an order that depends only on their records,
+  // so the rounding of the running sum cannot depend on the order the caller
+  // passed them in.  With up to kFastK slots the tile's alphas are copied to
+  // LDS during F's last layer and ranked at the start of the slot stage.
+  constexpr int kFastK = 8;
   float xr[kNT][8];
   TileInfo nti;
   if ((int)blockIdx.x < a.ntiles) {
@@ -574,6 +583,17 @@ __global__ __launch_bounds__(kThreads) void fwd_mfma_kernel(MfmaArgs a) {
 
       // ================= F layer 3 -> sigma =================
       if constexpr (MODE == FWD_FULL) fill_stage(sT1S);
+      if (MODE == FWD_FULL && a.canon && K > 1 && K <= kFastK) {
+        // the tile's alphas, slot by slot, into the LDS alpha table: 64-pixel
+        // blocks, lane i copying pixel i of its block (clamped to the frame)
+        for (int b = wave; b < 4 * K; b += kWaves) {
+          const int j = b >> 2, p0 = (b & 3) * 64;
+          const int q = min(q0 + p0 + lane, hw - 1);
+          __builtin_amdgcn_global_load_lds(
+              (const void *)(Lp + ((size_t)j * kNL + kAlpha) * hw + q),
+              (__attribute__((address_space(3))) void *)(L_alpha + j * kTilePx + p0), 4, 0, 0);
+        }
+      }
       if constexpr (MODE == FWD_BEGIN && PE > 0) {
         if (has_next) fill_stage(sF1);      // the next tile's first stage
       }
@@ -623,85 +643,82 @@ __global__ __launch_bounds__(kThreads) void fwd_mfma_kernel(MfmaArgs a) {
 #pragma unroll
           for (int k = 0; k < KS; ++k) sig[t][k] = st_sig[(t * KS + k) * 64];
       }
-      {
-        // Canonical slot order (FULL mode, if the handle asks for it): the
-        // pixel's slots are pooled in an order that depends only on their
-        // records, so the rounding of the running sum cannot depend on the
-        // order the caller passed them in.  With up to kFastK slots each lane
-        // holds the alphas of all of them and ranks its lane group's slots
-        // g and g + 4; the slot at rank r goes to byte r of the pixel's entry
-        // of the LDS table.  The alphas are requested before u's MFMAs.
-        constexpr int kFastK = 8;
-        const bool canon = MODE == FWD_FULL && a.canon && K > 1;
+      // Canonical order of each pixel's slots, into this wave's part of the
+      // LDS table (byte r of a pixel's entry: its slot of rank r).  Keys: the
+      // bits of alpha for active slots, 0xFFFFFF00 + j for an inactive slot j
+      // (above every active key, distinct), 0xFFFFFFFF past K.  With up to
+      // kFastK slots each lane ranks its lane group's slots g and g + 4 from the
+      // alphas in LDS; two active slots of equal alpha (and more
+      // than kFastK slots) take the full comparison of slot_order.h.
+      if (MODE == FWD_FULL && a.canon && K > 1) {
         uint8_t *perm_px[kNT];
 #pragma unroll
         for (int t = 0; t < kNT; ++t)
           perm_px[t] = L_perm + (size_t)(wave * (kNT * 16) + t * 16 + col) * a.kpad;
-        float alk[kNT][kFastK];
-        if (canon && K <= kFastK) {
+        if (K <= kFastK) {
+          float alk[kNT][kFastK];
 #pragma unroll
           for (int t = 0; t < kNT; ++t)
 #pragma unroll
             for (int j = 0; j < kFastK; ++j)
-              alk[t][j] = j < K ? Lp[((size_t)j * kNL + kAlpha) * hw + qc[t]] : 0.0f;
+              alk[t][j] = j < K ? L_alpha[j * kTilePx + wave * (kNT * 16) + t * 16 + col] : 0.0f;
+          unsigned slow = 0;
+#pragma unroll
+          for (int t = 0; t < kNT; ++t) {
+            uint32_t key[kFastK];
+#pragma unroll
+            for (int j = 0; j < kFastK; ++j)
+              key[j] = j >= K ? 0xFFFFFFFFu
+                              : (alk[t][j] > 0.0f ? __float_as_uint(alk[t][j]) : 0xFFFFFF00u + j);
+#pragma unroll
+            for (int sl = 0; sl < 2; ++sl) {
+              const int i = g + 4 * sl;
+              uint32_t ki = key[4 * sl];
+#pragma unroll
+              for (int jj = 1; jj < 4; ++jj) ki = g == jj ? key[4 * sl + jj] : ki;
+              int lt = 0, le = 0;
+#pragma unroll
+              for (int j = 0; j < kFastK; ++j) {
+                lt += key[j] < ki ? 1 : 0;
+                le += key[j] <= ki ? 1 : 0;
+              }
+              if (i < K) {
+                if (le == lt + 1)
+                  perm_px[t][lt] = (uint8_t)i;
+                else
+                  slow |= 1u << (2 * t + sl);
+              }
+            }
+          }
+          if (__builtin_amdgcn_ballot_w64(slow != 0)) {
+#pragma unroll
+            for (int t = 0; t < kNT; ++t)
+#pragma unroll
+              for (int sl = 0; sl < 2; ++sl)
+                if (slow & (1u << (2 * t + sl)))
+                  perm_px[t][slot_rank(Lp + qc[t], (size_t)hw, K, g + 4 * sl)] =
+                      (uint8_t)(g + 4 * sl);
+          }
+        } else {
+#pragma unroll
+          for (int t = 0; t < kNT; ++t)
+            for (int i = g; i < K; i += 4)
+              perm_px[t][slot_rank(Lp + qc[t], (size_t)hw, K, i)] = (uint8_t)i;
         }
+        // the wave reads the table back in its own slot loop (LDS operations of
+        // one wave complete in order)
+      }
+      {
+        // the slot-order table of this tile (written above): the lane's pixel
+        // of N-tile t has its entry at byte pofs + 16 t kpad
+        const bool canon = MODE == FWD_FULL && a.canon && K > 1;
+        const uint32_t pofs = (uint32_t)(wave * (kNT * 16) + col) * a.kpad;
         // u = W1s sigma + c1 in fp32 accumulator layout: the C operand of h's
         // first layer for every slot
         f32x4 u[kNT][MT];
         bias_init(u, bT1, g);
         mm<MT, KS>(u, stage_buf(sT1S), sig, lane);
-        if (canon) {
-          if (K <= kFastK) {
-            // Keys: active slots by alpha's bits, inactive ones made distinct
-            // by their index (0xFFFFFF00 + j, above every active key), absent
-            // ones (j >= K) above all.  A key's rank is the number of smaller
-            // keys; two active slots of equal alpha take the full comparison.
-            unsigned slow = 0;
-#pragma unroll
-            for (int t = 0; t < kNT; ++t) {
-              uint32_t key[kFastK];
-#pragma unroll
-              for (int j = 0; j < kFastK; ++j)
-                key[j] = j >= K ? 0xFFFFFFFFu
-                                : (alk[t][j] > 0.0f ? __float_as_uint(alk[t][j]) : 0xFFFFFF00u + j);
-#pragma unroll
-              for (int sl = 0; sl < 2; ++sl) {
-                const int i = g + 4 * sl;
-                uint32_t ki = key[4 * sl];
-#pragma unroll
-                for (int jj = 1; jj < 4; ++jj) ki = g == jj ? key[4 * sl + jj] : ki;
-                int lt = 0, le = 0;
-#pragma unroll
-                for (int j = 0; j < kFastK; ++j) {
-                  lt += key[j] < ki ? 1 : 0;
-                  le += key[j] <= ki ? 1 : 0;
-                }
-                if (i < K) {
-                  if (le == lt + 1)
-                    perm_px[t][lt] = (uint8_t)i;
-                  else
-                    slow |= 1u << (2 * t + sl);
-                }
-              }
-            }
-            if (__builtin_amdgcn_ballot_w64(slow != 0)) {
-#pragma unroll
-              for (int t = 0; t < kNT; ++t)
-#pragma unroll
-                for (int sl = 0; sl < 2; ++sl)
-                  if (slow & (1u << (2 * t + sl)))
-                    perm_px[t][slot_rank(Lp + qc[t], (size_t)hw, K, g + 4 * sl)] =
-                        (uint8_t)(g + 4 * sl);
-            }
-          } else {
-#pragma unroll
-            for (int t = 0; t < kNT; ++t)
-              for (int i = g; i < K; i += 4)
-                perm_px[t][slot_rank(Lp + qc[t], (size_t)hw, K, i)] = (uint8_t)i;
-          }
-          // this wave reads the table back in its own slot loop
-          asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
-        }
+
         if constexpr (kFp8) {
           // fp8: h's first layer runs in units of the activation scale (its
           // inputs b_i and u are divided by it), so its output quantises directly
@@ -735,11 +752,11 @@ __global__ __launch_bounds__(kThreads) void fwd_mfma_kernel(MfmaArgs a) {
         // Iteration i takes each pixel's slot of rank i (canonical order) or
         // slot i (input order).
         auto load_slot = [&](int i) {
-          size_t qs[kNT];
+          uint32_t qs[kNT];      // element offsets (frames of the MFMA path stay below 2^32)
 #pragma unroll
           for (int t = 0; t < kNT; ++t) {
-            const int si = canon ? (int)perm_px[t][i] : i;
-            qs[t] = (size_t)si * kNL * hw + qc[t];
+            const int si = canon ? (int)L_perm[pofs + t * 16 * a.kpad + i] : i;
+            qs[t] = (uint32_t)si * (uint32_t)(kNL * hw) + (uint32_t)qc[t];
             asm volatile("" : "+v"(qs[t]));   // per-slot addresses stay in the loop body
           }
 #pragma unroll
@@ -1194,23 +1211,24 @@ static int64_t resident_bytes(const PackedLayout &pl, int precision) {
   return pl.resident_bytes;
 }
 
-static size_t mfma_base_lds_bytes(const PackedLayout &pl, int precision, int kpad) {
+// order_bytes: the canonical order's LDS tables (order and alphas) per tile.
+static size_t mfma_base_lds_bytes(const PackedLayout &pl, int precision, int order_bytes) {
   int64_t stage_max = 0;
   for (int s = 0; s < pl.nstages; ++s)
     stage_max = std::max<int64_t>(stage_max, pl.stage_off[s + 1] - pl.stage_off[s]);
   return (size_t)(resident_bytes(pl, precision) + (int64_t)kNumLayers * pl.W * 4 +
-                  (int64_t)kTilePx * kpad + 2 * stage_max);
+                  (int64_t)order_bytes + 2 * stage_max);
 }
 
 // Waves whose sigma fits in the LDS the weights leave free (160 KiB per CU),
 // and how many of them sit in the stage buffers' tails: from F3's stage to
 // B1S's (stages 1-4, shifted by two with encoded inputs) buffer 1 holds the
 // first and third of them, buffer 0 the second and fourth.
-static void mfma_sig_lds(const PackedLayout &pl, int precision, int kpad, int *nlds,
+static void mfma_sig_lds(const PackedLayout &pl, int precision, int order_bytes, int *nlds,
                          int *ntail) {
   constexpr size_t kLdsMax = 160 * 1024;
   const size_t per_wave = (size_t)kNT * (pl.W / 32) * kFrag;
-  const size_t base = mfma_base_lds_bytes(pl, precision, kpad);
+  const size_t base = mfma_base_lds_bytes(pl, precision, order_bytes);
   int64_t stage_max = 0;
   for (int s = 0; s < pl.nstages; ++s)
     stage_max = std::max<int64_t>(stage_max, pl.stage_off[s + 1] - pl.stage_off[s]);
@@ -1232,15 +1250,15 @@ static void mfma_sig_lds(const PackedLayout &pl, int precision, int kpad, int *n
   *nlds = n;
 }
 
-static int mfma_sig_free_waves(const PackedLayout &pl, int precision, int kpad) {
+static int mfma_sig_free_waves(const PackedLayout &pl, int precision, int order_bytes) {
   int n, t;
-  mfma_sig_lds(pl, precision, kpad, &n, &t);
+  mfma_sig_lds(pl, precision, order_bytes, &n, &t);
   return n - t;
 }
 
-static size_t mfma_lds_bytes(const PackedLayout &pl, int precision, int kpad) {
-  return mfma_base_lds_bytes(pl, precision, kpad) +
-         (size_t)mfma_sig_free_waves(pl, precision, kpad) * kNT * (pl.W / 32) * kFrag;
+static size_t mfma_lds_bytes(const PackedLayout &pl, int precision, int order_bytes) {
+  return mfma_base_lds_bytes(pl, precision, order_bytes) +
+         (size_t)mfma_sig_free_waves(pl, precision, order_bytes) * kNT * (pl.W / 32) * kFrag;
 }
 
 template <int W, int PREC, int MODE, int PE>
@@ -1302,7 +1320,9 @@ static hipError_t launch_impl(int W, int precision, int pool, const uint8_t *pac
   // canonical order: a table of slot_kmax bytes per pixel, rounded up to 4
   a.canon = slot_kmax > 1 ? 1 : 0;
   a.kpad = a.canon ? (slot_kmax + 3) / 4 * 4 : 0;
-  mfma_sig_lds(pl, precision, a.kpad, &a.sig_lds_waves, &a.sig_tail_waves);
+  a.aslots = a.canon ? std::min(slot_kmax, 8) : 0;
+  const int order_bytes = kTilePx * (a.kpad + 4 * a.aslots);
+  mfma_sig_lds(pl, precision, order_bytes, &a.sig_lds_waves, &a.sig_tail_waves);
   a.packed = packed;
   for (int s = 0; s <= kMaxStages; ++s) a.stage_off[s] = s <= pl.nstages ? pl.stage_off[s] : 0;
   a.res_off = pl.resident_off;
@@ -1325,7 +1345,7 @@ static hipError_t launch_impl(int W, int precision, int pool, const uint8_t *pac
   a.inv_sa = 1.0f / fp8_act_scale;
   if (ntiles <= 0) return hipSuccess;
   grid = std::max(1, std::min(grid, ntiles));   // the scratch holds `grid` workgroups
-  const size_t lds = mfma_lds_bytes(pl, precision, a.kpad);
+  const size_t lds = mfma_lds_bytes(pl, precision, order_bytes);
   if (lds > 160 * 1024) return hipErrorInvalidValue;
   if (precision == GN_BF16) {
     if (W == 64) return launch_pe<64, GN_BF16>(pl.pe, mode, a, grid, lds, stream);

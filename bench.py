@@ -3,10 +3,17 @@
 
 One step = one fused forward pass (F, T over all K slots, pool, B, R) over one
 512 x 512 frame with K = 8 transparency layers at width 128, inputs resident
-in HBM.  Prints ONE JSON line (rank 0).
+in HBM, each pixel's slots pooled in the library's default canonical order.
+Prints ONE JSON line: the headline (exactly --warmup untimed launches, then
+--steps timed ones) with its roofline, and beside it, labelled: the same
+launches after 300 untimed ones (steady clocks), the other precision of the
+bf16 / fp8_t pair, input-order pooling, the 256^2 K=4 workload, the plain
+FP32 path, object streaming, encoded inputs, coherent coverage, the x2
+super-sampling pipeline, the spatial networks, a training step, Poisson
+serving (p50 / p99 latency) and the FP64 oracle on the host cores.
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision bf16|fp8_t]
-                  [--no-cpu-baseline] [--serve-seconds S]
+                  [--no-cpu-baseline] [--serve-seconds S] [--headline-only]
   python bench.py --copy-probe      # plain device copy of known size, for
                                     # scaling rocprofv3 FETCH/WRITE counters
 """
@@ -45,10 +52,20 @@ def peak_tflops(precision, W, K):
         return PEAK_TFLOPS[precision]
     f = fp8_t_share(W, K)
     return 1.0 / (f / PEAK_TFLOPS["fp8"] + (1.0 - f) / PEAK_TFLOPS["bf16"])
+
+
 # Algorithmic work per pixel of the method (sigma-hoisted, dense over the K
 # slots): 9 W^2 + 2 K W^2 + (36 + 12 K) W multiply-adds.
 def alg_flop_per_px(W, K):
     return 2 * (9 * W * W + 2 * K * W * W + (36 + 12 * K) * W)
+
+
+# The spatial networks (U-Net F and B, 3 x 3 h and R) per pixel, with h's sigma
+# part hoisted and dense over the K slots: F 9*30 W + 9 W^2 / 4 (half
+# resolution) + 18 W^2 + W^2; h 9 W^2 once, per slot 9*12 W + 2 W^2; B 18 W^2 +
+# 9 W^2 / 4 + 18 W^2 + W^2; R 9 (W + 3) W + 9 W^2 + 3 W multiply-adds.
+def spatial_flop_per_px(W, K):
+    return 2 * (87.5 * W * W + 2 * K * W * W + 300 * W + 108 * K * W)
 
 
 # Matrix-core work the fused kernel issues per pixel (its padding included):
@@ -541,6 +558,35 @@ def sr_phase(W, pool, precision, torch, steps=100, k=8):
             "sr_train_step_16x256sq_ms": t_train * 1e3}
 
 
+def spatial_phase(W, torch, steps=20, k=8, h=512, w=512):
+    """The spatial networks' forward (bf16 matrix cores) on an h x w frame
+    with k slots: ms per frame (HIP events after untimed calls), pixels/s and
+    the fraction of the dense bf16 peak on the algorithmic FLOP count."""
+    from paper_2405_19056_amd import synth
+    from paper_2405_19056_amd.glassnet import GlassNet
+    d = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")  # noqa: E731
+    fr = synth.make_frame(1, h, w, k, seed=2)
+    g, L, s = d(fr.gbuf), d(fr.layers), d(fr.scene)
+    sw = d(synth.make_spatial_weights(W, np.random.default_rng(7)))
+    out = torch.empty((1, 3, h, w), dtype=torch.float32, device="cuda:0")
+    with GlassNet(None, W, k_max=k, precision="bf16", seed=7) as net:
+        for _ in range(5):
+            net.spatial_forward(sw, g, L, s, out=out)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            net.spatial_forward(sw, g, L, s, out=out)
+        e1.record()
+        torch.cuda.synchronize()
+    t = e0.elapsed_time(e1) / 1e3 / steps
+    px = h * w
+    f = spatial_flop_per_px(W, k)
+    return {"workload": f"spatial networks, {h}x{w} frame, K={k}, width {W}, bf16",
+            "ms_per_frame": t * 1e3, "pixels_per_s": px / t, "alg_flop_per_px": f,
+            "tflops": f * px / t / 1e12, "frac": f * px / t / 1e12 / PEAK_TFLOPS["bf16"]}
+
+
 def copy_probe():
     """A plain device-to-device copy of 1 GiB, for counter scaling."""
     import torch
@@ -578,6 +624,9 @@ def main():
     ap.add_argument("--super-sampling-only", action="store_true",
                     help="only time the 512^2 pipeline (forward at 256^2 + x2 super-sampling)")
     ap.add_argument("--stream-reps", type=int, default=30)
+    ap.add_argument("--headline-only", action="store_true",
+                    help="time only the headline handle (for profiler runs): no input-order, "
+                         "other-precision or 256^2 handles")
     ap.add_argument("--backward-calls", type=int, default=0,
                     help="only time this many backward calls of the training workload")
     args = ap.parse_args()
@@ -612,8 +661,9 @@ def main():
     out = torch.empty((fr.n, 3, H, Wd), dtype=torch.float32, device="cuda:0")
     px = fr.n * H * Wd
 
-    def open_net(precision, k_max=K, wts=w, Wn=W):
-        net = GlassNet(wts, Wn, k_max=k_max, pool=c["pool"], precision=precision)
+    def open_net(precision, k_max=K, wts=w, Wn=W, order="canonical"):
+        net = GlassNet(wts, Wn, k_max=k_max, pool=c["pool"], precision=precision,
+                       slot_order=order)
         if precision == "fp8_t":
             # static activation scale from a separate seeded calibration frame
             cal = synth.make_frame(1, 128, 128, k_max, seed=999)
@@ -629,25 +679,32 @@ def main():
         dist = launch_distribution(net, g, L, s, out, torch)
         stream = (None if args.no_stream else
                   stream_phase(net, g, L, s, out, torch, reps=args.stream_reps))
-    # the other precision of the pair (bf16 <-> fp8_t) on the same frame, timed
-    # the same way
     other = "fp8_t" if args.precision == "bf16" else "bf16"
-    with open_net(other) as net:
-        _, kern_o = time_forward(net, g, L, s, out, args.steps, args.warmup, torch)
-        _, kern_o_steady = time_forward(net, g, L, s, out, 200, 300, torch)
-    # the 256^2, K=4 workload (bf16): rate, roofline and the oracle beside it
     c2 = synth.CONFIGS[WORKLOAD_256]
     w2, fr2, _ = synth.config_inputs(WORKLOAD_256)
-    g2, L2, s2 = d(fr2.gbuf), d(fr2.layers), d(fr2.scene)
-    out2 = torch.empty((fr2.n, 3, fr2.h, fr2.w), dtype=torch.float32, device="cuda:0")
-    with open_net(args.precision, k_max=c2["k"], wts=w2, Wn=c2["width"]) as net:
-        step2, kern2 = time_forward(net, g2, L2, s2, out2, args.steps, args.warmup, torch)
-        _, kern2_steady = time_forward(net, g2, L2, s2, out2, 200, 300, torch)
+    kern_in = kern_in_steady = kern_o = kern_o_steady = kern2 = kern2_steady = step2 = None
+    if not args.headline_only:
+        # the same frame pooled in input order (not the default canonical
+        # order), timed the same way: a labelled variant
+        with open_net(args.precision, order="input") as net:
+            _, kern_in = time_forward(net, g, L, s, out, args.steps, args.warmup, torch)
+            _, kern_in_steady = time_forward(net, g, L, s, out, 200, 300, torch)
+        # the other precision of the pair (bf16 <-> fp8_t) on the same frame
+        with open_net(other) as net:
+            _, kern_o = time_forward(net, g, L, s, out, args.steps, args.warmup, torch)
+            _, kern_o_steady = time_forward(net, g, L, s, out, 200, 300, torch)
+        # the 256^2, K=4 workload: rate, roofline and the oracle beside it
+        g2, L2, s2 = d(fr2.gbuf), d(fr2.layers), d(fr2.scene)
+        out2 = torch.empty((fr2.n, 3, fr2.h, fr2.w), dtype=torch.float32, device="cuda:0")
+        with open_net(args.precision, k_max=c2["k"], wts=w2, Wn=c2["width"]) as net:
+            step2, kern2 = time_forward(net, g2, L2, s2, out2, args.steps, args.warmup, torch)
+            _, kern2_steady = time_forward(net, g2, L2, s2, out2, 200, 300, torch)
     pe = (None if args.no_variants else
           pe_phase(W, K, c["pool"], args.precision, g, L, s, out, torch))
     coherent = (None if args.no_variants else
                 coherent_phase(W, K, c["pool"], args.precision, w, torch))
     sr = None if args.no_variants else sr_phase(W, c["pool"], args.precision, torch)
+    spatial = None if args.no_variants else spatial_phase(W, torch)
 
     fp32 = None
     if not args.no_fp32:
@@ -712,15 +769,21 @@ def main():
                              "pixels_per_s": px / kern_steady,
                              "frac": alg * px / kern_steady / 1e12 / peak},
         },
-        other: precision_entry(other, kern_o, kern_o_steady, W, K, px),
-        "workload_256sq_k4": dict(
+        "gpu_sclk": gpu_clock_mhz(torch),
+    }
+    if not args.headline_only:
+        res[other] = precision_entry(other, kern_o, kern_o_steady, W, K, px)
+        res["input_order"] = {
+            "variant": "slots pooled in input order (not the default canonical order; results "
+                       "differ by the pool's fp32 rounding)",
+            "kernel_ms": kern_in * 1e3, "pixels_per_s": px / kern_in,
+            "steady_state_kernel_ms": kern_in_steady * 1e3}
+        res["workload_256sq_k4"] = dict(
             precision_entry(args.precision, kern2, kern2_steady, c2["width"], c2["k"],
                             fr2.n * fr2.h * fr2.w),
             workload="256x256 frame, K=4 (active count U{0..4}), width 128, mean pool",
             value=fr2.n * fr2.h * fr2.w / step2, unit="pixels/s", ms_per_step=step2 * 1e3,
-            alg_flop_per_px=alg_flop_per_px(c2["width"], c2["k"])),
-        "gpu_sclk": gpu_clock_mhz(torch),
-    }
+            alg_flop_per_px=alg_flop_per_px(c2["width"], c2["k"]))
     if fp32:
         res["fp32_path"] = fp32
         res["speedup_vs_fp32_path"] = res["value"] / fp32["value"]
@@ -732,6 +795,8 @@ def main():
         res["coherent_coverage"] = coherent
     if sr:
         res["super_sampling"] = sr
+    if spatial:
+        res["spatial"] = spatial
     if not args.no_train:
         res["train_step"] = train_phase(torch)
     if args.k_sweep:
@@ -753,7 +818,7 @@ def main():
                                "one_thread": {"value": v1, "cores": thr1, "sample": sample1,
                                               "gflops_fp64": 2 * mac(W, K) * v1 / 1e9}}
         v2, thr2, sample2 = cpu_baseline(w2, fr2, c2["width"], c2["pool"], budget_s=5.0)
-        res["workload_256sq_k4"]["cpu_baseline"] = {
+        res.setdefault("workload_256sq_k4", {})["cpu_baseline"] = {
             "value": v2, "unit": "pixels/s", "cores": thr2, "kind": "oracle", "sample": sample2,
             "gflops_fp64": 2 * mac(c2["width"], c2["k"]) * v2 / 1e9}
     print(json.dumps(res))

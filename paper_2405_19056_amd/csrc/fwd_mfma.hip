@@ -684,7 +684,7 @@ __global__ __launch_bounds__(kThreads) void fwd_mfma_kernel(MfmaArgs a) {
               }
               if (i < K) {
                 if (le == lt + 1)
-                  perm_px[t][lt] = (uint8_t)i;
+                  perm_px[t][lt] = ki >= 0xFFFFFF00u ? (uint8_t)0xFF : (uint8_t)i;
                 else
                   slow |= 1u << (2 * t + sl);
               }
@@ -697,13 +697,14 @@ __global__ __launch_bounds__(kThreads) void fwd_mfma_kernel(MfmaArgs a) {
               for (int sl = 0; sl < 2; ++sl)
                 if (slow & (1u << (2 * t + sl)))
                   perm_px[t][slot_rank(Lp + qc[t], (size_t)hw, K, g + 4 * sl)] =
-                      (uint8_t)(g + 4 * sl);
+                      slot_active(Lp + qc[t], hw, g + 4 * sl) ? (uint8_t)(g + 4 * sl) : (uint8_t)0xFF;
           }
         } else {
 #pragma unroll
           for (int t = 0; t < kNT; ++t)
             for (int i = g; i < K; i += 4)
-              perm_px[t][slot_rank(Lp + qc[t], (size_t)hw, K, i)] = (uint8_t)i;
+              perm_px[t][slot_rank(Lp + qc[t], (size_t)hw, K, i)] =
+                  slot_active(Lp + qc[t], hw, i) ? (uint8_t)i : (uint8_t)0xFF;
         }
         // the wave reads the table back in its own slot loop (LDS operations of
         // one wave complete in order)
@@ -750,12 +751,17 @@ __global__ __launch_bounds__(kThreads) void fwd_mfma_kernel(MfmaArgs a) {
         constexpr int kRaw = PE > 0 ? 3 : 4;
         float nxt[kNT][kRaw];
         // Iteration i takes each pixel's slot of rank i (canonical order) or
-        // slot i (input order).
+        // slot i (input order).  In canonical order the inactive slots come
+        // last and their table bytes are 0xFF: such a pixel loads nothing and
+        // presents zeros (alpha 0: its term is masked out exactly), so half the
+        // loads of the workloads' slot stage never reach the memory system.
         auto load_slot = [&](int i) {
           uint32_t qs[kNT];      // element offsets (frames of the MFMA path stay below 2^32)
+          bool act[kNT];
 #pragma unroll
           for (int t = 0; t < kNT; ++t) {
             const int si = canon ? (int)L_perm[pofs + t * 16 * a.kpad + i] : i;
+            act[t] = si != 0xFF;
             qs[t] = (uint32_t)si * (uint32_t)(kNL * hw) + (uint32_t)qc[t];
             asm volatile("" : "+v"(qs[t]));   // per-slot addresses stay in the loop body
           }
@@ -764,9 +770,9 @@ __global__ __launch_bounds__(kThreads) void fwd_mfma_kernel(MfmaArgs a) {
 #pragma unroll
             for (int j = 0; j < kRaw; ++j) {
               if constexpr (PE > 0)
-                nxt[t][j] = Lp[(size_t)(3 * g + j) * hw + qs[t]];
+                nxt[t][j] = act[t] ? Lp[(size_t)(3 * g + j) * hw + qs[t]] : 0.0f;
               else
-                nxt[t][j] = g < 3 ? Lp[(size_t)(4 * g + j) * hw + qs[t]] : 0.0f;
+                nxt[t][j] = g < 3 && act[t] ? Lp[(size_t)(4 * g + j) * hw + qs[t]] : 0.0f;
             }
         };
         if (K > 0) load_slot(0);

@@ -45,6 +45,12 @@ __device__ __forceinline__ bool slot_before(P L, size_t hw, int j, int i, uint32
   return j < i;
 }
 
+// Whether slot i of the pixel takes part in the pool (alpha > 0).
+template <class P>
+__device__ __forceinline__ bool slot_active(P L, int hw, int i) {
+  return slot_key(L[((size_t)i * kNL + kAlpha) * (size_t)hw]) != kInactiveKey;
+}
+
 // Position of slot i in the canonical order among the pixel's k slots.
 template <class P>
 __device__ __forceinline__ int slot_rank(P L, size_t hw, int k, int i) {

@@ -66,6 +66,7 @@ struct MfmaArgs {
   int canon;                           // FULL: pool each pixel's slots in canonical order
   int kpad;                            // bytes per pixel of the LDS slot-order table
   int aslots;                          // slots whose alphas the LDS alpha table holds
+  int alpha_alias;                     // 1: the alpha table sits in sigma's parking area
 };
 
 // Two floats -> packed bf16 pair (round to nearest even), one v_cvt_pk_bf16_f32.
@@ -359,10 +360,14 @@ __global__ __launch_bounds__(kThreads) void fwd_mfma_kernel(MfmaArgs a) {
   // slot-order table: for each pixel of the tile, its slots' indices in
   // canonical order (kpad bytes per pixel, a multiple of 4), and the tile's
   // alphas [slot][pixel] that the order is computed from (aslots slots)
+  // (in sigma's LDS parking area, free until F's last layer ends, when that
+  // area holds at least the table)
   uint8_t *L_perm = lds + res_bytes + Shape<W>::kBiasBytes;
-  float *L_alpha = (float *)(L_perm + (size_t)kTilePx * a.kpad);
-  uint8_t *L_stage0 = (uint8_t *)L_alpha + (size_t)kTilePx * 4 * a.aslots;
+  uint8_t *L_stage0 =
+      L_perm + (size_t)kTilePx * a.kpad + (a.alpha_alias ? 0 : (size_t)kTilePx * 4 * a.aslots);
   uint8_t *L_stage1 = L_stage0 + stage_max;
+  float *L_alpha = a.alpha_alias ? (float *)(L_stage1 + stage_max)
+                                 : (float *)(L_perm + (size_t)kTilePx * a.kpad);
   // FWD_FINISH runs an odd number of stages per tile, so its buffer parity
   // flips from one tile to the next (par); every other mode keeps par = 0.
   int par = 0;
@@ -533,11 +538,27 @@ __global__ __launch_bounds__(kThreads) void fwd_mfma_kernel(MfmaArgs a) {
                                           (size_t)(1 + (wave - nfree) / 2) * kSigBytes;
     uint8_t *sig_slot = a.sig_scratch + ((size_t)blockIdx.x * kWaves + wave) * kSigBytes;
 
+    // The tile's alphas, slot by slot, into the LDS alpha table (canonical
+    // order with up to kFastK slots): 64-pixel blocks, lane i copying pixel i
+    // of its block (clamped to the frame).  Issued with F's second layer and
+    // ranked before its last.
+    const bool canon_fast = MODE == FWD_FULL && a.canon && K > 1 && K <= kFastK;
+    auto copy_alphas = [&]() {
+      for (int b = wave; b < 4 * K; b += kWaves) {
+        const int j = b >> 2, p0 = (b & 3) * 64;
+        const int q = min(q0 + p0 + lane, hw - 1);
+        __builtin_amdgcn_global_load_lds(
+            (const void *)(Lp + ((size_t)j * kNL + kAlpha) * hw + q),
+            (__attribute__((address_space(3))) void *)(L_alpha + j * kTilePx + p0), 4, 0, 0);
+      }
+    };
+
     if constexpr (kTrunk) {
       u32x4 h2[kNT][KS];
       if constexpr (PE == 0) {
         // ================= stage 0: F layers 1-2 =================
         if constexpr (MODE == FWD_FULL) fill_stage(sF3);
+        if (canon_fast) copy_alphas();
         {
           u32x4 x[kNT][1];
 #pragma unroll
@@ -576,6 +597,7 @@ __global__ __launch_bounds__(kThreads) void fwd_mfma_kernel(MfmaArgs a) {
         wait_vm();
         __syncthreads();
         fill_stage(sF3);
+        if (canon_fast) copy_alphas();
         layer<MT, KS, true>(h2, stage_buf(sF2), h1, bF2, g, lane);
         wait_vm();
         __syncthreads();
@@ -583,73 +605,14 @@ __global__ __launch_bounds__(kThreads) void fwd_mfma_kernel(MfmaArgs a) {
 
       // ================= F layer 3 -> sigma =================
       if constexpr (MODE == FWD_FULL) fill_stage(sT1S);
-      if (MODE == FWD_FULL && a.canon && K > 1 && K <= kFastK) {
-        // the tile's alphas, slot by slot, into the LDS alpha table: 64-pixel
-        // blocks, lane i copying pixel i of its block (clamped to the frame)
-        for (int b = wave; b < 4 * K; b += kWaves) {
-          const int j = b >> 2, p0 = (b & 3) * 64;
-          const int q = min(q0 + p0 + lane, hw - 1);
-          __builtin_amdgcn_global_load_lds(
-              (const void *)(Lp + ((size_t)j * kNL + kAlpha) * hw + q),
-              (__attribute__((address_space(3))) void *)(L_alpha + j * kTilePx + p0), 4, 0, 0);
-        }
-      }
-      if constexpr (MODE == FWD_BEGIN && PE > 0) {
-        if (has_next) fill_stage(sF1);      // the next tile's first stage
-      }
-      layer<MT, KS, false>(sig, stage_buf(sF3), h2, bF3, g, lane);
-      if constexpr (MODE == FWD_BEGIN) {
-        // sigma goes to the streaming state; the next tile's F input is requested
-#pragma unroll
-        for (int t = 0; t < kNT; ++t)
-#pragma unroll
-          for (int k = 0; k < KS; ++k) st_sig[(t * KS + k) * 64] = sig[t][k];
-        if (has_next) {
-          nti = resolve(tile + gridDim.x);
-          load_x(nti, lane, xr);
-        }
-        if constexpr (PE > 0) {
-          // the next tile's first stage has landed; this stage's buffer is free
-          wait_vm();
-          __syncthreads();
-        }
-      } else {
-        if (sig_in_lds) {
-#pragma unroll
-          for (int t = 0; t < kNT; ++t)
-#pragma unroll
-            for (int k = 0; k < KS; ++k) *(u32x4 *)(sig_lds + (t * KS + k) * kFrag + lane * 16) = sig[t][k];
-        } else {
-#pragma unroll
-          for (int t = 0; t < kNT; ++t)
-#pragma unroll
-            for (int k = 0; k < KS; ++k) *(u32x4 *)(sig_slot + (t * KS + k) * kFrag + lane * 16) = sig[t][k];
-        }
-        // the kNT x KS stores above stay in flight; the same wave reads them back
-        // in stage 3, after stage 2's full wait
-        if (sig_in_lds)
-          stage_sync_after_stores<0>();
-        else
-          stage_sync_after_stores<kNT * KS>();
-      }
-    }
-
-    if constexpr (kSlots) {
-      // ================= stage 2: u = W1s sigma + c1, then the slot loop =======
-      if constexpr (MODE == FWD_FULL) fill_stage(sT3);
-      if constexpr (MODE == FWD_ACC) {
-#pragma unroll
-        for (int t = 0; t < kNT; ++t)
-#pragma unroll
-          for (int k = 0; k < KS; ++k) sig[t][k] = st_sig[(t * KS + k) * 64];
-      }
       // Canonical order of each pixel's slots, into this wave's part of the
       // LDS table (byte r of a pixel's entry: its slot of rank r).  Keys: the
       // bits of alpha for active slots, 0xFFFFFF00 + j for an inactive slot j
       // (above every active key, distinct), 0xFFFFFFFF past K.  With up to
       // kFastK slots each lane ranks its lane group's slots g and g + 4 from the
-      // alphas in LDS; two active slots of equal alpha (and more
-      // than kFastK slots) take the full comparison of slot_order.h.
+      // alphas in LDS (they landed by the last barrier); two active slots of
+      // equal alpha (and more than kFastK slots) take the full comparison of
+      // slot_order.h.
       if (MODE == FWD_FULL && a.canon && K > 1) {
         uint8_t *perm_px[kNT];
 #pragma unroll
@@ -708,6 +671,58 @@ __global__ __launch_bounds__(kThreads) void fwd_mfma_kernel(MfmaArgs a) {
         }
         // the wave reads the table back in its own slot loop (LDS operations of
         // one wave complete in order)
+      }
+      // the alpha table shares sigma's parking area: every wave has read it
+      // before any wave parks sigma there
+      if (canon_fast && a.alpha_alias) __syncthreads();
+      if constexpr (MODE == FWD_BEGIN && PE > 0) {
+        if (has_next) fill_stage(sF1);      // the next tile's first stage
+      }
+      layer<MT, KS, false>(sig, stage_buf(sF3), h2, bF3, g, lane);
+      if constexpr (MODE == FWD_BEGIN) {
+        // sigma goes to the streaming state; the next tile's F input is requested
+#pragma unroll
+        for (int t = 0; t < kNT; ++t)
+#pragma unroll
+          for (int k = 0; k < KS; ++k) st_sig[(t * KS + k) * 64] = sig[t][k];
+        if (has_next) {
+          nti = resolve(tile + gridDim.x);
+          load_x(nti, lane, xr);
+        }
+        if constexpr (PE > 0) {
+          // the next tile's first stage has landed; this stage's buffer is free
+          wait_vm();
+          __syncthreads();
+        }
+      } else {
+        if (sig_in_lds) {
+#pragma unroll
+          for (int t = 0; t < kNT; ++t)
+#pragma unroll
+            for (int k = 0; k < KS; ++k) *(u32x4 *)(sig_lds + (t * KS + k) * kFrag + lane * 16) = sig[t][k];
+        } else {
+#pragma unroll
+          for (int t = 0; t < kNT; ++t)
+#pragma unroll
+            for (int k = 0; k < KS; ++k) *(u32x4 *)(sig_slot + (t * KS + k) * kFrag + lane * 16) = sig[t][k];
+        }
+        // the kNT x KS stores above stay in flight; the same wave reads them back
+        // in stage 3, after stage 2's full wait
+        if (sig_in_lds)
+          stage_sync_after_stores<0>();
+        else
+          stage_sync_after_stores<kNT * KS>();
+      }
+    }
+
+    if constexpr (kSlots) {
+      // ================= stage 2: u = W1s sigma + c1, then the slot loop =======
+      if constexpr (MODE == FWD_FULL) fill_stage(sT3);
+      if constexpr (MODE == FWD_ACC) {
+#pragma unroll
+        for (int t = 0; t < kNT; ++t)
+#pragma unroll
+          for (int k = 0; k < KS; ++k) sig[t][k] = st_sig[(t * KS + k) * 64];
       }
       {
         // the slot-order table of this tile (written above): the lane's pixel
@@ -1327,8 +1342,16 @@ static hipError_t launch_impl(int W, int precision, int pool, const uint8_t *pac
   a.canon = slot_kmax > 1 ? 1 : 0;
   a.kpad = a.canon ? (slot_kmax + 3) / 4 * 4 : 0;
   a.aslots = a.canon ? std::min(slot_kmax, 8) : 0;
-  const int order_bytes = kTilePx * (a.kpad + 4 * a.aslots);
+  // the alpha table goes into sigma's parking area when that area holds it,
+  // else into LDS of its own
+  int order_bytes = kTilePx * a.kpad;
   mfma_sig_lds(pl, precision, order_bytes, &a.sig_lds_waves, &a.sig_tail_waves);
+  const int alpha_bytes = kTilePx * 4 * a.aslots;
+  a.alpha_alias = (a.sig_lds_waves - a.sig_tail_waves) * kNT * (W / 32) * kFrag >= alpha_bytes;
+  if (!a.alpha_alias) {
+    order_bytes += alpha_bytes;
+    mfma_sig_lds(pl, precision, order_bytes, &a.sig_lds_waves, &a.sig_tail_waves);
+  }
   a.packed = packed;
   for (int s = 0; s <= kMaxStages; ++s) a.stage_off[s] = s <= pl.nstages ? pl.stage_off[s] : 0;
   a.res_off = pl.resident_off;

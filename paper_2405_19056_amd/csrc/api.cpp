@@ -115,6 +115,9 @@ gn_status glassnet_create(const gn_config *cfg, const float *host_weights, size_
     return fail(GN_E_INVAL, "k_max %d outside [0, %d]", cfg->k_max, GN_MAX_K);
   if (cfg->pool != GN_POOL_MEAN && cfg->pool != GN_POOL_SUM)
     return fail(GN_E_INVAL, "unknown pool %d", cfg->pool);
+  if (cfg->precision == GN_FP8_ALL)
+    return fail(GN_E_UNSUPPORTED, "GN_FP8_ALL is not built: FP8 in every layer misses the "
+                                  "6e-2 error bar (about 8e-2); use GN_FP8_T");
   if (cfg->precision != GN_FP32 && cfg->precision != GN_BF16 && cfg->precision != GN_FP8_T)
     return fail(GN_E_INVAL, "unknown precision %d", cfg->precision);
   if (cfg->precision == GN_FP8_T && cfg->width != 128)
@@ -623,7 +626,7 @@ gn_status glassnet_spatial_forward(gn_handle *h, const float *sp_w, const gn_fra
                                       : gn_check_device(h, e, "spatial weight copy");
     }
   }
-  const size_t need = gn::spatial_workspace_bytes(h->W, frame->n, frame->h, frame->w) + 4096;
+  const size_t need = gn::spatial_workspace_bytes(h->W, frame->n, frame->h, frame->w, frame->k) + 4096;
   if (need > h->sp_ws_bytes) {
     // grown workspaces replace the old one once the stream's earlier work is done
     e = hipStreamSynchronize(s);

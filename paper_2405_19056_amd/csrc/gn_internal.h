@@ -191,7 +191,7 @@ hipError_t launch_sr_backward(const float *w, float *wt, const float *lowres, co
 // master vector) and the forward (bf16 matrix cores, fp32 accumulation).
 size_t spatial_num_params(int W);
 size_t spatial_weight_bytes(int W);
-size_t spatial_workspace_bytes(int W, int n, int H, int Wd);
+size_t spatial_workspace_bytes(int W, int n, int H, int Wd, int k);
 hipError_t spatial_pack(const float *master, int W, uint8_t *packed, hipStream_t s);
 hipError_t spatial_forward(const uint8_t *packed, int W, int pool, const float *gbuf,
                            const float *layers, const float *scene, int n, int H, int Wd, int k,

@@ -30,10 +30,15 @@
 // The input fragments of the next K-step are loaded while the current one's
 // MFMAs run.
 //
-// Epilogues: bias (optionally times a per-pixel scale), an added fp32 plane
-// block (h's hoisted sigma part u), ReLU, then one of: bf16 activation
-// store, fp32 store, the masked pool of Eq. (5) (Z += [alpha > 0] relu(.)
-// in fp32), or R's 3 outputs to the caller's [n][3][H][W] fp32 image.
+// Epilogues: bias, ReLU, then one of: bf16 activation store, fp32 store, or
+// R's 3 outputs to the caller's [n][3][H][W] fp32 image.
+//
+// h over the buffers, the pool and T's last layer run in one kernel of their
+// own (sp_slots_kernel below): the per-buffer activations and the running
+// sum stay on the chip.  (The generic table also packs T's layers as
+// ordinary convs; only their biases are read from it.)
+#include <algorithm>
+
 #include "gn_internal.h"
 
 namespace gn {
@@ -78,15 +83,9 @@ struct SpConvArgs {
   int n, H, Wd;             // output (= in0) size
   int cout_pad;             // output channel count of the bf16 / fp32 layouts (MT * 16)
   // epilogue
-  const float *bscale;      // [n][H][W] per-pixel factor of the bias, or null
-  const float *add;         // fp32 [n][H][W][cout_pad] added before ReLU, or null
   int relu;
   uint8_t *out_bf;          // bf16 [n][H][W][cout_pad], or null
   float *out_f32;           // fp32 [n][H][W][cout_pad], or null
-  float *pool;              // fp32 [n][H][W][cout_pad]: += [alpha > 0] value, or null
-  const float *alpha;       // the slot's alpha plane: [n] frames of stride alpha_fstride
-  int64_t alpha_fstride;    // floats between frames of the alpha plane
-  int pool_first;           // the pool starts from zero (first slot)
   float *out_rgb;           // fp32 [n][3][H][W] (3 real outputs), or null
 };
 
@@ -103,9 +102,11 @@ __global__ __launch_bounds__(kThreads) void sp_conv_kernel(SpConvArgs a) {
   const int64_t nseg = (int64_t)a.n * H * segs;
   const bool live = seg < nseg;
   const int64_t sg = live ? seg : nseg - 1;
-  const int f = (int)(sg / ((int64_t)H * segs));
+  // the wave's row segment (wave-uniform)
+  const int f = __builtin_amdgcn_readfirstlane((int)(sg / ((int64_t)H * segs)));
   const int rem = (int)(sg - (int64_t)f * H * segs);
-  const int y = rem / segs, x0 = (rem - (rem / segs) * segs) * kWavePx;
+  const int y = __builtin_amdgcn_readfirstlane(rem / segs);
+  const int x0 = __builtin_amdgcn_readfirstlane((rem - (rem / segs) * segs) * kWavePx);
   const int r = a.ksize >> 1;
   const int cb0 = a.c0 >> 5;                              // 32-channel blocks of in0
   const int cbt = (a.c0 + a.c1) >> 5;
@@ -123,29 +124,39 @@ __global__ __launch_bounds__(kThreads) void sp_conv_kernel(SpConvArgs a) {
   };
 
   // B fragment of K-step s for N-tile t: pixel (y + dy - r, x0 + 16 t + col + dx - r),
-  // channels 32 cb + 8 g .. + 7 of the concatenated input; zero outside the frame
+  // channels 32 cb + 8 g .. + 7 of the concatenated input; zero outside the
+  // frame.  The row base is wave-uniform; every lane loads (from a clamped
+  // pixel), so each step issues exactly kNT loads: the chunk waits below count
+  // on that.
   auto load_b = [&](int s, u32x4 (&b)[kNT]) {
     const int tap = s / cbt, cb = s - tap * cbt;
     const int dy = tap / a.ksize - r, dx = tap % a.ksize - r;
     const int yy = y + dy;
     const bool yok = yy >= 0 && yy < H;
+    const int yc = min(max(yy, 0), H - 1);
+    const uint8_t *row;
+    int cs, shift;                       // channel stride and the column shift of the source
+    if (cb < cb0) {
+      row = a.in0 + (((int64_t)f * H + yc) * Wd) * a.c0 * 2 + (32 * cb) * 2;
+      cs = a.c0;
+      shift = 0;
+    } else if (a.up1) {
+      const int H1 = H >> 1, W1 = Wd >> 1;
+      row = a.in1 + (((int64_t)f * H1 + (yc >> 1)) * W1) * a.c1 * 2 + (32 * (cb - cb0)) * 2;
+      cs = a.c1;
+      shift = 1;
+    } else {
+      row = a.in1 + (((int64_t)f * H + yc) * Wd) * a.c1 * 2 + (32 * (cb - cb0)) * 2;
+      cs = a.c1;
+      shift = 0;
+    }
 #pragma unroll
     for (int t = 0; t < kNT; ++t) {
       const int xx = x0 + 16 * t + col + dx;
-      u32x4 v = {0u, 0u, 0u, 0u};
-      if (yok && xx >= 0 && xx < Wd) {
-        if (cb < cb0) {
-          v = *(const u32x4 *)(a.in0 + ((((int64_t)f * H + yy) * Wd + xx) * a.c0 + 32 * cb + 8 * g) * 2);
-        } else if (a.up1) {
-          const int H1 = H >> 1, W1 = Wd >> 1;
-          v = *(const u32x4 *)(a.in1 + ((((int64_t)f * H1 + (yy >> 1)) * W1 + (xx >> 1)) * a.c1 +
-                                        32 * (cb - cb0) + 8 * g) * 2);
-        } else {
-          v = *(const u32x4 *)(a.in1 + ((((int64_t)f * H + yy) * Wd + xx) * a.c1 +
-                                        32 * (cb - cb0) + 8 * g) * 2);
-        }
-      }
-      b[t] = v;
+      const bool ok = yok && xx >= 0 && xx < Wd;
+      const int xc = min(max(xx, 0), Wd - 1) >> shift;
+      const u32x4 v = *(const u32x4 *)(row + (uint32_t)((xc * cs + 8 * g) * 2));
+      b[t] = ok ? v : u32x4{0u, 0u, 0u, 0u};
     }
   };
 
@@ -159,8 +170,14 @@ __global__ __launch_bounds__(kThreads) void sp_conv_kernel(SpConvArgs a) {
   u32x4 bcur[kNT], bnext[kNT];
   load_b(0, bcur);
   for (int c = 0; c < nchunks; ++c) {
-    // the chunk's weights have landed (each wave's own copies, then everyone's)
-    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    // The chunk's weights have landed: each wave waits for its own copies,
+    // then for everyone's.  Issued after the copies of chunk c (at the start
+    // of chunk c - 1) are only the input loads of chunk c - 1's steps, kNT per
+    // step, the last kChunk kNT of them still allowed in flight.
+    if (c == 0)
+      asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    else
+      asm volatile("s_waitcnt vmcnt(%0)" ::"n"(kChunk * kNT) : "memory");
     __syncthreads();
     if (c + 1 < nchunks) fill(c + 1);
     const uint8_t *Wc = lds + (c & 1) * kChunkBytes;
@@ -186,15 +203,10 @@ __global__ __launch_bounds__(kThreads) void sp_conv_kernel(SpConvArgs a) {
     const int xx = x0 + 16 * t + col;
     if (xx >= Wd) continue;
     const int64_t px = ((int64_t)f * H + y) * Wd + xx;
-    const float bs = a.bscale ? a.bscale[px] : 1.0f;
-    float m = 1.0f;
-    if (a.pool) m = a.alpha[(int64_t)f * a.alpha_fstride + (int64_t)y * Wd + xx] > 0.0f ? 1.0f : 0.0f;
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt) {
       const int c0 = 16 * mt + 4 * g;
-      const f32x4 bv = *(const f32x4 *)(a.bias + c0);
-      f32x4 v = acc[t][mt] + bv * bs;
-      if (a.add) v += *(const f32x4 *)(a.add + px * a.cout_pad + c0);
+      f32x4 v = acc[t][mt] + *(const f32x4 *)(a.bias + c0);
       if (a.relu) {
 #pragma unroll
         for (int j = 0; j < 4; ++j) v[j] = fmaxf(v[j], 0.0f);
@@ -204,16 +216,159 @@ __global__ __launch_bounds__(kThreads) void sp_conv_kernel(SpConvArgs a) {
         *(uint2 *)(a.out_bf + (px * a.cout_pad + c0) * 2) = pk;
       }
       if (a.out_f32) *(f32x4 *)(a.out_f32 + px * a.cout_pad + c0) = v;
-      if (a.pool) {
-        f32x4 *zp = (f32x4 *)(a.pool + px * a.cout_pad + c0);
-        const f32x4 z = a.pool_first ? f32x4{0.f, 0.f, 0.f, 0.f} : *zp;
-        *zp = z + v * m;
-      }
       if (a.out_rgb && mt == 0 && g == 0) {
         const int64_t hw = (int64_t)H * Wd, q = (int64_t)y * Wd + xx;
         a.out_rgb[((int64_t)f * 3 + 0) * hw + q] = v[0];
         a.out_rgb[((int64_t)f * 3 + 1) * hw + q] = v[1];
         a.out_rgb[((int64_t)f * 3 + 2) * hw + q] = v[2];
+      }
+    }
+  }
+}
+
+// ---- h over every buffer, the pool and T's last layer, in one kernel ----------
+// With sigma's part u = conv3 sigma + c1 computed once, each buffer i needs
+//   z1 = relu(conv3_b b_i + u), z2 = relu(A2 z1 + c2), Z += [alpha_i > 0] z2,
+// and after the last buffer tau = A3 (Z / max(c, 1)) + [c > 0] c3 (mean; the
+// sum: A3 Z + c c3).  A wave owns 16 pixels of one row and every channel; u
+// and Z stay in registers across the buffers and z1 feeds h's second layer
+// from registers, so the per-buffer activations never leave the chip.
+//
+// Weights stay in LDS for the whole kernel (persistent workgroups):
+//   conv3_b: 5 K-steps; lane group g of step s presents tap 2 s + (g >> 1)
+//     (the tenth tap is zero), channels 8 (g & 1) .. + 7 of the buffer
+//     (12 real, 16 packed);
+//   A2, A3: W / 32 K-steps in register order: element e of lane group g in
+//     step s multiplies channel 32 s + 4 g + e (e < 4) or 32 s + 16 + 4 g +
+//     e - 4, which is where M-tiles 2 s and 2 s + 1 of the previous layer's
+//     accumulators hold them.
+struct SpSlotsArgs {
+  const uint8_t *frag;      // conv3_b, A2, A3 fragments, contiguous
+  const float *bias;        // c2 then c3, 16 MT floats each
+  const uint8_t *bpk;       // bf16 [n][k][H][W][16]: each buffer's 12 channels, zero padded
+  const float *layers;      // the caller's buffers (alpha)
+  const float *u;           // fp32 [n][H][W][16 MT]
+  uint8_t *tau;             // bf16 [n][H][W][16 MT]
+  int n, H, Wd, k, mean;
+};
+
+constexpr int kSlotSteps1 = 5;               // conv3_b K-steps (9 taps x 16 channels)
+
+template <int MT>
+__global__ __launch_bounds__(kThreads) void sp_slots_kernel(SpSlotsArgs a) {
+  extern __shared__ __attribute__((aligned(1024))) uint8_t lds[];
+  constexpr int W = 16 * MT, KS = MT / 2;
+  constexpr int kBytes = (kSlotSteps1 + 2 * KS) * MT * kFrag;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int g = lane >> 4, col = lane & 15;
+  // every fragment, then the biases, into LDS once
+  for (int off = wave * kFrag; off < kBytes; off += kWaves * kFrag)
+    __builtin_amdgcn_global_load_lds((const void *)(a.frag + off + lane * 16),
+                                     (__attribute__((address_space(3))) void *)(lds + off), 16, 0, 0);
+  float *lbias = (float *)(lds + kBytes);
+  if (threadIdx.x < 2 * W) lbias[threadIdx.x] = a.bias[threadIdx.x];
+  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+  __syncthreads();
+  const uint8_t *F1 = lds, *F2 = lds + kSlotSteps1 * MT * kFrag, *F3 = F2 + KS * MT * kFrag;
+
+  const int H = a.H, Wd = a.Wd, k = a.k;
+  const int64_t hw = (int64_t)H * Wd;
+  const int segs = (Wd + 15) >> 4;
+  const int64_t nseg = (int64_t)a.n * H * segs;
+  const int64_t ntiles = (nseg + kWaves - 1) / kWaves;
+  // workgroups reach the 8 XCDs round-robin: each XCD takes a contiguous run
+  // of tiles (neighbouring rows share its L2)
+  const int per = gridDim.x >> 3, xcd = blockIdx.x & 7, slot = blockIdx.x >> 3;
+  for (int64_t base = 0; base < ntiles; base += gridDim.x) {
+    const int64_t seg = (base + (int64_t)xcd * per + slot) * kWaves + wave;
+    if (seg >= nseg) continue;
+    const int f = __builtin_amdgcn_readfirstlane((int)(seg / ((int64_t)H * segs)));
+    const int rem = (int)(seg - (int64_t)f * H * segs);
+    const int y = __builtin_amdgcn_readfirstlane(rem / segs);
+    const int x0 = __builtin_amdgcn_readfirstlane((rem - y * segs) * 16);
+    const int x = x0 + col;
+    const bool xin = x < Wd;
+    const int xc = min(x, Wd - 1);
+    const int64_t px = ((int64_t)f * H + y) * Wd + xc;
+
+    f32x4 u[MT], Z[MT];
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) {
+      u[mt] = *(const f32x4 *)(a.u + px * W + 16 * mt + 4 * g);
+      Z[mt] = f32x4{0.f, 0.f, 0.f, 0.f};
+    }
+    float cnt = 0.0f;
+    for (int i = 0; i < k; ++i) {
+      const int64_t fb = (int64_t)f * k + i;
+      const float al = a.layers[(fb * kNL + kAlpha) * hw + (int64_t)y * Wd + xc];
+      const bool act = xin && al > 0.0f;
+      if (!__builtin_amdgcn_ballot_w64(act)) continue;    // adds exactly nothing
+      // the buffer's conv3 inputs: tap 2 s + (g >> 1), zero outside the frame
+      u32x4 b[kSlotSteps1];
+      const uint8_t *bi = a.bpk + fb * hw * 32;
+#pragma unroll
+      for (int s = 0; s < kSlotSteps1; ++s) {
+        const int tap = 2 * s + (g >> 1);
+        const int yy = y + tap / 3 - 1, xx = x + tap % 3 - 1;
+        const bool ok = tap < 9 && yy >= 0 && yy < H && xx >= 0 && xx < Wd;
+        const int yc = min(max(yy, 0), H - 1), xq = min(max(xx, 0), Wd - 1);
+        const u32x4 v = *(const u32x4 *)(bi + ((int64_t)yc * Wd + xq) * 32 + 16 * (g & 1));
+        b[s] = ok ? v : u32x4{0u, 0u, 0u, 0u};
+      }
+      f32x4 acc[MT];
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt) acc[mt] = u[mt];
+#pragma unroll
+      for (int s = 0; s < kSlotSteps1; ++s)
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt)
+          acc[mt] = mma(*(const u32x4 *)(F1 + (s * MT + mt) * kFrag + lane * 16), b[s], acc[mt]);
+      // z1 in register order, then h's second layer
+      u32x4 zb[KS];
+#pragma unroll
+      for (int s = 0; s < KS; ++s) {
+        const f32x4 p = acc[2 * s], q = acc[2 * s + 1];
+        zb[s] = u32x4{pk_bf16(fmaxf(p[0], 0.f), fmaxf(p[1], 0.f)),
+                      pk_bf16(fmaxf(p[2], 0.f), fmaxf(p[3], 0.f)),
+                      pk_bf16(fmaxf(q[0], 0.f), fmaxf(q[1], 0.f)),
+                      pk_bf16(fmaxf(q[2], 0.f), fmaxf(q[3], 0.f))};
+      }
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt) acc[mt] = *(const f32x4 *)(lbias + 16 * mt + 4 * g);
+#pragma unroll
+      for (int s = 0; s < KS; ++s)
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt)
+          acc[mt] = mma(*(const u32x4 *)(F2 + (s * MT + mt) * kFrag + lane * 16), zb[s], acc[mt]);
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) Z[mt][j] += act ? fmaxf(acc[mt][j], 0.0f) : 0.0f;
+      cnt += act ? 1.0f : 0.0f;
+    }
+    // the pool's finish and T's last layer
+    const float inv = a.mean ? 1.0f / fmaxf(cnt, 1.0f) : 1.0f;
+    const float bs = a.mean ? (cnt > 0.0f ? 1.0f : 0.0f) : cnt;
+    u32x4 zb[KS];
+#pragma unroll
+    for (int s = 0; s < KS; ++s) {
+      const f32x4 p = Z[2 * s] * inv, q = Z[2 * s + 1] * inv;
+      zb[s] = u32x4{pk_bf16(p[0], p[1]), pk_bf16(p[2], p[3]), pk_bf16(q[0], q[1]),
+                    pk_bf16(q[2], q[3])};
+    }
+    f32x4 acc[MT];
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) acc[mt] = *(const f32x4 *)(lbias + W + 16 * mt + 4 * g) * bs;
+#pragma unroll
+    for (int s = 0; s < KS; ++s)
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt)
+        acc[mt] = mma(*(const u32x4 *)(F3 + (s * MT + mt) * kFrag + lane * 16), zb[s], acc[mt]);
+    if (xin) {
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt) {
+        const uint2 pk = {pk_bf16(acc[mt][0], acc[mt][1]), pk_bf16(acc[mt][2], acc[mt][3])};
+        *(uint2 *)(a.tau + (px * W + 16 * mt + 4 * g) * 2) = pk;
       }
     }
   }
@@ -260,6 +415,52 @@ __global__ void sp_pack_planes_kernel(const float *__restrict__ src, int nch, in
   for (int j = 0; j < 4; ++j) dst[j] = u32x4{w[4 * j], w[4 * j + 1], w[4 * j + 2], w[4 * j + 3]};
 }
 
+// Every buffer's 12 planes as bf16 [n][k][H][W][16] (zero channels 12..15):
+// one thread per (frame, buffer, pixel).
+__global__ void sp_pack_slots_kernel(const float *__restrict__ layers, int64_t total, int hw,
+                                     uint8_t *__restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= total) return;
+  const int64_t fb = i / hw;                 // frame * k + buffer
+  const int q = (int)(i - fb * hw);
+  const float *src = layers + fb * kNL * hw + q;
+  uint32_t w[8];
+  for (int j = 0; j < 8; ++j) {
+    const int c = 2 * j;
+    w[j] = pk_bf16(c < kNL ? src[(int64_t)c * hw] : 0.0f, c + 1 < kNL ? src[(int64_t)(c + 1) * hw] : 0.0f);
+  }
+  u32x4 *dst = (u32x4 *)(out + i * 32);
+  dst[0] = u32x4{w[0], w[1], w[2], w[3]};
+  dst[1] = u32x4{w[4], w[5], w[6], w[7]};
+}
+
+// The fragments of sp_slots_kernel: blockIdx.y 0 packs conv3_b (T1's buffer
+// columns, master [W][12 + W][3][3]), 1 and 2 pack A2 and A3 ([W][W]) in
+// register order.  Fragment (s, mt), lane l = 16 g + m, element j.
+__global__ void sp_pack_slots_frag_kernel(const float *__restrict__ master, int W, int64_t t1,
+                                          int64_t t2, int64_t t3, uint8_t *__restrict__ out) {
+  const int MT = W / 16, KS = MT / 2, which = blockIdx.y;
+  const int steps = which == 0 ? kSlotSteps1 : KS;
+  const int64_t base = which == 0 ? 0 : (int64_t)(kSlotSteps1 + (which - 1) * KS) * MT * 512;
+  const int64_t n = (int64_t)steps * MT * 512;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int j = (int)(e & 7), l = (int)((e >> 3) & 63);
+    const int64_t frag = e >> 9;
+    const int mt = (int)(frag % MT), s = (int)(frag / MT);
+    const int g = l >> 4, row = 16 * mt + (l & 15);
+    float v = 0.0f;
+    if (which == 0) {
+      const int tap = 2 * s + (g >> 1), ch = 8 * (g & 1) + j;
+      if (tap < 9 && ch < kNL) v = master[t1 + ((int64_t)row * (kNL + W) + ch) * 9 + tap];
+    } else {
+      const int ch = 32 * s + (j < 4 ? 4 * g + j : 16 + 4 * g + j - 4);
+      v = master[(which == 1 ? t2 : t3) + (int64_t)row * W + ch];
+    }
+    ((__bf16 *)(out + base * 2))[e] = (__bf16)v;
+  }
+}
+
 // 2 x 2 average of a bf16 [n][H][W][C] block (H, W even) into [n][H/2][W/2][C]:
 // one thread per output pixel and 8 channels, the sum in fp32.
 __global__ void sp_avgpool_kernel(const uint8_t *__restrict__ in, int n, int H, int Wd, int C,
@@ -285,32 +486,6 @@ __global__ void sp_avgpool_kernel(const uint8_t *__restrict__ in, int n, int H, 
   *(u32x4 *)(out + (p * C + 8 * c8) * 2) = u32x4{w[0], w[1], w[2], w[3]};
 }
 
-// The pool of Eq. (5) into T's last layer: the active-slot count c of every
-// pixel, zs = Z / max(c, 1) (mean) or Z (sum) as bf16 [n][H][W][Wc], and the
-// per-pixel factor of that layer's bias ([c > 0] for the mean, c for the
-// sum).  With no slot Z is never written: zs = 0.
-__global__ void sp_pool_finish_kernel(const float *__restrict__ Z, const float *__restrict__ layers,
-                                      int k, int64_t npx, int hw, int Wc, int mean,
-                                      uint8_t *__restrict__ zs, float *__restrict__ bscale) {
-  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= npx) return;
-  const int f = (int)(p / hw), q = (int)(p - (int64_t)f * hw);
-  float c = 0.0f;
-  for (int i = 0; i < k; ++i)
-    c += layers[(((int64_t)f * k + i) * kNL + kAlpha) * hw + q] > 0.0f ? 1.0f : 0.0f;
-  const float inv = mean ? 1.0f / fmaxf(c, 1.0f) : 1.0f;
-  bscale[p] = mean ? (c > 0.0f ? 1.0f : 0.0f) : c;
-  for (int ch = 0; ch < Wc; ch += 8) {
-    uint32_t w[4];
-    for (int j = 0; j < 4; ++j) {
-      const float a = k > 0 ? Z[p * Wc + ch + 2 * j] * inv : 0.0f;
-      const float b = k > 0 ? Z[p * Wc + ch + 2 * j + 1] * inv : 0.0f;
-      w[j] = pk_bf16(a, b);
-    }
-    *(u32x4 *)(zs + (p * Wc + ch) * 2) = u32x4{w[0], w[1], w[2], w[3]};
-  }
-}
-
 // Weight fragments of one conv: element e of fragment (step, mt), lane l,
 // position j holds W[16 mt + (l & 15)][ci][tap] for step = tap * cbt + cb and
 // concatenated input channel 32 cb + 8 (l >> 4) + j, mapped to the master
@@ -324,35 +499,47 @@ struct SpPackDesc {
   int mt;                   // M-tiles
 };
 
-__global__ void sp_pack_weights_kernel(const float *__restrict__ master, SpPackDesc d,
-                                       uint8_t *__restrict__ packed) {
+// All convolutions in one launch: blockIdx.y selects the conv; the biases
+// (padded to whole M-tiles, zero past cout and for T1's buffer part, whose
+// bias T1's sigma part carries) go after the fragments.
+struct SpPackAll {
+  SpPackDesc d[15];
+  int64_t bias_src[15];     // master float offset of each conv's bias (-1: none)
+  int64_t bias_dst[15];     // float offset in the packed bias block
+  int64_t bias_block;       // byte offset of the bias block
+};
+
+__global__ void sp_pack_all_kernel(const float *__restrict__ master, SpPackAll all,
+                                   uint8_t *__restrict__ packed) {
+  const SpPackDesc &d = all.d[blockIdx.y];
+  const int64_t e0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (blockIdx.x == 0 && threadIdx.x < 16 * d.mt) {
+    const int o = threadIdx.x;
+    const int64_t src = all.bias_src[blockIdx.y];
+    ((float *)(packed + all.bias_block))[all.bias_dst[blockIdx.y] + o] =
+        src >= 0 && o < d.cout ? master[src + o] : 0.0f;
+  }
   const int cbt = (d.c0pad + d.c1pad) >> 5;
   const int steps = d.k * d.k * cbt;
   const int64_t n = (int64_t)steps * d.mt * 64 * 8;
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= n) return;
-  const int j = (int)(e & 7), l = (int)((e >> 3) & 63);
-  const int64_t frag = e >> 9;
-  const int mt = (int)(frag % d.mt), step = (int)(frag / d.mt);
-  const int tap = step / cbt, cb = step - tap * cbt;
-  const int row = 16 * mt + (l & 15);
-  const int cc = 32 * cb + 8 * (l >> 4) + j;           // concatenated padded channel
-  int ci = -1;
-  if (cc < d.c0pad) {
-    if (cc < d.c0real) ci = cc;
-  } else if (cc - d.c0pad < d.c1real) {
-    ci = d.c0real + (cc - d.c0pad);
+  for (int64_t e = e0; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+    const int j = (int)(e & 7), l = (int)((e >> 3) & 63);
+    const int64_t frag = e >> 9;
+    const int mt = (int)(frag % d.mt), step = (int)(frag / d.mt);
+    const int tap = step / cbt, cb = step - tap * cbt;
+    const int row = 16 * mt + (l & 15);
+    const int cc = 32 * cb + 8 * (l >> 4) + j;           // concatenated padded channel
+    int ci = -1;
+    if (cc < d.c0pad) {
+      if (cc < d.c0real) ci = cc;
+    } else if (cc - d.c0pad < d.c1real) {
+      ci = d.c0real + (cc - d.c0pad);
+    }
+    float v = 0.0f;
+    if (row < d.cout && ci >= 0)
+      v = master[d.woff + (((int64_t)row * d.cin + d.col0 + ci) * d.k * d.k) + tap];
+    ((__bf16 *)(packed + d.out_off))[e] = (__bf16)v;
   }
-  float v = 0.0f;
-  if (row < d.cout && ci >= 0)
-    v = master[d.woff + (((int64_t)row * d.cin + d.col0 + ci) * d.k * d.k) + tap];
-  ((__bf16 *)(packed + d.out_off))[e] = (__bf16)v;
-}
-
-__global__ void sp_pack_bias_kernel(const float *__restrict__ master, int64_t boff, int cout,
-                                    int cpad, float *__restrict__ out) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < cpad) out[i] = i < cout ? master[boff + i] : 0.0f;
 }
 
 }  // namespace
@@ -371,6 +558,8 @@ struct SpLayout {
   SpPackDesc d[kSpConvs];
   int64_t bias_off[kSpConvs];      // float offset of each conv's padded bias in the bias block
   int64_t frag_bytes, bias_floats;
+  int64_t slots_off, slots_bytes;  // sp_slots_kernel's fragments (after the bias block)
+  int64_t t1, t2, t3;              // master offsets of T's three weight tensors
 };
 
 static int64_t sp_master_offsets(int W, int64_t woff[14], int64_t boff[14], int cout[14],
@@ -434,6 +623,12 @@ static SpLayout sp_layout(int W) {
   }
   L.frag_bytes = fb;
   L.bias_floats = bf;
+  const int MT = W / 16;
+  L.slots_off = (fb + 4 * bf + 1023) / 1024 * 1024;
+  L.slots_bytes = (int64_t)(kSlotSteps1 + MT) * MT * kFrag;
+  L.t1 = wo[4];
+  L.t2 = wo[5];
+  L.t3 = wo[6];
   return L;
 }
 
@@ -450,30 +645,58 @@ static int64_t sp_bias_master(int W, int c, bool *zero) {
 
 size_t spatial_weight_bytes(int W) {
   const SpLayout L = sp_layout(W);
-  return (size_t)L.frag_bytes + sizeof(float) * (size_t)L.bias_floats;
+  return (size_t)(L.slots_off + L.slots_bytes);
 }
 
-// Device bytes of the activations a call of n frames of H x W needs.
-size_t spatial_workspace_bytes(int W, int n, int H, int Wd) {
+// Device bytes of the activations a call of n frames of H x W with k buffers
+// needs.
+size_t spatial_workspace_bytes(int W, int n, int H, int Wd, int k) {
   const int64_t px = (int64_t)n * H * Wd, half = px / 4;
-  // bf16: x/b/ld (32 ch), e1, e2, sigma, tau, z1, zs, phi, r1, r2 (W ch each),
-  // half-res d and m (W ch); fp32: u and Z (W ch), bscale
-  return (size_t)(2 * (px * 32 + 9 * px * W + 2 * half * W) + 4 * (2 * px * W + px));
+  // bf16: x/L_d (32 ch), e1, e2, sigma, tau, phi, r1, r2 (W ch each), half-res
+  // d and m (W ch), the k buffers (16 ch each); fp32: u (W ch); rounding slack
+  return (size_t)(2 * (px * 32 + 7 * px * W + 2 * half * W + px * 16 * (int64_t)k) +
+                  4 * px * W + 16 * 256);
 }
 
 hipError_t spatial_pack(const float *master, int W, uint8_t *packed, hipStream_t s) {
   const SpLayout L = sp_layout(W);
-  float *bias = (float *)(packed + L.frag_bytes);
+  static_assert(kSpConvs == 15, "SpPackAll holds 15 convolutions");
+  SpPackAll all;
+  int64_t most = 0;
   for (int c = 0; c < kSpConvs; ++c) {
-    const SpPackDesc &d = L.d[c];
-    const int64_t n = (int64_t)d.k * d.k * ((d.c0pad + d.c1pad) / 32) * d.mt * 64 * 8;
-    hipLaunchKernelGGL(sp_pack_weights_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
-                       master, d, packed);
+    all.d[c] = L.d[c];
     bool zero = false;
     const int64_t bo = sp_bias_master(W, c, &zero);
-    hipLaunchKernelGGL(sp_pack_bias_kernel, dim3(1), dim3(256), 0, s, master, bo,
-                       zero ? 0 : d.cout, d.mt * 16, bias + L.bias_off[c]);
+    all.bias_src[c] = zero ? -1 : bo;
+    all.bias_dst[c] = L.bias_off[c];
+    const SpPackDesc &d = L.d[c];
+    most = std::max<int64_t>(most, (int64_t)d.k * d.k * ((d.c0pad + d.c1pad) / 32) * d.mt * 512);
   }
+  all.bias_block = L.frag_bytes;
+  const unsigned bx = (unsigned)std::min<int64_t>((most + 255) / 256, 1024);
+  hipLaunchKernelGGL(sp_pack_all_kernel, dim3(bx, kSpConvs), dim3(256), 0, s, master, all,
+                     packed);
+  hipLaunchKernelGGL(sp_pack_slots_frag_kernel, dim3(64, 3), dim3(256), 0, s, master, W, L.t1,
+                     L.t2, L.t3, packed + L.slots_off);
+  return hipGetLastError();
+}
+
+template <int MT>
+static hipError_t sp_slots_launch(const SpSlotsArgs &a, hipStream_t s) {
+  static bool attr = false;
+  const size_t lds = (size_t)(kSlotSteps1 + MT) * MT * kFrag + 2 * 16 * MT * sizeof(float);
+  if (!attr) {
+    hipError_t e = hipFuncSetAttribute((const void *)sp_slots_kernel<MT>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    attr = true;
+  }
+  const int64_t nseg = (int64_t)a.n * a.H * ((a.Wd + 15) / 16);
+  const int64_t ntiles = (nseg + kWaves - 1) / kWaves;
+  // persistent: one workgroup per CU (the weights fill most of its LDS), a
+  // multiple of the 8 XCDs
+  const unsigned grid = (unsigned)std::min<int64_t>(256, (ntiles + 7) / 8 * 8);
+  hipLaunchKernelGGL(sp_slots_kernel<MT>, dim3(grid), dim3(kThreads), lds, s, a);
   return hipGetLastError();
 }
 
@@ -514,11 +737,11 @@ hipError_t spatial_forward(const uint8_t *packed, int W, int pool, const float *
   auto take = [&](int64_t bytes) { uint8_t *q = p; p += (bytes + 255) & ~(int64_t)255; return q; };
   uint8_t *x32 = take(px * 32 * 2);                   // x, then each b_i, then L_d
   uint8_t *e1 = take(px * W * 2), *e2 = take(px * W * 2), *sig = take(px * W * 2);
-  uint8_t *tau = take(px * W * 2), *z1 = take(px * W * 2), *zs = take(px * W * 2);
+  uint8_t *tau = take(px * W * 2);
   uint8_t *phi = take(px * W * 2), *r1 = take(px * W * 2), *r2 = take(px * W * 2);
   uint8_t *dh = take(half * W * 2), *mh = take(half * W * 2);
-  float *u = (float *)take(px * W * 4), *Z = (float *)take(px * W * 4);
-  float *bscale = (float *)take(px * 4);
+  uint8_t *bpk = take(px * 16 * 2 * (int64_t)k);
+  float *u = (float *)take(px * W * 4);
   const int MT = W / 16;
   const unsigned pg = (unsigned)((px + 255) / 256);
   hipError_t e = hipSuccess;
@@ -569,37 +792,33 @@ hipError_t spatial_forward(const uint8_t *packed, int W, int pool, const float *
   // F: sigma = U-Net([G; s])
   hipLaunchKernelGGL(sp_pack_x_kernel, dim3(pg), dim3(256), 0, s, gbuf, scene, px, hw, x32);
   unet(SP_F1, x32, 32, nullptr, 0, sig);
-  // T: u = conv3 sigma (T1's sigma columns) + c1; per slot z1 = relu(conv3 b_i + u),
-  // Z += [alpha_i > 0] relu(conv1 z1 + c2)
+  // T: u = conv3 sigma (T1's sigma columns) + c1; then, in one kernel, per
+  // buffer z1 = relu(conv3 b_i + u), Z += [alpha_i > 0] relu(A2 z1 + c2), and
+  // tau = A3 (Z / max(c, 1)) + [c > 0] c3 (mean) or A3 Z + c c3 (sum)
   {
     SpConvArgs a = conv(SP_T1S, sig, W, nullptr, 0, 0, H, Wd);
     a.out_f32 = u;
     run(a, MT);
   }
-  for (int i = 0; i < k; ++i) {
-    const float *Li = layers + (int64_t)i * kNL * hw;          // frame stride k * 12 * hw
-    hipLaunchKernelGGL(sp_pack_planes_kernel, dim3(pg), dim3(256), 0, s, Li, kNL,
-                       (int64_t)k * kNL * hw, px, hw, x32);
-    SpConvArgs a = conv(SP_T1B, x32, 32, nullptr, 0, 0, H, Wd);
-    a.add = u;
-    a.relu = 1;
-    a.out_bf = z1;
-    run(a, MT);
-    a = conv(SP_T2, z1, W, nullptr, 0, 0, H, Wd);
-    a.relu = 1;
-    a.pool = Z;
-    a.alpha = Li + (int64_t)kAlpha * hw;
-    a.alpha_fstride = (int64_t)k * kNL * hw;
-    a.pool_first = i == 0;
-    run(a, MT);
+  if (k > 0) {
+    const int64_t tot = px * k;
+    hipLaunchKernelGGL(sp_pack_slots_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s,
+                       layers, tot, hw, bpk);
   }
-  hipLaunchKernelGGL(sp_pool_finish_kernel, dim3(pg), dim3(256), 0, s, Z, layers, k, px, hw, W,
-                     pool == GN_POOL_MEAN ? 1 : 0, zs, bscale);
   {
-    SpConvArgs a = conv(SP_T3, zs, W, nullptr, 0, 0, H, Wd);     // tau = A3 zs + bscale c3
-    a.bscale = bscale;
-    a.out_bf = tau;
-    run(a, MT);
+    SpSlotsArgs a;
+    a.frag = packed + L.slots_off;
+    a.bias = bias + L.bias_off[SP_T2];       // c2, then c3 (T3's bias block follows T2's)
+    a.bpk = bpk;
+    a.layers = layers;
+    a.u = u;
+    a.tau = tau;
+    a.n = n;
+    a.H = H;
+    a.Wd = Wd;
+    a.k = k;
+    a.mean = pool == GN_POOL_MEAN ? 1 : 0;
+    if (e == hipSuccess) e = MT == 8 ? sp_slots_launch<8>(a, s) : sp_slots_launch<4>(a, s);
   }
   // B: phi = U-Net([sigma; tau])
   unet(SP_B1, sig, W, tau, W, phi);

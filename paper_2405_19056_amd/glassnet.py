@@ -16,7 +16,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libglassnet.so")
 
 GN_OK, GN_E_INVAL, GN_E_NOMEM, GN_E_DEVICE, GN_E_UNSUPPORTED, GN_E_AGAIN, GN_E_BUSY = 0, -1, -2, -3, -4, -5, -6
-PRECISION = {"fp32": 0, "bf16": 1, "fp8_t": 2}
+PRECISION = {"fp32": 0, "bf16": 1, "fp8_t": 2, "fp8_all": 3}
 POOL = {"mean": 0, "sum": 1}
 SLOT_ORDER = {"canonical": 0, "input": 1}
 NUM_G, NUM_L, NUM_S, NUM_OUT = 14, 12, 16, 3

@@ -77,6 +77,11 @@ def test_create_rejects_bad_config_before_touching_a_device():
     with pytest.raises(gb.GlassNetError) as e:
         gb.GlassNet(np.zeros(gb.num_params(64), np.float32), width=64, precision="fp8_t")
     assert e.value.status == gb.GN_E_UNSUPPORTED
+    # FP8 in every layer is not built (its emulated error misses the FP8 bar)
+    with pytest.raises(gb.GlassNetError) as e:
+        gb.GlassNet(np.zeros(gb.num_params(128), np.float32), width=128, precision="fp8_all")
+    assert e.value.status == gb.GN_E_UNSUPPORTED
+    assert "GN_FP8_ALL" in gb.last_error()
 
 
 def test_binding_refuses_a_missing_library(monkeypatch):

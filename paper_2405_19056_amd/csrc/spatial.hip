@@ -53,7 +53,15 @@ typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 constexpr int kWaves = 8, kThreads = kWaves * 64;
 constexpr int kNT = 4;                       // N-tiles (16 pixels) per wave
 constexpr int kWavePx = kNT * 16;            // pixels per wave (one row segment)
-constexpr int kChunk = 4;                    // K-steps per LDS weight chunk
+constexpr int kChunk = 4;                    // K-steps per LDS weight chunk (even)
+static_assert(kChunk % 2 == 0, "the conv loop takes the steps of a chunk in pairs");
+
+// K-steps of a conv's packed weights: taps x 32-channel blocks, rounded up to
+// whole chunks with zero fragments (the conv loop then runs whole chunks,
+// straight-line code the compiler keeps its loads ahead in).
+__host__ __device__ inline int padded_steps(int taps, int cbt) {
+  return (taps * cbt + kChunk - 1) / kChunk * kChunk;
+}
 constexpr int kFrag = 1024;                  // one A fragment: 64 lanes x 16 bytes
 
 __device__ __forceinline__ uint32_t pk_bf16(float a, float b) {
@@ -69,6 +77,19 @@ __device__ __forceinline__ float bf16_to_f32(uint16_t v) {
   return __uint_as_float((uint32_t)v << 16);
 }
 
+// Input loads go through buffer resources bounded by the input's size: a
+// load at an offset past the bound returns zeros (the conv's zero padding),
+// so no select on the loaded value holds up the next K-step's loads.
+typedef __amdgpu_buffer_rsrc_t rsrc_t;
+constexpr uint32_t kOutside = 0x80000000u;     // past every bound (inputs stay under 2 GiB)
+__device__ __forceinline__ rsrc_t make_rsrc(const void *base, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)bytes,
+                                           0x00020000);
+}
+__device__ __forceinline__ u32x4 bld(rsrc_t r, uint32_t off) {
+  return __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
+}
+
 }  // namespace
 
 // One convolution launch (host fills it; see SpConv in the launcher).
@@ -79,6 +100,7 @@ struct SpConvArgs {
   const uint8_t *wfrag;     // A fragments [step][mt][lane] (16 B each)
   const float *bias;        // [MT * 16] (zero past the real outputs)
   int steps;                // K-steps = taps x (c0 + c1) / 32
+  int steps_pad;            // the packed steps: steps rounded up to whole chunks
   int ksize;                // 1 or 3
   int n, H, Wd;             // output (= in0) size
   int cout_pad;             // output channel count of the bf16 / fp32 layouts (MT * 16)
@@ -98,7 +120,13 @@ __global__ __launch_bounds__(kThreads) void sp_conv_kernel(SpConvArgs a) {
   const int g = lane >> 4, col = lane & 15;
   const int H = a.H, Wd = a.Wd;
   const int segs = (Wd + kWavePx - 1) / kWavePx;          // row segments per row
-  const int64_t seg = (int64_t)blockIdx.x * kWaves + wave;
+  // Workgroups reach the 8 XCDs round-robin: give each XCD a contiguous run
+  // of tiles, so that the rows a 3 x 3 conv reads twice more (for the rows
+  // above and below) are mostly in its own L2.
+  const int full = gridDim.x & ~7;
+  const int tile = (int)blockIdx.x < full ? (blockIdx.x & 7) * (full >> 3) + (blockIdx.x >> 3)
+                                          : (int)blockIdx.x;
+  const int64_t seg = (int64_t)tile * kWaves + wave;
   const int64_t nseg = (int64_t)a.n * H * segs;
   const bool live = seg < nseg;
   const int64_t sg = live ? seg : nseg - 1;
@@ -112,52 +140,55 @@ __global__ __launch_bounds__(kThreads) void sp_conv_kernel(SpConvArgs a) {
   const int cbt = (a.c0 + a.c1) >> 5;
 
   constexpr int kChunkBytes = kChunk * MT * kFrag;
-  const int nchunks = (a.steps + kChunk - 1) / kChunk;
+  const int nchunks = a.steps_pad / kChunk;
   auto fill = [&](int c) {
-    const int s0 = c * kChunk, s1 = min(a.steps, s0 + kChunk);
-    const int64_t bytes = (int64_t)(s1 - s0) * MT * kFrag;
-    const uint8_t *src = a.wfrag + (int64_t)s0 * MT * kFrag;
-    for (int64_t off = (int64_t)wave * kFrag; off < bytes; off += kWaves * kFrag)
+    const uint8_t *src = a.wfrag + (int64_t)c * kChunkBytes;
+    // a compile-time count of copies per wave (the compiler then knows how
+    // many vector-memory operations are in flight behind them)
+    constexpr int kCopies = (kChunk * MT + kWaves - 1) / kWaves;
+#pragma unroll
+    for (int i = 0; i < kCopies; ++i) {
+      const int off = (i * kWaves + wave) * kFrag;
+      if (off >= kChunkBytes) break;
       __builtin_amdgcn_global_load_lds((const void *)(src + off + lane * 16),
                                        (__attribute__((address_space(3))) void *)(lds + (c & 1) * kChunkBytes + off),
                                        16, 0, 0);
+    }
   };
 
   // B fragment of K-step s for N-tile t: pixel (y + dy - r, x0 + 16 t + col + dx - r),
-  // channels 32 cb + 8 g .. + 7 of the concatenated input; zero outside the
-  // frame.  The row base is wave-uniform; every lane loads (from a clamped
-  // pixel), so each step issues exactly kNT loads: the chunk waits below count
-  // on that.
+  // channels 32 cb + 8 g .. + 7 of the concatenated input; outside the frame
+  // the offset is past the buffer's bound and the load returns zeros.  Every
+  // lane loads, so each step issues exactly kNT loads: the chunk waits below
+  // count on that.
+  const int H1 = a.up1 ? H >> 1 : H, W1 = a.up1 ? Wd >> 1 : Wd;
+  const uint8_t *in0 = a.in0, *in1 = a.in1 ? a.in1 : a.in0;
+  const uint32_t bytes0 = (uint32_t)((int64_t)a.n * H * Wd * a.c0 * 2);
+  const uint32_t bytes1 = (uint32_t)((int64_t)a.n * H1 * W1 * a.c1 * 2);
   auto load_b = [&](int s, u32x4 (&b)[kNT]) {
     const int tap = s / cbt, cb = s - tap * cbt;
     const int dy = tap / a.ksize - r, dx = tap % a.ksize - r;
     const int yy = y + dy;
     const bool yok = yy >= 0 && yy < H;
     const int yc = min(max(yy, 0), H - 1);
-    const uint8_t *row;
-    int cs, shift;                       // channel stride and the column shift of the source
-    if (cb < cb0) {
-      row = a.in0 + (((int64_t)f * H + yc) * Wd) * a.c0 * 2 + (32 * cb) * 2;
-      cs = a.c0;
-      shift = 0;
-    } else if (a.up1) {
-      const int H1 = H >> 1, W1 = Wd >> 1;
-      row = a.in1 + (((int64_t)f * H1 + (yc >> 1)) * W1) * a.c1 * 2 + (32 * (cb - cb0)) * 2;
-      cs = a.c1;
-      shift = 1;
-    } else {
-      row = a.in1 + (((int64_t)f * H + yc) * Wd) * a.c1 * 2 + (32 * (cb - cb0)) * 2;
-      cs = a.c1;
-      shift = 0;
-    }
+    const bool first = cb < cb0;
+    const int shift = first ? 0 : a.up1;
+    const int cs = first ? a.c0 : a.c1;
+    // byte offset of the row's first pixel and the channel block
+    const uint32_t rowoff =
+        first ? (uint32_t)((((int64_t)f * H + yc) * Wd * a.c0 + 32 * cb) * 2)
+              : (uint32_t)((((int64_t)f * H1 + (yc >> shift)) * W1 * a.c1 + 32 * (cb - cb0)) * 2);
+    uint32_t off[kNT];
 #pragma unroll
     for (int t = 0; t < kNT; ++t) {
       const int xx = x0 + 16 * t + col + dx;
       const bool ok = yok && xx >= 0 && xx < Wd;
-      const int xc = min(max(xx, 0), Wd - 1) >> shift;
-      const u32x4 v = *(const u32x4 *)(row + (uint32_t)((xc * cs + 8 * g) * 2));
-      b[t] = ok ? v : u32x4{0u, 0u, 0u, 0u};
+      off[t] = ok ? rowoff + (uint32_t)((((xx >> shift) * cs) + 8 * g) * 2) : kOutside;
     }
+    // the source is wave-uniform: its resource is built in scalar registers
+    const rsrc_t rs = make_rsrc(first ? in0 : in1, first ? bytes0 : bytes1);
+#pragma unroll
+    for (int t = 0; t < kNT; ++t) b[t] = bld(rs, off[t]);
   };
 
   f32x4 acc[kNT][MT];
@@ -166,33 +197,53 @@ __global__ __launch_bounds__(kThreads) void sp_conv_kernel(SpConvArgs a) {
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt) acc[t][mt] = f32x4{0.f, 0.f, 0.f, 0.f};
 
+  // one K-step: all MT weight fragments requested from LDS first (held there
+  // by a scheduling barrier, else each read sinks next to its MFMAs and is
+  // waited for alone), then the MFMAs
+  auto step = [&](const uint8_t *Ws, const u32x4 (&b)[kNT]) {
+    u32x4 w[MT];
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) w[mt] = *(const u32x4 *)(Ws + mt * kFrag + lane * 16);
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+      for (int t = 0; t < kNT; ++t) acc[t][mt] = mma(w[mt], b[t], acc[t][mt]);
+    __builtin_amdgcn_sched_barrier(0);
+  };
+
   fill(0);
-  u32x4 bcur[kNT], bnext[kNT];
-  load_b(0, bcur);
+  // Two input sets: b0 holds the current step's fragments (chunks have an
+  // even step count, so each chunk starts with its first step in b0); the
+  // next step's loads (clamped to the last step: a harmless re-read) are in
+  // flight while the current step's MFMAs run.
+  u32x4 b0[kNT], b1[kNT];
+  load_b(0, b0);
   for (int c = 0; c < nchunks; ++c) {
     // The chunk's weights have landed: each wave waits for its own copies,
     // then for everyone's.  Issued after the copies of chunk c (at the start
     // of chunk c - 1) are only the input loads of chunk c - 1's steps, kNT per
     // step, the last kChunk kNT of them still allowed in flight.
+    // (A plain __syncthreads would also drain those input loads.)  The
+    // LDS reads of the buffer the next fill overwrites are drained too.
     if (c == 0)
-      asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+      asm volatile("s_waitcnt vmcnt(0)\n\ts_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
     else
-      asm volatile("s_waitcnt vmcnt(%0)" ::"n"(kChunk * kNT) : "memory");
-    __syncthreads();
+      asm volatile("s_waitcnt vmcnt(%0)\n\ts_waitcnt lgkmcnt(0)\n\ts_barrier" ::"n"(kChunk * kNT)
+                   : "memory");
     if (c + 1 < nchunks) fill(c + 1);
     const uint8_t *Wc = lds + (c & 1) * kChunkBytes;
-    const int s0 = c * kChunk, s1 = min(a.steps, s0 + kChunk);
-    for (int s = s0; s < s1; ++s) {
-      if (s + 1 < a.steps) load_b(s + 1, bnext);     // the next step's inputs, in flight
-      const uint8_t *Ws = Wc + (int64_t)(s - s0) * MT * kFrag;
+    const int s0 = c * kChunk;
+    // steps past the real ones multiply zero weights (their inputs re-read
+    // the last real step's)
 #pragma unroll
-      for (int mt = 0; mt < MT; ++mt) {
-        const u32x4 w = *(const u32x4 *)(Ws + mt * kFrag + lane * 16);
-#pragma unroll
-        for (int t = 0; t < kNT; ++t) acc[t][mt] = mma(w, bcur[t], acc[t][mt]);
-      }
-#pragma unroll
-      for (int t = 0; t < kNT; ++t) bcur[t] = bnext[t];
+    for (int j = 0; j < kChunk; j += 2) {
+      load_b(min(s0 + j + 1, a.steps - 1), b1);
+      __builtin_amdgcn_sched_barrier(0);
+      step(Wc + j * MT * kFrag, b0);
+      load_b(min(s0 + j + 2, a.steps - 1), b0);
+      __builtin_amdgcn_sched_barrier(0);
+      step(Wc + (j + 1) * MT * kFrag, b1);
     }
   }
 
@@ -298,22 +349,33 @@ __global__ __launch_bounds__(kThreads) void sp_slots_kernel(SpSlotsArgs a) {
       Z[mt] = f32x4{0.f, 0.f, 0.f, 0.f};
     }
     float cnt = 0.0f;
-    for (int i = 0; i < k; ++i) {
+    // buffer i's conv3 inputs (tap 2 s + (g >> 1); outside the frame the
+    // offset is past the plane's bound and the load returns zeros) and its
+    // alpha; the next buffer's are loaded while this one's MFMAs run
+    auto load_slot = [&](int i, u32x4 (&b)[kSlotSteps1], float &al) {
       const int64_t fb = (int64_t)f * k + i;
-      const float al = a.layers[(fb * kNL + kAlpha) * hw + (int64_t)y * Wd + xc];
-      const bool act = xin && al > 0.0f;
-      if (!__builtin_amdgcn_ballot_w64(act)) continue;    // adds exactly nothing
-      // the buffer's conv3 inputs: tap 2 s + (g >> 1), zero outside the frame
-      u32x4 b[kSlotSteps1];
-      const uint8_t *bi = a.bpk + fb * hw * 32;
+      al = a.layers[(fb * kNL + kAlpha) * hw + (int64_t)y * Wd + xc];
+      const rsrc_t rb = make_rsrc(a.bpk + fb * hw * 32, (uint32_t)(hw * 32));
 #pragma unroll
       for (int s = 0; s < kSlotSteps1; ++s) {
         const int tap = 2 * s + (g >> 1);
         const int yy = y + tap / 3 - 1, xx = x + tap % 3 - 1;
         const bool ok = tap < 9 && yy >= 0 && yy < H && xx >= 0 && xx < Wd;
-        const int yc = min(max(yy, 0), H - 1), xq = min(max(xx, 0), Wd - 1);
-        const u32x4 v = *(const u32x4 *)(bi + ((int64_t)yc * Wd + xq) * 32 + 16 * (g & 1));
-        b[s] = ok ? v : u32x4{0u, 0u, 0u, 0u};
+        b[s] = bld(rb, ok ? (uint32_t)(yy * Wd + xx) * 32 + 16 * (g & 1) : kOutside);
+      }
+    };
+    u32x4 b[kSlotSteps1], bn[kSlotSteps1];
+    float al = 0.0f, aln = 0.0f;
+    if (k > 0) load_slot(0, b, al);
+    for (int i = 0; i < k; ++i) {
+      if (i + 1 < k) load_slot(i + 1, bn, aln);
+      __builtin_amdgcn_sched_barrier(0);
+      const bool act = xin && al > 0.0f;
+      if (!__builtin_amdgcn_ballot_w64(act)) {          // adds exactly nothing
+#pragma unroll
+        for (int s = 0; s < kSlotSteps1; ++s) b[s] = bn[s];
+        al = aln;
+        continue;
       }
       f32x4 acc[MT];
 #pragma unroll
@@ -345,6 +407,9 @@ __global__ __launch_bounds__(kThreads) void sp_slots_kernel(SpSlotsArgs a) {
 #pragma unroll
         for (int j = 0; j < 4; ++j) Z[mt][j] += act ? fmaxf(acc[mt][j], 0.0f) : 0.0f;
       cnt += act ? 1.0f : 0.0f;
+#pragma unroll
+      for (int s = 0; s < kSlotSteps1; ++s) b[s] = bn[s];
+      al = aln;
     }
     // the pool's finish and T's last layer
     const float inv = a.mean ? 1.0f / fmaxf(cnt, 1.0f) : 1.0f;
@@ -521,7 +586,7 @@ __global__ void sp_pack_all_kernel(const float *__restrict__ master, SpPackAll a
   }
   const int cbt = (d.c0pad + d.c1pad) >> 5;
   const int steps = d.k * d.k * cbt;
-  const int64_t n = (int64_t)steps * d.mt * 64 * 8;
+  const int64_t n = (int64_t)padded_steps(d.k * d.k, cbt) * d.mt * 64 * 8;
   for (int64_t e = e0; e < n; e += (int64_t)gridDim.x * blockDim.x) {
     const int j = (int)(e & 7), l = (int)((e >> 3) & 63);
     const int64_t frag = e >> 9;
@@ -536,7 +601,7 @@ __global__ void sp_pack_all_kernel(const float *__restrict__ master, SpPackAll a
       ci = d.c0real + (cc - d.c0pad);
     }
     float v = 0.0f;
-    if (row < d.cout && ci >= 0)
+    if (step < steps && row < d.cout && ci >= 0)      // padding steps stay zero
       v = master[d.woff + (((int64_t)row * d.cin + d.col0 + ci) * d.k * d.k) + tap];
     ((__bf16 *)(packed + d.out_off))[e] = (__bf16)v;
   }
@@ -617,7 +682,7 @@ static SpLayout sp_layout(int W) {
     d.c1pad = m.c1pad;
     d.mt = (d.cout + 15) / 16;
     d.out_off = fb;
-    fb += (int64_t)d.k * d.k * ((d.c0pad + d.c1pad) / 32) * d.mt * kFrag;
+    fb += (int64_t)padded_steps(d.k * d.k, (d.c0pad + d.c1pad) / 32) * d.mt * kFrag;
     L.bias_off[c] = bf;
     bf += d.mt * 16;
   }
@@ -670,7 +735,8 @@ hipError_t spatial_pack(const float *master, int W, uint8_t *packed, hipStream_t
     all.bias_src[c] = zero ? -1 : bo;
     all.bias_dst[c] = L.bias_off[c];
     const SpPackDesc &d = L.d[c];
-    most = std::max<int64_t>(most, (int64_t)d.k * d.k * ((d.c0pad + d.c1pad) / 32) * d.mt * 512);
+    most = std::max<int64_t>(most, (int64_t)padded_steps(d.k * d.k, (d.c0pad + d.c1pad) / 32) *
+                                       d.mt * 512);
   }
   all.bias_block = L.frag_bytes;
   const unsigned bx = (unsigned)std::min<int64_t>((most + 255) / 256, 1024);
@@ -759,6 +825,7 @@ hipError_t spatial_forward(const uint8_t *packed, int W, int pool, const float *
     a.bias = bias + L.bias_off[c];
     a.ksize = d.k;
     a.steps = d.k * d.k * ((c0 + c1) / 32);
+    a.steps_pad = padded_steps(d.k * d.k, (c0 + c1) / 32);
     a.n = n;
     a.H = Hc;
     a.Wd = Wc;

@@ -114,6 +114,41 @@ __device__ __forceinline__ float upsampled(const float *__restrict__ lo_f, int h
   return (1.0f - fy) * top + fy * bot;
 }
 
+// LDS staging with many loads in flight: element e < N of a block goes to
+// dst(e) from byte offset off(e) of the buffer behind r (kOutside, past the
+// buffer's bound, reads zero: the callers' zero padding).  Loads guarded by a
+// branch or followed by a select on their value are each waited for before
+// the next one issues; these are neither, so the compiler issues a group of
+// them before the first store.
+typedef __amdgpu_buffer_rsrc_t rsrc_t;
+constexpr uint32_t kOutside = 0x80000000u;   // past every bound (buffers stay under 2 GiB)
+__device__ __forceinline__ rsrc_t make_rsrc(const void *base, int64_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0,
+                                           (int)std::min<int64_t>(bytes, kOutside), 0x00020000);
+}
+
+template <int N, class Off, class Dst>
+__device__ __forceinline__ void stage(int tid, rsrc_t r, Off off, Dst dst) {
+  constexpr int kIt = (N + kThreads - 1) / kThreads, kG = 8;
+  // groups of kG loads, then their kG stores (in program order: the
+  // compiler does not move a buffer load above an LDS store)
+  for (int i0 = 0; i0 < kIt; i0 += kG) {
+    float v[kG];
+#pragma unroll
+    for (int j = 0; j < kG; ++j) {
+      const int e = min(tid + (i0 + j) * kThreads, N - 1);
+      v[j] = i0 + j < kIt
+                 ? __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off(e), 0, 0))
+                 : 0.0f;
+    }
+#pragma unroll
+    for (int j = 0; j < kG; ++j) {
+      const int e = tid + (i0 + j) * kThreads;
+      if (i0 + j < kIt && (N % kThreads == 0 || e < N)) *dst(e) = v[j];
+    }
+  }
+}
+
 // SAVE (the backward's recompute): instead of the output, write relu(z1) and
 // relu(z2) of the tile's own pixels to a1_out, a2_out [n][32][2h][2w].
 template <bool SAVE>
@@ -135,18 +170,28 @@ __global__ __launch_bounds__(kThreads, 2) void sr_forward_kernel(
 
   // stage 0: the input over the tile and a two-pixel halo (zero outside the
   // image and in the three padding channels)
-  for (int e = tid; e < kInP * kE0 * kE0; e += kThreads) {
-    const int c = e / (kE0 * kE0), r = (e / kE0) % kE0, q = e % kE0;
-    const int Y = oy0 - 2 + r, X = ox0 - 2 + q;
-    float v = 0.0f;
-    if (c < kIn && Y >= 0 && Y < H && X >= 0 && X < W) {
-      if (c < 3) {
-        v = upsampled(lo_f, h, w, c, Y, X);
-      } else {
-        v = g_f[(c - 3) * plane_hi + (int64_t)Y * W + X];
-      }
+  {
+    constexpr int E2 = kE0 * kE0;
+    auto inside = [&](int e) {
+      const int Y = oy0 - 2 + (e / kE0) % kE0, X = ox0 - 2 + e % kE0;
+      return Y >= 0 && Y < H && X >= 0 && X < W;
+    };
+    auto pix = [&](int e) {
+      return (int64_t)(oy0 - 2 + (e / kE0) % kE0) * W + ox0 - 2 + e % kE0;
+    };
+    // the 14 G-buffer channels, the upsampled render, the padding channels
+    const rsrc_t rg = make_rsrc(g_f, 4 * (kIn - 3) * plane_hi);
+    stage<(kIn - 3) * E2>(
+        tid, rg,
+        [&](int e) {
+          return inside(e) ? (uint32_t)(4 * ((e / E2) * plane_hi + pix(e))) : kOutside;
+        },
+        [&](int e) { return in_s + 3 * E2 + e; });
+    for (int e = tid; e < 3 * E2; e += kThreads) {
+      const int Y = oy0 - 2 + (e / kE0) % kE0, X = ox0 - 2 + e % kE0;
+      in_s[e] = inside(e) ? upsampled(lo_f, h, w, e / E2, Y, X) : 0.0f;
     }
-    in_s[e] = v;
+    for (int e = tid; e < (kInP - kIn) * E2; e += kThreads) in_s[kIn * E2 + e] = 0.0f;
   }
 
   // stage 1: conv1 + ReLU over the tile and a one-pixel halo
@@ -302,12 +347,16 @@ __global__ __launch_bounds__(kThreads, 2) void sr_bwd_dz1_kernel(
   const int tid = threadIdx.x, lane = tid % 64, wave = tid / 64;
   const int col = lane % 16, grp = lane / 16;
   const int64_t plane = (int64_t)H * W;
-  for (int e = tid; e < kC * kP1; e += kThreads) {
-    const int o = e / kP1, q = e % kP1;
-    const int Y = oy0 - 1 + q / kE1, X = ox0 - 1 + q % kE1;
-    d_s[o * kA1Stride + q] = (Y >= 0 && Y < H && X >= 0 && X < W)
-                                 ? dz2[((int64_t)f * kC + o) * plane + (int64_t)Y * W + X]
-                                 : 0.0f;
+  {
+    const rsrc_t rd = make_rsrc(dz2 + (int64_t)f * kC * plane, 4 * kC * plane);
+    stage<kC * kP1>(
+        tid, rd,
+        [&](int e) {
+          const int o = e / kP1, q = e % kP1, Y = oy0 - 1 + q / kE1, X = ox0 - 1 + q % kE1;
+          return Y >= 0 && Y < H && X >= 0 && X < W
+                     ? (uint32_t)(4 * (o * plane + (int64_t)Y * W + X)) : kOutside;
+        },
+        [&](int e) { return d_s + (e / kP1) * kA1Stride + e % kP1; });
   }
   float a[kS2][2];
 #pragma unroll
@@ -342,16 +391,20 @@ __global__ __launch_bounds__(kThreads, 2) void sr_bwd_dz1_kernel(
 // The two conv gradients are GEMMs over the tile's 256 pixels on the matrix
 // cores: dW[o][(c, tap)] = sum_p dz[o][p] act[c][p + tap], with dz (32 x 256)
 // as the 16-row operand, held in registers, and the activation windows
-// (columns (c, tap) in packed order, c * 9 + tap) gathered from LDS.
+// (columns (c, tap) in packed order, c * 9 + tap) gathered from LDS.  One
+// more column reads a plane of ones: its sums are the bias gradients
+// sum_p dz[o][p].
 constexpr int kDzStride = kT * kT + 4;   // LDS row of dz: rows land in distinct banks
-constexpr int kWgLds = kC * kDzStride + kC * kP1;  // floats: two workgroups per CU
+// floats: dz rows, the activation windows, the plane of ones (two workgroups per CU)
+constexpr int kWgLds = kC * kDzStride + kC * kP1 + kP1;
 
 // dz_s rows (32 x 256, stride kDzStride) against the windows of act_s
-// (channels of kP1 floats, the tile plus a one-pixel halo), added to acc:
-// columns n = c * 9 + tap < ncol, column tile j = wave + 4 jj of 16.
+// (channels of kP1 floats, the tile plus a one-pixel halo) and, as column
+// ncol, against ones_s, added to acc: column tile j = wave + 4 jj of 16.
 template <int NJ>
-__device__ __forceinline__ void wgrad_gemm(const float *dz_s, const float *act_s, int ncol,
-                                           f32x4 (&acc)[NJ][2], int lane, int wave) {
+__device__ __forceinline__ void wgrad_gemm(const float *dz_s, const float *act_s,
+                                           const float *ones_s, int ncol, f32x4 (&acc)[NJ][2],
+                                           int lane, int wave) {
   const int col = lane % 16, grp = lane / 16;
   float a[kT * kT / 4][2];
 #pragma unroll
@@ -362,10 +415,11 @@ __device__ __forceinline__ void wgrad_gemm(const float *dz_s, const float *act_s
 #pragma unroll
   for (int jj = 0; jj < NJ; ++jj) {
     const int j = wave + (kThreads / 64) * jj;
-    if (16 * j >= ncol) continue;
-    const int n = min(16 * j + col, ncol - 1);
+    if (16 * j > ncol) continue;
+    const int n = min(16 * j + col, ncol);
     const int c = n / 9, tap = n % 9;
-    const float *src = act_s + c * kP1 + (tap / 3) * kE1 + tap % 3 + grp;
+    const float *src = n == ncol ? ones_s + grp
+                                 : act_s + c * kP1 + (tap / 3) * kE1 + tap % 3 + grp;
 #pragma unroll
     for (int s = 0; s < kT * kT / 4; ++s) {
       // pixel p = 4 s + grp: row s / 4, column 4 (s % 4) + grp
@@ -376,25 +430,30 @@ __device__ __forceinline__ void wgrad_gemm(const float *dz_s, const float *act_s
   }
 }
 
+// Column n < ncol to out[row * ncol + n], the ones column to bias[row].
 template <int NJ>
 __device__ __forceinline__ void wgrad_store(const f32x4 (&acc)[NJ][2], int ncol,
-                                            float *__restrict__ out, int lane, int wave) {
+                                            float *__restrict__ out, float *__restrict__ bias,
+                                            int lane, int wave) {
   const int col = lane % 16, grp = lane / 16;
 #pragma unroll
   for (int jj = 0; jj < NJ; ++jj) {
     const int n = 16 * (wave + (kThreads / 64) * jj) + col;
-    if (n >= ncol) continue;
+    if (n > ncol) continue;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      out[(4 * grp + i) * ncol + n] = acc[jj][0][i];
-      out[(16 + 4 * grp + i) * ncol + n] = acc[jj][1][i];
+      float *d0 = n < ncol ? out + (4 * grp + i) * ncol + n : bias + 4 * grp + i;
+      float *d1 = n < ncol ? out + (16 + 4 * grp + i) * ncol + n : bias + 16 + 4 * grp + i;
+      *d0 = acc[jj][0][i];
+      *d1 = acc[jj][1][i];
     }
   }
 }
 
-constexpr int kNJ2 = (kC * 9 / 16 + 3) / 4;    // conv2 column tiles per wave (5)
-constexpr int kNJ1 = (kIn * 9 + 15) / 16;      // conv1 column tiles (10)
-constexpr int kNJ1w = (kNJ1 + 3) / 4;          // per wave (3)
+constexpr int kNJ2 = (kC * 9 / 16 + 1 + 3) / 4;    // conv2 column tiles (19) per wave (5)
+constexpr int kNJ1 = (kIn * 9 + 1 + 15) / 16;      // conv1 column tiles (10)
+constexpr int kNJ1w = (kNJ1 + 3) / 4;              // per wave (3)
+static_assert((kC * 9 + 1 + 15) / 16 <= 4 * kNJ2, "conv2 columns and the ones column");
 
 // Persistent: workgroup b takes tiles b, b + gridDim.x, ... (in that order)
 // and keeps its running sums of every weight gradient in registers, written
@@ -403,39 +462,61 @@ __global__ __launch_bounds__(kThreads, 2) void sr_bwd_wgrad_kernel(
     const float *__restrict__ lowres, const float *__restrict__ gbuf, const float *__restrict__ dy,
     const float *__restrict__ a1, const float *__restrict__ a2, const float *__restrict__ dz1,
     const float *__restrict__ dz2, float *__restrict__ partial, int n, int h, int w) {
-  __shared__ float buf[kWgLds];   // 74.8 KB
+  __shared__ float buf[kWgLds];   // 76.1 KB
   const int H = 2 * h, W = 2 * w;
   const int tx_n = (W + kT - 1) / kT, ty_n = (H + kT - 1) / kT;
   const int ntiles = n * tx_n * ty_n;
   const int tid = threadIdx.x, lane = tid % 64, wave = tid / 64;
+  const int col = lane % 16, grp = lane / 16;
   const int64_t plane = (int64_t)H * W, plane_lo = (int64_t)h * w;
   constexpr int kOffW2 = kC * kIn * 9 + kC, kOffB2p = kOffW2 + kC * kC * 9;
   constexpr int kOffW3p = kOffB2p + kC, kOffB3p = kOffW3p + kSrOut * kC;
   f32x4 acc2[kNJ2][2] = {}, acc1[kNJ1w][2] = {};
-  float acc_head = 0.0f, acc_b = 0.0f, acc_b1 = 0.0f;   // per thread: head / b2 / b1
-  float *dz_s = buf;
+  // the head on waves 0..2: column tile `wave` of [a2^T | 1] against dy
+  f32x4 acc_h = {0.f, 0.f, 0.f, 0.f};
+  float *dz_s = buf, *ones_s = buf + kC * kDzStride + kC * kP1;
+  for (int e = tid; e < kP1; e += kThreads) ones_s[e] = 1.0f;
   for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
     const int f = t / (tx_n * ty_n), oy0 = ((t / tx_n) % ty_n) * kT, ox0 = (t % tx_n) * kT;
-    // phase 0: the head.  a2_s [32][256] and dy_s [3][256] over the tile's
-    // own pixels (zero outside the image)
+    // plane offsets of the tile's own pixel p and of halo position q (clamped
+    // into the image), and whether they lie inside it
+    // byte offsets of channel c at the tile's own pixel p and at halo
+    // position q within frame f's planes; kOutside outside the image
+    auto own = [&](int c, int p) {
+      const int Y = oy0 + p / kT, X = ox0 + p % kT;
+      return Y < H && X < W ? (uint32_t)(4 * (c * plane + (int64_t)Y * W + X)) : kOutside;
+    };
+    auto halo = [&](int c, int q) {
+      const int Y = oy0 - 1 + q / kE1, X = ox0 - 1 + q % kE1;
+      return Y >= 0 && Y < H && X >= 0 && X < W ? (uint32_t)(4 * (c * plane + (int64_t)Y * W + X))
+                                                : kOutside;
+    };
+    auto halo_in = [&](int q) {
+      const int Y = oy0 - 1 + q / kE1, X = ox0 - 1 + q % kE1;
+      return Y >= 0 && Y < H && X >= 0 && X < W;
+    };
+    const int64_t fb = 4 * kC * plane;   // bytes of one frame's 32 planes
+    // phase 0: the head, dW3[k][o] = sum_p dy[k][p] a2[o][p] and b3[k] =
+    // sum_p dy[k][p] on the matrix cores: dy (3 rows of 16) the row operand,
+    // [a2^T | 1] (33 of 48 columns) the column operand, over the tile's own
+    // pixels (zero outside the image).  a2_s [32][256], dy_s [3][256].
     {
       float *a2_s = buf, *dy_s = buf + kC * kT * kT;
-      for (int e = tid; e < kC * kT * kT; e += kThreads) {
-        const int o = e / (kT * kT), p = e % (kT * kT);
-        const int Y = oy0 + p / kT, X = ox0 + p % kT;
-        const bool in = Y < H && X < W;
-        a2_s[e] = in ? a2[((int64_t)f * kC + o) * plane + (int64_t)Y * W + X] : 0.0f;
-        if (o < kSrOut)
-          dy_s[e] = in ? dy[((int64_t)f * kSrOut + o) * plane + (int64_t)Y * W + X] : 0.0f;
-      }
+      constexpr int P = kT * kT;
+      stage<kC * P>(tid, make_rsrc(a2 + (int64_t)f * kC * plane, fb),
+                    [&](int e) { return own(e / P, e % P); }, [&](int e) { return a2_s + e; });
+      stage<kSrOut * P>(tid, make_rsrc(dy + (int64_t)f * kSrOut * plane, 4 * kSrOut * plane),
+                        [&](int e) { return own(e / P, e % P); }, [&](int e) { return dy_s + e; });
       __syncthreads();
-      if (tid < kSrOut * kC) {
-        const int k = tid / kC, o = tid % kC;
-        for (int p = 0; p < kT * kT; ++p)
-          acc_head = fmaf(dy_s[k * kT * kT + p], a2_s[o * kT * kT + p], acc_head);
-      } else if (tid < kSrOut * kC + kSrOut) {
-        const int k = tid - kSrOut * kC;
-        for (int p = 0; p < kT * kT; ++p) acc_head += dy_s[k * kT * kT + p];
+      if (wave < 3) {
+        const int nc = 16 * wave + col;            // column: a2 channel, 32 = ones
+#pragma unroll 8
+        for (int s = 0; s < kT * kT / 4; ++s) {
+          const int p = 4 * s + grp;
+          const float av = col < kSrOut ? dy_s[col * kT * kT + p] : 0.0f;
+          const float bv = nc < kC ? a2_s[nc * kT * kT + p] : (nc == kC ? 1.0f : 0.0f);
+          acc_h = mfma4(av, bv, acc_h);
+        }
       }
       __syncthreads();
     }
@@ -443,56 +524,46 @@ __global__ __launch_bounds__(kThreads, 2) void sr_bwd_wgrad_kernel(
     // act_s [32][18][18] = a1 over the tile and a one-pixel halo; zero
     // outside the image.
     float *act_s = buf + kC * kDzStride;
-    for (int e = tid; e < kC * kT * kT; e += kThreads) {
-      const int o = e / (kT * kT), p = e % (kT * kT);
-      const int Y = oy0 + p / kT, X = ox0 + p % kT;
-      dz_s[o * kDzStride + p] =
-          (Y < H && X < W) ? dz2[((int64_t)f * kC + o) * plane + (int64_t)Y * W + X] : 0.0f;
-    }
-    for (int e = tid; e < kC * kP1; e += kThreads) {
-      const int c = e / kP1, r = (e / kE1) % kE1, q = e % kE1;
-      const int Y = oy0 - 1 + r, X = ox0 - 1 + q;
-      act_s[e] = (Y >= 0 && Y < H && X >= 0 && X < W)
-                     ? a1[((int64_t)f * kC + c) * plane + (int64_t)Y * W + X] : 0.0f;
-    }
+    constexpr int P = kT * kT;
+    stage<kC * P>(tid, make_rsrc(dz2 + (int64_t)f * kC * plane, fb),
+                  [&](int e) { return own(e / P, e % P); },
+                  [&](int e) { return dz_s + (e / P) * kDzStride + e % P; });
+    stage<kC * kP1>(tid, make_rsrc(a1 + (int64_t)f * kC * plane, fb),
+                    [&](int e) { return halo(e / kP1, e % kP1); }, [&](int e) { return act_s + e; });
     __syncthreads();
-    wgrad_gemm<kNJ2>(dz_s, act_s, kC * 9, acc2, lane, wave);
-    if (tid < kC)
-      for (int p = 0; p < kT * kT; ++p) acc_b += dz_s[tid * kDzStride + p];
+    wgrad_gemm<kNJ2>(dz_s, act_s, ones_s, kC * 9, acc2, lane, wave);
     __syncthreads();
     // phase B: conv1.  dz_s = dz1 over the tile's own pixels, x_s
     // [17][18][18] = the input over the tile and a one-pixel halo.
     float *x_s = buf + kC * kDzStride;
-    for (int e = tid; e < kC * kT * kT; e += kThreads) {
-      const int o = e / (kT * kT), p = e % (kT * kT);
-      const int Y = oy0 + p / kT, X = ox0 + p % kT;
-      dz_s[o * kDzStride + p] =
-          (Y < H && X < W) ? dz1[((int64_t)f * kC + o) * plane + (int64_t)Y * W + X] : 0.0f;
-    }
+    stage<kC * P>(tid, make_rsrc(dz1 + (int64_t)f * kC * plane, fb),
+                  [&](int e) { return own(e / P, e % P); },
+                  [&](int e) { return dz_s + (e / P) * kDzStride + e % P; });
+    // the 14 G-buffer channels, then the upsampled render
+    stage<(kIn - 3) * kP1>(tid, make_rsrc(gbuf + (int64_t)f * (kIn - 3) * plane,
+                                          4 * (kIn - 3) * plane),
+                           [&](int e) { return halo(e / kP1, e % kP1); },
+                           [&](int e) { return x_s + 3 * kP1 + e; });
     const float *lo_f = lowres + (int64_t)f * 3 * plane_lo;
-    for (int e = tid; e < kIn * kP1; e += kThreads) {
-      const int c = e / kP1, r = (e / kE1) % kE1, q = e % kE1;
-      const int Y = oy0 - 1 + r, X = ox0 - 1 + q;
-      float v = 0.0f;
-      if (Y >= 0 && Y < H && X >= 0 && X < W)
-        v = c < 3 ? upsampled(lo_f, h, w, c, Y, X)
-                  : gbuf[((int64_t)f * (kIn - 3) + c - 3) * plane + (int64_t)Y * W + X];
-      x_s[e] = v;
+    for (int e = tid; e < 3 * kP1; e += kThreads) {
+      const int q = e % kP1, Y = oy0 - 1 + q / kE1, X = ox0 - 1 + q % kE1;
+      x_s[e] = halo_in(q) ? upsampled(lo_f, h, w, e / kP1, Y, X) : 0.0f;
     }
     __syncthreads();
-    wgrad_gemm<kNJ1w>(dz_s, x_s, kIn * 9, acc1, lane, wave);
-    if (tid < kC)
-      for (int p = 0; p < kT * kT; ++p) acc_b1 += dz_s[tid * kDzStride + p];
+    wgrad_gemm<kNJ1w>(dz_s, x_s, ones_s, kIn * 9, acc1, lane, wave);
     __syncthreads();
   }
   float *out = partial + (int64_t)blockIdx.x * kSrParams;
-  wgrad_store<kNJ2>(acc2, kC * 9, out + kOffW2, lane, wave);
-  wgrad_store<kNJ1w>(acc1, kIn * 9, out, lane, wave);
-  if (tid < kSrOut * kC) out[kOffW3p + tid] = acc_head;
-  else if (tid < kSrOut * kC + kSrOut) out[kOffB3p + tid - kSrOut * kC] = acc_head;
-  if (tid < kC) {
-    out[kOffB2p + tid] = acc_b;
-    out[kC * kIn * 9 + tid] = acc_b1;
+  wgrad_store<kNJ2>(acc2, kC * 9, out + kOffW2, out + kOffB2p, lane, wave);
+  wgrad_store<kNJ1w>(acc1, kIn * 9, out, out + kC * kIn * 9, lane, wave);
+  // head: lane (col, grp) holds rows 4 grp + i (outputs k) of column 16 wave + col
+  if (wave < 3 && grp == 0) {
+    const int nc = 16 * wave + col;
+#pragma unroll
+    for (int i = 0; i < kSrOut; ++i) {
+      if (nc < kC) out[kOffW3p + i * kC + nc] = acc_h[i];
+      else if (nc == kC) out[kOffB3p + i] = acc_h[i];
+    }
   }
 }
 

@@ -98,22 +98,6 @@ __device__ __forceinline__ f32x4 mfma4(float a, float b, f32x4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
-// Channel c of the render upsampled x2 at output pixel (Y, X), inside the
-// image: source position (Y + 0.5) / 2 - 0.5, i.e. rows Y/2 - 1 and Y/2 at
-// weights 1/4 and 3/4 for even Y, rows (Y-1)/2 and (Y+1)/2 at 3/4 and 1/4 for
-// odd Y (clamped into the image); likewise for columns.
-__device__ __forceinline__ float upsampled(const float *__restrict__ lo_f, int h, int w, int c,
-                                           int Y, int X) {
-  const int y0 = (Y >> 1) - ((Y & 1) ? 0 : 1), x0 = (X >> 1) - ((X & 1) ? 0 : 1);
-  const float fy = (Y & 1) ? 0.25f : 0.75f, fx = (X & 1) ? 0.25f : 0.75f;
-  const int ya = max(y0, 0), yb = min(y0 + 1, h - 1);
-  const int xa = max(x0, 0), xb = min(x0 + 1, w - 1);
-  const float *p = lo_f + (int64_t)c * h * w;
-  const float top = (1.0f - fx) * p[(int64_t)ya * w + xa] + fx * p[(int64_t)ya * w + xb];
-  const float bot = (1.0f - fx) * p[(int64_t)yb * w + xa] + fx * p[(int64_t)yb * w + xb];
-  return (1.0f - fy) * top + fy * bot;
-}
-
 // LDS staging with many loads in flight: element e < N of a block goes to
 // dst(e) from byte offset off(e) of the buffer behind r (kOutside, past the
 // buffer's bound, reads zero: the callers' zero padding).  Loads guarded by a
@@ -145,6 +129,51 @@ __device__ __forceinline__ void stage(int tid, rsrc_t r, Off off, Dst dst) {
     for (int j = 0; j < kG; ++j) {
       const int e = tid + (i0 + j) * kThreads;
       if (i0 + j < kIt && (N % kThreads == 0 || e < N)) *dst(e) = v[j];
+    }
+  }
+}
+
+// The render's 3 channels upsampled x2 into LDS over a square window of edge
+// E at (y0, x0) of the output image: element e < 3 E^2 is channel e / E^2,
+// row (e / E) % E, column e % E.  Output pixel (Y, X) samples source
+// position (Y + 0.5) / 2 - 0.5: rows Y/2 - 1 and Y/2 at weights 1/4 and 3/4
+// for even Y, rows (Y-1)/2 and (Y+1)/2 at 3/4 and 1/4 for odd Y (clamped
+// into the image); likewise for columns.  Outside the image
+// the four source offsets are past the buffer's bound, so the loads read
+// zeros and the blend is zero; groups of 4 elements issue their 16 loads
+// before any store.
+template <int E>
+__device__ __forceinline__ void stage_up(int tid, rsrc_t rlo, int h, int w, int y0, int x0,
+                                         float *dst) {
+  constexpr int N = 3 * E * E, kIt = (N + kThreads - 1) / kThreads, kG = 4;
+  const int H = 2 * h, W = 2 * w;
+  for (int i0 = 0; i0 < kIt; i0 += kG) {
+    float v[kG][4], fx[kG], fy[kG];
+#pragma unroll
+    for (int j = 0; j < kG; ++j) {
+      const int e = min(tid + (i0 + j) * kThreads, N - 1);
+      const int c = e / (E * E), Y = y0 + (e / E) % E, X = x0 + e % E;
+      const bool ok = i0 + j < kIt && Y >= 0 && Y < H && X >= 0 && X < W;
+      const int sy = (Y >> 1) - ((Y & 1) ? 0 : 1), sx = (X >> 1) - ((X & 1) ? 0 : 1);
+      fy[j] = (Y & 1) ? 0.25f : 0.75f;
+      fx[j] = (X & 1) ? 0.25f : 0.75f;
+      const int ya = max(sy, 0), yb = min(sy + 1, h - 1), xa = max(sx, 0), xb = min(sx + 1, w - 1);
+      const uint32_t base = (uint32_t)(c * h * w);
+      const uint32_t o[4] = {base + ya * w + xa, base + ya * w + xb, base + yb * w + xa,
+                             base + yb * w + xb};
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+        v[j][k] = __builtin_bit_cast(
+            float, __builtin_amdgcn_raw_buffer_load_b32(rlo, ok ? 4 * o[k] : kOutside, 0, 0));
+    }
+#pragma unroll
+    for (int j = 0; j < kG; ++j) {
+      const int e = tid + (i0 + j) * kThreads;
+      if (i0 + j < kIt && (N % kThreads == 0 || e < N)) {
+        const float top = (1.0f - fx[j]) * v[j][0] + fx[j] * v[j][1];
+        const float bot = (1.0f - fx[j]) * v[j][2] + fx[j] * v[j][3];
+        dst[e] = (1.0f - fy[j]) * top + fy[j] * bot;
+      }
     }
   }
 }
@@ -187,10 +216,7 @@ __global__ __launch_bounds__(kThreads, 2) void sr_forward_kernel(
           return inside(e) ? (uint32_t)(4 * ((e / E2) * plane_hi + pix(e))) : kOutside;
         },
         [&](int e) { return in_s + 3 * E2 + e; });
-    for (int e = tid; e < 3 * E2; e += kThreads) {
-      const int Y = oy0 - 2 + (e / kE0) % kE0, X = ox0 - 2 + e % kE0;
-      in_s[e] = inside(e) ? upsampled(lo_f, h, w, e / E2, Y, X) : 0.0f;
-    }
+    stage_up<kE0>(tid, make_rsrc(lo_f, 4 * 3 * plane_lo), h, w, oy0 - 2, ox0 - 2, in_s);
     for (int e = tid; e < (kInP - kIn) * E2; e += kThreads) in_s[kIn * E2 + e] = 0.0f;
   }
 
@@ -406,26 +432,25 @@ __device__ __forceinline__ void wgrad_gemm(const float *dz_s, const float *act_s
                                            const float *ones_s, int ncol, f32x4 (&acc)[NJ][2],
                                            int lane, int wave) {
   const int col = lane % 16, grp = lane / 16;
-  float a[kT * kT / 4][2];
-#pragma unroll
-  for (int s = 0; s < kT * kT / 4; ++s) {
-    a[s][0] = dz_s[col * kDzStride + 4 * s + grp];
-    a[s][1] = dz_s[(16 + col) * kDzStride + 4 * s + grp];
-  }
+  // the wave's column tiles; a tile past the last column repeats the ones
+  // column (its sums are never stored)
+  const float *src[NJ];
 #pragma unroll
   for (int jj = 0; jj < NJ; ++jj) {
-    const int j = wave + (kThreads / 64) * jj;
-    if (16 * j > ncol) continue;
-    const int n = min(16 * j + col, ncol);
+    const int n = min(16 * (wave + (kThreads / 64) * jj) + col, ncol);
     const int c = n / 9, tap = n % 9;
-    const float *src = n == ncol ? ones_s + grp
-                                 : act_s + c * kP1 + (tap / 3) * kE1 + tap % 3 + grp;
+    src[jj] = n == ncol ? ones_s + grp : act_s + c * kP1 + (tap / 3) * kE1 + tap % 3 + grp;
+  }
+#pragma unroll 4
+  for (int s = 0; s < kT * kT / 4; ++s) {
+    // pixel p = 4 s + grp: row s / 4, column 4 (s % 4) + grp
+    const float a0 = dz_s[col * kDzStride + 4 * s + grp];
+    const float a1 = dz_s[(16 + col) * kDzStride + 4 * s + grp];
 #pragma unroll
-    for (int s = 0; s < kT * kT / 4; ++s) {
-      // pixel p = 4 s + grp: row s / 4, column 4 (s % 4) + grp
-      const float b = src[(s / 4) * kE1 + 4 * (s % 4)];
-      acc[jj][0] = mfma4(a[s][0], b, acc[jj][0]);
-      acc[jj][1] = mfma4(a[s][1], b, acc[jj][1]);
+    for (int jj = 0; jj < NJ; ++jj) {
+      const float b = src[jj][(s / 4) * kE1 + 4 * (s % 4)];
+      acc[jj][0] = mfma4(a0, b, acc[jj][0]);
+      acc[jj][1] = mfma4(a1, b, acc[jj][1]);
     }
   }
 }
@@ -491,10 +516,6 @@ __global__ __launch_bounds__(kThreads, 2) void sr_bwd_wgrad_kernel(
       return Y >= 0 && Y < H && X >= 0 && X < W ? (uint32_t)(4 * (c * plane + (int64_t)Y * W + X))
                                                 : kOutside;
     };
-    auto halo_in = [&](int q) {
-      const int Y = oy0 - 1 + q / kE1, X = ox0 - 1 + q % kE1;
-      return Y >= 0 && Y < H && X >= 0 && X < W;
-    };
     const int64_t fb = 4 * kC * plane;   // bytes of one frame's 32 planes
     // phase 0: the head, dW3[k][o] = sum_p dy[k][p] a2[o][p] and b3[k] =
     // sum_p dy[k][p] on the matrix cores: dy (3 rows of 16) the row operand,
@@ -544,11 +565,8 @@ __global__ __launch_bounds__(kThreads, 2) void sr_bwd_wgrad_kernel(
                                           4 * (kIn - 3) * plane),
                            [&](int e) { return halo(e / kP1, e % kP1); },
                            [&](int e) { return x_s + 3 * kP1 + e; });
-    const float *lo_f = lowres + (int64_t)f * 3 * plane_lo;
-    for (int e = tid; e < 3 * kP1; e += kThreads) {
-      const int q = e % kP1, Y = oy0 - 1 + q / kE1, X = ox0 - 1 + q % kE1;
-      x_s[e] = halo_in(q) ? upsampled(lo_f, h, w, e / kP1, Y, X) : 0.0f;
-    }
+    stage_up<kE1>(tid, make_rsrc(lowres + (int64_t)f * 3 * plane_lo, 4 * 3 * plane_lo), h, w,
+                  oy0 - 1, ox0 - 1, x_s);
     __syncthreads();
     wgrad_gemm<kNJ1w>(dz_s, x_s, ones_s, kIn * 9, acc1, lane, wave);
     __syncthreads();

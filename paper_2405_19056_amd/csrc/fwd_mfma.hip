@@ -35,6 +35,7 @@ typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 typedef int i32x8 __attribute__((ext_vector_type(8)));
+typedef int i32x4 __attribute__((ext_vector_type(4)));
 typedef const float __attribute__((address_space(1))) gcfloat;
 typedef float __attribute__((address_space(1))) gfloat;
 typedef u32x4 __attribute__((address_space(1))) gu32x4;
@@ -178,9 +179,14 @@ __device__ __forceinline__ uint2 ld_frag16(const uint8_t *chunk, int idx, int la
   return *(const uint2 *)(chunk + (size_t)idx * 512 + lane * 8);
 }
 
-// One fp8 A fragment of the 16x16x128 instruction: 64 lanes x 32 bytes.
+// One fp8 A fragment of the 16x16x128 instruction: 64 lanes x 32 bytes,
+// stored as two 1 KiB halves (bytes 0-15 of every lane, then bytes 16-31),
+// so each 16-byte LDS read has consecutive lanes 16 bytes apart (a 32-byte
+// lane stride would put two lanes on every bank).
 __device__ __forceinline__ i32x8 ld_frag8(const uint8_t *chunk, int idx, int lane) {
-  return *(const i32x8 *)(chunk + (size_t)idx * 2 * kFrag + lane * 32);
+  const uint8_t *f = chunk + (size_t)idx * 2 * kFrag + lane * 16;
+  const i32x4 lo = *(const i32x4 *)f, hi = *(const i32x4 *)(f + kFrag);
+  return i32x8{lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
 }
 
 template <int MT_>
@@ -1165,7 +1171,9 @@ __global__ void pack_bf16_kernel(PackArgs p) {
 // fp8 copy of h's second layer (the layer that runs once per slot): per output
 // row n a scale s_n = max_k |A2[n][k]| / 448 and bytes E4M3(A2[n][k] / s_n),
 // stored as MT fragments of 64 lanes x 32 bytes.  Lane 16 g + (n & 15) of
-// fragment n >> 4 holds, at byte 4 q + r, input k = 16 q + 4 g + r.
+// fragment n >> 4 holds, at byte 4 q + r, input k = 16 q + 4 g + r; a
+// fragment keeps bytes 0-15 of every lane in its first KiB and bytes 16-31
+// in its second (ld_frag8).
 // One block per output row, one thread per input.
 __global__ void pack_fp8_t2_kernel(PackArgs p, uint8_t *q8, float *scale) {
   __shared__ float red[256];
@@ -1185,7 +1193,7 @@ __global__ void pack_fp8_t2_kernel(PackArgs p, uint8_t *q8, float *scale) {
   const uint8_t b = (uint8_t)(__builtin_amdgcn_cvt_pk_fp8_f32(x, 0.0f, 0, false) & 0xff);
   const int g = (k & 15) >> 2, j = 4 * (k >> 4) + (k & 3);
   const int lane = 16 * g + (n & 15);
-  q8[(size_t)(n >> 4) * 2048 + lane * 32 + j] = b;
+  q8[(size_t)(n >> 4) * 2048 + (j >> 4) * 1024 + lane * 16 + (j & 15)] = b;
 }
 
 __global__ void pack_bias_kernel(PackArgs p) {

@@ -51,8 +51,9 @@ typedef float f32x2 __attribute__((ext_vector_type(2)));
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kWaves = 8, kThreads = kWaves * 64;
-constexpr int kNT = 4;                       // N-tiles (16 pixels) per wave
-constexpr int kWavePx = kNT * 16;            // pixels per wave (one row segment)
+// N-tiles (16 pixels) per wave of the generic conv: 4 for the narrow convs,
+// 2 for the W = 128 ones (half the registers: two workgroups per CU, four
+// waves per SIMD to hide the input loads' latency)
 constexpr int kChunk = 4;                    // K-steps per LDS weight chunk (even)
 static_assert(kChunk % 2 == 0, "the conv loop takes the steps of a chunk in pairs");
 
@@ -113,8 +114,9 @@ struct SpConvArgs {
 
 namespace {
 
-template <int MT>
-__global__ __launch_bounds__(kThreads) void sp_conv_kernel(SpConvArgs a) {
+template <int MT, int kNT>
+__global__ __launch_bounds__(kThreads, kNT == 2 ? 4 : 1) void sp_conv_kernel(SpConvArgs a) {
+  constexpr int kWavePx = kNT * 16;            // pixels per wave (one row segment)
   extern __shared__ __attribute__((aligned(1024))) uint8_t lds[];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int g = lane >> 4, col = lane & 15;
@@ -200,16 +202,23 @@ __global__ __launch_bounds__(kThreads) void sp_conv_kernel(SpConvArgs a) {
   // one K-step: all MT weight fragments requested from LDS first (held there
   // by a scheduling barrier, else each read sinks next to its MFMAs and is
   // waited for alone), then the MFMAs
+  // (With two N-tiles per wave the fragments come in two groups of MT / 2,
+  // the second group's reads issued behind the first group's MFMAs: fewer
+  // registers, for four waves per SIMD.)
   auto step = [&](const uint8_t *Ws, const u32x4 (&b)[kNT]) {
-    u32x4 w[MT];
+    constexpr int kG = kNT >= 4 || MT < 8 ? MT : MT / 2;
 #pragma unroll
-    for (int mt = 0; mt < MT; ++mt) w[mt] = *(const u32x4 *)(Ws + mt * kFrag + lane * 16);
-    __builtin_amdgcn_sched_barrier(0);
+    for (int m0 = 0; m0 < MT; m0 += kG) {
+      u32x4 w[kG];
 #pragma unroll
-    for (int mt = 0; mt < MT; ++mt)
+      for (int i = 0; i < kG; ++i) w[i] = *(const u32x4 *)(Ws + (m0 + i) * kFrag + lane * 16);
+      __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-      for (int t = 0; t < kNT; ++t) acc[t][mt] = mma(w[mt], b[t], acc[t][mt]);
-    __builtin_amdgcn_sched_barrier(0);
+      for (int i = 0; i < kG; ++i)
+#pragma unroll
+        for (int t = 0; t < kNT; ++t) acc[t][m0 + i] = mma(w[i], b[t], acc[t][m0 + i]);
+      __builtin_amdgcn_sched_barrier(0);
+    }
   };
 
   fill(0);
@@ -766,27 +775,27 @@ static hipError_t sp_slots_launch(const SpSlotsArgs &a, hipStream_t s) {
   return hipGetLastError();
 }
 
-template <int MT>
+template <int MT, int NT>
 static hipError_t sp_launch(const SpConvArgs &a, hipStream_t s) {
   static bool attr = false;
   const size_t lds = 2 * (size_t)kChunk * MT * kFrag;
   if (!attr) {
-    hipError_t e = hipFuncSetAttribute((const void *)sp_conv_kernel<MT>,
+    hipError_t e = hipFuncSetAttribute((const void *)sp_conv_kernel<MT, NT>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     attr = true;
   }
-  const int64_t segs = (int64_t)a.n * a.H * ((a.Wd + kWavePx - 1) / kWavePx);
+  const int64_t segs = (int64_t)a.n * a.H * ((a.Wd + 16 * NT - 1) / (16 * NT));
   const unsigned grid = (unsigned)((segs + kWaves - 1) / kWaves);
-  hipLaunchKernelGGL(sp_conv_kernel<MT>, dim3(grid), dim3(kThreads), lds, s, a);
+  hipLaunchKernelGGL((sp_conv_kernel<MT, NT>), dim3(grid), dim3(kThreads), lds, s, a);
   return hipGetLastError();
 }
 
 static hipError_t sp_conv(const SpConvArgs &a0, int mt, hipStream_t s) {
   switch (mt) {
-    case 1: return sp_launch<1>(a0, s);
-    case 4: return sp_launch<4>(a0, s);
-    case 8: return sp_launch<8>(a0, s);
+    case 1: return sp_launch<1, 4>(a0, s);
+    case 4: return sp_launch<4, 4>(a0, s);
+    case 8: return sp_launch<8, 2>(a0, s);
   }
   return hipErrorInvalidValue;
 }

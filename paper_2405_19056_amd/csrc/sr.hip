@@ -339,8 +339,9 @@ __global__ __launch_bounds__(kThreads, 2) void sr_forward_kernel(
 //   dz2 = [a2 > 0] W3^T dy                       per pixel
 //   dz1 = [a1 > 0] (conv2's transpose of dz2)    per pixel, 3x3 neighbourhood
 //   dW3 = sum dy a2^T, dW2 = sum dz2 (a1 window)^T, dW1 = sum dz1 (x window)^T
-// per 16 x 16 tile into fp32 partials, then fp64 sums over the tiles in a
-// fixed order (deterministic).  The transposed conv and the two conv weight
+// per persistent workgroup into one row of fp32 partials, then fp32 sums of
+// those rows, in groups and then over the groups, each in a fixed order
+// (deterministic).  The transposed conv and the two conv weight
 // gradients run on the fp32 matrix cores; the rest is per-pixel vector work.
 
 __global__ __launch_bounds__(kThreads) void sr_bwd_dz2_kernel(

@@ -113,7 +113,8 @@ def _per_tensor_relF(g, ref):
                                    (1, 3, 200)])
 def test_sr_backward_matches_oracle(n, h, w):
     """Against the FP64 oracle's gradient, every tensor within relF 1e-4 (fp32
-    sums over up to 2^16 pixels per weight, per-tile partials added in fp64);
+    sums over up to 2^16 pixels per weight, per-workgroup partials added in
+    fp32 in a fixed order);
     repeated calls are bitwise equal."""
     torch = torch_dev()
     wts = synth.make_sr_weights(np.random.default_rng(h * 7 + w))

@@ -185,6 +185,38 @@ def test_slot_permutations_are_bitwise(precision, k):
 
 
 @pytest.mark.parametrize("precision", ["fp32", "bf16", "fp8_t"])
+@pytest.mark.parametrize("k,W,pe,order", [(8, 128, 0, "canonical"), (3, 64, 0, "canonical"),
+                                          (12, 128, 0, "canonical"), (6, 128, 2, "canonical"),
+                                          (8, 128, 0, "input")])
+def test_pixel_permutations_are_bitwise(precision, k, W, pe, order):
+    """Pixels are independent (Sec. 3.4), and every path computes each one
+    the same whichever lane, wave and tile it lands in: moving pixels around
+    the frame (tail tile included) changes which pixels share a wave, its
+    slot-skip decisions and the tail lanes' duplicates, but no output bit.
+    Canonical order with the register ranking (k <= 8) and the general one
+    (k = 12), encoded inputs, input order and the plane pipeline."""
+    if precision == "fp8_t" and W != 128:
+        pytest.skip("fp8_t is built for W = 128")
+    h, w = 48, 44                     # 2112 px: 8 full tiles and a ragged one
+    wts, fr = frame(2, h, w, k, W, seed=40 + k + pe, alpha_mode="uniform_count")
+    if pe:
+        wts = synth.make_weights(W, synth.streams(40 + k)["weights"], pe_levels=pe)
+    rng = np.random.default_rng(k * 7 + pe)
+    with GlassNet(wts, W, k_max=16, precision=precision, pe_levels=pe, slot_order=order) as net:
+        if precision == "fp8_t":
+            calibrate(net, W, 4)
+        y0 = run(net, fr)
+        for _ in range(3):
+            perm = rng.permutation(h * w)
+            g = fr.gbuf.reshape(2, -1, h * w)[:, :, perm].reshape(fr.gbuf.shape)
+            L = fr.layers.reshape(2, k, -1, h * w)[:, :, :, perm].reshape(fr.layers.shape)
+            y = run(net, synth.Frame(g, L, fr.scene))
+            back = np.empty_like(y.reshape(2, 3, h * w))
+            back[:, :, perm] = y.reshape(2, 3, h * w)
+            assert np.array_equal(back.reshape(y0.shape), y0)
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16", "fp8_t"])
 def test_equal_alphas_take_the_full_record_order(precision):
     """Active slots of equal alpha are ordered by their other planes: a frame
     whose slots share a handful of alpha values (and some fully duplicated

@@ -875,6 +875,7 @@ __global__ __launch_bounds__(kThreads) void fwd_mfma_kernel(MfmaArgs a) {
                 zq[t][mt] = relu_pack_fp8x4(mma16(w, bi[t][0], u[t][mt]));
             }
           }
+          __builtin_amdgcn_s_setprio(1);   // as for the bf16 layer 2 below
           // h layer 2 on the fp8 matrix cores (K = 128 in one instruction),
           // the running sum kept in units of the dequantisation factor s
           // (applied at the pool); each M-tile's fragment is requested one
@@ -924,6 +925,13 @@ __global__ __launch_bounds__(kThreads) void fwd_mfma_kernel(MfmaArgs a) {
               }
             }
           }
+          // h layer 2 at raised wave priority: of the two waves that share a
+          // SIMD, the one in this layer issues first, which offsets the pair
+          // so that one's matrix-core work overlaps the other's layer 1 and
+          // LDS reads (1-1.5% of the 512^2 K = 8 frame in bf16, ~1% in fp8;
+          // issuing the next M-tile's MFMAs before each M-tile's relu and
+          // running sum was slower in both forms).
+          __builtin_amdgcn_s_setprio(1);
           // h layer 2 and the masked running sum: Z += m * relu(A2 z1 + c2).
           // The fragments stream one K-step ahead of the MFMAs that use them.
           u32x4 wnext = ld_frag(T2, 0, lane);
@@ -952,6 +960,7 @@ __global__ __launch_bounds__(kThreads) void fwd_mfma_kernel(MfmaArgs a) {
           }
 #pragma unroll
           for (int t = 0; t < kNT; ++t) cnt[t] += m[t];
+          __builtin_amdgcn_s_setprio(0);
         }
       }
       if constexpr (MODE == FWD_ACC) {

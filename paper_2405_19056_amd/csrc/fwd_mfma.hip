@@ -222,7 +222,11 @@ __device__ __forceinline__ void to_frags(const f32x4 (&acc)[kNT][MT_], u32x4 (&o
 // for M-tiles 2p and 2p+1.  The pair's weight fragments are read up front and
 // the next pair's are requested before this pair's MFMAs issue, so LDS
 // latency overlaps matrix-core work instead of stalling every K-step.
-template <int MT_, int KS_, bool RELU>
+// EARLY: a scheduling barrier keeps the next M-tiles' fragment reads ahead of
+// the current M-tiles' MFMAs (left alone, the scheduler sinks each read next
+// to its MFMAs and waits for it alone): 3.5-5% of the bf16 frame.  The fp8
+// form's kernel spills with it, so it leaves the placement to the scheduler.
+template <int MT_, int KS_, bool RELU, bool EARLY>
 __device__ __forceinline__ void layer(u32x4 (&out)[kNT][MT_ / 2], const uint8_t *chunk,
                                       const u32x4 (&in)[kNT][KS_], const float *bias, int g,
                                       int lane) {
@@ -241,6 +245,7 @@ __device__ __forceinline__ void layer(u32x4 (&out)[kNT][MT_ / 2], const uint8_t 
         for (int ks = 0; ks < KS_; ++ks)
           wb[cur ^ 1][h][ks] = ld_frag(chunk, (2 * (p + 1) + h) * KS_ + ks, lane);
     }
+    if constexpr (EARLY) __builtin_amdgcn_sched_barrier(0);
     f32x4 acc[kNT][2];
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
@@ -274,8 +279,9 @@ __device__ __forceinline__ void layer(u32x4 (&out)[kNT][MT_ / 2], const uint8_t 
 }
 
 // acc[t][mt] += A(chunk) . in[t] over the chunk's KS_ K-steps, one M-tile's
-// fragments read ahead of its MFMAs and the next M-tile's requested early.
-template <int MT_, int KS_>
+// fragments read ahead of its MFMAs and the next M-tile's requested early
+// (EARLY as for layer).
+template <int MT_, int KS_, bool EARLY>
 __device__ __forceinline__ void mm(f32x4 (&acc)[kNT][MT_], const uint8_t *chunk,
                                    const u32x4 (&in)[kNT][KS_], int lane) {
   u32x4 wb[2][KS_];
@@ -288,6 +294,7 @@ __device__ __forceinline__ void mm(f32x4 (&acc)[kNT][MT_], const uint8_t *chunk,
 #pragma unroll
       for (int ks = 0; ks < KS_; ++ks) wb[cur ^ 1][ks] = ld_frag(chunk, (mt + 1) * KS_ + ks, lane);
     }
+    if constexpr (EARLY) __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int ks = 0; ks < KS_; ++ks)
 #pragma unroll
@@ -386,6 +393,7 @@ __global__ __launch_bounds__(kThreads) void fwd_mfma_kernel(MfmaArgs a) {
   };
   // bf16: [T1A | T2 (bf16)]; fp8: [T1A | T2 (fp8, 2 KiB fragments) | T2 row scales]
   constexpr bool kFp8 = PREC == GN_FP8_T;
+  constexpr bool kEarly = !kFp8;      // fragment reads held ahead of their MFMAs (layer, mm)
   constexpr int kT1ABytes = (MT * kNK16 * 512 + 1023) & ~1023;   // K=16 fragments of 512 B
   if constexpr (kSlots) {
     if (kFp8) {
@@ -573,8 +581,8 @@ __global__ __launch_bounds__(kThreads) void fwd_mfma_kernel(MfmaArgs a) {
                             pk_bf16(xr[t][4], xr[t][5]), pk_bf16(xr[t][6], xr[t][7])};
           const uint8_t *S = stage_buf(sF1);
           u32x4 h1[kNT][KS];
-          layer<MT, 1, true>(h1, S, x, bF1, g, lane);
-          layer<MT, KS, true>(h2, S + f1_bytes, h1, bF2, g, lane);
+          layer<MT, 1, true, kEarly>(h1, S, x, bF1, g, lane);
+          layer<MT, KS, true, kEarly>(h2, S + f1_bytes, h1, bF2, g, lane);
         }
         if constexpr (MODE == FWD_FULL) {
           wait_vm();
@@ -588,7 +596,7 @@ __global__ __launch_bounds__(kThreads) void fwd_mfma_kernel(MfmaArgs a) {
         {
           u32x4 x[kNT][kF1A];
           enc_frags<0, kF1A>(xr, x);
-          mm<MT, kF1A>(acc, stage_buf(sF1), x, lane);
+          mm<MT, kF1A, kEarly>(acc, stage_buf(sF1), x, lane);
         }
         wait_vm();
         __syncthreads();
@@ -597,14 +605,14 @@ __global__ __launch_bounds__(kThreads) void fwd_mfma_kernel(MfmaArgs a) {
         {
           u32x4 x[kNT][kF1B];
           enc_frags<kF1A, kF1B>(xr, x);
-          mm<MT, kF1B>(acc, stage_buf(sF1B), x, lane);
+          mm<MT, kF1B, kEarly>(acc, stage_buf(sF1B), x, lane);
           to_frags<MT, true>(acc, h1);
         }
         wait_vm();
         __syncthreads();
         fill_stage(sF3);
         if (canon_fast) copy_alphas();
-        layer<MT, KS, true>(h2, stage_buf(sF2), h1, bF2, g, lane);
+        layer<MT, KS, true, kEarly>(h2, stage_buf(sF2), h1, bF2, g, lane);
         wait_vm();
         __syncthreads();
       }
@@ -684,7 +692,7 @@ __global__ __launch_bounds__(kThreads) void fwd_mfma_kernel(MfmaArgs a) {
       if constexpr (MODE == FWD_BEGIN && PE > 0) {
         if (has_next) fill_stage(sF1);      // the next tile's first stage
       }
-      layer<MT, KS, false>(sig, stage_buf(sF3), h2, bF3, g, lane);
+      layer<MT, KS, false, kEarly>(sig, stage_buf(sF3), h2, bF3, g, lane);
       if constexpr (MODE == FWD_BEGIN) {
         // sigma goes to the streaming state; the next tile's F input is requested
 #pragma unroll
@@ -739,7 +747,7 @@ __global__ __launch_bounds__(kThreads) void fwd_mfma_kernel(MfmaArgs a) {
         // first layer for every slot
         f32x4 u[kNT][MT];
         bias_init(u, bT1, g);
-        mm<MT, KS>(u, stage_buf(sT1S), sig, lane);
+        mm<MT, KS, kEarly>(u, stage_buf(sT1S), sig, lane);
 
         if constexpr (kFp8) {
           // fp8: h's first layer runs in units of the activation scale (its
@@ -1030,7 +1038,7 @@ __global__ __launch_bounds__(kThreads) void fwd_mfma_kernel(MfmaArgs a) {
             acc[t][mt] = *(const f32x4 *)(bT3 + 16 * mt + 4 * g) * bs;
           }
         }
-        mm<MT, KS>(acc, stage_buf(sT3), zs, lane);
+        mm<MT, KS, kEarly>(acc, stage_buf(sT3), zs, lane);
         to_frags<MT, false>(acc, tau);
       }
       wait_vm();
@@ -1040,13 +1048,13 @@ __global__ __launch_bounds__(kThreads) void fwd_mfma_kernel(MfmaArgs a) {
       fill_stage(sB1T);
       f32x4 accB[kNT][MT];
       bias_init(accB, bB1, g);
-      mm<MT, KS>(accB, stage_buf(sB1S), sig2, lane);
+      mm<MT, KS, kEarly>(accB, stage_buf(sB1S), sig2, lane);
       wait_vm();
       __syncthreads();
 
       fill_stage(sB2);
       u32x4 hb[kNT][KS];
-      mm<MT, KS>(accB, stage_buf(sB1T), tau, lane);
+      mm<MT, KS, kEarly>(accB, stage_buf(sB1T), tau, lane);
       to_frags<MT, true>(accB, hb);
       wait_vm();
       __syncthreads();
@@ -1061,7 +1069,7 @@ __global__ __launch_bounds__(kThreads) void fwd_mfma_kernel(MfmaArgs a) {
         for (int c = 0; c < 3; ++c) ldr[t][c] = g == 0 ? Gp[(size_t)(11 + c) * hw + qc[t]] : 0.0f;
       {
         u32x4 hb2[kNT][KS];
-        layer<MT, KS, true>(hb2, stage_buf(sB2), hb, bB2, g, lane);
+        layer<MT, KS, true, kEarly>(hb2, stage_buf(sB2), hb, bB2, g, lane);
 #pragma unroll
         for (int t = 0; t < kNT; ++t)
 #pragma unroll
@@ -1073,7 +1081,7 @@ __global__ __launch_bounds__(kThreads) void fwd_mfma_kernel(MfmaArgs a) {
       // ================= stage 7: B layer 3 -> phi =================
       fill_stage(sR1);
       u32x4 phi[kNT][KS];
-      layer<MT, KS, false>(phi, stage_buf(sB3), hb, bB3, g, lane);
+      layer<MT, KS, false, kEarly>(phi, stage_buf(sB3), hb, bB3, g, lane);
       wait_vm();
       __syncthreads();
 
@@ -1087,8 +1095,8 @@ __global__ __launch_bounds__(kThreads) void fwd_mfma_kernel(MfmaArgs a) {
           ld[t][0] = u32x4{pk_bf16(ldr[t][0], ldr[t][1]), pk_bf16(ldr[t][2], 0.0f), 0u, 0u};
         f32x4 acc[kNT][MT];
         bias_init(acc, bR1, g);
-        mm<MT, KS>(acc, stage_buf(sR1), phi, lane);
-        mm<MT, 1>(acc, stage_buf(sR1) + r1p_bytes, ld, lane);
+        mm<MT, KS, kEarly>(acc, stage_buf(sR1), phi, lane);
+        mm<MT, 1, kEarly>(acc, stage_buf(sR1) + r1p_bytes, ld, lane);
         to_frags<MT, true>(acc, hr);
       }
       wait_vm();
@@ -1109,10 +1117,10 @@ __global__ __launch_bounds__(kThreads) void fwd_mfma_kernel(MfmaArgs a) {
       }
       {
         u32x4 hr2[kNT][KS];
-        layer<MT, KS, true>(hr2, stage_buf(sR2), hr, bR2, g, lane);
+        layer<MT, KS, true, kEarly>(hr2, stage_buf(sR2), hr, bR2, g, lane);
         f32x4 y[kNT][1];
         bias_init(y, bR3, g);
-        mm<1, KS>(y, stage_buf(sR2) + r2_bytes, hr2, lane);
+        mm<1, KS, kEarly>(y, stage_buf(sR2) + r2_bytes, hr2, lane);
         // Lane group 0 holds rows 0..2.  Tail lanes store the value of pixel
         // hw - 1 they recomputed (bitwise the same as that pixel's own lane),
         // so exactly 3 kNT store instructions issue, with a non-empty mask.

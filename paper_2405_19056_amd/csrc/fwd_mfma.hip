@@ -224,9 +224,9 @@ __device__ __forceinline__ void to_frags(const f32x4 (&acc)[kNT][MT_], u32x4 (&o
 // latency overlaps matrix-core work instead of stalling every K-step.
 // EARLY: a scheduling barrier keeps the next M-tiles' fragment reads ahead of
 // the current M-tiles' MFMAs (left alone, the scheduler sinks each read next
-// to its MFMAs and waits for it alone): 3.5-5% of the bf16 frame, 1% of the
-// fp8 one, whose kernel spills with it in T3, B and R and there leaves the
-// placement to the scheduler.
+// to its MFMAs and waits for it alone): 3.5-5% of the bf16 frame, 2% of the
+// fp8 one, whose kernel spills with it in T3 and B's first layer and there
+// leaves the placement to the scheduler.
 template <int MT_, int KS_, bool RELU, bool EARLY>
 __device__ __forceinline__ void layer(u32x4 (&out)[kNT][MT_ / 2], const uint8_t *chunk,
                                       const u32x4 (&in)[kNT][KS_], const float *bias, int g,
@@ -394,9 +394,9 @@ __global__ __launch_bounds__(kThreads) void fwd_mfma_kernel(MfmaArgs a) {
   };
   // bf16: [T1A | T2 (bf16)]; fp8: [T1A | T2 (fp8, 2 KiB fragments) | T2 row scales]
   constexpr bool kFp8 = PREC == GN_FP8_T;
-  // fragment reads held ahead of their MFMAs (layer, mm): in F and sigma's
-  // part of h in both forms, in T3, B and R in bf16 (fp8 spills there)
-  constexpr bool kEarly = true, kEarlyHead = !kFp8;
+  // fragment reads held ahead of their MFMAs (layer, mm): everywhere in bf16;
+  // in fp8 everywhere but T3 and B's first layer (it spills there)
+  constexpr bool kEarly = true, kEarlyT3B1 = !kFp8;
   constexpr int kT1ABytes = (MT * kNK16 * 512 + 1023) & ~1023;   // K=16 fragments of 512 B
   if constexpr (kSlots) {
     if (kFp8) {
@@ -1041,7 +1041,7 @@ __global__ __launch_bounds__(kThreads) void fwd_mfma_kernel(MfmaArgs a) {
             acc[t][mt] = *(const f32x4 *)(bT3 + 16 * mt + 4 * g) * bs;
           }
         }
-        mm<MT, KS, kEarlyHead>(acc, stage_buf(sT3), zs, lane);
+        mm<MT, KS, kEarlyT3B1>(acc, stage_buf(sT3), zs, lane);
         to_frags<MT, false>(acc, tau);
       }
       wait_vm();
@@ -1051,13 +1051,13 @@ __global__ __launch_bounds__(kThreads) void fwd_mfma_kernel(MfmaArgs a) {
       fill_stage(sB1T);
       f32x4 accB[kNT][MT];
       bias_init(accB, bB1, g);
-      mm<MT, KS, kEarlyHead>(accB, stage_buf(sB1S), sig2, lane);
+      mm<MT, KS, kEarlyT3B1>(accB, stage_buf(sB1S), sig2, lane);
       wait_vm();
       __syncthreads();
 
       fill_stage(sB2);
       u32x4 hb[kNT][KS];
-      mm<MT, KS, kEarlyHead>(accB, stage_buf(sB1T), tau, lane);
+      mm<MT, KS, kEarlyT3B1>(accB, stage_buf(sB1T), tau, lane);
       to_frags<MT, true>(accB, hb);
       wait_vm();
       __syncthreads();
@@ -1072,7 +1072,7 @@ __global__ __launch_bounds__(kThreads) void fwd_mfma_kernel(MfmaArgs a) {
         for (int c = 0; c < 3; ++c) ldr[t][c] = g == 0 ? Gp[(size_t)(11 + c) * hw + qc[t]] : 0.0f;
       {
         u32x4 hb2[kNT][KS];
-        layer<MT, KS, true, kEarlyHead>(hb2, stage_buf(sB2), hb, bB2, g, lane);
+        layer<MT, KS, true, kEarly>(hb2, stage_buf(sB2), hb, bB2, g, lane);
 #pragma unroll
         for (int t = 0; t < kNT; ++t)
 #pragma unroll
@@ -1084,7 +1084,7 @@ __global__ __launch_bounds__(kThreads) void fwd_mfma_kernel(MfmaArgs a) {
       // ================= stage 7: B layer 3 -> phi =================
       fill_stage(sR1);
       u32x4 phi[kNT][KS];
-      layer<MT, KS, false, kEarlyHead>(phi, stage_buf(sB3), hb, bB3, g, lane);
+      layer<MT, KS, false, kEarly>(phi, stage_buf(sB3), hb, bB3, g, lane);
       wait_vm();
       __syncthreads();
 
@@ -1098,8 +1098,8 @@ __global__ __launch_bounds__(kThreads) void fwd_mfma_kernel(MfmaArgs a) {
           ld[t][0] = u32x4{pk_bf16(ldr[t][0], ldr[t][1]), pk_bf16(ldr[t][2], 0.0f), 0u, 0u};
         f32x4 acc[kNT][MT];
         bias_init(acc, bR1, g);
-        mm<MT, KS, kEarlyHead>(acc, stage_buf(sR1), phi, lane);
-        mm<MT, 1, kEarlyHead>(acc, stage_buf(sR1) + r1p_bytes, ld, lane);
+        mm<MT, KS, kEarly>(acc, stage_buf(sR1), phi, lane);
+        mm<MT, 1, kEarly>(acc, stage_buf(sR1) + r1p_bytes, ld, lane);
         to_frags<MT, true>(acc, hr);
       }
       wait_vm();
@@ -1120,10 +1120,10 @@ __global__ __launch_bounds__(kThreads) void fwd_mfma_kernel(MfmaArgs a) {
       }
       {
         u32x4 hr2[kNT][KS];
-        layer<MT, KS, true, kEarlyHead>(hr2, stage_buf(sR2), hr, bR2, g, lane);
+        layer<MT, KS, true, kEarly>(hr2, stage_buf(sR2), hr, bR2, g, lane);
         f32x4 y[kNT][1];
         bias_init(y, bR3, g);
-        mm<1, KS, kEarlyHead>(y, stage_buf(sR2) + r2_bytes, hr2, lane);
+        mm<1, KS, kEarly>(y, stage_buf(sR2) + r2_bytes, hr2, lane);
         // Lane group 0 holds rows 0..2.  Tail lanes store the value of pixel
         // hw - 1 they recomputed (bitwise the same as that pixel's own lane),
         // so exactly 3 kNT store instructions issue, with a non-empty mask.
